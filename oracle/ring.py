@@ -1,0 +1,196 @@
+"""Ring-polymer dynamics in FP64 (oracle side).
+
+Ring polymer (Sec. 2.1): P beads per atom joined by harmonic springs.  The
+oracle samples exp(-beta_P H_P) with beta_P = beta / P and
+  H_P = sum_k sum_i [ |p_i^k|^2 / (2 m_i) + 1/2 m_i w_P^2 |q_i^k - q_i^{k+1}|^2 ] + sum_k V(q^k),
+  w_P = P k_B T / hbar  (bead index k+1 taken modulo P),
+which has the same configurational distribution as the effective Hamiltonian
+of Sec. 2.1 (springs with sqrt(P)/(beta hbar) and V/P at inverse temperature
+beta) once the momenta are integrated out.  Physical masses are used for
+every mode.
+
+Normal modes (Sec. 2.1 and 2.3 name the normal-mode transformation): the
+orthonormal matrix C with columns
+  k = 0:              1/sqrt(P)
+  1 <= k < P/2:       sqrt(2/P) cos(2 pi j k / P)
+  k = P/2:            (-1)^j / sqrt(P)
+  P/2 < k < P:        sqrt(2/P) sin(2 pi j k / P)
+gives q~_k = sum_j C_jk q_j, and the free ring polymer decouples into
+oscillators of frequency w_k = 2 w_P sin(k pi / P).
+
+Integrator: PILE-L (Ceriotti, Parrinello, Markland, Manolopoulos, J. Chem.
+Phys. 133, 124104 (2010)), named by Table S3, in the symmetric splitting
+O(dt/2) B(dt/2) A(dt) [forces] B(dt/2) O(dt/2):
+  O: p~_k <- c1_k p~_k + sqrt(m k_B T P) c2_k xi,  c1 = exp(-gamma_k dt/2), c2 = sqrt(1 - c1^2),
+     gamma_0 = 1/tau0, gamma_k = 2 lambda w_k;  tau0 <= 0 switches the thermostat off;
+  B: p <- p + dt/2 F;
+  A: centroid drifts, every other mode rotates exactly in its phase space.
+Units: A, fs, amu, eV; momenta in amu A/fs, so a kick is dt/2 F / MVV2E and
+energies carry a factor MVV2E.
+"""
+import numpy as np
+
+from .constants import KB, HBAR, MVV2E
+from . import philox
+
+
+def nm_matrix(P):
+    """C[j, k] as defined in the module docstring (P = 1 or even)."""
+    if P == 1:
+        return np.ones((1, 1))
+    if P % 2:
+        raise ValueError("odd P > 1 is not supported")
+    j = np.arange(P)[:, None]
+    C = np.empty((P, P))
+    C[:, 0] = 1.0 / np.sqrt(P)
+    for k in range(1, P):
+        if k < P // 2:
+            C[:, k] = np.sqrt(2.0 / P) * np.cos(2 * np.pi * j[:, 0] * k / P)
+        elif k == P // 2:
+            C[:, k] = (-1.0) ** j[:, 0] / np.sqrt(P)
+        else:
+            C[:, k] = np.sqrt(2.0 / P) * np.sin(2 * np.pi * j[:, 0] * k / P)
+    return C
+
+
+def mode_frequencies(P, T):
+    wP = P * KB * T / HBAR
+    return 2.0 * wP * np.sin(np.arange(P) * np.pi / P), wP
+
+
+class RingPolymers:
+    """State and OBABO stepping of a list of independent ring polymers.
+
+    systems: list of (n_atoms, n_beads, temperature, masses[n_atoms]).
+    force_fn(q[sum P_s N_s, 3]) -> (E_bead[sum P_s], F[sum P_s N_s, 3]).
+    State arrays use the bead-major, system-concatenated layout
+    index = off_s + k N_s + i; the thermostat noise of (system, mode k, atom i)
+    uses the same index as its Philox counter.
+    """
+
+    def __init__(self, systems, dt, tau0, pile_lambda, seed, force_fn):
+        self.systems = systems
+        self.dt, self.tau0, self.lam, self.seed = dt, tau0, pile_lambda, seed
+        self.force_fn = force_fn
+        self.offsets = np.cumsum([0] + [n * P for n, P, _, _ in systems])
+        self.total = int(self.offsets[-1])
+        self.heat = np.zeros(len(systems))
+        self.step_count = 0
+        self.q = self.p = self.F = self.E = None
+
+    # -- per-system views ---------------------------------------------------
+    def _view(self, a, s):
+        n, P, _, _ = self.systems[s]
+        return a[self.offsets[s]:self.offsets[s + 1]].reshape(P, n, 3)
+
+    def set_state(self, q, p, step=0):
+        self.q = np.array(q, dtype=np.float64).reshape(-1, 3)
+        self.p = np.array(p, dtype=np.float64).reshape(-1, 3)
+        self.step_count = step
+        self.E, self.F = self.force_fn(self.q)
+
+    # -- the four sub-steps ---------------------------------------------------
+    def _o_step(self, s, pt, xi):
+        n, P, T, m = self.systems[s]
+        wk, _ = mode_frequencies(P, T)
+        if self.tau0 > 0:
+            gamma = 2.0 * self.lam * wk
+            gamma[0] = 1.0 / self.tau0
+        else:
+            gamma = np.zeros(P)
+        c1 = np.exp(-gamma * self.dt / 2)
+        c2 = np.sqrt(1.0 - c1 * c1)
+        sigma = np.sqrt(m * KB * T * P / MVV2E)
+        ke0 = 0.5 * MVV2E * np.sum(pt * pt / m[None, :, None])
+        pt = c1[:, None, None] * pt + sigma[None, :, None] * c2[:, None, None] * xi
+        ke1 = 0.5 * MVV2E * np.sum(pt * pt / m[None, :, None])
+        self.heat[s] -= ke1 - ke0
+        return pt
+
+    def _a_step(self, s, qt, pt):
+        n, P, T, m = self.systems[s]
+        wk, _ = mode_frequencies(P, T)
+        dt = self.dt
+        qn, pn = qt.copy(), pt.copy()
+        qn[0] = qt[0] + dt * pt[0] / m[:, None]
+        for k in range(1, P):
+            c, sn = np.cos(wk[k] * dt), np.sin(wk[k] * dt)
+            pn[k] = c * pt[k] - (m[:, None] * wk[k] * sn) * qt[k]
+            qn[k] = sn * pt[k] / (m[:, None] * wk[k]) + c * qt[k]
+        return qn, pn
+
+    def _noise(self, half, noise):
+        if noise is not None:
+            return np.asarray(noise[half], dtype=np.float64).reshape(-1, 3)
+        return philox.thermostat_noise(self.seed, self.step_count, half, self.total)
+
+    def step(self, noise=None):
+        """One OBABO step; noise optionally [2, total, 3] replaces Philox."""
+        xi0 = self._noise(0, noise)
+        for s in range(len(self.systems)):
+            n, P, T, m = self.systems[s]
+            C = nm_matrix(P)
+            p, q, F = self._view(self.p, s), self._view(self.q, s), self._view(self.F, s)
+            pt = np.einsum("jk,jnc->knc", C, p)
+            pt = self._o_step(s, pt, self._view(xi0, s))
+            pt = pt + (self.dt / 2) * np.einsum("jk,jnc->knc", C, F) / MVV2E
+            qt = np.einsum("jk,jnc->knc", C, q)
+            qt, pt = self._a_step(s, qt, pt)
+            q[...] = np.einsum("jk,knc->jnc", C, qt)
+            p[...] = np.einsum("jk,knc->jnc", C, pt)
+        self.E, self.F = self.force_fn(self.q)
+        xi1 = self._noise(1, noise)
+        for s in range(len(self.systems)):
+            n, P, T, m = self.systems[s]
+            C = nm_matrix(P)
+            p, F = self._view(self.p, s), self._view(self.F, s)
+            p += (self.dt / 2) * F / MVV2E
+            pt = np.einsum("jk,jnc->knc", C, p)
+            pt = self._o_step(s, pt, self._view(xi1, s))
+            p[...] = np.einsum("jk,knc->jnc", C, pt)
+        self.step_count += 1
+
+    # -- estimators (Sec. 2.1 finite-P average; Fig. S-beads virial KE) -------
+    def estimators(self):
+        out = []
+        for s in range(len(self.systems)):
+            n, P, T, m = self.systems[s]
+            beta = 1.0 / (KB * T)
+            _, wP = mode_frequencies(P, T)
+            q, p, F = self._view(self.q, s), self._view(self.p, s), self._view(self.F, s)
+            E = self.E[self._bead_slice(s)]
+            dq = np.roll(q, -1, axis=0) - q
+            e_spring = 0.5 * MVV2E * wP * wP * np.sum(m[None, :, None] * dq * dq) if P > 1 else 0.0
+            qbar = q.mean(axis=0)
+            k_beads = 0.5 * MVV2E * np.sum(p * p / m[None, :, None])
+            v_sum = float(np.sum(E))
+            out.append(dict(
+                V_bar=v_sum / P,
+                K_prim=3 * n * P / (2 * beta) - e_spring / P,
+                K_cv=3 * n / (2 * beta) - np.sum((q - qbar[None]) * F) / (2 * P),
+                E_spring=e_spring,
+                K_beads=k_beads,
+                T_beads=2 * k_beads / (3 * n * P * KB),
+                H_conserved=k_beads + e_spring + v_sum + self.heat[s],
+                heat_bath=self.heat[s]))
+        return out
+
+    def _bead_slice(self, s):
+        b0 = sum(P for _, P, _, _ in self.systems[:s])
+        return slice(b0, b0 + self.systems[s][1])
+
+
+def harmonic_force_fn(systems, omega):
+    """V = sum_i 1/2 m_i omega^2 |q_i|^2 per bead (isotropic oscillator about
+    the origin); returns E per bead and F = -m omega^2 q."""
+    masses = np.concatenate([np.tile(m, P) for n, P, _, m in systems])
+    bead_off = np.cumsum([0] + [P for _, P, _, _ in systems])
+    bead_id = np.concatenate([bead_off[s] + np.repeat(np.arange(P), n)
+                              for s, (n, P, _, _) in enumerate(systems)])
+
+    def fn(q):
+        k = masses * omega * omega * MVV2E
+        e_atom = 0.5 * k * np.sum(q * q, axis=1)
+        E = np.bincount(bead_id, weights=e_atom, minlength=int(bead_off[-1]))
+        return E, -k[:, None] * q
+    return fn

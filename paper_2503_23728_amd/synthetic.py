@@ -1,0 +1,443 @@
+"""Seeded synthetic workloads for ring-polymer MD with a symmetry-function
+neural potential.
+
+This module only draws inputs: geometries, element tables, descriptor grids,
+random network weights and initial momenta.  It holds none of the method's
+arithmetic (no neighbour search, descriptors, network evaluation, normal
+modes or thermostat), so both the FP64 CPU oracle and the GPU library can be
+fed from it without sharing any computation.
+
+The systems mirror the paper's two case studies by shape only: the formic
+acid dimer (Sec. 3.1) and liquid water / ice-Ih (Sec. 3.2, Table S3), with
+the cutoff of Tables S1/S2 (0.6 nm) and the PIMD settings of Table S3 /
+Sec. S1.  The potential family is the Behler-Parrinello descriptor network
+the introduction cites; its grid and widths are hyperparameters stated here.
+
+Units: Angstrom, fs, amu, eV.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+# Element data: IUPAC conventional atomic weights.
+ELEMENT_MASS = {"H": 1.008, "C": 12.011, "O": 15.999}
+
+# Constants used only to draw thermal initial momenta (CODATA 2018).
+_KB_EV_PER_K = 8.617333262e-5
+_AMU_A2_PER_FS2_IN_EV = 103.64269652680505
+
+CUTOFF_A = 6.0
+
+ZETAS = (1, 2, 4, 8)
+LAMBDAS = (1.0, -1.0)
+
+
+@dataclass
+class Model:
+    """Per-element Behler-Parrinello network and its descriptor grid.
+
+    Feature order (D features per centre atom):
+      radial block first, index e * n_rad + s for neighbour element e and
+      radial function s;
+      then one angular block per unordered neighbour-element pair (e1 <= e2)
+      in lexicographic order, index within the block
+      (i_eta * len(ZETAS) + i_zeta) * len(LAMBDAS) + i_lambda.
+    Layers: W[l] has shape [out, in] (float32), b[l] shape [out]; the last
+    layer has out = 1.
+    """
+    elements: list
+    masses: np.ndarray
+    cutoff: float
+    rad_center: np.ndarray
+    rad_eta: np.ndarray
+    ang_eta: np.ndarray
+    hidden: list
+    weights: list           # weights[e] = [(W0, b0), (W1, b1), ..., (Wout, bout)]
+    feat_shift: np.ndarray  # [n_el, D] float32
+    feat_scale: np.ndarray  # [n_el, D] float32
+
+    @property
+    def n_elements(self):
+        return len(self.elements)
+
+    @property
+    def n_rad(self):
+        return len(self.rad_center)
+
+    @property
+    def n_ang(self):
+        return len(self.ang_eta) * len(ZETAS) * len(LAMBDAS)
+
+    @property
+    def n_pairs(self):
+        n = self.n_elements
+        return n * (n + 1) // 2
+
+    @property
+    def n_features(self):
+        return self.n_elements * self.n_rad + self.n_pairs * self.n_ang
+
+
+@dataclass
+class System:
+    n_atoms: int
+    n_beads: int
+    temperature: float
+    box: np.ndarray          # [3]; zeros for a non-periodic system
+    species: np.ndarray      # [n_atoms] int32 index into the element table
+    q0: np.ndarray           # [n_atoms, 3] float64 classical geometry
+
+
+@dataclass
+class Workload:
+    name: str
+    systems: list
+    model: Model
+    dt: float
+    tau0: float
+    pile_lambda: float
+    n_steps: int
+    philox_seed: int
+    momentum_seed: int
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def bead_atoms(self):
+        return sum(s.n_atoms * s.n_beads for s in self.systems)
+
+
+# ----------------------------------------------------------------------------
+# descriptor grid and random network
+# ----------------------------------------------------------------------------
+
+def radial_grid(n_rad, r_lo=0.8, r_hi=5.5):
+    """Shifted Gaussians: centres evenly spaced on [r_lo, r_hi], width = spacing."""
+    spacing = (r_hi - r_lo) / (n_rad - 1)
+    centres = r_lo + spacing * np.arange(n_rad, dtype=np.float64)
+    etas = np.full(n_rad, 1.0 / (2.0 * spacing * spacing))
+    return centres, etas
+
+
+def angular_etas(n_ang):
+    if n_ang == 8:
+        return np.array([0.01])
+    if n_ang == 16:
+        return np.array([0.005, 0.02])
+    raise ValueError("n_ang must be 8 or 16")
+
+
+def make_model(elements, n_rad, n_ang, hidden, seed, rad_scale=1.0, ang_scale=1.0):
+    """Random-weight network, W ~ N(0, 1/fan_in), zero biases.
+
+    feat_shift = 0; feat_scale is a per-block constant (radial / angular)
+    chosen so the normalised features of the synthetic geometries are O(1).
+    """
+    rng = np.random.default_rng(seed)
+    rc, re = radial_grid(n_rad)
+    ae = angular_etas(n_ang)
+    n_el = len(elements)
+    n_pairs = n_el * (n_el + 1) // 2
+    D = n_el * n_rad + n_pairs * n_ang
+    weights = []
+    for _e in range(n_el):
+        layers = []
+        fan_in = D
+        for width in list(hidden) + [1]:
+            W = rng.normal(0.0, 1.0 / math.sqrt(fan_in), size=(width, fan_in)).astype(np.float32)
+            b = np.zeros(width, dtype=np.float32)
+            layers.append((W, b))
+            fan_in = width
+        weights.append(layers)
+    shift = np.zeros((n_el, D), dtype=np.float32)
+    scale = np.empty((n_el, D), dtype=np.float32)
+    scale[:, : n_el * n_rad] = rad_scale
+    scale[:, n_el * n_rad:] = ang_scale
+    return Model(elements=list(elements),
+                 masses=np.array([ELEMENT_MASS[e] for e in elements]),
+                 cutoff=CUTOFF_A, rad_center=rc, rad_eta=re, ang_eta=ae,
+                 hidden=list(hidden), weights=weights,
+                 feat_shift=shift, feat_scale=scale)
+
+
+# ----------------------------------------------------------------------------
+# geometries
+# ----------------------------------------------------------------------------
+
+def formic_acid_dimer():
+    """Planar cyclic formic-acid dimer with an inversion centre at the origin.
+
+    Bond lengths: C=O 1.22, C-O 1.31, O-H 0.98, C-H 1.09 A;
+    the two O-H...O hydrogen bonds have O...O = 2.70 A.
+    Returns (elements, species, positions) with the element table [H, C, O];
+    atom order per monomer: C, O(carbonyl), O(hydroxyl), H(formyl), H(hydroxyl).
+    """
+    def monomer(half_sep):
+        C = np.array([-half_sep, 0.0, 0.0])
+        Oc = C + 1.22 * np.array([math.cos(math.radians(60)), math.sin(math.radians(60)), 0.0])
+        Oh = C + 1.31 * np.array([math.cos(math.radians(-60)), math.sin(math.radians(-60)), 0.0])
+        Hf = C + 1.09 * np.array([-1.0, 0.0, 0.0])
+        return C, Oc, Oh, Hf
+
+    # solve for the C...C half separation giving O(c, A)...O(h, B) = 2.70 A
+    lo, hi = 1.0, 4.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        _, Oc, Oh, _ = monomer(mid)
+        OhB = -Oh
+        if np.linalg.norm(OhB - Oc) < 2.70:
+            lo = mid
+        else:
+            hi = mid
+    C, Oc, Oh, Hf = monomer(0.5 * (lo + hi))
+    CB, OcB, OhB, HfB = -C, -Oc, -Oh, -Hf
+    Hh = Oh + 0.98 * (OcB - Oh) / np.linalg.norm(OcB - Oh)     # A's hydroxyl H points at B's C=O
+    HhB = -Hh
+    pos = np.array([C, Oc, Oh, Hf, Hh, CB, OcB, OhB, HfB, HhB])
+    elements = ["H", "C", "O"]
+    species = np.array([1, 2, 2, 0, 0, 1, 2, 2, 0, 0], dtype=np.int32)
+    return elements, species, pos
+
+
+def _random_rotation(rng):
+    u1, u2, u3 = rng.random(3)
+    a = math.sqrt(1 - u1)
+    b = math.sqrt(u1)
+    x, y, z, w = a * math.sin(2 * math.pi * u2), a * math.cos(2 * math.pi * u2), \
+        b * math.sin(2 * math.pi * u3), b * math.cos(2 * math.pi * u3)
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def _water_body(r_oh=0.96, angle_deg=104.52):
+    h = math.radians(angle_deg) / 2
+    return np.array([[0.0, 0.0, 0.0],
+                     [r_oh * math.sin(h), r_oh * math.cos(h), 0.0],
+                     [-r_oh * math.sin(h), r_oh * math.cos(h), 0.0]])
+
+
+def _min_image(d, box):
+    return d - box * np.round(d / box)
+
+
+def water_grid(n_side, box_len, rng, min_sep=1.0):
+    """n_side^3 water molecules, O on a simple cubic grid, random orientations.
+
+    An orientation is redrawn while any intermolecular atom pair (minimum
+    image) is closer than min_sep.  Element table [H, O]; order O, H, H.
+    """
+    box = np.full(3, box_len)
+    spacing = box_len / n_side
+    body = _water_body()
+    placed = np.zeros((0, 3))
+    pos = []
+    for ix in range(n_side):
+        for iy in range(n_side):
+            for iz in range(n_side):
+                o = spacing * (np.array([ix, iy, iz]) + 0.5)
+                for _attempt in range(1000):
+                    mol = o + body @ _random_rotation(rng).T
+                    if len(placed) == 0:
+                        break
+                    d = _min_image(mol[:, None, :] - placed[None, :, :], box)
+                    if np.min(np.einsum("ijk,ijk->ij", d, d)) >= min_sep * min_sep:
+                        break
+                else:
+                    raise RuntimeError("could not place water molecule")
+                pos.append(mol)
+                placed = np.concatenate([placed, mol])
+    pos = np.concatenate(pos)
+    species = np.tile(np.array([1, 0, 0], dtype=np.int32), n_side ** 3)
+    return ["H", "O"], species, pos, box
+
+
+ICE_FRACTIONAL = np.array([
+    [0.0, 1 / 3, 1 / 16], [0.0, 1 / 3, 7 / 16],
+    [0.5, 1 / 6, 9 / 16], [0.5, 1 / 6, 15 / 16],
+    [0.5, 5 / 6, 1 / 16], [0.5, 5 / 6, 7 / 16],
+    [0.0, 2 / 3, 9 / 16], [0.0, 2 / 3, 15 / 16]])
+
+
+def ice_oxygens(a=4.5, c=7.35, reps=(3, 2, 2)):
+    """O sublattice of hexagonal ice in an orthorhombic (a, a*sqrt3, c) cell."""
+    cell = np.array([a, a * math.sqrt(3.0), c])
+    pts = []
+    for i in range(reps[0]):
+        for j in range(reps[1]):
+            for k in range(reps[2]):
+                pts.append((ICE_FRACTIONAL + np.array([i, j, k])) * cell)
+    return np.concatenate(pts), cell * np.array(reps)
+
+
+def ice_ih(rng, r_oh=0.96, bond_cut=3.0, n_flips_per_o=10):
+    """Proton-disordered ice-Ih obeying the ice rules.
+
+    The O-O hydrogen-bond graph is 4-regular.  Orienting every edge along a
+    seeded random Euler circuit gives each O two donated and two accepted
+    bonds; random directed-loop reversals then decorrelate the arrangement.
+    Each donated bond carries one H at r_oh from the donor.
+    Element table [H, O]; atom order per molecule O, H, H.
+    """
+    O, box = ice_oxygens()
+    n = len(O)
+    d = _min_image(O[:, None, :] - O[None, :, :], box)
+    r = np.sqrt(np.einsum("ijk,ijk->ij", d, d))
+    nbrs = [list(np.nonzero((r[i] < bond_cut) & (np.arange(n) != i))[0]) for i in range(n)]
+    if any(len(v) != 4 for v in nbrs):
+        raise RuntimeError("ice O graph is not 4-regular")
+    # Hierholzer's algorithm with random edge choice
+    unused = {i: list(v) for i, v in enumerate(nbrs)}
+    for v in unused.values():
+        rng.shuffle(v)
+    stack, circuit = [0], []
+    while stack:
+        v = stack[-1]
+        if unused[v]:
+            w = unused[v].pop()
+            unused[w].remove(v)
+            stack.append(w)
+        else:
+            circuit.append(stack.pop())
+    succ = {i: set() for i in range(n)}
+    for a, b in zip(circuit[:-1], circuit[1:]):
+        succ[b].add(a)   # circuit was built in reverse; orientation b -> a
+    # directed-loop reversals keep in = out = 2 everywhere
+    for _ in range(n_flips_per_o * n):
+        start = int(rng.integers(n))
+        path, seen = [start], {start: 0}
+        while True:
+            nxt = list(succ[path[-1]])
+            w = nxt[int(rng.integers(len(nxt)))]
+            if w in seen:
+                loop = path[seen[w]:] + [w]
+                break
+            seen[w] = len(path)
+            path.append(w)
+        for a, b in zip(loop[:-1], loop[1:]):
+            succ[a].remove(b)
+            succ[b].add(a)
+    pos = []
+    for i in range(n):
+        donors = sorted(succ[i])
+        assert len(donors) == 2
+        mol = [O[i]]
+        for j in donors:
+            v = _min_image(O[j] - O[i], box)
+            mol.append(O[i] + r_oh * v / np.linalg.norm(v))
+        pos.append(np.array(mol))
+    species = np.tile(np.array([1, 0, 0], dtype=np.int32), n)
+    return ["H", "O"], species, np.concatenate(pos), box
+
+
+# ----------------------------------------------------------------------------
+# the five workloads
+# ----------------------------------------------------------------------------
+
+def _fad_system(rng, n_beads, temperature):
+    elements, species, pos = formic_acid_dimer()
+    q0 = pos + rng.uniform(-0.05, 0.05, size=pos.shape)
+    return elements, System(n_atoms=len(species), n_beads=n_beads, temperature=temperature,
+                            box=np.zeros(3), species=species, q0=q0)
+
+
+# Feature scales: angular blocks are sums over O(K^2) triplets, so they are
+# divided by a per-workload constant that brings them to O(1).
+_FAD_SCALES = dict(rad_scale=1.0, ang_scale=1.0)
+_WATER_SCALES = dict(rad_scale=2.0, ang_scale=10.0)
+
+
+def workload(c, seed_offset=0):
+    """Build workload number c (1..5) as described in the module docstring.
+
+    Seeds: geometry 1000+c, weights 2000+c, momenta 3000+c, Philox 4000+c,
+    each shifted by seed_offset (parity tests use 0, 100, 200).
+    """
+    gs, ws, ms, ps = (1000 + c + seed_offset, 2000 + c + seed_offset,
+                      3000 + c + seed_offset, 4000 + c + seed_offset)
+    rng = np.random.default_rng(gs)
+    if c == 1:
+        elements, sys1 = _fad_system(rng, 8, 300.0)
+        model = make_model(elements, 8, 8, [64, 64], ws, **_FAD_SCALES)
+        return Workload("fad-10atom-P8", [sys1], model, dt=0.25, tau0=100.0, pile_lambda=1.0,
+                        n_steps=500, philox_seed=ps, momentum_seed=ms)
+    if c == 2:
+        elements, species, pos, box = water_grid(4, 12.42, rng)
+        s = System(len(species), 32, 300.0, box, species, pos)
+        model = make_model(elements, 16, 16, [128, 128, 64], ws, **_WATER_SCALES)
+        return Workload("water-64-P32", [s], model, dt=0.25, tau0=100.0, pile_lambda=1.0,
+                        n_steps=200, philox_seed=ps, momentum_seed=ms)
+    if c == 3:
+        elements, species, pos, box = ice_ih(rng)
+        s = System(len(species), 32, 250.0, box, species, pos)
+        model = make_model(elements, 16, 16, [128, 128, 64], ws, **_WATER_SCALES)
+        return Workload("ice-96-P32", [s], model, dt=0.25, tau0=100.0, pile_lambda=1.0,
+                        n_steps=4000, philox_seed=ps, momentum_seed=ms)
+    if c == 4:
+        systems = []
+        elements = None
+        for _ in range(512):
+            p = int(rng.choice([8, 16, 32, 64]))
+            t = float(rng.uniform(100.0, 400.0))
+            elements, s = _fad_system(rng, p, t)
+            systems.append(s)
+        model = make_model(elements, 8, 8, [64, 64], ws, **_FAD_SCALES)
+        return Workload("fad-batch-512", systems, model, dt=0.25, tau0=100.0, pile_lambda=1.0,
+                        n_steps=200, philox_seed=ps, momentum_seed=ms)
+    if c == 5:
+        elements, species, pos, box = water_grid(16, 49.7, rng)
+        s = System(len(species), 32, 300.0, box, species, pos)
+        model = make_model(elements, 16, 16, [128, 128, 64], ws, **_WATER_SCALES)
+        return Workload("water-4096-P32", [s], model, dt=0.25, tau0=100.0, pile_lambda=1.0,
+                        n_steps=200, philox_seed=ps, momentum_seed=ms)
+    raise ValueError(f"unknown workload {c}")
+
+
+def small_workload(kind, seed=7, n_beads=4):
+    """Small variants for fast tests: 'fad' (10 atoms), 'water8' (8 H2O in a
+    periodic 12.5 A box, so the cell grid is 2x2x2 and stencils wrap)."""
+    rng = np.random.default_rng(seed)
+    if kind == "fad":
+        elements, s = _fad_system(rng, n_beads, 300.0)
+        model = make_model(elements, 8, 8, [64, 64], seed + 1, **_FAD_SCALES)
+        return Workload("fad-small", [s], model, 0.25, 100.0, 1.0, 10, seed + 2, seed + 3)
+    if kind == "water8":
+        elements, species, pos, box = water_grid(2, 12.5, rng)
+        s = System(len(species), n_beads, 300.0, box, species, pos)
+        model = make_model(elements, 16, 16, [128, 128, 64], seed + 1, **_WATER_SCALES)
+        return Workload("water8", [s], model, 0.25, 100.0, 1.0, 10, seed + 2, seed + 3)
+    raise ValueError(kind)
+
+
+def initial_state(wl):
+    """All beads at the classical geometry (unwrapped) and thermal bead momenta
+    p ~ N(0, m kB T P), drawn with numpy default_rng(momentum_seed).
+
+    Returns q, p as float32 arrays [sum_s P_s N_s, 3] in the bead-major,
+    system-concatenated layout (index off_s + k * N_s + i).
+    """
+    rng = np.random.default_rng(wl.momentum_seed)
+    qs, ps = [], []
+    masses = wl.model.masses
+    for s in wl.systems:
+        m = masses[s.species]
+        q = np.broadcast_to(s.q0, (s.n_beads, s.n_atoms, 3))
+        sd = np.sqrt(m * _KB_EV_PER_K * s.temperature * s.n_beads / _AMU_A2_PER_FS2_IN_EV)
+        p = rng.normal(size=(s.n_beads, s.n_atoms, 3)) * sd[None, :, None]
+        qs.append(q.reshape(-1, 3))
+        ps.append(p.reshape(-1, 3))
+    return (np.concatenate(qs).astype(np.float32), np.concatenate(ps).astype(np.float32))
+
+
+def perturbed_beads(wl, amplitude=0.05, seed=11):
+    """Bead positions with independent jitter per bead (so the beads differ),
+    float32 [sum P_s N_s, 3]; used for force-parity tests."""
+    rng = np.random.default_rng(seed)
+    qs = []
+    for s in wl.systems:
+        q = s.q0[None] + rng.uniform(-amplitude, amplitude, size=(s.n_beads, s.n_atoms, 3))
+        qs.append(q.reshape(-1, 3))
+    return np.concatenate(qs).astype(np.float32)

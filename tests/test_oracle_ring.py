@@ -1,0 +1,245 @@
+"""Pins of the oracle's normal modes, PILE-L integrator, estimators, Philox
+noise and quantum-harmonic-oscillator closed forms.
+
+Expectations come from outside the oracle: orthonormality and the spring
+identity of the normal-mode matrix, numpy's real FFT, exact energy
+conservation of the free ring polymer, a textbook velocity-Verlet loop for
+P = 1, the dt^2 scaling of the NVE error, the exact finite-P harmonic
+averages (Sec. S1) sampled by the thermostat, and moments of the noise.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import philox, qho, ring
+from oracle.constants import KB, HBAR, MVV2E
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- normal modes
+
+@pytest.mark.parametrize("P", [1, 2, 4, 6, 8, 32, 64, 128])
+def test_nm_matrix_orthonormal(P):
+    C = ring.nm_matrix(P)
+    assert np.allclose(C.T @ C, np.eye(P), atol=1e-13)
+
+
+@pytest.mark.parametrize("P", [2, 4, 8, 10, 32])
+def test_nm_matrix_is_the_real_fft(P):
+    rng = np.random.default_rng(P)
+    q = rng.normal(size=P)
+    qt = ring.nm_matrix(P).T @ q
+    X = np.fft.rfft(q)                       # X_m = sum_j q_j exp(-2 pi i j m / P)
+    want = np.empty(P)
+    want[0] = X[0].real / np.sqrt(P)
+    for m in range(1, P // 2):
+        want[m] = np.sqrt(2.0 / P) * X[m].real
+        want[P - m] = np.sqrt(2.0 / P) * X[m].imag    # column P-m is -sin(2 pi j m/P), as is Im X_m
+    want[P // 2] = X[P // 2].real / np.sqrt(P)
+    assert np.allclose(qt, want, atol=1e-12)
+
+
+@pytest.mark.parametrize("P", [2, 8, 32])
+def test_spring_energy_is_diagonal_in_normal_modes(P):
+    rng = np.random.default_rng(1)
+    m, T = 1.008, 300.0
+    q = rng.normal(size=(P, 3))
+    wk, wP = ring.mode_frequencies(P, T)
+    bead = 0.5 * m * wP ** 2 * np.sum((np.roll(q, -1, axis=0) - q) ** 2)
+    qt = ring.nm_matrix(P).T @ q
+    mode = 0.5 * m * np.sum(wk[:, None] ** 2 * qt ** 2)
+    assert mode == pytest.approx(bead, rel=1e-12)
+
+
+# ---------------------------------------------------------------- integrator
+
+def _systems(n, P, T, mass=1.008):
+    return [(n, P, T, np.full(n, mass))]
+
+
+def _hamiltonian(rp, V):
+    est = rp.estimators()[0]
+    return est["K_beads"] + est["E_spring"] + V
+
+
+def test_free_ring_polymer_conserves_energy():
+    # V = 0, thermostat off: the A step is exact, so H_P is conserved to rounding
+    systems = _systems(5, 16, 300.0)
+    rp = ring.RingPolymers(systems, 0.5, 0.0, 1.0, 1, lambda q: (np.zeros(16), np.zeros_like(q)))
+    rng = np.random.default_rng(2)
+    rp.set_state(rng.normal(0, 0.1, (80, 3)), rng.normal(0, 1.0, (80, 3)))
+    h0 = _hamiltonian(rp, 0.0)
+    for _ in range(500):
+        rp.step()
+    assert _hamiltonian(rp, 0.0) == pytest.approx(h0, rel=1e-11)
+
+
+def test_single_bead_nve_is_velocity_verlet():
+    omega = 0.02
+    systems = _systems(4, 1, 300.0, mass=15.999)
+    fn = ring.harmonic_force_fn(systems, omega)
+    rp = ring.RingPolymers(systems, 0.5, 0.0, 1.0, 1, fn)
+    rng = np.random.default_rng(3)
+    q0, p0 = rng.normal(0, 0.2, (4, 3)), rng.normal(0, 1.0, (4, 3))
+    rp.set_state(q0, p0)
+    for _ in range(200):
+        rp.step()
+    # textbook velocity Verlet: kick, drift, force, kick
+    m, k = 15.999, 15.999 * omega ** 2 * MVV2E
+    q, p = q0.copy(), p0.copy()
+    f = -k * q
+    for _ in range(200):
+        p = p + 0.25 * f / MVV2E
+        q = q + 0.5 * p / m
+        f = -k * q
+        p = p + 0.25 * f / MVV2E
+    assert np.allclose(rp.q, q, rtol=1e-12, atol=1e-14)
+    assert np.allclose(rp.p, p, rtol=1e-12, atol=1e-14)
+
+
+def test_nve_energy_error_scales_as_dt_squared():
+    omega = 0.05
+    P = 8
+    systems = _systems(3, P, 300.0)
+    errs = []
+    for dt in (0.5, 0.25):
+        fn = ring.harmonic_force_fn(systems, omega)
+        rp = ring.RingPolymers(systems, dt, 0.0, 1.0, 1, fn)
+        rng = np.random.default_rng(4)
+        rp.set_state(rng.normal(0, 0.1, (P * 3, 3)), rng.normal(0, 3.0, (P * 3, 3)))
+        h0 = rp.estimators()[0]["H_conserved"]
+        worst = 0.0
+        for _ in range(int(100 / dt)):
+            rp.step()
+            worst = max(worst, abs(rp.estimators()[0]["H_conserved"] - h0))
+        errs.append(worst)
+    ratio = errs[0] / errs[1]
+    assert 3.5 < ratio < 4.5
+
+
+def test_thermostat_heat_balances_energy():
+    # with the thermostat on, H_P + heat stays constant up to the integration error
+    omega = 0.02
+    systems = _systems(6, 8, 300.0)
+    fn = ring.harmonic_force_fn(systems, omega)
+    rp = ring.RingPolymers(systems, 0.25, 50.0, 1.0, 9, fn)
+    rng = np.random.default_rng(5)
+    rp.set_state(rng.normal(0, 0.1, (48, 3)), rng.normal(0, 1.0, (48, 3)))
+    h0 = rp.estimators()[0]["H_conserved"]
+    for _ in range(400):
+        rp.step()
+    est = rp.estimators()[0]
+    assert abs(est["heat_bath"]) > 1e-3
+    assert abs(est["H_conserved"] - h0) < 1e-3 * abs(est["heat_bath"])
+
+
+def test_single_bead_estimators_are_classical():
+    systems = _systems(4, 1, 250.0)
+    fn = ring.harmonic_force_fn(systems, 0.03)
+    rp = ring.RingPolymers(systems, 0.5, 100.0, 1.0, 3, fn)
+    rng = np.random.default_rng(6)
+    rp.set_state(rng.normal(0, 0.1, (4, 3)), rng.normal(0, 1.0, (4, 3)))
+    rp.step()
+    est = rp.estimators()[0]
+    assert est["E_spring"] == 0.0
+    assert est["K_prim"] == pytest.approx(1.5 * 4 * KB * 250.0, rel=1e-14)
+    assert est["K_cv"] == pytest.approx(1.5 * 4 * KB * 250.0, rel=1e-14)
+
+
+def _block_mean(x, nblocks=20):
+    b = np.array_split(np.asarray(x), nblocks)
+    means = np.array([v.mean() for v in b])
+    return means.mean(), means.std(ddof=1) / np.sqrt(nblocks)
+
+
+@pytest.mark.parametrize("P", [1, 4, 8])
+def test_pile_l_samples_exact_finite_P_harmonic_average(P):
+    # Sec. S1 oscillator: many independent atoms in one ring polymer system
+    g = json.load(open(os.path.join(GOLDEN, "qho_s1.json")))
+    m, w = g["mass_amu"], g["omega_per_fs"]
+    T = 100.0                                   # beta hbar w = 0.95: P = 8 far from classical and quantum
+    n = 600
+    systems = _systems(n, P, T, mass=m)
+    rp = ring.RingPolymers(systems, g["dt_fs"], 100.0, 1.0, 17, ring.harmonic_force_fn(systems, w))
+    rng = np.random.default_rng(7)
+    rp.set_state(rng.normal(0, 0.3, (n * P, 3)), rng.normal(0, 0.2, (n * P, 3)))
+    for _ in range(1500):
+        rp.step()
+    x2, kcv = [], []
+    for t in range(3000):
+        rp.step()
+        if t % 5 == 0:
+            x2.append(np.mean(rp.q ** 2))
+            kcv.append(rp.estimators()[0]["K_cv"] / (3 * n))
+    mean, err = _block_mean(x2)
+    want = qho.x2_beads_sum(m, w, T, P)
+    assert abs(mean - want) < 3.5 * err + 2e-3 * want
+    # virial (centroid) kinetic energy = half the harmonic energy per dimension
+    kmean, kerr = _block_mean(kcv)
+    assert abs(kmean - 0.5 * qho.energy_beads(m, w, T, P)) < 3.5 * kerr + 2e-3 * kmean
+
+
+def test_bead_temperature_is_P_times_T():
+    P, n, T = 8, 800, 200.0
+    systems = _systems(n, P, T)
+    rp = ring.RingPolymers(systems, 0.5, 20.0, 1.0, 23, ring.harmonic_force_fn(systems, 0.01))
+    rp.set_state(np.zeros((n * P, 3)), np.zeros((n * P, 3)))
+    temps = []
+    for t in range(600):
+        rp.step()
+        if t > 200:
+            temps.append(rp.estimators()[0]["T_beads"])
+    mean, err = _block_mean(temps)
+    assert abs(mean - P * T) < 3.5 * err + 5e-3 * P * T
+
+
+# ---------------------------------------------------------------- QHO closed forms
+
+def test_qho_bead_sum_equals_closed_form_and_limits():
+    g = json.load(open(os.path.join(GOLDEN, "qho_s1.json")))
+    m, w, T = g["mass_amu"], g["omega_per_fs"], g["temperature_K"]
+    beta = 1.0 / (KB * T)
+    assert beta * HBAR * w == pytest.approx(g["beta_hbar_omega"], abs=0.01)
+    for P in g["beads_sweep"]:
+        assert qho.x2_beads_sum(m, w, T, P) == pytest.approx(qho.x2_beads_closed(m, w, T, P), rel=1e-12)
+    assert qho.x2_beads_sum(m, w, T, 1) == pytest.approx(qho.x2_classical(m, w, T), rel=1e-14)
+    assert qho.x2_beads_sum(m, w, T, 4096) == pytest.approx(qho.x2_exact(m, w, T), rel=1e-6)
+    # <E> = k <x^2> reaches hbar w/2 coth(beta hbar w/2) and k_B T in the two limits
+    assert qho.energy_beads(m, w, T, 4096) == pytest.approx(qho.energy_exact(w, T), rel=1e-6)
+    assert qho.energy_beads(m, w, 5000.0, 1) == pytest.approx(KB * 5000.0, rel=1e-12)
+    # the bead sum increases monotonically towards the quantum value
+    vals = [qho.x2_beads_sum(m, w, T, P) for P in g["beads_sweep"]]
+    assert all(a < b for a, b in zip(vals[:-1], vals[1:]))
+
+
+# ---------------------------------------------------------------- Philox noise
+
+def test_philox_words_are_uniform_and_counter_sensitive():
+    x = np.concatenate(philox.noise_words(4001, 7, 0, 200000))
+    u = (x.astype(np.float64) + 0.5) / 2.0 ** 32
+    assert abs(u.mean() - 0.5) < 4 * np.sqrt(1 / 12 / len(u))
+    counts = np.bincount((x >> np.uint64(24)).astype(np.int64), minlength=256)
+    chi2 = np.sum((counts - len(x) / 256) ** 2 / (len(x) / 256))
+    assert chi2 < 255 + 5 * np.sqrt(2 * 255)
+    a = np.stack(philox.noise_words(4001, 7, 0, 1000))
+    for other in (philox.noise_words(4001, 8, 0, 1000), philox.noise_words(4001, 7, 1, 1000),
+                  philox.noise_words(4002, 7, 0, 1000)):
+        assert np.mean(np.stack(other) == a) < 1e-3
+    # a counter in the high step word changes the stream as well
+    b = np.stack(philox.noise_words(4001, 7 + (1 << 32), 0, 1000))
+    assert np.mean(b == a) < 1e-3
+
+
+def test_philox_normals_moments():
+    z = philox.thermostat_noise(99, 3, 1, 400000).ravel()
+    n = len(z)
+    assert abs(z.mean()) < 4 / np.sqrt(n)
+    assert abs(z.var() - 1) < 4 * np.sqrt(2 / n)
+    assert abs(np.mean(z ** 4) - 3) < 4 * np.sqrt(96 / n)
+    # the three components are uncorrelated
+    zz = philox.thermostat_noise(99, 3, 1, 200000)
+    c = np.corrcoef(zz.T)
+    assert np.abs(c - np.eye(3)).max() < 4 / np.sqrt(200000)
