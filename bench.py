@@ -1,0 +1,217 @@
+"""Throughput of the ML-PIMD hot path on one MI355X.
+
+One step = one full normal-mode PILE-L integrator step of every bead of
+every ring polymer: O/B/A in normal modes, neighbour search, descriptors,
+MLP, adjoint forces, B/O.  The state is resident in HBM before the timed
+region; the timed region is exactly `--steps` steps.
+
+Prints one JSON line: bead-atom force evaluations per second (the whole
+job), ns/day, the plain-FP32 comparison path (FP32 MLP, every kernel
+enqueued one by one, one context per system), the roofline of the dominant
+kernel (algorithmic FLOPs per launch / mean launch time from HIP events on
+the launch stream, against the FP32 vector peak) and the FP64 CPU oracle
+timed on a bounded sample on the host cores.
+
+Workloads (--config): 1 formic-acid-dimer 10 atoms P=8; 2 water 64 H2O P=32
+(default); 3 ice 96 H2O P=32; 4 512 dimer-like ring polymers with P in
+{8,16,32,64}; 5 water 4096 H2O P=32.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
+HBM_PEAK_GBS = 8000.0
+
+
+def flops_model(n_rad, n_eta, pairs, triplets, triplets_in):
+    """Algorithmic FLOPs of the descriptor forward and adjoint passes.
+
+    Counted from the definitions, one FLOP per add, multiply, square root,
+    exponential or cosine:
+      forward  per pair:    displacement 3, r 6, f_c 4, exp(-eta r^2) f_c 3 n_eta, radial 6 n_rad
+               per triplet: r_jk^2 and the cutoff test 9;  in range: r_jk 1, f_c 4, cos 7,
+                            (1 +- cos)^zeta 8, per eta: exp 2, product 3, 8 features x 2
+      adjoint  per pair:    forward pair terms + derivative factors 2 n_eta + radial derivative
+                            10 n_rad + slot vector 4 + virial 18
+               per triplet: test 9;  in range: r_jk and 1/r_jk 2, f_c and f_c' 7, cos 7,
+                            powers and their derivatives 14, per eta: exp 2, S 16, S' 16,
+                            four partials 14, gradient coefficients 10, two vectors 24,
+                            slot accumulation 6
+    """
+    fwd_pair = 13 + 3 * n_eta + 6 * n_rad
+    fwd_trip_in = 20 + 21 * n_eta
+    adj_pair = fwd_pair + 2 * n_eta + 10 * n_rad + 22
+    adj_trip_in = 30 + 48 * n_eta + 40
+    fwd = pairs * fwd_pair + triplets * 9 + triplets_in * fwd_trip_in
+    adj = pairs * adj_pair + triplets * 9 + triplets_in * adj_trip_in
+    return fwd, adj
+
+
+def time_steps(eng, steps, warmup):
+    import torch
+    eng.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(eng.stream)
+    eng.step(steps)
+    stop.record(eng.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, start.elapsed_time(stop) / 1e3
+
+
+def plain_fp32(wl, steps, warmup, device):
+    """The comparison path: FP32 MLP, no graph, one context per system."""
+    import torch
+    from paper_2503_23728_amd import synthetic as S
+    from paper_2503_23728_amd.pimd import Pimd
+    q, p = S.initial_state(wl)
+    engines = []
+    off = 0
+    for s in wl.systems:
+        n = s.n_atoms * s.n_beads
+        e = Pimd(
+            [s], wl.model, wl.dt, wl.tau0, wl.pile_lambda, wl.philox_seed, precision="fp32", device=device)
+        e.set_graph(False)
+        e.set_state(torch.from_numpy(q[off:off + n]).to(device), torch.from_numpy(p[off:off + n]).to(device))
+        engines.append(e)
+        off += n
+    for e in engines:
+        e.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for e in engines:
+            e.step(1)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(wl, budget_s=20.0):
+    """FP64 oracle steps on the host cores over a bounded sample of the
+    workload: whole integrator steps of the first ring polymer(s), repeated
+    until about budget_s seconds have passed."""
+    import numpy as np
+    from paper_2503_23728_amd import synthetic as S
+    from oracle import bpnn, ring
+    q, p = S.initial_state(wl)
+    systems, rows, n_sys = [], 0, 0
+    for s in wl.systems:
+        systems.append(s)
+        rows += s.n_atoms * s.n_beads
+        n_sys += 1
+        if rows >= 1000 or n_sys >= 16:
+            break
+    sub = S.Workload(wl.name, systems, wl.model, wl.dt, wl.tau0, wl.pile_lambda, wl.n_steps, wl.philox_seed,
+                     wl.momentum_seed)
+
+    def fn(qq):
+        E, F, _ = bpnn.energy_forces(sub, qq.astype(np.float32))
+        return E, F
+    rp = ring.RingPolymers([(s.n_atoms, s.n_beads, s.temperature, wl.model.masses[s.species]) for s in systems],
+                           wl.dt, wl.tau0, wl.pile_lambda, wl.philox_seed, fn)
+    rp.set_state(q[:rows].astype(np.float64), p[:rows].astype(np.float64))
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        rp.step()
+        n += 1
+        if time.perf_counter() - t0 > budget_s or n >= 200:
+            break
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    return dict(value=rows * n / dt, unit="bead-atom force evals/s", cores=min(cores, threads), kind="oracle",
+                sample=f"{n} FP64 oracle integrator steps of {len(systems)} ring polymer(s), {rows} bead-atoms "
+                       f"({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "bf16-plain"])
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-FP32 comparison path")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile-reps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described in the design notes, not built)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2503_23728_amd import synthetic as S
+    from paper_2503_23728_amd.pimd import Pimd
+
+    device = "cuda:0"
+    wl = S.workload(args.config)
+    B = wl.bead_atoms
+    eng = Pimd.from_workload(wl, precision=args.precision, device=device)
+    q, p = S.initial_state(wl)
+    eng.set_state(torch.from_numpy(q).to(device), torch.from_numpy(p).to(device))
+    print(f"[bench] {wl.name}: {B} bead-atoms, {len(wl.systems)} systems; warmup {args.warmup}", file=sys.stderr,
+          flush=True)
+    wall, gpu_s = time_steps(eng, args.steps, args.warmup)
+    ms_per_step = 1e3 * wall / args.steps
+    value = B * args.steps / wall
+    ns_day = args.steps * wl.dt * 1e-6 / wall * 86400.0
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # per-stage timing with HIP events on the launch stream (kernels one by one)
+    stages = eng.profile_stages(args.profile_reps)
+    pairs, trip, trip_in = eng.work_counts()
+    m = wl.model
+    fwd_flops, adj_flops = flops_model(m.n_rad, len(m.ang_eta), pairs, trip, trip_in)
+    adj_ms = stages["adjoint"]
+    achieved = adj_flops / (adj_ms * 1e-3) / 1e12
+    roofline = {"kernel": "k_adjoint (descriptor adjoint with recomputation)", "bound": "alu",
+                "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": adj_flops, "launch_ms": round(adj_ms, 4),
+                "forward": {"kernel": "k_descriptors", "flops_per_launch": fwd_flops,
+                            "launch_ms": round(stages["descriptors"], 4),
+                            "achieved": round(fwd_flops / (stages["descriptors"] * 1e-3) / 1e12, 3)},
+                "work": {"pairs": pairs, "triplets": trip, "triplets_in_range": trip_in}}
+    print(f"[bench] stages {json.dumps({k: round(v, 4) for k, v in stages.items()})}", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "bead·atom force evals/s + PIMD ns/day vs plain FP32, at force err vs FP64",
+        "value": value, "unit": "bead-atom force evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "f32 (MLP GEMM operands bf16 x3 split)",
+                  "bf16-plain": "f32 (MLP GEMM operands bf16)"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": wl.name, "systems": len(wl.systems), "bead_atoms": B,
+                   "beads": sum(s.n_beads for s in wl.systems), "dt_fs": wl.dt, "precision": args.precision,
+                   "launch": "hip graph per step"},
+        "ns_per_day": ns_day, "gpu_event_s": gpu_s,
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "roofline": roofline,
+    }
+    if not args.no_plain:
+        psteps = max(1, min(args.steps, 50 if len(wl.systems) > 1 else args.steps))
+        pwall = plain_fp32(wl, psteps, min(args.warmup, 5), device)
+        pval = B * psteps / pwall
+        out["plain_fp32"] = {"value": pval, "steps": psteps, "ms_per_step": 1e3 * pwall / psteps,
+                             "launch": "eager, one context per system"}
+        out["vs_plain_fp32"] = value / pval
+        print(f"[bench] plain fp32: {1e3 * pwall / psteps:.3f} ms/step", file=sys.stderr, flush=True)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,249 @@
+/*
+ * pimd.h -- C ABI of the MI355X ring-polymer (path-integral) MD library.
+ *
+ * The calls follow the paper's statement of the problem (Sec. 2.1 and 2.3):
+ * a system (coordinates, masses, periodic box) is wrapped with a potential
+ * that returns energies and forces, a normal-mode PIMD integrator with a
+ * Langevin thermostat advances it, and finite-P estimators are read back
+ * (the estimator of Sec. 2.1; the virial kinetic energy of the bead test in
+ * Sec. S3).  The potential is a Behler-Parrinello symmetry-function network
+ * (the descriptor family named in the Introduction) whose forces come from a
+ * hand-written adjoint of the energy (the energy-model route of Sec. 2.2), or
+ * an isotropic harmonic well (the oscillator of Sec. S1).
+ *
+ * Units: Angstrom, fs, amu, eV; momenta in amu*A/fs.
+ *
+ * Layout of every per-bead-atom array ("state layout"): float32 [B][3] with
+ * B = sum_s P_s N_s; system s occupies the rows off_s .. off_s + P_s N_s - 1
+ * (off_s = sum_{t<s} P_t N_t), bead k of system s starts at off_s + k N_s and
+ * lists its N_s atoms in input order.  Per-bead arrays have sum_s P_s rows,
+ * system-major then bead.
+ *
+ * Memory and threads: pointers named *_dev are device pointers on the
+ * device that was current at pimd_init; the caller owns them.  The library
+ * owns no device memory: every internal buffer lives in the caller's
+ * workspace (pimd_workspace_size bytes, 256-byte aligned), which must stay
+ * valid until pimd_destroy.  All device work is enqueued on the stream given
+ * to pimd_init (the caller's, e.g. torch's current stream) and runs
+ * asynchronously unless a call says it synchronises.  A context is not
+ * thread-safe; separate contexts are independent.
+ *
+ * Errors: every call returns a pimd_status and never aborts.  Arguments are
+ * checked on the host before any HIP call, so argument errors need no GPU.
+ * Faults found on the device (neighbour overflow, non-finite energy or
+ * forces) are latched in a device status word and returned by the next
+ * synchronising call; pimd_last_error gives a message.
+ */
+#ifndef PIMD_H
+#define PIMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pimd_ctx pimd_ctx;
+
+typedef enum {
+    PIMD_OK = 0,
+    PIMD_E_ARG = 1,          /* invalid argument (null pointer, bad size or value)       */
+    PIMD_E_UNSUPPORTED = 2,  /* valid but outside what the library implements            */
+    PIMD_E_DEVICE = 3,       /* a HIP runtime call failed                                  */
+    PIMD_E_OOM = 4,          /* the workspace is smaller than pimd_workspace_size           */
+    PIMD_E_CAPACITY = 5,     /* an atom had more than max_neighbors neighbours              */
+    PIMD_E_NONFINITE = 6,    /* an energy, force or state value became NaN or infinite      */
+    PIMD_E_STATE = 7         /* call out of order (e.g. pimd_step before pimd_set_state)    */
+} pimd_status;
+
+/* MLP GEMM operand precision (accumulation is FP32 except in FP64_MLP):
+ *   FP32        FP32 operands;
+ *   BF16_MLP    BF16 operands in a three-term split (a_hi b_hi + a_lo b_hi + a_hi b_lo,
+ *               every part bfloat16), about FP32 accuracy;
+ *   BF16_PLAIN  BF16 operands rounded once (one product per tile);
+ *   FP64_MLP    FP64 operands, activations and accumulation (FP64 MFMA).
+ * Descriptors, adjoint and integrator are FP32 in every mode. */
+enum { PIMD_PREC_FP32 = 0, PIMD_PREC_BF16_MLP = 1, PIMD_PREC_BF16_PLAIN = 2, PIMD_PREC_FP64_MLP = 3 };
+enum { PIMD_POT_BPNN = 0, PIMD_POT_HARMONIC = 1 };
+
+/*
+ * Behler-Parrinello model.  Symmetry functions of centre atom i with
+ * neighbours N(i) = { j : |d_ij| < cutoff } (d_ij the minimum-image vector
+ * q_j - q_i), f_c(r) = (cos(pi r / cutoff) + 1) / 2:
+ *   radial   G[e*n_rad + s] = sum_{j, Z_j = e} exp(-rad_eta[s] (r_ij - rad_center[s])^2) f_c(r_ij)
+ *   angular  G[n_el*n_rad + pair*n_ang + (ie*4 + iz)*2 + il]
+ *            = 2^(1-zeta) sum_{j<k, {Z_j,Z_k} = pair} (1 + lambda cos theta_jik)^zeta
+ *              exp(-ang_eta[ie] (r_ij^2 + r_ik^2 + r_jk^2)) f_c(r_ij) f_c(r_ik) f_c(r_jk)
+ *   with zeta = {1,2,4,8}[iz], lambda = {+1,-1}[il], r_jk = |d_ik - d_ij|,
+ *   pair = lexicographic index of (min(Z_j,Z_k), max(Z_j,Z_k)), n_ang = 8*n_ang_eta,
+ *   D = n_el*n_rad + n_el*(n_el+1)/2 * n_ang features.
+ * Network per element e: x = (G - feat_shift[e]) / feat_scale[e];
+ *   h_l = tanh(W_l h_{l-1} + b_l) for the n_hidden hidden layers, E_i = w_o . h + b_o.
+ * params: for each element in order, for each layer (hidden layers, then the
+ *   output layer with one output): W [out][in] row-major, then b [out]; float32.
+ * All arrays are host pointers, copied during pimd_init.
+ */
+typedef struct {
+    int32_t n_elements;          /* 1..4 */
+    const double *mass_amu;      /* [n_elements] */
+    double cutoff_A;             /* > 0; below half of every periodic box length */
+    int32_t n_rad;               /* 1..32, n_elements*n_rad <= 64 */
+    const double *rad_center_A;  /* [n_rad] */
+    const double *rad_eta;       /* [n_rad] 1/A^2 */
+    int32_t n_ang_eta;           /* 1 or 2 */
+    const double *ang_eta;       /* [n_ang_eta] 1/A^2 */
+    int32_t n_hidden;            /* 1..3 */
+    int32_t hidden[3];           /* widths, multiples of 16, <= 128 */
+    const float *params;         /* packed weights, see above */
+    const float *feat_shift;     /* [n_elements][D] */
+    const float *feat_scale;     /* [n_elements][D], non-zero */
+} pimd_bpnn_model;
+
+/*
+ * Ring polymers.  n_systems independent systems, each with its own atom
+ * count, bead count (1 or even, <= 128), temperature and orthorhombic box.
+ * Integrator: normal-mode PIMD with the PILE-L thermostat in the splitting
+ * O(dt/2) B(dt/2) A(dt) [forces] B(dt/2) O(dt/2); the ring polymer is sampled
+ * as exp(-beta H_P / P) with springs of frequency w_P = P k_B T / hbar on
+ * physical masses; mode k has w_k = 2 w_P sin(k pi / P) (normal-mode matrix
+ * columns: 1/sqrt(P); sqrt(2/P) cos(2 pi j k/P) for 0<k<P/2; (-1)^j/sqrt(P);
+ * sqrt(2/P) sin(2 pi j k/P) for k>P/2).  Friction gamma_0 = 1/tau0,
+ * gamma_k = 2 pile_lambda w_k; tau0_fs <= 0 switches the thermostat off (NVE).
+ * Thermostat noise: Philox4x32-10 with key = seed, counter = (row index of
+ * (system, mode, atom) in the state layout, half (0 before / 1 after the
+ * force), step lo, step hi), words u = (x + 1/2) 2^-32, Box-Muller on
+ * (u0,u1) -> x, y and (u2,u3) -> z.
+ */
+typedef struct {
+    int32_t n_systems;                 /* >= 1 */
+    const int32_t *n_atoms;            /* [n_systems], >= 1 */
+    const int32_t *n_beads;            /* [n_systems], 1 or even, <= 128 */
+    const double *temperature_K;       /* [n_systems], > 0 */
+    const double *box_A;               /* [n_systems][3]; (0,0,0) = non-periodic */
+    const int32_t *species;            /* [sum n_atoms], 0 <= Z < n_elements */
+    double dt_fs;                      /* > 0 */
+    double tau0_fs;                    /* centroid friction time; <= 0 => NVE */
+    double pile_lambda;                /* >= 0 */
+    uint64_t seed;                     /* Philox key */
+    int32_t precision;                 /* PIMD_PREC_* (MLP GEMM operand precision) */
+    int32_t potential;                 /* PIMD_POT_* */
+    const pimd_bpnn_model *model;      /* PIMD_POT_BPNN: the model; HARMONIC: masses only */
+    double harmonic_omega_per_fs;      /* PIMD_POT_HARMONIC: V = sum 1/2 m w^2 |q|^2 */
+    int32_t max_neighbors;             /* neighbour slots per atom, 0 => 128; <= 256 */
+} pimd_config;
+
+/* Finite-P estimators of one system (Sec. 2.1; virial kinetic energy of
+ * Sec. S3), eV except T_beads (K):
+ *   V_bar  = sum_k V(q^k) / P
+ *   E_spring = sum_k sum_i 1/2 m_i w_P^2 |q_i^{k+1} - q_i^k|^2
+ *   K_prim = 3NP/(2 beta) - E_spring / P
+ *   K_cv   = 3N/(2 beta) - 1/(2P) sum_k sum_i (q_i^k - qbar_i) . F_i^k
+ *   K_beads = sum |p|^2 / (2m),  T_beads = 2 K_beads / (3 N P k_B)  (-> P T)
+ *   heat_bath = -(sum of kinetic-energy changes made by every O step)
+ *   H_conserved = K_beads + E_spring + sum_k V(q^k) + heat_bath */
+typedef struct {
+    double V_bar, K_prim, K_cv, E_spring, K_beads, T_beads, H_conserved, heat_bath;
+} pimd_estimates;
+
+/* Bytes of device workspace a context needs for cfg.  No GPU needed. */
+pimd_status pimd_workspace_size(const pimd_config *cfg, size_t *bytes);
+
+/* Validate cfg, carve the workspace and upload tables and weights.
+ * workspace_dev: device memory of ws_bytes (>= pimd_workspace_size), 256-byte
+ * aligned, owned by the caller.  hip_stream: a hipStream_t (NULL = default).
+ * On success *out holds a new context; the state must be set with
+ * pimd_set_state before pimd_step. */
+pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_bytes,
+                      void *hip_stream, pimd_ctx **out);
+
+/* Replace the stream later calls enqueue on. */
+pimd_status pimd_set_stream(pimd_ctx *ctx, void *hip_stream);
+
+/* Copy positions and momenta (state layout, device) into the context and set
+ * the step counter; forces are evaluated at the first pimd_step. */
+pimd_status pimd_set_state(pimd_ctx *ctx, const float *q_dev, const float *p_dev, int64_t step);
+
+/* Copy positions, momenta (state layout; either may be NULL) and optionally
+ * the forces of the current positions (forces_dev, NULL to skip) out of the
+ * context.  Synchronises; returns a latched device fault, if any. */
+pimd_status pimd_get_state(pimd_ctx *ctx, float *q_dev, float *p_dev, float *forces_dev, int64_t *step);
+
+/* Potential energy of every bead at positions q_dev (state layout):
+ * energy_dev[sum P_s] (eV); forces_dev [B][3] = -dE/dq (eV/A) or NULL for
+ * energy only; virial_dev [sum P_s][9] (row-major W_ab = -sum_i sum_j
+ * d_ij,a dE_i/dd_ij,b, eV) or NULL.  The integrator state is not touched.
+ * Asynchronous. */
+pimd_status pimd_energy_forces(pimd_ctx *ctx, const float *q_dev, float *energy_dev,
+                               float *forces_dev, float *virial_dev);
+
+/* Advance every system by n_steps full integrator steps (one force
+ * evaluation each).  After the first step the step is replayed as a captured
+ * HIP graph.  Asynchronous. */
+pimd_status pimd_step(pimd_ctx *ctx, int32_t n_steps);
+
+/* Estimators of the current state for every system (out_host[n_systems]).
+ * Synchronises; returns a latched device fault, if any. */
+pimd_status pimd_estimators(pimd_ctx *ctx, pimd_estimates *out_host);
+
+/* Test hook: the next pimd_step uses xi_dev ([2][B][3] float32 normals:
+ * half 0 then half 1, rows indexed like the Philox counter) instead of
+ * Philox for its two O steps.  The buffer is copied at this call. */
+pimd_status pimd_inject_noise(pimd_ctx *ctx, const float *xi_dev);
+
+/* Debug: neighbour list of global bead `bead` from the last force
+ * evaluation, as (i, j) pairs of atom indices within the bead, sorted by
+ * (i, j): ij_host[2*cap].  Synchronises. */
+pimd_status pimd_debug_neighbors(pimd_ctx *ctx, int32_t bead, int32_t *ij_host, int64_t cap,
+                                 int64_t *count);
+
+/* Debug: normalised descriptors of the last force evaluation, [B][D]
+ * float32 (device).  BPNN only. */
+pimd_status pimd_debug_descriptors(pimd_ctx *ctx, float *xhat_dev);
+
+/* Debug: copy an internal buffer of the last force evaluation to dst_dev
+ * (device memory of at least the buffer's size, else PIMD_E_ARG):
+ *   PIMD_BUF_XHAT   [B][D] float32 normalised descriptors
+ *   PIMD_BUF_DEDG   [B][D] float32 dE/dG
+ *   PIMD_BUF_SLOTS  [B][max_neighbors][4] float32 slot vectors dE_i/d d_ij (xyz, 0)
+ *   PIMD_BUF_NBR    [B][max_neighbors] int32 neighbour keys (element << 27 | row)
+ *   PIMD_BUF_NCOUNT [B] int32 neighbour counts
+ *   PIMD_BUF_EATOM  [B] float32 atomic energies */
+enum { PIMD_BUF_XHAT = 0, PIMD_BUF_DEDG = 1, PIMD_BUF_SLOTS = 2, PIMD_BUF_NBR = 3, PIMD_BUF_NCOUNT = 4,
+       PIMD_BUF_EATOM = 5 };
+pimd_status pimd_debug_copy(pimd_ctx *ctx, int32_t buffer, void *dst_dev, size_t bytes);
+
+/* Debug: Philox words of the thermostat for (step, half): words_dev[n][4]
+ * uint32 for counter rows 0..n-1. */
+pimd_status pimd_debug_philox(pimd_ctx *ctx, int64_t step, int32_t half, int64_t n, uint32_t *words_dev);
+
+/* Launch mode of pimd_step: enabled = 1 (default) replays the step as a
+ * captured HIP graph; 0 enqueues every kernel of every step one by one. */
+pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled);
+
+/* Stage timing: runs n_reps integrator steps with the kernels enqueued one
+ * by one, records HIP events between the stages on the context stream and
+ * writes the mean milliseconds per step of each stage to
+ * ms_host[PIMD_N_STAGES] in this order: integrate (before the force),
+ * neighbour search (wrap, cells, lists), descriptors, MLP, adjoint, force
+ * assembly with bead sums, integrate (after the force) with the step
+ * bookkeeping.  Advances the state by n_reps steps.  Synchronises. */
+#define PIMD_N_STAGES 7
+pimd_status pimd_profile_stages(pimd_ctx *ctx, int32_t n_reps, double *ms_host);
+
+/* Work of the last force evaluation (BPNN): neighbour pairs (i, j), j<k
+ * neighbour pairs of every centre (triplets) and the triplets with
+ * r_jk < cutoff.  Synchronises. */
+pimd_status pimd_work_counts(pimd_ctx *ctx, int64_t *pairs, int64_t *triplets, int64_t *triplets_in_range);
+
+/* Sizes of a configured context: total bead-atoms B, total beads, features D. */
+pimd_status pimd_sizes(const pimd_ctx *ctx, int64_t *bead_atoms, int64_t *beads, int32_t *features);
+
+const char *pimd_last_error(const pimd_ctx *ctx);  /* ctx may be NULL: last init error */
+const char *pimd_status_str(pimd_status s);
+void pimd_destroy(pimd_ctx *ctx);                   /* synchronises; NULL is a no-op */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIMD_H */

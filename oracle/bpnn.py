@@ -102,10 +102,10 @@ def mlp_energy_grad(model, species_of_centres, xhat, bf16=False):
     Forward: h_0 = xhat, h_l = tanh(W_l h_{l-1} + b_l), E = w_out . h_L + b_out.
     Input gradient by the transposed chain:
       g_L = w_out * (1 - h_L^2), g_{l-1} = (W_l^T g_l) * (1 - h_{l-1}^2), dE/dxhat = W_1^T g_1.
-    bf16=True rounds the GEMM operands (inputs, activations, upstream
-    gradients and weights) to bfloat16 before each product and accumulates
-    in FP64; it mirrors a BF16-operand / wide-accumulate GEMM and is for
-    diagnosis only.
+    bf16=True rounds the operands of the layer products (inputs,
+    activations, upstream gradients and weights) to bfloat16 before each
+    product and accumulates in FP64 (the energy readout stays unrounded); it
+    mirrors a BF16-operand / wide-accumulate GEMM and is for diagnosis only.
     """
     rnd = _round_bf16 if bf16 else (lambda a: a)
     n, D = xhat.shape
@@ -120,7 +120,7 @@ def mlp_energy_grad(model, species_of_centres, xhat, bf16=False):
             hs.append(np.tanh(rnd(hs[-1]) @ rnd(W.astype(np.float64)).T + b.astype(np.float64)))
         Wo, bo = layers[-1]
         wo = Wo.astype(np.float64)[0]
-        E[sel] = rnd(hs[-1]) @ rnd(wo) + float(bo[0])
+        E[sel] = hs[-1] @ wo + float(bo[0])
         g = wo[None, :] * (1.0 - hs[-1] ** 2)
         for l in range(len(layers) - 2, -1, -1):
             up = rnd(g) @ rnd(layers[l][0].astype(np.float64))

@@ -1,0 +1,98 @@
+// Device helpers: wave-level synchronisation and reductions, bfloat16
+// rounding, and the Philox4x32-10 generator of the thermostat noise.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pimd_internal.hpp"
+
+namespace pimd {
+
+// Orders the LDS accesses of one wave across lanes (lanes of a wave run in
+// lock step; this stops the compiler from moving accesses across the point).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// Butterfly sum over the 64 lanes; every lane gets the total.  The order of
+// the additions is fixed, so the result is bitwise reproducible.
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Sum over the 16 lanes that share lane / 16.
+__device__ __forceinline__ float row16_sum(float v)
+{
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t lanes_below_mask()
+{
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// float -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// products mixed with the other counter words and the round key; the key
+// advances by the Weyl constants after each round.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = c.x * 0xD2511F53u, hi0 = __umulhi(c.x, 0xD2511F53u);
+        const uint32_t lo1 = c.z * 0xCD9E8D57u, hi1 = __umulhi(c.z, 0xCD9E8D57u);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Thermostat normal for component comp (0, 1, 2) of counter row `row`:
+// u = (x + 1/2) 2^-32; Box-Muller on (u0, u1) gives x and y, on (u2, u3) z.
+__device__ __forceinline__ float thermostat_normal(uint32_t k0, uint32_t k1, int64_t step, int half,
+                                                   int64_t row, int comp)
+{
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)row, (uint32_t)half, (uint32_t)step,
+                                             (uint32_t)((uint64_t)step >> 32)), k0, k1);
+    const float scale = 2.3283064365386963e-10f;  // 2^-32
+    const uint32_t xr = comp < 2 ? w.x : w.z;
+    const uint32_t xa = comp < 2 ? w.y : w.w;
+    const float ur = fmaf((float)xr, scale, 0.5f * scale);
+    const float ua = fmaf((float)xa, scale, 0.5f * scale);
+    const float r = sqrtf(-2.0f * logf(ur));
+    float sn, cs;
+    sincospif(2.0f * ua, &sn, &cs);
+    return comp == 1 ? r * sn : r * cs;
+}
+
+}  // namespace pimd

@@ -1,0 +1,340 @@
+// Ring-polymer propagation in normal modes with the PILE-L thermostat
+// (Sec. 2.1: normal-mode transformation of the ring polymer; Table S3:
+// PILE-L), split as O(dt/2) B(dt/2) A(dt) [forces] B(dt/2) O(dt/2).
+//
+// A workgroup owns `ncol` columns (atom, xyz) of one system and P threads per
+// column.  The P bead values of each column are staged in LDS; thread k of a
+// column forms normal mode k as the dot product with column k of the
+// orthonormal matrix C (kept transposed in LDS with a padded stride), applies
+// the O/B/A updates of that mode, and the inverse transform is the same dot
+// product with row j of C.  For P <= 128 this dense form costs about as much as
+// a real FFT and needs no bit reversal; HBM traffic (q, p, F once each) bounds
+// the kernel either way.
+//
+//   O: p~_k <- c1_k p~_k + sqrt(m) sig_T c2_k xi,   (kinetic-energy change -> heat bath)
+//   B: p~_k <- p~_k + dt/2 F~_k / MVV2E
+//   A: k = 0: q~ += dt p~/m;  k > 0: exact rotation at w_k in (q~, p~/(m w_k)).
+// Noise xi: Philox4x32-10, counter (row of (system, mode k, atom), half, step),
+// unless the caller injected a buffer.
+#include "device_common.hpp"
+
+namespace pimd {
+
+struct IntegArgs {
+    float *q, *p;
+    const float *F;
+    const SysInfo *sys;
+    const ModeInfo *modes;
+    const IntegUnit *units;
+    const float *cmat;
+    const float *mass_atom;
+    const int64_t *step;
+    double *dke_part;
+    const float *xi;     // injected noise [2][B][3] or null
+    int B;
+    float dt;
+    uint32_t key0, key1;
+};
+
+__device__ __forceinline__ float noise_value(const IntegArgs &a, int half, int64_t row, int comp, int64_t step)
+{
+    if (a.xi)
+        return a.xi[((int64_t)half * a.B + row) * 3 + comp];
+    return thermostat_normal(a.key0, a.key1, step, half, row, comp);
+}
+
+__device__ double block_sum_double(double v, double *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = blockDim.x >> 1; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o)
+            red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// LDS: CT[P][P+1] | s0[256] | s1[256] | s2[256] | red[256] doubles
+template <bool PRE>
+__global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
+{
+    extern __shared__ float ism[];
+    const IntegUnit u = a.units[blockIdx.x];
+    const SysInfo S = a.sys[u.sys];
+    const int P = S.P, N = S.N;
+    float *CT = ism;
+    float *s0 = CT + P * (P + 1);
+    float *s1 = s0 + 256;
+    float *s2 = s1 + 256;
+    double *red = reinterpret_cast<double *>(s2 + 256);
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < P * P; idx += 256) {
+        const int j = idx / P, k = idx - j * P;
+        CT[k * (P + 1) + j] = a.cmat[S.cmat0 + idx];  // C[j][k]
+    }
+    const int cl = tid / P, kk = tid - cl * P;
+    const bool valid = cl < u.ncol;
+    const int col = u.col0 + cl;
+    const int atom = col / 3, cc = col - 3 * (col / 3);
+    const int64_t row = (int64_t)S.ba0 + (int64_t)kk * N + atom;   // bead kk (loads) = mode kk (noise)
+    const int64_t step = *a.step;
+    float m = 1.0f;
+    if (valid) {
+        m = a.mass_atom[S.atom0 + atom];
+        s0[tid] = a.p[row * 3 + cc];
+        s1[tid] = a.F[row * 3 + cc];
+        if (PRE)
+            s2[tid] = a.q[row * 3 + cc];
+    }
+    __syncthreads();
+    const float kick = 0.5f * a.dt / (float)kMvv2e;
+    float dke = 0.0f;
+    float pt = 0.0f, qt = 0.0f;
+    if (valid) {
+        const float *ct = CT + kk * (P + 1);
+        const float *sp = s0 + cl * P, *sf = s1 + cl * P, *sq = s2 + cl * P;
+        const ModeInfo M = a.modes[S.mode0 + kk];
+        const float sig = sqrtf(m) * S.sig_T;
+        if (PRE) {
+            float Ft = 0.0f;
+            for (int j = 0; j < P; ++j) {
+                const float c = ct[j];
+                pt += c * sp[j];
+                Ft += c * sf[j];
+                qt += c * sq[j];
+            }
+            // O(dt/2), half 0
+            const float xi = noise_value(a, 0, row, cc, step);
+            const float pn = M.c1 * pt + sig * M.c2 * xi;
+            dke = 0.5f * (pn * pn - pt * pt) / m * (float)kMvv2e;
+            pt = pn + kick * Ft;  // B(dt/2)
+            // A(dt)
+            if (kk == 0) {
+                qt += a.dt * pt / m;
+            } else {
+                const float mw = m * M.w;
+                const float qn = M.sw * pt / mw + M.cw * qt;
+                const float pn2 = M.cw * pt - mw * M.sw * qt;
+                qt = qn;
+                pt = pn2;
+            }
+        } else {
+            // B(dt/2) in bead space, then to modes
+            for (int j = 0; j < P; ++j)
+                pt += ct[j] * (sp[j] + kick * sf[j]);
+            const float xi = noise_value(a, 1, row, cc, step);
+            const float pn = M.c1 * pt + sig * M.c2 * xi;
+            dke = 0.5f * (pn * pn - pt * pt) / m * (float)kMvv2e;
+            pt = pn;
+        }
+    }
+    __syncthreads();
+    if (valid) {
+        s0[tid] = pt;
+        if (PRE)
+            s2[tid] = qt;
+    }
+    __syncthreads();
+    if (valid) {
+        // back to beads: x_j = sum_k C[j][k] x~_k, with j = kk
+        float pj = 0.0f, qj = 0.0f;
+        const float *sp = s0 + cl * P, *sq = s2 + cl * P;
+        for (int k = 0; k < P; ++k) {
+            const float c = CT[k * (P + 1) + kk];
+            pj += c * sp[k];
+            if (PRE)
+                qj += c * sq[k];
+        }
+        a.p[row * 3 + cc] = pj;
+        if (PRE)
+            a.q[row * 3 + cc] = qj;
+    }
+    const double tot = block_sum_double((double)dke, red);
+    if (tid == 0)
+        a.dke_part[2 * blockIdx.x + (PRE ? 0 : 1)] = tot;
+}
+
+// heat_bath[s] -= (sum of O-step kinetic-energy changes of the step); step += 1
+__global__ void k_finish_step(const SysInfo *__restrict__ sys, const double *__restrict__ dke_part,
+                              double *__restrict__ heat, int64_t *__restrict__ step, int n_sys)
+{
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n_sys; s += gridDim.x * blockDim.x) {
+        const SysInfo S = sys[s];
+        double d = 0.0;
+        for (int u = S.unit0; u < S.unit0 + S.nunit; ++u)
+            d += dke_part[2 * u] + dke_part[2 * u + 1];
+        heat[s] -= d;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        step[0] += 1;
+}
+
+// Estimator terms per column (atom, xyz) of every system:
+// [0] m sum_k (q_{k+1} - q_k)^2, [1] sum_k (q_k - qbar) F_k, [2] sum_k p_k^2 / m
+__global__ __launch_bounds__(256) void k_estimator_terms(const float *__restrict__ q, const float *__restrict__ p,
+                                                         const float *__restrict__ F, const SysInfo *__restrict__ sys,
+                                                         const int32_t *__restrict__ col_sys,
+                                                         const float *__restrict__ mass_atom,
+                                                         float *__restrict__ out, int ncol)
+{
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= ncol)
+        return;
+    const SysInfo S = sys[col_sys[col]];
+    const int gatom = col / 3, cc = col - 3 * gatom;
+    const int atom = gatom - S.atom0;
+    const float m = mass_atom[gatom];
+    float qbar = 0.0f;
+    for (int k = 0; k < S.P; ++k)
+        qbar += q[((int64_t)S.ba0 + (int64_t)k * S.N + atom) * 3 + cc];
+    qbar /= (float)S.P;
+    float spring = 0.0f, cv = 0.0f, ke = 0.0f;
+    for (int k = 0; k < S.P; ++k) {
+        const int64_t r = (int64_t)S.ba0 + (int64_t)k * S.N + atom;
+        const int64_t rn = (int64_t)S.ba0 + (int64_t)((k + 1) % S.P) * S.N + atom;
+        const float qk = q[r * 3 + cc];
+        const float dq = q[rn * 3 + cc] - qk;
+        spring += dq * dq;
+        cv += (qk - qbar) * F[r * 3 + cc];
+        const float pk = p[r * 3 + cc];
+        ke += pk * pk;
+    }
+    out[3 * (int64_t)col + 0] = m * spring;
+    out[3 * (int64_t)col + 1] = cv;
+    out[3 * (int64_t)col + 2] = ke / m;
+}
+
+// Isotropic harmonic well V = 1/2 m w^2 |q|^2 per atom (the oscillator of Sec. S1).
+__global__ __launch_bounds__(256) void k_harmonic(const float *__restrict__ q, const BeadInfo *__restrict__ beads,
+                                                  const int32_t *__restrict__ bead_of_ba,
+                                                  const SysInfo *__restrict__ sys,
+                                                  const float *__restrict__ mass_atom, float w2_mvv2e,
+                                                  float *__restrict__ E_atom, float *__restrict__ F,
+                                                  float *__restrict__ vir_atom, int B)
+{
+    const int ba = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ba >= B)
+        return;
+    const BeadInfo bi = beads[bead_of_ba[ba]];
+    const float m = mass_atom[sys[bi.sys].atom0 + (ba - bi.ba0)];
+    const float k = m * w2_mvv2e;
+    const float x = q[3 * ba], y = q[3 * ba + 1], z = q[3 * ba + 2];
+    E_atom[ba] = 0.5f * k * (x * x + y * y + z * z);
+    const float f[3] = {-k * x, -k * y, -k * z};
+    if (F) {
+        F[3 * ba] = f[0];
+        F[3 * ba + 1] = f[1];
+        F[3 * ba + 2] = f[2];
+    }
+    const float r[3] = {x, y, z};
+    for (int a2 = 0; a2 < 3; ++a2)
+        for (int b2 = 0; b2 < 3; ++b2)
+            vir_atom[9 * (int64_t)ba + 3 * a2 + b2] = r[a2] * f[b2];
+}
+
+__global__ void k_philox_words(uint32_t k0, uint32_t k1, int64_t step, int half, int64_t n, uint32_t *out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n)
+        return;
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)t, (uint32_t)half, (uint32_t)step,
+                                             (uint32_t)((uint64_t)step >> 32)), k0, k1);
+    out[4 * t + 0] = w.x;
+    out[4 * t + 1] = w.y;
+    out[4 * t + 2] = w.z;
+    out[4 * t + 3] = w.w;
+}
+
+__global__ void k_check_finite(const float *a, int64_t n, uint32_t *status)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n && !isfinite(a[t]))
+        atomicOr(status, kStatusNonFinite);
+}
+
+static IntegArgs integ_args(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi)
+{
+    IntegArgs a;
+    a.q = d.q;
+    a.p = d.p;
+    a.F = d.F;
+    a.sys = d.sys;
+    a.modes = d.modes;
+    a.units = d.units;
+    a.cmat = d.cmat;
+    a.mass_atom = d.mass_atom;
+    a.step = d.step;
+    a.dke_part = d.dke_part;
+    a.xi = xi;
+    a.B = z.B;
+    a.dt = dt;
+    a.key0 = k0;
+    a.key1 = k1;
+    return a;
+}
+
+static size_t integ_lds(int max_P)
+{
+    return (size_t)max_P * (max_P + 1) * sizeof(float) + 3 * 256 * sizeof(float) + 256 * sizeof(double);
+}
+
+size_t integrator_lds_bytes(int max_P) { return integ_lds(max_P); }
+
+hipError_t configure_integrator_lds(int max_P)
+{
+    const int b = (int)integ_lds(max_P);
+    hipError_t e = hipFuncSetAttribute((const void *)k_integrate<true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_integrate<false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    return e;
+}
+
+void launch_integrate_pre(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi,
+                          int max_P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_integrate<true>, dim3(z.n_units), dim3(256), integ_lds(max_P), s,
+                       integ_args(d, z, dt, k0, k1, xi));
+}
+
+void launch_integrate_post(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi,
+                           int max_P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_integrate<false>, dim3(z.n_units), dim3(256), integ_lds(max_P), s,
+                       integ_args(d, z, dt, k0, k1, xi));
+}
+
+void launch_finish_step(const DevBuffers &d, const Sizes &z, hipStream_t s)
+{
+    const int grid = (z.n_sys + 255) / 256;
+    hipLaunchKernelGGL(k_finish_step, dim3(grid), dim3(256), 0, s, d.sys, d.dke_part, d.heat, d.step, z.n_sys);
+}
+
+void launch_estimator_terms(const DevBuffers &d, const Sizes &z, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_estimator_terms, dim3((z.ncol + 255) / 256), dim3(256), 0, s, d.q, d.p, d.F, d.sys,
+                       d.col_sys, d.mass_atom, d.est_cols, z.ncol);
+}
+
+void launch_harmonic(const float *q, const DevBuffers &d, const Sizes &z, float w2_mvv2e, float *F, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_harmonic, dim3((z.B + 255) / 256), dim3(256), 0, s, q, d.beads, d.bead_of_ba, d.sys,
+                       d.mass_atom, w2_mvv2e, d.E_atom, F, d.vir_atom, z.B);
+}
+
+void launch_philox_words(uint32_t k0, uint32_t k1, int64_t step, int half, int64_t n, uint32_t *out, hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    hipLaunchKernelGGL(k_philox_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, k0, k1, step, half, n,
+                       out);
+}
+
+void launch_check_finite(const float *a, int64_t n, uint32_t *status, hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, n, status);
+}
+
+}  // namespace pimd

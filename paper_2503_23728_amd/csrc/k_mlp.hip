@@ -1,0 +1,402 @@
+// Per-element MLP of the Behler-Parrinello potential on MFMA, fused:
+// forward through the hidden tanh layers, the energy readout, and the input
+// gradient dE/dx by the transposed chain, divided by the feature scale
+// (dE/dG), for one 16-row tile per workgroup.
+//
+//   h_l = tanh(W_l h_{l-1} + b_l),  E = w_o . h_L + b_o
+//   g_L = w_o * (1 - h_L^2),  g_{l-1} = (W_l^T g_l) * (1 - h_{l-1}^2),  dE/dx = W_1^T g_1
+//
+// Each GEMM is rows(16) x K times K x N with the 16x16 MFMA tiles of gfx950,
+// accumulating in FP32; the operand precision modes are listed at MlpCfg.  Activations pass between layers through a per-wave
+// LDS tile; (1 - h^2) of every hidden layer stays in registers in the MFMA
+// output layout, which is also the layout of the backward GEMM outputs.
+// Weights are read from global memory (L2-resident, shared by all waves):
+// W[out][in] serves the forward B operand and its transpose WT[in][out] the
+// backward one, so each lane reads contiguous k.
+#include "device_common.hpp"
+
+namespace pimd {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+
+// MODE 0: FP32 operands (v_mfma_f32_16x16x4f32).
+// MODE 1: BF16 operands, three-term split: with a = a_hi + a_lo and
+//         b = b_hi + b_lo (each part bfloat16), acc += a_hi b_hi + a_lo b_hi + a_hi b_lo
+//         (v_mfma_f32_16x16x16bf16_1k, FP32 accumulation); the dropped a_lo b_lo term is
+//         below 2^-16 of the product.
+// MODE 2: BF16 operands, one term: acc += bf16(a) bf16(b).
+// (Mode 3, FP64 operands and activations, is the separate kernel k_mlp_f64.)
+template <int MODE>
+struct MlpCfg {
+    static constexpr int S = MODE == 0 ? 130 : 136;  // LDS row stride (floats)
+};
+
+__device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// acc[t] = A[16][K] * B[K][16 ct ...] for the column tiles ct = w + 4t < nct,
+// with B[k][n] = Bt[n][k] (row-major Bt[N][ldb]); A is the LDS tile.
+template <int MODE>
+__device__ __forceinline__ void gemm16_cols(const float *act, int K, const float *Bt, const uint16_t *Btb,
+                                            const uint16_t *Btb_lo, int ldb, int nct, int w, f32x4 (&acc)[8])
+{
+    constexpr int S = MlpCfg<MODE>::S;
+    const int lane = lane_id();
+    const int lr = lane & 15, lg = lane >> 4;
+    acc[0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    acc[1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    if (MODE == 0) {
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const float a = act[lr * S + k0 + lg];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ct = w + 4 * t;
+                if (ct < nct) {
+                    const float b = Bt[(ct * 16 + lr) * ldb + k0 + lg];
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+                }
+            }
+        }
+    } else {
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            const float4 av = *reinterpret_cast<const float4 *>(act + lr * S + k0 + lg * 4);
+            const float af[4] = {av.x, av.y, av.z, av.w};
+            i16x4 ahi, alo;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint16_t h = f32_to_bf16(af[u]);
+                ahi[u] = (short)h;
+                alo[u] = (short)f32_to_bf16(af[u] - bf16_value(h));
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ct = w + 4 * t;
+                if (ct < nct) {
+                    const int64_t o = (int64_t)(ct * 16 + lr) * ldb + k0 + lg * 4;
+                    const i16x4 bhi = *reinterpret_cast<const i16x4 *>(Btb + o);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc[t], 0, 0, 0);
+                    if (MODE == 1) {
+                        const i16x4 blo = *reinterpret_cast<const i16x4 *>(Btb_lo + o);
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc[t], 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc[t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// One workgroup per 16-row tile (tiles of all elements in one launch); the
+// four waves split the output columns of every GEMM (column tiles w and w+4),
+// and the activations of the tile live in LDS between layers.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, const MlpTile *__restrict__ tiles,
+                                             const float *__restrict__ xhat, int D, int Dp, MlpNets nets,
+                                             float *__restrict__ E_atom, float *__restrict__ dEdG)
+{
+    constexpr int S = MlpCfg<MODE>::S;
+    __shared__ __attribute__((aligned(16))) float act[16 * S];
+    __shared__ float epart[4][16];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const MlpTile tile = tiles[blockIdx.x];
+    const MlpNet &net = nets.net[tile.e];
+    const int32_t *trows = rows + tile.row0;
+    const int nrows = tile.nrows;
+
+    for (int idx = threadIdx.x; idx < 16 * Dp; idx += 256) {
+        const int r = idx / Dp, c = idx - r * Dp;
+        act[r * S + c] = (r < nrows && c < D) ? xhat[(int64_t)trows[r] * D + c] : 0.0f;
+    }
+    __syncthreads();
+
+    f32x4 dsave[3][2];
+    f32x4 acc[8];
+    int K = Dp;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (l < net.n_hidden) {
+            const MlpLayer L = net.layer[l];
+            gemm16_cols<MODE>(act, K, L.W, L.Wb, L.Wb_lo, L.in_pad, L.out / 16, w, acc);
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ct = w + 4 * t;
+                if (ct < L.out / 16) {
+                    const int col = ct * 16 + lr;
+                    const float bias = L.b[col];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        // tanh and 1 - tanh^2 = sech^2 from e = exp(-2|z|): tanh = sign(z)(1 - e)/(1 + e),
+                        // sech^2 = 4e/(1 + e)^2, free of the cancellation in 1 - h^2 for saturated units
+                        const float z = acc[t][q] + bias;
+                        const float e = expf(-2.0f * fabsf(z));
+                        const float ope = 1.0f + e;
+                        dsave[l][t][q] = 4.0f * e / (ope * ope);
+                        act[(lg * 4 + q) * S + col] = copysignf((1.0f - e) / ope, z);
+                    }
+                }
+            }
+            __syncthreads();
+            K = L.out;
+        }
+    }
+    // energy readout (FP32 on the VALU in every mode); waves hold column slices
+    const int nlast = K / 16;
+    float e_part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int ct = w + 4 * t;
+        if (ct < nlast) {
+            const int col = ct * 16 + lr;
+            const float wo = net.wo[col];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                e_part[q] += act[(lg * 4 + q) * S + col] * wo;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        e_part[q] = row16_sum(e_part[q]);
+    if (lr == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            epart[w][lg * 4 + q] = e_part[q];
+    __syncthreads();
+    if (threadIdx.x < 16 && (int)threadIdx.x < nrows)
+        E_atom[trows[threadIdx.x]] = ((epart[0][threadIdx.x] + epart[1][threadIdx.x]) +
+                                      (epart[2][threadIdx.x] + epart[3][threadIdx.x])) + net.bo;
+    // g_L = w_o * (1 - h_L^2)
+    const int nh = net.n_hidden;
+#pragma unroll
+    for (int l = 2; l >= 0; --l) {
+        if (l == nh - 1) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ct = w + 4 * t;
+                if (ct < nlast) {
+                    const int col = ct * 16 + lr;
+                    const float wo = net.wo[col];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        act[(lg * 4 + q) * S + col] = wo * dsave[l][t][q];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // g_{l-1} = (W_l^T g_l) * (1 - h_{l-1}^2)
+#pragma unroll
+    for (int l = 2; l >= 1; --l) {
+        if (l < nh) {
+            const MlpLayer L = net.layer[l];
+            gemm16_cols<MODE>(act, L.out, L.WT, L.WTb, L.WTb_lo, L.out, L.in_pad / 16, w, acc);
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ct = w + 4 * t;
+                if (ct < L.in_pad / 16) {
+                    const int col = ct * 16 + lr;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        act[(lg * 4 + q) * S + col] = acc[t][q] * dsave[l - 1][t][q];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // dE/dx = W_1^T g_1 and dE/dG = dE/dx / scale
+    const MlpLayer L0 = net.layer[0];
+    gemm16_cols<MODE>(act, L0.out, L0.WT, L0.WTb, L0.WTb_lo, L0.out, Dp / 16, w, acc);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int ct = w + 4 * t;
+        if (ct < Dp / 16) {
+            const int col = ct * 16 + lr;
+            if (col < D) {
+                const float is = net.inv_scale[col];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = lg * 4 + q;
+                    if (r < nrows)
+                        dEdG[(int64_t)trows[r] * D + col] = acc[t][q] * is;
+                }
+            }
+        }
+    }
+}
+
+// FP64 variant (precision mode 3): the same chain with FP64 operands,
+// activations and accumulation on v_mfma_f64_16x16x4f64, so the MLP adds no
+// error visible next to the FP32 descriptors.
+__device__ __forceinline__ void gemm16_cols_f64(const double *act, int K, const double *Bt, int ldb, int nct, int w,
+                                                f64x4 (&acc)[2])
+{
+    constexpr int S = 130;
+    const int lane = lane_id();
+    const int lr = lane & 15, lg = lane >> 4;
+    acc[0] = f64x4{0.0, 0.0, 0.0, 0.0};
+    acc[1] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const double a = act[lr * S + k0 + lg];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int ct = w + 4 * t;
+            if (ct < nct) {
+                const double b = Bt[(ct * 16 + lr) * ldb + k0 + lg];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_f64(const int32_t *__restrict__ rows, const MlpTile *__restrict__ tiles,
+                                                 const float *__restrict__ xhat, int D, int Dp, MlpNets nets,
+                                                 float *__restrict__ E_atom, float *__restrict__ dEdG)
+{
+    constexpr int S = 130;
+    __shared__ double act[16 * S];
+    __shared__ double epart[4][16];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const MlpTile tile = tiles[blockIdx.x];
+    const MlpNet &net = nets.net[tile.e];
+    const int32_t *trows = rows + tile.row0;
+    const int nrows = tile.nrows;
+    for (int idx = threadIdx.x; idx < 16 * Dp; idx += 256) {
+        const int r = idx / Dp, c = idx - r * Dp;
+        act[r * S + c] = (r < nrows && c < D) ? (double)xhat[(int64_t)trows[r] * D + c] : 0.0;
+    }
+    __syncthreads();
+    f64x4 dsave[3][2];
+    f64x4 acc[2];
+    int K = Dp;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (l < net.n_hidden) {
+            const MlpLayer L = net.layer[l];
+            gemm16_cols_f64(act, K, L.W64, L.in_pad, L.out / 16, w, acc);
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ct = w + 4 * t;
+                if (ct < L.out / 16) {
+                    const int col = ct * 16 + lr;
+                    const double bias = (double)L.b[col];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double z = acc[t][q] + bias;
+                        const double e = exp(-2.0 * fabs(z));
+                        const double ope = 1.0 + e;
+                        dsave[l][t][q] = 4.0 * e / (ope * ope);
+                        act[(lg * 4 + q) * S + col] = copysign((1.0 - e) / ope, z);
+                    }
+                }
+            }
+            __syncthreads();
+            K = L.out;
+        }
+    }
+    const int nlast = K / 16;
+    double e_part[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int ct = w + 4 * t;
+        if (ct < nlast) {
+            const int col = ct * 16 + lr;
+            const double wo = (double)net.wo[col];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                e_part[q] += act[(lg * 4 + q) * S + col] * wo;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1)
+            e_part[q] += __shfl_xor(e_part[q], o, kWave);
+    if (lr == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            epart[w][lg * 4 + q] = e_part[q];
+    __syncthreads();
+    if (threadIdx.x < 16 && (int)threadIdx.x < nrows)
+        E_atom[trows[threadIdx.x]] = (float)(((epart[0][threadIdx.x] + epart[1][threadIdx.x]) +
+                                              (epart[2][threadIdx.x] + epart[3][threadIdx.x])) + (double)net.bo);
+    const int nh = net.n_hidden;
+#pragma unroll
+    for (int l = 2; l >= 0; --l) {
+        if (l == nh - 1) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ct = w + 4 * t;
+                if (ct < nlast) {
+                    const int col = ct * 16 + lr;
+                    const double wo = (double)net.wo[col];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        act[(lg * 4 + q) * S + col] = wo * dsave[l][t][q];
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 2; l >= 1; --l) {
+        if (l < nh) {
+            const MlpLayer L = net.layer[l];
+            gemm16_cols_f64(act, L.out, L.WT64, L.out, L.in_pad / 16, w, acc);
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ct = w + 4 * t;
+                if (ct < L.in_pad / 16) {
+                    const int col = ct * 16 + lr;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        act[(lg * 4 + q) * S + col] = acc[t][q] * dsave[l - 1][t][q];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const MlpLayer L0 = net.layer[0];
+    gemm16_cols_f64(act, L0.out, L0.WT64, L0.out, Dp / 16, w, acc);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int ct = w + 4 * t;
+        if (ct < Dp / 16) {
+            const int col = ct * 16 + lr;
+            if (col < D) {
+                const double is = (double)net.inv_scale[col];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = lg * 4 + q;
+                    if (r < nrows)
+                        dEdG[(int64_t)trows[r] * D + col] = (float)(acc[t][q] * is);
+                }
+            }
+        }
+    }
+}
+
+void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int mlp_mode, hipStream_t s)
+{
+    if (n_tiles <= 0)
+        return;
+    if (mlp_mode == 3)
+        hipLaunchKernelGGL(k_mlp_f64, dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp, nets,
+                           d.E_atom, d.dEdG);
+    else if (mlp_mode == 1)
+        hipLaunchKernelGGL(k_mlp<1>, dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp, nets,
+                           d.E_atom, d.dEdG);
+    else if (mlp_mode == 2)
+        hipLaunchKernelGGL(k_mlp<2>, dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp, nets,
+                           d.E_atom, d.dEdG);
+    else
+        hipLaunchKernelGGL(k_mlp<0>, dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp, nets,
+                           d.E_atom, d.dEdG);
+}
+
+}  // namespace pimd

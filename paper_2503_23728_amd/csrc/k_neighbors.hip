@@ -1,0 +1,269 @@
+// Per-bead cell lists and neighbour lists (the molecular graph of Sec. 2.2
+// with the cutoff of Tables S1/S2), periodic orthorhombic boxes.
+//
+// Membership is decided in float32 with one rounding per operation (no
+// contraction into fused multiply-adds), so it is reproducible bit for bit:
+//   x_w = x - L floor(x invL)            wrap into the box, invL = fl32(1/L)
+//   d   = x_w[j] - x_w[i]; d -= L rint(d invL)
+//   r2  = (dx dx + dy dy) + dz dz;  j is a neighbour iff j != i and r2 < fl32(rc^2)
+// Non-periodic systems test every pair on the raw positions.
+//
+// Output per centre row i: nbr[i][0..cnt) holds keys (element << 27) | row,
+// sorted ascending, i.e. grouped by element and ascending row within a
+// group; nbr_grp[i][e] counts each element's group.
+#include "device_common.hpp"
+
+namespace pimd {
+
+#pragma clang fp contract(off)
+
+__device__ __forceinline__ float wrap_coord(float x, float L, float invL)
+{
+    const float t = x * invL;
+    const float f = floorf(t);
+    const float m = L * f;
+    return x - m;
+}
+
+__device__ __forceinline__ int cell_of(float xw, float scale, int nc)
+{
+    int c = (int)(xw * scale);
+    c = c < 0 ? 0 : c;
+    return c >= nc ? nc - 1 : c;
+}
+
+__global__ __launch_bounds__(256) void k_wrap_bin(const float *__restrict__ q, const BeadInfo *__restrict__ beads,
+                                                  const int32_t *__restrict__ bead_of_ba,
+                                                  const int32_t *__restrict__ species_atom,
+                                                  const SysInfo *__restrict__ sys, float4 *__restrict__ pos4,
+                                                  float4 *__restrict__ posu4,
+                                                  int32_t *__restrict__ cell_count, int32_t *__restrict__ atom_cell,
+                                                  int32_t *__restrict__ atom_slot, int B)
+{
+    const int ba = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ba >= B)
+        return;
+    const BeadInfo bi = beads[bead_of_ba[ba]];
+    const int local = (ba - bi.ba0);
+    const int atom = sys[bi.sys].atom0 + local % bi.n;
+    const int z = species_atom[atom];
+    float x = q[3 * ba + 0], y = q[3 * ba + 1], w = q[3 * ba + 2];
+    posu4[ba] = make_float4(x, y, w, __int_as_float(z));
+    if (bi.periodic) {
+        x = wrap_coord(x, bi.L[0], bi.invL[0]);
+        y = wrap_coord(y, bi.L[1], bi.invL[1]);
+        w = wrap_coord(w, bi.L[2], bi.invL[2]);
+        const int cx = cell_of(x, bi.cell_scale[0], bi.nc[0]);
+        const int cy = cell_of(y, bi.cell_scale[1], bi.nc[1]);
+        const int cz = cell_of(w, bi.cell_scale[2], bi.nc[2]);
+        const int c = bi.cell0 + (cx * bi.nc[1] + cy) * bi.nc[2] + cz;
+        atom_cell[ba] = c;
+        atom_slot[ba] = atomicAdd(&cell_count[c], 1);
+    }
+    pos4[ba] = make_float4(x, y, w, __int_as_float(z));
+}
+
+// Exclusive scan of the cell counts of one bead (one workgroup per bead).
+__global__ __launch_bounds__(256) void k_cell_scan(const BeadInfo *__restrict__ beads,
+                                                   const int32_t *__restrict__ cell_count,
+                                                   int32_t *__restrict__ cell_start)
+{
+    const BeadInfo bi = beads[blockIdx.x];
+    if (!bi.periodic)
+        return;
+    const int ncell = bi.nc[0] * bi.nc[1] * bi.nc[2];
+    __shared__ int32_t part[256];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0)
+        carry = 0;
+    __syncthreads();
+    for (int base = 0; base < ncell; base += 256) {
+        const int c = base + threadIdx.x;
+        const int v = c < ncell ? cell_count[bi.cell0 + c] : 0;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const int t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+            __syncthreads();
+            part[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (c < ncell)
+            cell_start[bi.cell0 + c] = carry + part[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 255)
+            carry += part[255];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cell_fill(const BeadInfo *__restrict__ beads,
+                                                   const int32_t *__restrict__ bead_of_ba,
+                                                   const int32_t *__restrict__ atom_cell,
+                                                   const int32_t *__restrict__ atom_slot,
+                                                   const int32_t *__restrict__ cell_start,
+                                                   int32_t *__restrict__ cell_atoms, int B)
+{
+    const int ba = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ba >= B)
+        return;
+    const BeadInfo bi = beads[bead_of_ba[ba]];
+    if (!bi.periodic)
+        return;
+    cell_atoms[bi.ba0 + cell_start[atom_cell[ba]] + atom_slot[ba]] = ba;
+}
+
+__device__ __forceinline__ bool within_cutoff(const float4 &pi, const float4 &pj, const BeadInfo &bi, float rc2)
+{
+    float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+    if (bi.periodic) {
+        const float sx = bi.L[0] * rintf(dx * bi.invL[0]);
+        const float sy = bi.L[1] * rintf(dy * bi.invL[1]);
+        const float sz = bi.L[2] * rintf(dz * bi.invL[2]);
+        dx = dx - sx;
+        dy = dy - sy;
+        dz = dz - sz;
+    }
+    const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    const float r2 = (xx + yy) + zz;
+    return r2 < rc2;
+}
+
+// One wave per centre row.  Candidates come from the (deduplicated) 27-cell
+// stencil, or every atom of the bead when the system is not periodic;
+// accepted keys are compacted into LDS and rank-sorted.
+__global__ __launch_bounds__(256) void k_neighbors(const float4 *__restrict__ pos4,
+                                                   const BeadInfo *__restrict__ beads,
+                                                   const int32_t *__restrict__ bead_of_ba,
+                                                   const int32_t *__restrict__ cell_count,
+                                                   const int32_t *__restrict__ cell_start,
+                                                   const int32_t *__restrict__ cell_atoms, float rc2, int Kmax,
+                                                   int n_el, int32_t *__restrict__ nbr, int32_t *__restrict__ nbr_cnt,
+                                                   int32_t *__restrict__ nbr_grp, uint32_t *__restrict__ status, int B)
+{
+    extern __shared__ int32_t nl_lds[];
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6;
+    int32_t *buf = nl_lds + w * (Kmax + kWave);
+    const uint64_t below = lanes_below_mask();
+    for (int i = blockIdx.x * 4 + w; i < B; i += gridDim.x * 4) {
+        const BeadInfo bi = beads[bead_of_ba[i]];
+        const float4 pi = pos4[i];
+        int count = 0;
+        auto consider = [&](int j, bool valid) {
+            bool acc = false;
+            float4 pj;
+            if (valid && j != i) {
+                pj = pos4[j];
+                acc = within_cutoff(pi, pj, bi, rc2);
+            }
+            const uint64_t m = __ballot(acc);
+            const int pos = count + __popcll(m & below);
+            if (acc && pos < Kmax) {
+                const int z = __float_as_int(pj.w);
+                buf[pos] = (z << kKeyShift) | j;
+            }
+            count += __popcll(m);
+        };
+        if (bi.periodic) {
+            const int cx = cell_of(pi.x, bi.cell_scale[0], bi.nc[0]);
+            const int cy = cell_of(pi.y, bi.cell_scale[1], bi.nc[1]);
+            const int cz = cell_of(pi.z, bi.cell_scale[2], bi.nc[2]);
+            int ax[3][3], an[3];
+            const int cc[3] = {cx, cy, cz};
+            for (int d = 0; d < 3; ++d) {
+                const int nc = bi.nc[d];
+                if (nc < 3) {
+                    an[d] = nc;
+                    for (int t = 0; t < nc; ++t)
+                        ax[d][t] = t;
+                } else {
+                    an[d] = 3;
+                    ax[d][0] = (cc[d] + nc - 1) % nc;
+                    ax[d][1] = cc[d];
+                    ax[d][2] = (cc[d] + 1) % nc;
+                }
+            }
+            for (int a = 0; a < an[0]; ++a)
+                for (int b = 0; b < an[1]; ++b)
+                    for (int c = 0; c < an[2]; ++c) {
+                        const int cell = bi.cell0 + (ax[0][a] * bi.nc[1] + ax[1][b]) * bi.nc[2] + ax[2][c];
+                        const int st = cell_start[cell], ct = cell_count[cell];
+                        for (int t0 = 0; t0 < ct; t0 += kWave) {
+                            const int t = t0 + lane;
+                            const bool valid = t < ct;
+                            const int j = valid ? cell_atoms[bi.ba0 + st + t] : 0;
+                            consider(j, valid);
+                        }
+                    }
+        } else {
+            for (int t0 = 0; t0 < bi.n; t0 += kWave) {
+                const int t = t0 + lane;
+                consider(bi.ba0 + t, t < bi.n);
+            }
+        }
+        wave_sync();
+        if (count > Kmax && lane == 0)
+            atomicOr(status, kStatusOverflow);
+        const int K = count < Kmax ? count : Kmax;
+        int32_t *out = nbr + (int64_t)i * Kmax;
+        for (int s = lane; s < K; s += kWave) {
+            const int v = buf[s];
+            int rank = 0;
+            for (int u = 0; u < K; ++u)
+                rank += buf[u] < v;
+            out[rank] = v;
+        }
+        if (lane < kMaxElements) {
+            int c = 0;
+            for (int u = 0; u < K; ++u)
+                c += (buf[u] >> kKeyShift) == lane;
+            if (lane < n_el)
+                nbr_grp[(int64_t)i * kMaxElements + lane] = c;
+        }
+        if (lane == 0)
+            nbr_cnt[i] = K;
+        wave_sync();
+    }
+}
+
+__global__ void k_zero_i32(int32_t *p, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n)
+        p[t] = 0;
+}
+
+void launch_zero_i32(int32_t *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+}
+
+void launch_wrap_bin(const float *q, const DevBuffers &d, const Sizes &z, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_wrap_bin, dim3((z.B + 255) / 256), dim3(256), 0, s, q, d.beads, d.bead_of_ba,
+                       d.species_atom, d.sys, d.pos4, d.posu4, d.cell_count, d.atom_cell, d.atom_slot, z.B);
+}
+
+void launch_cell_scan(const DevBuffers &d, const Sizes &z, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cell_scan, dim3(z.n_beads_total), dim3(256), 0, s, d.beads, d.cell_count, d.cell_start);
+}
+
+void launch_cell_fill(const DevBuffers &d, const Sizes &z, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cell_fill, dim3((z.B + 255) / 256), dim3(256), 0, s, d.beads, d.bead_of_ba, d.atom_cell,
+                       d.atom_slot, d.cell_start, d.cell_atoms, z.B);
+}
+
+void launch_neighbors(const DevBuffers &d, const Sizes &z, float rc2, int n_el, hipStream_t s)
+{
+    const size_t lds = (size_t)4 * (z.Kmax + kWave) * sizeof(int32_t);
+    const int grid = (z.B + 3) / 4;
+    hipLaunchKernelGGL(k_neighbors, dim3(grid), dim3(256), lds, s, d.pos4, d.beads, d.bead_of_ba, d.cell_count,
+                       d.cell_start, d.cell_atoms, rc2, z.Kmax, n_el, d.nbr, d.nbr_cnt, d.nbr_grp, d.status, z.B);
+}
+
+}  // namespace pimd

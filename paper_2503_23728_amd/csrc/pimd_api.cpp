@@ -1,0 +1,1179 @@
+// Host runtime behind the C ABI of include/pimd.h: argument validation (no
+// HIP call before it passes), workspace planning, upload of tables and
+// weights, the force pipeline, the integrator step and its captured graph,
+// estimators and debug hooks.
+#include "../../include/pimd.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "pimd_internal.hpp"
+
+using namespace pimd;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+const double kPi = 3.14159265358979323846;
+
+struct Layout {
+    size_t total = 0;
+    std::map<std::string, size_t> off;
+    void add(const std::string &name, size_t bytes)
+    {
+        total = (total + 255) & ~size_t(255);
+        off[name] = total;
+        total += bytes;
+    }
+};
+
+// Everything derived from the config on the host.
+struct Plan {
+    int n_sys = 0, n_el = 0, B = 0, n_beads = 0, n_atoms = 0, ncol = 0, total_cells = 0, n_units = 0;
+    int D = 0, Dp = 0, Kmax = 0, max_P = 1, n_rad = 0, n_ang_eta = 0;
+    bool any_periodic = false, bpnn = false;
+    std::vector<int> cells_per_sys;            // cells per bead of each system
+    std::vector<std::array<int, 3>> nc;
+    size_t mlp_f32_floats = 0, mlp_bf16_elems = 0, mlp_f64_elems = 0, cmat_floats = 0, modes = 0;
+    std::vector<int> distinct_P;
+};
+
+int n_features(int n_el, int n_rad, int n_ang_eta) { return n_el * n_rad + n_el * (n_el + 1) / 2 * n_ang_eta * 8; }
+
+pimd_status fail(std::string *err, pimd_status s, const std::string &msg)
+{
+    if (err)
+        *err = msg;
+    return s;
+}
+
+// All checks are on host data only.
+pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
+{
+    if (!cfg)
+        return fail(err, PIMD_E_ARG, "config is NULL");
+    if (cfg->n_systems < 1)
+        return fail(err, PIMD_E_ARG, "n_systems must be >= 1");
+    if (!cfg->n_atoms || !cfg->n_beads || !cfg->temperature_K || !cfg->box_A || !cfg->species)
+        return fail(err, PIMD_E_ARG, "a per-system array is NULL");
+    if (!(cfg->dt_fs > 0.0) || !std::isfinite(cfg->dt_fs))
+        return fail(err, PIMD_E_ARG, "dt_fs must be positive");
+    if (!std::isfinite(cfg->tau0_fs))
+        return fail(err, PIMD_E_ARG, "tau0_fs must be finite");
+    if (!(cfg->pile_lambda >= 0.0) || !std::isfinite(cfg->pile_lambda))
+        return fail(err, PIMD_E_ARG, "pile_lambda must be >= 0");
+    if (cfg->precision != PIMD_PREC_FP32 && cfg->precision != PIMD_PREC_BF16_MLP &&
+        cfg->precision != PIMD_PREC_BF16_PLAIN && cfg->precision != PIMD_PREC_FP64_MLP)
+        return fail(err, PIMD_E_ARG, "unknown precision");
+    if (cfg->potential != PIMD_POT_BPNN && cfg->potential != PIMD_POT_HARMONIC)
+        return fail(err, PIMD_E_ARG, "unknown potential");
+    if (cfg->max_neighbors < 0 || cfg->max_neighbors > kMaxNeighbors)
+        return fail(err, PIMD_E_UNSUPPORTED, "max_neighbors must be in [0, 256]");
+    const pimd_bpnn_model *m = cfg->model;
+    if (!m)
+        return fail(err, PIMD_E_ARG, "model is NULL (it carries the element masses)");
+    if (m->n_elements < 1 || m->n_elements > kMaxElements)
+        return fail(err, PIMD_E_UNSUPPORTED, "n_elements must be in [1, 4]");
+    if (!m->mass_amu)
+        return fail(err, PIMD_E_ARG, "mass_amu is NULL");
+    for (int e = 0; e < m->n_elements; ++e)
+        if (!(m->mass_amu[e] > 0.0) || !std::isfinite(m->mass_amu[e]))
+            return fail(err, PIMD_E_ARG, "masses must be positive");
+    pl.bpnn = cfg->potential == PIMD_POT_BPNN;
+    pl.n_el = m->n_elements;
+    if (pl.bpnn) {
+        if (!(m->cutoff_A > 0.0) || !std::isfinite(m->cutoff_A))
+            return fail(err, PIMD_E_ARG, "cutoff must be positive");
+        if (m->n_rad < 1 || m->n_rad > kMaxRad || m->n_elements * m->n_rad > 64)
+            return fail(err, PIMD_E_UNSUPPORTED, "n_rad must be in [1, 32] with n_elements*n_rad <= 64");
+        if (m->n_ang_eta < 1 || m->n_ang_eta > 2)
+            return fail(err, PIMD_E_UNSUPPORTED, "n_ang_eta must be 1 or 2");
+        if (!m->rad_center_A || !m->rad_eta || !m->ang_eta || !m->params || !m->feat_shift || !m->feat_scale)
+            return fail(err, PIMD_E_ARG, "a model array is NULL");
+        for (int s = 0; s < m->n_rad; ++s)
+            if (!std::isfinite(m->rad_center_A[s]) || !(m->rad_eta[s] >= 0.0))
+                return fail(err, PIMD_E_ARG, "bad radial grid");
+        for (int s = 0; s < m->n_ang_eta; ++s)
+            if (!(m->ang_eta[s] >= 0.0) || !std::isfinite(m->ang_eta[s]))
+                return fail(err, PIMD_E_ARG, "bad angular eta");
+        if (m->n_hidden < 1 || m->n_hidden > 3)
+            return fail(err, PIMD_E_UNSUPPORTED, "n_hidden must be in [1, 3]");
+        for (int l = 0; l < m->n_hidden; ++l)
+            if (m->hidden[l] < 16 || m->hidden[l] > 128 || m->hidden[l] % 16)
+                return fail(err, PIMD_E_UNSUPPORTED, "hidden widths must be multiples of 16 in [16, 128]");
+        pl.n_rad = m->n_rad;
+        pl.n_ang_eta = m->n_ang_eta;
+        pl.D = n_features(m->n_elements, m->n_rad, m->n_ang_eta);
+        pl.Dp = (pl.D + 15) & ~15;
+        if (pl.Dp > 128)
+            return fail(err, PIMD_E_UNSUPPORTED, "descriptor length above 128");
+        for (int e = 0; e < m->n_elements; ++e)
+            for (int f = 0; f < pl.D; ++f)
+                if (!(m->feat_scale[(size_t)e * pl.D + f] != 0.0f) || !std::isfinite(m->feat_scale[(size_t)e * pl.D + f]))
+                    return fail(err, PIMD_E_ARG, "feat_scale must be finite and non-zero");
+    } else {
+        if (!(cfg->harmonic_omega_per_fs > 0.0) || !std::isfinite(cfg->harmonic_omega_per_fs))
+            return fail(err, PIMD_E_ARG, "harmonic_omega_per_fs must be positive");
+    }
+    pl.n_sys = cfg->n_systems;
+    pl.Kmax = cfg->max_neighbors == 0 ? 128 : cfg->max_neighbors;
+    int64_t B = 0, nb = 0, na = 0, cells = 0;
+    for (int s = 0; s < cfg->n_systems; ++s) {
+        const int N = cfg->n_atoms[s], P = cfg->n_beads[s];
+        if (N < 1)
+            return fail(err, PIMD_E_ARG, "n_atoms must be >= 1");
+        if (P < 1)
+            return fail(err, PIMD_E_ARG, "n_beads must be >= 1");
+        if (P > kMaxBeads || (P > 1 && (P & 1)))
+            return fail(err, PIMD_E_UNSUPPORTED, "n_beads must be 1 or even and <= 128");
+        if (!(cfg->temperature_K[s] > 0.0) || !std::isfinite(cfg->temperature_K[s]))
+            return fail(err, PIMD_E_ARG, "temperature must be positive");
+        const double *L = cfg->box_A + 3 * s;
+        const bool zero = L[0] == 0.0 && L[1] == 0.0 && L[2] == 0.0;
+        std::array<int, 3> nc = {0, 0, 0};
+        if (!zero) {
+            for (int d = 0; d < 3; ++d)
+                if (!(L[d] > 0.0) || !std::isfinite(L[d]))
+                    return fail(err, PIMD_E_ARG, "box lengths must be all positive or all zero");
+            if (pl.bpnn) {
+                for (int d = 0; d < 3; ++d)
+                    if (!(m->cutoff_A < 0.5 * L[d]))
+                        return fail(err, PIMD_E_UNSUPPORTED, "cutoff must be below half of every box length");
+                for (int d = 0; d < 3; ++d)
+                    nc[d] = std::max(1, (int)std::floor(L[d] / (m->cutoff_A + 1e-4)));
+                pl.any_periodic = true;
+            }
+        }
+        pl.nc.push_back(nc);
+        const int per_bead = zero || !pl.bpnn ? 0 : nc[0] * nc[1] * nc[2];
+        pl.cells_per_sys.push_back(per_bead);
+        cells += (int64_t)per_bead * P;
+        B += (int64_t)N * P;
+        nb += P;
+        na += N;
+        pl.max_P = std::max(pl.max_P, P);
+        if (std::find(pl.distinct_P.begin(), pl.distinct_P.end(), P) == pl.distinct_P.end())
+            pl.distinct_P.push_back(P);
+        const int cols_per_unit = std::max(1, 256 / P);
+        pl.n_units += (3 * N + cols_per_unit - 1) / cols_per_unit;
+        pl.modes += P;
+    }
+    if (B >= (int64_t)kRowMask || cells > (int64_t)1 << 30)
+        return fail(err, PIMD_E_UNSUPPORTED, "too many bead-atoms (limit 2^27)");
+    for (int64_t a = 0; a < na; ++a)
+        if (cfg->species[a] < 0 || cfg->species[a] >= m->n_elements)
+            return fail(err, PIMD_E_ARG, "species index out of range");
+    pl.B = (int)B;
+    pl.n_beads = (int)nb;
+    pl.n_atoms = (int)na;
+    pl.ncol = 3 * (int)na;
+    pl.total_cells = (int)cells;
+    for (int P : pl.distinct_P)
+        pl.cmat_floats += (size_t)P * P;
+    if (pl.bpnn) {
+        int in = pl.Dp;
+        for (int e = 0; e < pl.n_el; ++e) {
+            in = pl.Dp;
+            for (int l = 0; l < m->n_hidden; ++l) {
+                const int out = m->hidden[l];
+                pl.mlp_f32_floats += 2 * (size_t)out * in + out;
+                pl.mlp_bf16_elems += 4 * (size_t)out * in;
+                pl.mlp_f64_elems += 2 * (size_t)out * in;
+                in = out;
+            }
+            pl.mlp_f32_floats += in;
+        }
+    }
+    return PIMD_OK;
+}
+
+Layout make_layout(const Plan &pl)
+{
+    Layout L;
+    const size_t B = pl.B, nb = pl.n_beads, K = pl.Kmax, D = pl.D;
+    L.add("q", B * 12);
+    L.add("p", B * 12);
+    L.add("F", B * 12);
+    L.add("E_bead", nb * 4);
+    L.add("W_bead", nb * 36);
+    L.add("xi", B * 24);
+    L.add("pos4", B * 16);
+    L.add("posu4", B * 16);
+    L.add("E_atom", B * 4);
+    L.add("vir_atom", B * 36);
+    if (pl.bpnn) {
+        L.add("atom_cell", B * 4);
+        L.add("atom_slot", B * 4);
+        L.add("cell_count", (size_t)pl.total_cells * 4);
+        L.add("cell_start", (size_t)pl.total_cells * 4);
+        L.add("cell_atoms", B * 4);
+        L.add("nbr", B * K * 4);
+        L.add("nbr_cnt", B * 4);
+        L.add("nbr_grp", B * kMaxElements * 4);
+        L.add("xhat", B * D * 4);
+        L.add("dEdG", B * D * 4);
+        L.add("vslot", B * K * 16);
+        L.add("mlp_f32", pl.mlp_f32_floats * 4);
+        L.add("mlp_bf16", pl.mlp_bf16_elems * 2);
+        L.add("mlp_f64", pl.mlp_f64_elems * 8);
+        L.add("norm", (size_t)pl.n_el * 2 * D * 4);
+        L.add("elem_rows", B * 4);
+        L.add("mlp_tiles", (B / 16 + kMaxElements + 1) * sizeof(MlpTile));
+    }
+    L.add("heat", (size_t)pl.n_sys * 8);
+    L.add("dke_part", (size_t)pl.n_units * 16);
+    L.add("step", 8);
+    L.add("status", 8);
+    L.add("est_cols", (size_t)pl.ncol * 12);
+    L.add("beads", nb * sizeof(BeadInfo));
+    L.add("bead_of_ba", B * 4);
+    L.add("species_atom", (size_t)pl.n_atoms * 4);
+    L.add("mass_atom", (size_t)pl.n_atoms * 4);
+    L.add("sys", (size_t)pl.n_sys * sizeof(SysInfo));
+    L.add("modes", pl.modes * sizeof(ModeInfo));
+    L.add("units", (size_t)pl.n_units * sizeof(IntegUnit));
+    L.add("cmat", pl.cmat_floats * 4);
+    L.add("col_sys", (size_t)pl.ncol * 4);
+    L.add("end", 0);
+    return L;
+}
+
+uint16_t bf16_bits(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+}  // namespace
+
+struct pimd_ctx {
+    Plan pl;
+    Sizes z{};
+    DevBuffers d{};
+    DescParams dp{};
+    MlpNets nets{};
+    int n_mlp_tiles = 0;
+    std::vector<SysInfo> sys_host;
+    std::vector<double> temperature, masses_el;
+    std::vector<int> species;
+    double dt = 0, tau0 = 0, lam = 0, omega = 0;
+    uint64_t seed = 0;
+    int precision = 0, potential = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool state_set = false, forces_valid = false, noise_pending = false, use_graph = true;
+    // stage timing: events recorded after each stage when non-null
+    hipEvent_t *stage_ev = nullptr;
+    int device = 0;
+    std::string err;
+};
+
+namespace {
+
+#define HIPCHK(ctx, call)                                                                       \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) {                                                                 \
+            (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);                     \
+            return PIMD_E_DEVICE;                                                               \
+        }                                                                                       \
+    } while (0)
+
+#define CHECK_LAUNCH(ctx)                                                                       \
+    do {                                                                                        \
+        hipError_t e_ = hipGetLastError();                                                      \
+        if (e_ != hipSuccess) {                                                                 \
+            (ctx)->err = std::string("kernel launch: ") + hipGetErrorString(e_);                \
+            return PIMD_E_DEVICE;                                                               \
+        }                                                                                       \
+    } while (0)
+
+pimd_status run_forces(pimd_ctx *c, const float *q, float *E_out, float *F_out, float *W_out)
+{
+    const DevBuffers &d = c->d;
+    const Sizes &z = c->z;
+    hipStream_t s = c->stream;
+    auto mark = [&](int k) {
+        if (c->stage_ev)
+            (void)hipEventRecord(c->stage_ev[k], s);
+    };
+    if (c->potential == PIMD_POT_HARMONIC) {
+        launch_harmonic(q, d, z, (float)(c->omega * c->omega * kMvv2e), F_out, s);
+        launch_bead_sums(d, z, E_out, W_out, W_out != nullptr, s);
+        for (int k = 2; k <= 6; ++k)
+            mark(k);
+        CHECK_LAUNCH(c);
+        return PIMD_OK;
+    }
+    if (z.any_periodic)
+        launch_zero_i32(d.cell_count, z.total_cells, s);
+    launch_wrap_bin(q, d, z, s);
+    if (z.any_periodic) {
+        launch_cell_scan(d, z, s);
+        launch_cell_fill(d, z, s);
+    }
+    launch_neighbors(d, z, c->dp.rc2, c->pl.n_el, s);
+    mark(2);
+    launch_descriptors(d, z, c->dp, s);
+    mark(3);
+    launch_mlp(d, c->nets, c->n_mlp_tiles, c->pl.D, c->pl.Dp, c->precision, s);
+    mark(4);
+    if (F_out || W_out) {
+        launch_adjoint(d, z, c->dp, s);
+        mark(5);
+        if (F_out)
+            launch_assemble_forces(d, z, F_out, s);
+    } else {
+        mark(5);
+    }
+    launch_bead_sums(d, z, E_out, W_out, W_out != nullptr, s);
+    mark(6);
+    CHECK_LAUNCH(c);
+    return PIMD_OK;
+}
+
+pimd_status run_step(pimd_ctx *c, hipStream_t s, const float *xi)
+{
+    const uint32_t k0 = (uint32_t)(c->seed & 0xFFFFFFFFu), k1 = (uint32_t)(c->seed >> 32);
+    hipStream_t saved = c->stream;
+    c->stream = s;
+    if (c->stage_ev)
+        (void)hipEventRecord(c->stage_ev[0], s);
+    launch_integrate_pre(c->d, c->z, (float)c->dt, k0, k1, xi, c->pl.max_P, s);
+    if (c->stage_ev)
+        (void)hipEventRecord(c->stage_ev[1], s);
+    pimd_status st = run_forces(c, c->d.q, c->d.E_bead, c->d.F, nullptr);
+    launch_integrate_post(c->d, c->z, (float)c->dt, k0, k1, xi, c->pl.max_P, s);
+    launch_finish_step(c->d, c->z, s);
+    if (c->stage_ev)
+        (void)hipEventRecord(c->stage_ev[7], s);
+    c->stream = saved;
+    if (st != PIMD_OK)
+        return st;
+    CHECK_LAUNCH(c);
+    return PIMD_OK;
+}
+
+pimd_status read_status(pimd_ctx *c)
+{
+    uint32_t st = 0;
+    HIPCHK(c, hipMemcpyAsync(&st, c->d.status, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (st == 0)
+        return PIMD_OK;
+    const uint32_t zero = 0;
+    HIPCHK(c, hipMemcpyAsync(c->d.status, &zero, 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (st & kStatusOverflow) {
+        c->err = "an atom has more neighbours than max_neighbors (" + std::to_string(c->pl.Kmax) + ")";
+        return PIMD_E_CAPACITY;
+    }
+    c->err = "non-finite energy, force or state value";
+    return PIMD_E_NONFINITE;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pimd_status_str(pimd_status s)
+{
+    switch (s) {
+    case PIMD_OK: return "ok";
+    case PIMD_E_ARG: return "invalid argument";
+    case PIMD_E_UNSUPPORTED: return "unsupported configuration";
+    case PIMD_E_DEVICE: return "HIP runtime error";
+    case PIMD_E_OOM: return "workspace too small";
+    case PIMD_E_CAPACITY: return "neighbour capacity exceeded";
+    case PIMD_E_NONFINITE: return "non-finite value";
+    case PIMD_E_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+const char *pimd_last_error(const pimd_ctx *ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
+
+pimd_status pimd_workspace_size(const pimd_config *cfg, size_t *bytes)
+{
+    if (!bytes)
+        return fail(&g_init_error, PIMD_E_ARG, "bytes is NULL");
+    Plan pl;
+    pimd_status st = validate(cfg, pl, &g_init_error);
+    if (st != PIMD_OK)
+        return st;
+    *bytes = make_layout(pl).total;
+    return PIMD_OK;
+}
+
+pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_bytes, void *hip_stream, pimd_ctx **out)
+{
+    if (!out)
+        return fail(&g_init_error, PIMD_E_ARG, "out is NULL");
+    *out = nullptr;
+    Plan pl;
+    pimd_status st = validate(cfg, pl, &g_init_error);
+    if (st != PIMD_OK)
+        return st;
+    const Layout L = make_layout(pl);
+    if (!workspace_dev)
+        return fail(&g_init_error, PIMD_E_ARG, "workspace is NULL");
+    if (((uintptr_t)workspace_dev) & 255)
+        return fail(&g_init_error, PIMD_E_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return fail(&g_init_error, PIMD_E_OOM, "workspace smaller than pimd_workspace_size");
+
+    pimd_ctx *c = new pimd_ctx();
+    c->pl = pl;
+    c->stream = (hipStream_t)hip_stream;
+    c->dt = cfg->dt_fs;
+    c->tau0 = cfg->tau0_fs;
+    c->lam = cfg->pile_lambda;
+    c->seed = cfg->seed;
+    c->precision = cfg->precision;
+    c->potential = cfg->potential;
+    c->omega = cfg->harmonic_omega_per_fs;
+    const pimd_bpnn_model *m = cfg->model;
+    c->masses_el.assign(m->mass_amu, m->mass_amu + m->n_elements);
+    c->species.assign(cfg->species, cfg->species + pl.n_atoms);
+    c->temperature.assign(cfg->temperature_K, cfg->temperature_K + pl.n_sys);
+
+    char *ws = (char *)workspace_dev;
+    auto at = [&](const char *name) -> void * {
+        auto it = L.off.find(name);
+        return it == L.off.end() ? nullptr : ws + it->second;
+    };
+    DevBuffers &d = c->d;
+    d.q = (float *)at("q");
+    d.p = (float *)at("p");
+    d.F = (float *)at("F");
+    d.E_bead = (float *)at("E_bead");
+    d.W_bead = (float *)at("W_bead");
+    d.xi = (float *)at("xi");
+    d.pos4 = (float4 *)at("pos4");
+    d.posu4 = (float4 *)at("posu4");
+    d.E_atom = (float *)at("E_atom");
+    d.vir_atom = (float *)at("vir_atom");
+    d.atom_cell = (int32_t *)at("atom_cell");
+    d.atom_slot = (int32_t *)at("atom_slot");
+    d.cell_count = (int32_t *)at("cell_count");
+    d.cell_start = (int32_t *)at("cell_start");
+    d.cell_atoms = (int32_t *)at("cell_atoms");
+    d.nbr = (int32_t *)at("nbr");
+    d.nbr_cnt = (int32_t *)at("nbr_cnt");
+    d.nbr_grp = (int32_t *)at("nbr_grp");
+    d.xhat = (float *)at("xhat");
+    d.dEdG = (float *)at("dEdG");
+    d.vslot = (float4 *)at("vslot");
+    d.mlp_f32 = (float *)at("mlp_f32");
+    d.mlp_bf16 = (uint16_t *)at("mlp_bf16");
+    d.mlp_f64 = (double *)at("mlp_f64");
+    d.norm = (float *)at("norm");
+    d.elem_rows = (int32_t *)at("elem_rows");
+    d.mlp_tiles = (MlpTile *)at("mlp_tiles");
+    d.heat = (double *)at("heat");
+    d.dke_part = (double *)at("dke_part");
+    d.step = (int64_t *)at("step");
+    d.status = (uint32_t *)at("status");
+    d.est_cols = (float *)at("est_cols");
+    d.beads = (BeadInfo *)at("beads");
+    d.bead_of_ba = (int32_t *)at("bead_of_ba");
+    d.species_atom = (int32_t *)at("species_atom");
+    d.mass_atom = (float *)at("mass_atom");
+    d.sys = (SysInfo *)at("sys");
+    d.modes = (ModeInfo *)at("modes");
+    d.units = (IntegUnit *)at("units");
+    d.cmat = (float *)at("cmat");
+    d.col_sys = (int32_t *)at("col_sys");
+
+    Sizes &z = c->z;
+    z.n_sys = pl.n_sys;
+    z.B = pl.B;
+    z.n_beads_total = pl.n_beads;
+    z.n_atoms_total = pl.n_atoms;
+    z.ncol = pl.ncol;
+    z.total_cells = pl.total_cells;
+    z.n_units = pl.n_units;
+    z.D = pl.D;
+    z.Kmax = pl.Kmax;
+    z.any_periodic = pl.any_periodic ? 1 : 0;
+
+    // ---- host tables
+    std::vector<BeadInfo> beads;
+    std::vector<int32_t> bead_of_ba(pl.B), col_sys(pl.ncol);
+    std::vector<float> mass_atom(pl.n_atoms);
+    std::vector<ModeInfo> modes;
+    std::vector<IntegUnit> units;
+    std::vector<float> cmat;
+    std::map<int, int> cmat_off;
+    for (int P : pl.distinct_P) {
+        cmat_off[P] = (int)cmat.size();
+        for (int j = 0; j < P; ++j)
+            for (int k = 0; k < P; ++k) {
+                double v;
+                if (P == 1)
+                    v = 1.0;
+                else if (k == 0)
+                    v = 1.0 / std::sqrt((double)P);
+                else if (k < P / 2)
+                    v = std::sqrt(2.0 / P) * std::cos(2.0 * kPi * j * k / P);
+                else if (k == P / 2)
+                    v = ((j & 1) ? -1.0 : 1.0) / std::sqrt((double)P);
+                else
+                    v = std::sqrt(2.0 / P) * std::sin(2.0 * kPi * j * k / P);
+                cmat.push_back((float)v);
+            }
+    }
+    int ba0 = 0, atom0 = 0, cell0 = 0, mode0 = 0;
+    for (int s = 0; s < pl.n_sys; ++s) {
+        const int N = cfg->n_atoms[s], P = cfg->n_beads[s];
+        const double T = cfg->temperature_K[s];
+        const double *Lb = cfg->box_A + 3 * s;
+        const bool periodic = pl.bpnn && (Lb[0] != 0.0 || Lb[1] != 0.0 || Lb[2] != 0.0);
+        SysInfo si{};
+        si.N = N;
+        si.P = P;
+        si.ba0 = ba0;
+        si.atom0 = atom0;
+        si.mode0 = mode0;
+        si.cmat0 = cmat_off[P];
+        si.unit0 = (int)units.size();
+        si.sig_T = (float)std::sqrt(kKB * T * P / kMvv2e);
+        const int cols_per_unit = std::max(1, 256 / P);
+        for (int c0 = 0; c0 < 3 * N; c0 += cols_per_unit) {
+            IntegUnit u{};
+            u.sys = s;
+            u.col0 = c0;
+            u.ncol = std::min(cols_per_unit, 3 * N - c0);
+            units.push_back(u);
+        }
+        si.nunit = (int)units.size() - si.unit0;
+        // modes
+        const double wP = P * kKB * T / kHbar;
+        for (int k = 0; k < P; ++k) {
+            const double w = 2.0 * wP * std::sin(k * kPi / P);
+            double gamma = 0.0;
+            if (c->tau0 > 0.0)
+                gamma = k == 0 ? 1.0 / c->tau0 : 2.0 * c->lam * w;
+            const double c1 = std::exp(-0.5 * gamma * c->dt);
+            ModeInfo mi{};
+            mi.c1 = (float)c1;
+            mi.c2 = (float)std::sqrt(std::max(0.0, 1.0 - c1 * c1));
+            mi.cw = (float)std::cos(w * c->dt);
+            mi.sw = (float)std::sin(w * c->dt);
+            mi.w = (float)w;
+            modes.push_back(mi);
+        }
+        for (int k = 0; k < P; ++k) {
+            BeadInfo bi{};
+            bi.sys = s;
+            bi.ba0 = ba0 + k * N;
+            bi.n = N;
+            bi.periodic = periodic ? 1 : 0;
+            for (int dd = 0; dd < 3; ++dd) {
+                bi.L[dd] = (float)Lb[dd];
+                bi.invL[dd] = periodic ? (float)(1.0 / Lb[dd]) : 0.0f;
+                bi.nc[dd] = periodic ? pl.nc[s][dd] : 1;
+                bi.cell_scale[dd] = periodic ? (float)(pl.nc[s][dd] / Lb[dd]) : 0.0f;
+                bi.L64[dd] = Lb[dd];
+                bi.invL64[dd] = periodic ? 1.0 / Lb[dd] : 0.0;
+            }
+            bi.cell0 = cell0;
+            cell0 += pl.cells_per_sys[s];
+            for (int i = 0; i < N; ++i)
+                bead_of_ba[bi.ba0 + i] = (int)beads.size();
+            beads.push_back(bi);
+        }
+        for (int i = 0; i < N; ++i) {
+            mass_atom[atom0 + i] = (float)m->mass_amu[cfg->species[atom0 + i]];
+            for (int cc = 0; cc < 3; ++cc)
+                col_sys[3 * (atom0 + i) + cc] = s;
+        }
+        c->sys_host.push_back(si);
+        ba0 += N * P;
+        atom0 += N;
+        mode0 += P;
+    }
+
+    std::vector<std::pair<size_t, std::vector<char>>> uploads;
+    auto push = [&](void *dst, const void *src, size_t bytes) {
+        if (!bytes)
+            return;
+        std::vector<char> v((const char *)src, (const char *)src + bytes);
+        uploads.push_back({(size_t)((char *)dst - ws), std::move(v)});
+    };
+    push(d.beads, beads.data(), beads.size() * sizeof(BeadInfo));
+    push(d.bead_of_ba, bead_of_ba.data(), bead_of_ba.size() * 4);
+    push(d.species_atom, cfg->species, (size_t)pl.n_atoms * 4);
+    push(d.mass_atom, mass_atom.data(), mass_atom.size() * 4);
+    push(d.sys, c->sys_host.data(), c->sys_host.size() * sizeof(SysInfo));
+    push(d.modes, modes.data(), modes.size() * sizeof(ModeInfo));
+    push(d.units, units.data(), units.size() * sizeof(IntegUnit));
+    push(d.cmat, cmat.data(), cmat.size() * 4);
+    push(d.col_sys, col_sys.data(), col_sys.size() * 4);
+
+    if (pl.bpnn) {
+        DescParams &dp = c->dp;
+        dp.n_el = m->n_elements;
+        dp.n_rad = m->n_rad;
+        dp.n_ang_eta = m->n_ang_eta;
+        dp.n_ang = 8 * m->n_ang_eta;
+        dp.D = pl.D;
+        dp.Kmax = pl.Kmax;
+        dp.rc = (float)m->cutoff_A;
+        dp.rc2 = (float)(m->cutoff_A * m->cutoff_A);
+        dp.pi_over_rc = (float)(kPi / m->cutoff_A);
+        dp.half_over_rc = (float)(0.5 / m->cutoff_A);
+        for (int s = 0; s < m->n_rad; ++s) {
+            dp.rad_center[s] = (float)m->rad_center_A[s];
+            dp.rad_eta[s] = (float)m->rad_eta[s];
+        }
+        for (int s = 0; s < m->n_ang_eta; ++s)
+            dp.ang_eta[s] = (float)m->ang_eta[s];
+        // rows grouped by element for the MLP gather, cut into 16-row tiles
+        std::vector<int32_t> rows;
+        std::vector<MlpTile> tiles;
+        for (int e = 0; e < pl.n_el; ++e) {
+            const int r0 = (int)rows.size();
+            for (int s = 0; s < pl.n_sys; ++s) {
+                const SysInfo &si = c->sys_host[s];
+                for (int k = 0; k < si.P; ++k)
+                    for (int i = 0; i < si.N; ++i)
+                        if (cfg->species[si.atom0 + i] == e)
+                            rows.push_back(si.ba0 + k * si.N + i);
+            }
+            for (int t = r0; t < (int)rows.size(); t += 16)
+                tiles.push_back(MlpTile{e, t, std::min(16, (int)rows.size() - t), 0});
+        }
+        c->n_mlp_tiles = (int)tiles.size();
+        push(d.elem_rows, rows.data(), rows.size() * 4);
+        push(d.mlp_tiles, tiles.data(), tiles.size() * sizeof(MlpTile));
+        // normalisation
+        std::vector<float> norm((size_t)pl.n_el * 2 * pl.D);
+        for (int e = 0; e < pl.n_el; ++e)
+            for (int f = 0; f < pl.D; ++f) {
+                norm[(size_t)e * 2 * pl.D + f] = m->feat_shift[(size_t)e * pl.D + f];
+                norm[(size_t)e * 2 * pl.D + pl.D + f] = 1.0f / m->feat_scale[(size_t)e * pl.D + f];
+            }
+        push(d.norm, norm.data(), norm.size() * 4);
+        // weights: f32 W[out][in_pad], WT[in_pad][out], b[out] per layer, then w_out; bf16 W, WT
+        std::vector<float> wf;
+        std::vector<uint16_t> wb;
+        std::vector<double> w64;
+        const float *src = m->params;
+        for (int e = 0; e < pl.n_el; ++e) {
+            MlpNet net{};
+            net.n_hidden = m->n_hidden;
+            int in = pl.D, in_pad = pl.Dp;
+            for (int l = 0; l < m->n_hidden; ++l) {
+                const int out = m->hidden[l];
+                const size_t oW = wf.size();
+                wf.resize(oW + (size_t)out * in_pad, 0.0f);
+                for (int o = 0; o < out; ++o)
+                    for (int k = 0; k < in; ++k)
+                        wf[oW + (size_t)o * in_pad + k] = src[(size_t)o * in + k];
+                const size_t oWT = wf.size();
+                wf.resize(oWT + (size_t)in_pad * out, 0.0f);
+                for (int o = 0; o < out; ++o)
+                    for (int k = 0; k < in; ++k)
+                        wf[oWT + (size_t)k * out + o] = src[(size_t)o * in + k];
+                src += (size_t)out * in;
+                const size_t ob = wf.size();
+                wf.insert(wf.end(), src, src + out);
+                src += out;
+                // bf16 parts: nearest-even rounding and the rounding remainder
+                auto split = [&](size_t o, size_t &hi, size_t &lo) {
+                    hi = wb.size();
+                    for (size_t t = 0; t < (size_t)out * in_pad; ++t)
+                        wb.push_back(bf16_bits(wf[o + t]));
+                    lo = wb.size();
+                    for (size_t t = 0; t < (size_t)out * in_pad; ++t) {
+                        uint32_t u = (uint32_t)wb[hi + t] << 16;
+                        float h;
+                        std::memcpy(&h, &u, 4);
+                        wb.push_back(bf16_bits(wf[o + t] - h));
+                    }
+                };
+                size_t bW, bWl, bWT, bWTl;
+                split(oW, bW, bWl);
+                split(oWT, bWT, bWTl);
+                const size_t dW = w64.size();
+                for (size_t t = 0; t < (size_t)out * in_pad; ++t)
+                    w64.push_back((double)wf[oW + t]);
+                const size_t dWT = w64.size();
+                for (size_t t = 0; t < (size_t)out * in_pad; ++t)
+                    w64.push_back((double)wf[oWT + t]);
+                MlpLayer &Ly = net.layer[l];
+                Ly.W = d.mlp_f32 + oW;
+                Ly.WT = d.mlp_f32 + oWT;
+                Ly.b = d.mlp_f32 + ob;
+                Ly.Wb = d.mlp_bf16 + bW;
+                Ly.WTb = d.mlp_bf16 + bWT;
+                Ly.Wb_lo = d.mlp_bf16 + bWl;
+                Ly.WTb_lo = d.mlp_bf16 + bWTl;
+                Ly.W64 = d.mlp_f64 + dW;
+                Ly.WT64 = d.mlp_f64 + dWT;
+                Ly.in_pad = in_pad;
+                Ly.out = out;
+                in = out;
+                in_pad = out;
+            }
+            const size_t owo = wf.size();
+            wf.insert(wf.end(), src, src + in);
+            src += in;
+            net.wo = d.mlp_f32 + owo;
+            net.bo = *src++;
+            net.inv_scale = d.norm + (size_t)e * 2 * pl.D + pl.D;
+            net.shift = d.norm + (size_t)e * 2 * pl.D;
+            c->nets.net[e] = net;
+        }
+        push(d.mlp_f32, wf.data(), wf.size() * 4);
+        push(d.mlp_bf16, wb.data(), wb.size() * 2);
+        push(d.mlp_f64, w64.data(), w64.size() * 8);
+    }
+    std::vector<double> zeros_d(pl.n_sys, 0.0);
+    push(d.heat, zeros_d.data(), zeros_d.size() * 8);
+    const int64_t zero64 = 0;
+    push(d.step, &zero64, 8);
+    push(d.status, &zero64, 8);
+
+    // ---- device work starts here
+    auto bail = [&](pimd_status s2, const std::string &msg) {
+        g_init_error = msg;
+        delete c;
+        return s2;
+    };
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess)
+        return bail(PIMD_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    for (auto &u : uploads) {
+        e = hipMemcpyAsync(ws + u.first, u.second.data(), u.second.size(), hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess)
+            return bail(PIMD_E_DEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess)
+        return bail(PIMD_E_DEVICE, std::string("upload sync: ") + hipGetErrorString(e));
+    if (pl.bpnn) {
+        e = configure_descriptor_lds(c->dp);
+        if (e != hipSuccess)
+            return bail(PIMD_E_DEVICE, std::string("descriptor LDS: ") + hipGetErrorString(e));
+    }
+    e = configure_integrator_lds(pl.max_P);
+    if (e != hipSuccess)
+        return bail(PIMD_E_DEVICE, std::string("integrator LDS: ") + hipGetErrorString(e));
+    e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return bail(PIMD_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    *out = c;
+    return PIMD_OK;
+}
+
+pimd_status pimd_set_stream(pimd_ctx *ctx, void *hip_stream)
+{
+    if (!ctx)
+        return PIMD_E_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return PIMD_OK;
+}
+
+pimd_status pimd_set_state(pimd_ctx *ctx, const float *q_dev, const float *p_dev, int64_t step)
+{
+    if (!ctx)
+        return PIMD_E_ARG;
+    if (!q_dev || !p_dev) {
+        ctx->err = "q and p must be non-NULL";
+        return PIMD_E_ARG;
+    }
+    if (step < 0) {
+        ctx->err = "step must be >= 0";
+        return PIMD_E_ARG;
+    }
+    const size_t bytes = (size_t)ctx->z.B * 12;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d.q, q_dev, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d.p, p_dev, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    std::vector<double> zeros(ctx->z.n_sys, 0.0);
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d.heat, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d.step, &step, 8, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->state_set = true;
+    ctx->forces_valid = false;
+    return PIMD_OK;
+}
+
+pimd_status pimd_get_state(pimd_ctx *ctx, float *q_dev, float *p_dev, float *forces_dev, int64_t *step)
+{
+    if (!ctx)
+        return PIMD_E_ARG;
+    if (!ctx->state_set) {
+        ctx->err = "state not set";
+        return PIMD_E_STATE;
+    }
+    const size_t n = (size_t)ctx->z.B * 3;
+    if (forces_dev && !ctx->forces_valid) {
+        pimd_status st = run_forces(ctx, ctx->d.q, ctx->d.E_bead, ctx->d.F, nullptr);
+        if (st != PIMD_OK)
+            return st;
+        ctx->forces_valid = true;
+    }
+    launch_check_finite(ctx->d.q, (int64_t)n, ctx->d.status, ctx->stream);
+    launch_check_finite(ctx->d.p, (int64_t)n, ctx->d.status, ctx->stream);
+    CHECK_LAUNCH(ctx);
+    if (q_dev)
+        HIPCHK(ctx, hipMemcpyAsync(q_dev, ctx->d.q, n * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    if (p_dev)
+        HIPCHK(ctx, hipMemcpyAsync(p_dev, ctx->d.p, n * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    if (forces_dev)
+        HIPCHK(ctx, hipMemcpyAsync(forces_dev, ctx->d.F, n * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    int64_t s = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&s, ctx->d.step, 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (step)
+        *step = s;
+    return read_status(ctx);
+}
+
+pimd_status pimd_energy_forces(pimd_ctx *ctx, const float *q_dev, float *energy_dev, float *forces_dev,
+                               float *virial_dev)
+{
+    if (!ctx)
+        return PIMD_E_ARG;
+    if (!q_dev || !energy_dev) {
+        ctx->err = "q and energy must be non-NULL";
+        return PIMD_E_ARG;
+    }
+    return run_forces(ctx, q_dev, energy_dev, forces_dev, virial_dev);
+}
+
+pimd_status pimd_step(pimd_ctx *ctx, int32_t n_steps)
+{
+    if (!ctx)
+        return PIMD_E_ARG;
+    if (n_steps < 0) {
+        ctx->err = "n_steps must be >= 0";
+        return PIMD_E_ARG;
+    }
+    if (!ctx->state_set) {
+        ctx->err = "pimd_set_state must come before pimd_step";
+        return PIMD_E_STATE;
+    }
+    if (n_steps == 0)
+        return PIMD_OK;
+    if (!ctx->forces_valid) {
+        pimd_status st = run_forces(ctx, ctx->d.q, ctx->d.E_bead, ctx->d.F, nullptr);
+        if (st != PIMD_OK)
+            return st;
+        ctx->forces_valid = true;
+    }
+    int done = 0;
+    if (ctx->noise_pending) {
+        pimd_status st = run_step(ctx, ctx->stream, ctx->d.xi);
+        ctx->noise_pending = false;
+        if (st != PIMD_OK)
+            return st;
+        ++done;
+    }
+    if (!ctx->use_graph) {
+        for (; done < n_steps; ++done) {
+            pimd_status st = run_step(ctx, ctx->stream, nullptr);
+            if (st != PIMD_OK)
+                return st;
+        }
+        return PIMD_OK;
+    }
+    if (done < n_steps && !ctx->gexec) {
+        HIPCHK(ctx, hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+        pimd_status st = run_step(ctx, ctx->capture, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->capture, &g);
+        if (st != PIMD_OK) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) {
+            ctx->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+            return PIMD_E_DEVICE;
+        }
+        ctx->graph = g;
+        HIPCHK(ctx, hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
+    }
+    for (; done < n_steps; ++done)
+        HIPCHK(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
+    return PIMD_OK;
+}
+
+pimd_status pimd_estimators(pimd_ctx *ctx, pimd_estimates *out_host)
+{
+    if (!ctx || !out_host)
+        return PIMD_E_ARG;
+    if (!ctx->state_set) {
+        ctx->err = "state not set";
+        return PIMD_E_STATE;
+    }
+    if (!ctx->forces_valid) {
+        pimd_status st = run_forces(ctx, ctx->d.q, ctx->d.E_bead, ctx->d.F, nullptr);
+        if (st != PIMD_OK)
+            return st;
+        ctx->forces_valid = true;
+    }
+    launch_estimator_terms(ctx->d, ctx->z, ctx->stream);
+    CHECK_LAUNCH(ctx);
+    std::vector<float> cols((size_t)ctx->z.ncol * 3), E(ctx->z.n_beads_total);
+    std::vector<double> heat(ctx->z.n_sys);
+    HIPCHK(ctx, hipMemcpyAsync(cols.data(), ctx->d.est_cols, cols.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(E.data(), ctx->d.E_bead, E.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(heat.data(), ctx->d.heat, heat.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    int bead0 = 0;
+    for (int s = 0; s < ctx->z.n_sys; ++s) {
+        const SysInfo &si = ctx->sys_host[s];
+        const double T = ctx->temperature[s];
+        const double beta = 1.0 / (kKB * T);
+        const double wP = si.P * kKB * T / kHbar;
+        double spring = 0, cv = 0, ke = 0, V = 0;
+        for (int col = 3 * si.atom0; col < 3 * (si.atom0 + si.N); ++col) {
+            spring += cols[3 * (size_t)col];
+            cv += cols[3 * (size_t)col + 1];
+            ke += cols[3 * (size_t)col + 2];
+        }
+        for (int k = 0; k < si.P; ++k)
+            V += E[bead0 + k];
+        bead0 += si.P;
+        pimd_estimates &o = out_host[s];
+        o.E_spring = si.P > 1 ? 0.5 * wP * wP * kMvv2e * spring : 0.0;
+        o.V_bar = V / si.P;
+        o.K_prim = 3.0 * si.N * si.P / (2.0 * beta) - o.E_spring / si.P;
+        o.K_cv = 3.0 * si.N / (2.0 * beta) - cv / (2.0 * si.P);
+        o.K_beads = 0.5 * kMvv2e * ke;
+        o.T_beads = 2.0 * o.K_beads / (3.0 * si.N * si.P * kKB);
+        o.heat_bath = heat[s];
+        o.H_conserved = o.K_beads + o.E_spring + V + heat[s];
+    }
+    return read_status(ctx);
+}
+
+pimd_status pimd_inject_noise(pimd_ctx *ctx, const float *xi_dev)
+{
+    if (!ctx)
+        return PIMD_E_ARG;
+    if (!xi_dev) {
+        ctx->err = "xi must be non-NULL";
+        return PIMD_E_ARG;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d.xi, xi_dev, (size_t)ctx->z.B * 24, hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->noise_pending = true;
+    return PIMD_OK;
+}
+
+pimd_status pimd_debug_neighbors(pimd_ctx *ctx, int32_t bead, int32_t *ij_host, int64_t cap, int64_t *count)
+{
+    if (!ctx || !count)
+        return PIMD_E_ARG;
+    if (ctx->potential != PIMD_POT_BPNN) {
+        ctx->err = "no neighbour list for this potential";
+        return PIMD_E_STATE;
+    }
+    if (bead < 0 || bead >= ctx->z.n_beads_total || cap < 0 || (cap > 0 && !ij_host)) {
+        ctx->err = "bad bead index or output buffer";
+        return PIMD_E_ARG;
+    }
+    // locate the bead
+    int b = bead, s = 0;
+    while (b >= ctx->sys_host[s].P) {
+        b -= ctx->sys_host[s].P;
+        ++s;
+    }
+    const SysInfo &si = ctx->sys_host[s];
+    const int row0 = si.ba0 + b * si.N;
+    const int K = ctx->pl.Kmax;
+    std::vector<int32_t> keys((size_t)si.N * K), cnt(si.N);
+    HIPCHK(ctx, hipMemcpyAsync(keys.data(), ctx->d.nbr + (size_t)row0 * K, keys.size() * 4, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(cnt.data(), ctx->d.nbr_cnt + row0, cnt.size() * 4, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    int64_t n = 0;
+    for (int i = 0; i < si.N; ++i) {
+        std::vector<int32_t> js;
+        for (int t = 0; t < cnt[i]; ++t)
+            js.push_back((keys[(size_t)i * K + t] & (int32_t)kRowMask) - row0);
+        std::sort(js.begin(), js.end());
+        for (int32_t j : js) {
+            if (n < cap) {
+                ij_host[2 * n] = i;
+                ij_host[2 * n + 1] = j;
+            }
+            ++n;
+        }
+    }
+    *count = n;
+    return n > cap ? PIMD_E_CAPACITY : PIMD_OK;
+}
+
+pimd_status pimd_debug_descriptors(pimd_ctx *ctx, float *xhat_dev)
+{
+    if (!ctx || !xhat_dev)
+        return PIMD_E_ARG;
+    if (ctx->potential != PIMD_POT_BPNN) {
+        ctx->err = "no descriptors for this potential";
+        return PIMD_E_STATE;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(xhat_dev, ctx->d.xhat, (size_t)ctx->z.B * ctx->z.D * 4, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    return PIMD_OK;
+}
+
+pimd_status pimd_debug_copy(pimd_ctx *ctx, int32_t buffer, void *dst_dev, size_t bytes)
+{
+    if (!ctx || !dst_dev)
+        return PIMD_E_ARG;
+    if (ctx->potential != PIMD_POT_BPNN && buffer != PIMD_BUF_EATOM) {
+        ctx->err = "buffer not used by this potential";
+        return PIMD_E_STATE;
+    }
+    const size_t B = ctx->z.B, D = ctx->z.D, K = ctx->z.Kmax;
+    const void *src = nullptr;
+    size_t need = 0;
+    switch (buffer) {
+    case PIMD_BUF_XHAT: src = ctx->d.xhat; need = B * D * 4; break;
+    case PIMD_BUF_DEDG: src = ctx->d.dEdG; need = B * D * 4; break;
+    case PIMD_BUF_SLOTS: src = ctx->d.vslot; need = B * K * 16; break;
+    case PIMD_BUF_NBR: src = ctx->d.nbr; need = B * K * 4; break;
+    case PIMD_BUF_NCOUNT: src = ctx->d.nbr_cnt; need = B * 4; break;
+    case PIMD_BUF_EATOM: src = ctx->d.E_atom; need = B * 4; break;
+    default: ctx->err = "unknown buffer"; return PIMD_E_ARG;
+    }
+    if (bytes < need) {
+        ctx->err = "destination smaller than the buffer";
+        return PIMD_E_ARG;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(dst_dev, src, need, hipMemcpyDeviceToDevice, ctx->stream));
+    return PIMD_OK;
+}
+
+pimd_status pimd_debug_philox(pimd_ctx *ctx, int64_t step, int32_t half, int64_t n, uint32_t *words_dev)
+{
+    if (!ctx || !words_dev || n < 0 || step < 0 || (half != 0 && half != 1))
+        return PIMD_E_ARG;
+    launch_philox_words((uint32_t)(ctx->seed & 0xFFFFFFFFu), (uint32_t)(ctx->seed >> 32), step, half, n, words_dev,
+                        ctx->stream);
+    CHECK_LAUNCH(ctx);
+    return PIMD_OK;
+}
+
+pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled)
+{
+    if (!ctx)
+        return PIMD_E_ARG;
+    ctx->use_graph = enabled != 0;
+    return PIMD_OK;
+}
+
+pimd_status pimd_profile_stages(pimd_ctx *ctx, int32_t n_reps, double *ms_host)
+{
+    if (!ctx || !ms_host || n_reps < 1)
+        return PIMD_E_ARG;
+    if (!ctx->state_set) {
+        ctx->err = "state not set";
+        return PIMD_E_STATE;
+    }
+    if (!ctx->forces_valid) {
+        pimd_status st = run_forces(ctx, ctx->d.q, ctx->d.E_bead, ctx->d.F, nullptr);
+        if (st != PIMD_OK)
+            return st;
+        ctx->forces_valid = true;
+    }
+    hipEvent_t ev[8];
+    for (int k = 0; k < 8; ++k)
+        HIPCHK(ctx, hipEventCreate(&ev[k]));
+    double acc[PIMD_N_STAGES] = {0};
+    pimd_status st = PIMD_OK;
+    ctx->stage_ev = ev;
+    for (int r = 0; r < n_reps && st == PIMD_OK; ++r) {
+        st = run_step(ctx, ctx->stream, nullptr);
+        if (st != PIMD_OK)
+            break;
+        hipError_t e = hipEventSynchronize(ev[7]);
+        if (e != hipSuccess) {
+            ctx->err = std::string("hipEventSynchronize: ") + hipGetErrorString(e);
+            st = PIMD_E_DEVICE;
+            break;
+        }
+        for (int k = 0; k < PIMD_N_STAGES; ++k) {
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            acc[k] += ms;
+        }
+    }
+    ctx->stage_ev = nullptr;
+    for (int k = 0; k < 8; ++k)
+        (void)hipEventDestroy(ev[k]);
+    if (st != PIMD_OK)
+        return st;
+    for (int k = 0; k < PIMD_N_STAGES; ++k)
+        ms_host[k] = acc[k] / n_reps;
+    return read_status(ctx);
+}
+
+pimd_status pimd_work_counts(pimd_ctx *ctx, int64_t *pairs, int64_t *triplets, int64_t *triplets_in_range)
+{
+    if (!ctx || !pairs || !triplets || !triplets_in_range)
+        return PIMD_E_ARG;
+    if (ctx->potential != PIMD_POT_BPNN) {
+        ctx->err = "no neighbour list for this potential";
+        return PIMD_E_STATE;
+    }
+    // the counters use the (otherwise idle until the next step) integrator partial-sum buffer
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(ctx->d.est_cols);
+    const unsigned long long zero3[3] = {0, 0, 0};
+    HIPCHK(ctx, hipMemcpyAsync(cnt, zero3, sizeof(zero3), hipMemcpyHostToDevice, ctx->stream));
+    launch_work_counts(ctx->d, ctx->z, ctx->dp, cnt, ctx->stream);
+    CHECK_LAUNCH(ctx);
+    unsigned long long h[3];
+    HIPCHK(ctx, hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    *pairs = (int64_t)h[0];
+    *triplets = (int64_t)h[1];
+    *triplets_in_range = (int64_t)h[2];
+    return PIMD_OK;
+}
+
+pimd_status pimd_sizes(const pimd_ctx *ctx, int64_t *bead_atoms, int64_t *beads, int32_t *features)
+{
+    if (!ctx)
+        return PIMD_E_ARG;
+    if (bead_atoms)
+        *bead_atoms = ctx->z.B;
+    if (beads)
+        *beads = ctx->z.n_beads_total;
+    if (features)
+        *features = ctx->z.D;
+    return PIMD_OK;
+}
+
+void pimd_destroy(pimd_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->gexec)
+        (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph)
+        (void)hipGraphDestroy(ctx->graph);
+    if (ctx->capture)
+        (void)hipStreamDestroy(ctx->capture);
+    delete ctx;
+}
+
+}  // extern "C"

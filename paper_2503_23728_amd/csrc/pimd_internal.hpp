@@ -1,0 +1,181 @@
+// Internal types shared by the host runtime (pimd_api.cpp) and the HIP
+// kernels.  Plain structs only; no STL in device-visible declarations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pimd {
+
+constexpr int kWave = 64;
+constexpr int kMaxElements = 4;
+constexpr int kMaxRad = 32;
+constexpr int kMaxBeads = 128;
+constexpr int kMaxNeighbors = 256;
+constexpr int kKeyShift = 27;                 // neighbour key = (element << 27) | row
+constexpr uint32_t kRowMask = (1u << kKeyShift) - 1u;
+
+// device status word bits
+constexpr uint32_t kStatusOverflow = 1u;
+constexpr uint32_t kStatusNonFinite = 2u;
+
+// physical constants (CODATA 2018), library side
+constexpr double kKB = 8.617333262e-5;        // eV / K
+constexpr double kHbar = 0.6582119569;        // eV fs
+constexpr double kMvv2e = 103.64269652680505; // eV per amu A^2 / fs^2
+
+// One entry per global bead.
+struct BeadInfo {
+    int32_t sys;        // system index
+    int32_t ba0;        // first row of the bead in the state layout
+    int32_t n;          // atoms in the bead
+    int32_t periodic;   // 1 if the system has a box
+    float L[3];         // box lengths
+    float invL[3];      // fl32(1 / L)
+    float cell_scale[3];// cells per unit length (nc / L)
+    int32_t nc[3];      // cells per axis
+    int32_t cell0;      // first cell of this bead in the cell arrays
+    int32_t pad;
+    double L64[3];      // box lengths in FP64 (displacements of the descriptor kernels)
+    double invL64[3];
+};
+
+// Descriptor grid and cutoff, passed by value to the descriptor kernels.
+struct DescParams {
+    int32_t n_el, n_rad, n_ang_eta, n_ang, D, Kmax;
+    float rc, rc2, pi_over_rc, half_over_rc;  // half_over_rc = 1/(2 rc): cos(pi r/rc) = cos(2 pi (r half_over_rc))
+    float rad_center[kMaxRad];
+    float rad_eta[kMaxRad];
+    float ang_eta[2];
+};
+
+// One layer of one element network on the device.
+struct MlpLayer {
+    const float *W;        // [out][in_pad]   forward B operand (B[k][n] = W[n][k])
+    const float *WT;       // [in_pad][out]   backward B operand
+    const uint16_t *Wb;    // bfloat16 copies of the two (nearest-even rounding) ...
+    const uint16_t *WTb;
+    const uint16_t *Wb_lo; // ... and of the rounding remainders W - bf16(W)
+    const uint16_t *WTb_lo;
+    const double *W64;     // FP64 copies of W and WT
+    const double *WT64;
+    const float *b;        // [out]
+    int32_t in_pad, out;
+};
+
+struct MlpNet {
+    MlpLayer layer[3];
+    int32_t n_hidden;
+    const float *wo;       // [out of last hidden]
+    float bo;
+    const float *inv_scale;// [D] 1 / feat_scale
+    const float *shift;    // [D] feat_shift (used by the descriptor kernel)
+};
+
+struct MlpNets {
+    MlpNet net[kMaxElements];
+};
+
+// 16-row tile of one element's rows for the MLP kernel.
+struct MlpTile {
+    int32_t e, row0, nrows, pad;
+};
+
+// Integrator work unit: `ncol` columns (atom, xyz) of one system, P threads each.
+struct IntegUnit {
+    int32_t sys;
+    int32_t col0;
+    int32_t ncol;
+    int32_t pad;
+};
+
+struct SysInfo {
+    int32_t N, P, ba0, atom0;   // atoms, beads, first row, first atom (in species order)
+    int32_t mode0;              // first entry of this system in the mode table
+    int32_t cmat0;              // offset of this P's normal-mode matrix in the C table
+    int32_t unit0, nunit;       // integrator units of this system
+    float sig_T;                // sqrt(k_B T P / MVV2E): thermal momentum per sqrt(amu)
+    float pad[3];
+};
+
+struct ModeInfo {
+    float c1, c2;       // O step: exp(-gamma dt/2), sqrt(1 - c1^2)
+    float cw, sw;       // cos(w dt), sin(w dt)
+    float w;            // mode frequency (1/fs)
+    float pad[3];
+};
+
+// Everything a step needs on the device, carved from the workspace.
+struct DevBuffers {
+    float *q, *p, *F, *E_bead;     // integrator state, forces of q, bead energies
+    float *xi;                     // injected noise [2][B][3]
+    float4 *pos4;                  // wrapped positions + species bits (neighbour search)
+    float4 *posu4;                 // unwrapped positions + species bits (displacements)
+    int32_t *atom_cell, *atom_slot;
+    int32_t *cell_count, *cell_start, *cell_atoms;
+    int32_t *nbr, *nbr_cnt, *nbr_grp;
+    float *xhat, *dEdG, *E_atom;
+    float4 *vslot;
+    float *vir_atom, *W_bead;
+    double *heat, *dke_part;       // heat bath per system; O-step energy changes per unit (2 halves)
+    int64_t *step;
+    uint32_t *status;
+    float *est_cols;               // estimator terms per column [ncol][3]
+    // tables
+    BeadInfo *beads;
+    int32_t *bead_of_ba;
+    int32_t *species_atom;         // [sum N]
+    int32_t *elem_rows;            // rows grouped by element (MLP gather)
+    MlpTile *mlp_tiles;            // 16-row tiles over all elements
+    float *mass_atom;              // [sum N]
+    SysInfo *sys;
+    ModeInfo *modes;
+    IntegUnit *units;
+    float *cmat;                   // normal-mode matrices, C[j][k] row-major per distinct P
+    int32_t *col_sys;              // [ncol] system of each column
+    float *mlp_f32;                // packed f32 weights (W, WT, b, wo per element)
+    uint16_t *mlp_bf16;            // packed bf16 weights (W, WT per element)
+    double *mlp_f64;               // packed f64 weights (W, WT per element)
+    float *norm;                   // [n_el][2][D] shift, 1/scale
+};
+
+// ---------------------------------------------------------------- launchers
+struct Sizes {
+    int32_t n_sys, B, n_beads_total, n_atoms_total, ncol, total_cells, n_units, D, Kmax;
+    int32_t any_periodic;
+};
+
+void launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
+void launch_wrap_bin(const float *q, const DevBuffers &d, const Sizes &z, hipStream_t s);
+void launch_cell_scan(const DevBuffers &d, const Sizes &z, hipStream_t s);
+void launch_cell_fill(const DevBuffers &d, const Sizes &z, hipStream_t s);
+void launch_neighbors(const DevBuffers &d, const Sizes &z, float rc2, int n_el, hipStream_t s);
+void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &dp, hipStream_t s);
+// mlp_mode: 0 FP32 operands; 1 BF16 operands, three-term split; 2 BF16 operands, one term; 3 FP64
+void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int mlp_mode, hipStream_t s);
+void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, hipStream_t s);
+void launch_assemble_forces(const DevBuffers &d, const Sizes &z, float *F, hipStream_t s);
+void launch_bead_sums(const DevBuffers &d, const Sizes &z, float *E_bead, float *W_bead, bool virial,
+                      hipStream_t s);
+void launch_harmonic(const float *q, const DevBuffers &d, const Sizes &z, float k_over_m,
+                     float *F, hipStream_t s);
+void launch_integrate_pre(const DevBuffers &d, const Sizes &z, float dt, uint32_t key0, uint32_t key1,
+                          const float *xi, int max_P, hipStream_t s);
+void launch_integrate_post(const DevBuffers &d, const Sizes &z, float dt, uint32_t key0, uint32_t key1,
+                           const float *xi, int max_P, hipStream_t s);
+void launch_finish_step(const DevBuffers &d, const Sizes &z, hipStream_t s);
+void launch_estimator_terms(const DevBuffers &d, const Sizes &z, hipStream_t s);
+void launch_philox_words(uint32_t key0, uint32_t key1, int64_t step, int half, int64_t n, uint32_t *out,
+                         hipStream_t s);
+void launch_check_finite(const float *a, int64_t n, uint32_t *status, hipStream_t s);
+
+void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &dp,
+                        unsigned long long *counts, hipStream_t s);
+
+// Raise the dynamic-LDS limit of kernels whose LDS grows with Kmax or P.
+hipError_t configure_descriptor_lds(const DescParams &dp);
+hipError_t configure_integrator_lds(int max_P);
+size_t descriptor_lds_bytes(const DescParams &dp, bool adjoint);
+size_t integrator_lds_bytes(int max_P);
+
+}  // namespace pimd

@@ -1,0 +1,246 @@
+"""Torch-facing wrapper of the ring-polymer library.
+
+PyTorch provides the device memory (the workspace and the state tensors)
+and the stream; every computation runs in libpimd.so.
+
+    eng = Pimd.from_workload(wl, device="cuda:0", precision="bf16")
+    eng.set_state(q, p)
+    eng.step(100)
+    est = eng.estimators()
+
+`PimdEnergy` is the autograd view: forward gives the per-bead energies,
+backward returns -gE[bead] * F from the adjoint kernels.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import abi
+
+
+def _check(st, ctx=None):
+    if st != abi.PIMD_OK:
+        raise abi.PimdError(st, abi.pimd_last_error(ctx))
+
+
+def _ptr(t):
+    return 0 if t is None else t.data_ptr()
+
+
+def pack_params(model):
+    """Concatenate per element: each layer's W [out][in] row-major, then b."""
+    parts = []
+    for layers in model.weights:
+        for W, b in layers:
+            parts.append(np.ascontiguousarray(W, dtype=np.float32).ravel())
+            parts.append(np.ascontiguousarray(b, dtype=np.float32).ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
+class _Keep:
+    """Host arrays that must outlive the config structs during pimd_init."""
+
+    def __init__(self):
+        self.items = []
+
+    def arr(self, a, dtype, ctype):
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.items.append(a)
+        return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
+                omega=0.0, max_neighbors=0, masses=None):
+    """Build the pimd_config (and the storage it points into).
+
+    systems: sequence with n_atoms, n_beads, temperature, box, species.
+    model: a synthetic.Model (BPNN) or None with `masses` (harmonic)."""
+    keep = _Keep()
+    m = abi.pimd_bpnn_model()
+    if model is not None:
+        m.n_elements = model.n_elements
+        m.mass_amu = keep.arr(model.masses, np.float64, ctypes.c_double)
+        m.cutoff_A = float(model.cutoff)
+        m.n_rad = model.n_rad
+        m.rad_center_A = keep.arr(model.rad_center, np.float64, ctypes.c_double)
+        m.rad_eta = keep.arr(model.rad_eta, np.float64, ctypes.c_double)
+        m.n_ang_eta = len(model.ang_eta)
+        m.ang_eta = keep.arr(model.ang_eta, np.float64, ctypes.c_double)
+        m.n_hidden = len(model.hidden)
+        for l, h in enumerate(model.hidden):
+            m.hidden[l] = h
+        m.params = keep.arr(pack_params(model), np.float32, ctypes.c_float)
+        m.feat_shift = keep.arr(model.feat_shift, np.float32, ctypes.c_float)
+        m.feat_scale = keep.arr(model.feat_scale, np.float32, ctypes.c_float)
+    else:
+        m.n_elements = len(masses)
+        m.mass_amu = keep.arr(masses, np.float64, ctypes.c_double)
+    keep.items.append(m)
+    cfg = abi.pimd_config()
+    cfg.n_systems = len(systems)
+    cfg.n_atoms = keep.arr([s.n_atoms for s in systems], np.int32, ctypes.c_int32)
+    cfg.n_beads = keep.arr([s.n_beads for s in systems], np.int32, ctypes.c_int32)
+    cfg.temperature_K = keep.arr([s.temperature for s in systems], np.float64, ctypes.c_double)
+    cfg.box_A = keep.arr(np.concatenate([np.asarray(s.box, dtype=np.float64) for s in systems]), np.float64,
+                         ctypes.c_double)
+    cfg.species = keep.arr(np.concatenate([np.asarray(s.species) for s in systems]), np.int32, ctypes.c_int32)
+    cfg.dt_fs = dt
+    cfg.tau0_fs = tau0
+    cfg.pile_lambda = pile_lambda
+    cfg.seed = seed
+    cfg.precision = {"fp32": abi.PIMD_PREC_FP32, "bf16": abi.PIMD_PREC_BF16_MLP,
+                     "bf16-plain": abi.PIMD_PREC_BF16_PLAIN, "fp64-mlp": abi.PIMD_PREC_FP64_MLP}[precision]
+    cfg.potential = {"bpnn": abi.PIMD_POT_BPNN, "harmonic": abi.PIMD_POT_HARMONIC}[potential]
+    cfg.model = ctypes.pointer(m)
+    cfg.harmonic_omega_per_fs = omega
+    cfg.max_neighbors = max_neighbors
+    return cfg, keep
+
+
+class Pimd:
+    """One library context: state, workspace and stream on one device."""
+
+    def __init__(self, systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
+                 omega=0.0, max_neighbors=0, masses=None, device="cuda:0", stream=None):
+        self.device = torch.device(device)
+        self.systems = list(systems)
+        self.cfg, self._keep = make_config(self.systems, model, dt, tau0, pile_lambda, seed, precision,
+                                           potential, omega, max_neighbors, masses)
+        st, nbytes = abi.pimd_workspace_size(self.cfg)
+        _check(st)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("torch returned a workspace that is not 256-byte aligned")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = None
+        st, ctx = abi.pimd_init(self.cfg, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        _check(st)
+        self.ctx = ctx
+        st, self.B, self.n_beads, self.D = abi.pimd_sizes(ctx)
+        _check(st, ctx)
+        bead_of_row = []
+        b0 = 0
+        for s in self.systems:
+            bead_of_row.append(b0 + np.repeat(np.arange(s.n_beads), s.n_atoms))
+            b0 += s.n_beads
+        self.bead_of_row = torch.as_tensor(np.concatenate(bead_of_row), device=self.device, dtype=torch.long)
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        return cls(wl.systems, wl.model, wl.dt, wl.tau0, wl.pile_lambda, wl.philox_seed, **kw)
+
+    def close(self):
+        """Destroy the library context (synchronises); the workspace is freed with the object."""
+        if getattr(self, "ctx", None):
+            abi.pimd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass     # interpreter shutdown: the binding may already be gone
+
+    def _vec(self, x, shape):
+        t = torch.as_tensor(x, dtype=torch.float32, device=self.device).contiguous()
+        if tuple(t.shape) != shape:
+            t = t.reshape(shape)
+        return t
+
+    def set_state(self, q, p, step=0):
+        q = self._vec(q, (self.B, 3))
+        p = self._vec(p, (self.B, 3))
+        _check(abi.pimd_set_state(self.ctx, q.data_ptr(), p.data_ptr(), int(step)), self.ctx)
+
+    def get_state(self, forces=True):
+        q = torch.empty(self.B, 3, device=self.device)
+        p = torch.empty_like(q)
+        F = torch.empty_like(q) if forces else None
+        st, step = abi.pimd_get_state(self.ctx, q.data_ptr(), p.data_ptr(), _ptr(F))
+        _check(st, self.ctx)
+        return q, p, F, step
+
+    def energy_forces(self, q, forces=True, virial=False):
+        q = self._vec(q, (self.B, 3))
+        E = torch.empty(self.n_beads, device=self.device)
+        F = torch.empty(self.B, 3, device=self.device) if forces else None
+        W = torch.empty(self.n_beads, 3, 3, device=self.device) if virial else None
+        _check(abi.pimd_energy_forces(self.ctx, q.data_ptr(), E.data_ptr(), _ptr(F), _ptr(W)), self.ctx)
+        return E, F, W
+
+    def step(self, n=1):
+        _check(abi.pimd_step(self.ctx, int(n)), self.ctx)
+
+    def estimators(self):
+        st, arr = abi.pimd_estimators(self.ctx, len(self.systems))
+        _check(st, self.ctx)
+        return [{f: getattr(a, f) for f, _ in abi.pimd_estimates._fields_} for a in arr]
+
+    def inject_noise(self, xi):
+        xi = self._vec(xi, (2, self.B, 3))
+        _check(abi.pimd_inject_noise(self.ctx, xi.data_ptr()), self.ctx)
+        self._xi_keep = xi
+
+    def set_graph(self, enabled):
+        _check(abi.pimd_set_graph(self.ctx, enabled), self.ctx)
+
+    def profile_stages(self, n_reps):
+        """Mean ms per step of each stage (abi.STAGE_NAMES), HIP events on the context stream."""
+        st, ms = abi.pimd_profile_stages(self.ctx, int(n_reps))
+        _check(st, self.ctx)
+        return dict(zip(abi.STAGE_NAMES, ms))
+
+    def work_counts(self):
+        """(pairs, triplets, triplets with r_jk < cutoff) of the last force evaluation."""
+        st, a, b, c = abi.pimd_work_counts(self.ctx)
+        _check(st, self.ctx)
+        return a, b, c
+
+    def debug_neighbors(self, bead):
+        cap = 1 << 22
+        st, buf, count = abi.pimd_debug_neighbors(self.ctx, bead, cap)
+        _check(st, self.ctx)
+        return np.ctypeslib.as_array(buf)[: 2 * count].reshape(-1, 2).copy()
+
+    def debug_descriptors(self):
+        x = torch.empty(self.B, self.D, device=self.device)
+        _check(abi.pimd_debug_descriptors(self.ctx, x.data_ptr()), self.ctx)
+        return x
+
+    def debug_buffer(self, name):
+        """Internal buffer of the last force evaluation: 'xhat', 'dEdG', 'slots', 'nbr', 'ncount', 'eatom'."""
+        K = self.cfg.max_neighbors or 128
+        spec = {"xhat": (abi.PIMD_BUF_XHAT, (self.B, self.D), torch.float32),
+                "dEdG": (abi.PIMD_BUF_DEDG, (self.B, self.D), torch.float32),
+                "slots": (abi.PIMD_BUF_SLOTS, (self.B, K, 4), torch.float32),
+                "nbr": (abi.PIMD_BUF_NBR, (self.B, K), torch.int32),
+                "ncount": (abi.PIMD_BUF_NCOUNT, (self.B,), torch.int32),
+                "eatom": (abi.PIMD_BUF_EATOM, (self.B,), torch.float32)}[name]
+        t = torch.empty(spec[1], dtype=spec[2], device=self.device)
+        _check(abi.pimd_debug_copy(self.ctx, spec[0], t.data_ptr(), t.numel() * t.element_size()), self.ctx)
+        return t
+
+    def debug_philox(self, step, half, n):
+        w = torch.empty(n, 4, dtype=torch.int32, device=self.device)
+        _check(abi.pimd_debug_philox(self.ctx, int(step), int(half), int(n), w.data_ptr()), self.ctx)
+        return w
+
+
+class PimdEnergy(torch.autograd.Function):
+    """E_bead = PimdEnergy.apply(q, engine): per-bead potential energies;
+    the backward pass runs the adjoint (descriptor recomputation) kernels."""
+
+    @staticmethod
+    def forward(ctx, q, engine):
+        E, _, _ = engine.energy_forces(q.detach(), forces=False)
+        ctx.save_for_backward(q.detach())
+        ctx.engine = engine
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        (q,) = ctx.saved_tensors
+        eng = ctx.engine
+        _, F, _ = eng.energy_forces(q, forces=True)
+        return -gE[eng.bead_of_row][:, None] * F, None

@@ -1,0 +1,102 @@
+"""The C-ABI library loads without a GPU, exports every function the header
+declares, and rejects bad arguments with the documented status before any
+HIP call."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2503_23728_amd import abi, synthetic as S
+from paper_2503_23728_amd.pimd import make_config
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return abi.lib()
+
+
+def test_exports_every_declared_function(lib):
+    names = abi.declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(abi._SIGNATURES)
+
+
+def test_status_strings(lib):
+    for s in range(8):
+        assert abi.pimd_status_str(s)
+    assert abi.pimd_status_str(99) == "unknown status"
+
+
+def _cfg(wl, **kw):
+    return make_config(wl.systems, wl.model, wl.dt, wl.tau0, wl.pile_lambda, wl.philox_seed, **kw)
+
+
+def test_workspace_size_of_valid_configs(lib):
+    for c in (1, 2, 3):
+        cfg, keep = _cfg(S.workload(c))
+        st, n = abi.pimd_workspace_size(cfg)
+        assert st == abi.PIMD_OK and n > 0
+
+
+def test_workspace_grows_with_max_neighbors(lib):
+    wl = S.workload(2)
+    a = abi.pimd_workspace_size(_cfg(wl, max_neighbors=64)[0])[1]
+    b = abi.pimd_workspace_size(_cfg(wl, max_neighbors=256)[0])[1]
+    assert b > a
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda cfg, k: setattr(cfg, "n_systems", 0), abi.PIMD_E_ARG),
+    (lambda cfg, k: setattr(cfg, "dt_fs", 0.0), abi.PIMD_E_ARG),
+    (lambda cfg, k: setattr(cfg, "precision", 7), abi.PIMD_E_ARG),
+    (lambda cfg, k: setattr(cfg, "potential", 9), abi.PIMD_E_ARG),
+    (lambda cfg, k: setattr(cfg, "max_neighbors", 1000), abi.PIMD_E_UNSUPPORTED),
+    (lambda cfg, k: setattr(cfg, "species", None), abi.PIMD_E_ARG),
+    (lambda cfg, k: setattr(cfg, "model", None), abi.PIMD_E_ARG),
+    (lambda cfg, k: cfg.n_beads.__setitem__(0, 3), abi.PIMD_E_UNSUPPORTED),     # odd P
+    (lambda cfg, k: cfg.n_beads.__setitem__(0, 256), abi.PIMD_E_UNSUPPORTED),   # P > 128
+    (lambda cfg, k: cfg.n_atoms.__setitem__(0, 0), abi.PIMD_E_ARG),
+    (lambda cfg, k: cfg.temperature_K.__setitem__(0, -1.0), abi.PIMD_E_ARG),
+    (lambda cfg, k: cfg.box_A.__setitem__(0, 11.0), abi.PIMD_E_UNSUPPORTED),     # R_c >= L/2
+    (lambda cfg, k: cfg.box_A.__setitem__(1, 0.0), abi.PIMD_E_ARG),              # partly zero box
+    (lambda cfg, k: cfg.species.__setitem__(0, 5), abi.PIMD_E_ARG),
+    (lambda cfg, k: setattr(cfg.model.contents, "n_elements", 0), abi.PIMD_E_UNSUPPORTED),
+    (lambda cfg, k: setattr(cfg.model.contents, "n_ang_eta", 3), abi.PIMD_E_UNSUPPORTED),
+    (lambda cfg, k: cfg.model.contents.hidden.__setitem__(0, 40), abi.PIMD_E_UNSUPPORTED),
+    (lambda cfg, k: cfg.model.contents.feat_scale.__setitem__(0, 0.0), abi.PIMD_E_ARG),
+])
+def test_bad_configs_are_rejected_without_a_gpu(lib, mutate, status):
+    cfg, keep = _cfg(S.workload(2))
+    mutate(cfg, keep)
+    st, _ = abi.pimd_workspace_size(cfg)
+    assert st == status
+    assert abi.pimd_last_error(None)
+    st, ctx = abi.pimd_init(cfg, 256, 1 << 30, 0)
+    assert st == status and ctx is None
+
+
+def test_init_rejects_bad_workspace_before_device_work(lib):
+    cfg, keep = _cfg(S.workload(1))
+    st, n = abi.pimd_workspace_size(cfg)
+    assert abi.pimd_init(cfg, 0, n, 0)[0] == abi.PIMD_E_ARG           # NULL workspace
+    assert abi.pimd_init(cfg, 4096 + 8, n, 0)[0] == abi.PIMD_E_ARG    # misaligned
+    assert abi.pimd_init(cfg, 4096, n - 1, 0)[0] == abi.PIMD_E_OOM     # too small
+
+
+def test_harmonic_config_needs_omega(lib):
+    wl = S.small_workload("fad")
+    cfg, keep = make_config(wl.systems, None, 0.5, 100.0, 1.0, 1, potential="harmonic", omega=0.0,
+                            masses=wl.model.masses)
+    assert abi.pimd_workspace_size(cfg)[0] == abi.PIMD_E_ARG
+    cfg, keep = make_config(wl.systems, None, 0.5, 100.0, 1.0, 1, potential="harmonic", omega=0.01,
+                            masses=wl.model.masses)
+    assert abi.pimd_workspace_size(cfg)[0] == abi.PIMD_OK
+
+
+def test_null_context_calls_are_argument_errors(lib):
+    assert lib.pimd_step(None, 1) == abi.PIMD_E_ARG
+    assert lib.pimd_set_state(None, None, None, 0) == abi.PIMD_E_ARG
+    assert lib.pimd_energy_forces(None, None, None, None, None) == abi.PIMD_E_ARG
+    lib.pimd_destroy(None)
