@@ -20,9 +20,16 @@
 
 namespace pimd {
 
-struct StagedA {  // per neighbour slot
-    float4 d;     // dx, dy, dz, r
-    float4 e;     // fc, E_0 = exp(-eta_0 r^2) fc, E_1, 1/r
+// Per-neighbour records staged in LDS, shared by all triplets of a centre.
+// Three arrays of 16-byte entries (not one interleaved struct), so gathers by
+// slot index spread over the LDS banks:
+//   recD[n] = d_ij (x, y, z), 1/r_ij
+//   recE[n] = E_0, E_1 (E_eta = exp(-eta r^2) f_c(r)), dE_0/dr, dE_1/dr
+//   rr[n]   = r, f_c, f_c', 0   (pair terms)
+struct Recs {
+    float4 *D;
+    float4 *E;
+    float4 *rr;
 };
 
 // Displacement d_ij = q_j - q_i (minimum image) of the unwrapped float32
@@ -45,41 +52,95 @@ __device__ __forceinline__ void displacement(const float4 &pi, const float4 &pj,
     inv_r = (float)(1.0 / r64);
 }
 
-// Slot pair t of a block -> (a, b) slot offsets inside the two groups.
-__device__ __forceinline__ void decode_pair(int t, bool tri, int n2, float inv_n2, int &a, int &b)
+// Cutoff function and derivative from x = r/rc in [0, 1):
+//   f_c = (cos(pi x) + 1)/2 = cos^2(pi x/2),  f_c' = -(pi/rc) sin(pi x/2) cos(pi x/2).
+// sin and cos of pi u (u = x/2) come from their Taylor series on the reduced
+// argument w = min(u, 1/2 - u) <= 1/4 (five and six terms: truncation below
+// 3e-8); the reflection keeps both relative-accurate, so f_c has no
+// cancellation near the cutoff.
+__device__ __forceinline__ void cutoff_fn(float x, float pi_over_rc, float &fc, float &dfc)
 {
-    if (tri) {
-        // t = b (b - 1)/2 + a, 0 <= a < b
-        int bb = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
-        if (bb * (bb - 1) / 2 > t)
-            --bb;
-        if ((bb + 1) * bb / 2 <= t)
-            ++bb;
-        b = bb;
-        a = t - bb * (bb - 1) / 2;
-    } else {
-        int aa = (int)(((float)t + 0.5f) * inv_n2);
-        int bb = t - aa * n2;
-        if (bb < 0) {
-            --aa;
-            bb += n2;
-        } else if (bb >= n2) {
-            ++aa;
-            bb -= n2;
-        }
-        a = aa;
-        b = bb;
+    const float u = 0.5f * x;
+    const float w = fminf(u, 0.5f - u);
+    const float t = 3.14159265358979f * w;
+    const float t2 = t * t;
+    float ps = 2.7557319224e-06f;
+    ps = fmaf(ps, t2, -1.9841269841e-04f);
+    ps = fmaf(ps, t2, 8.3333333333e-03f);
+    ps = fmaf(ps, t2, -1.6666666667e-01f);
+    ps = fmaf(ps, t2, 1.0f);
+    ps *= t;
+    float pc = -2.7557319224e-07f;
+    pc = fmaf(pc, t2, 2.4801587302e-05f);
+    pc = fmaf(pc, t2, -1.3888888889e-03f);
+    pc = fmaf(pc, t2, 4.1666666667e-02f);
+    pc = fmaf(pc, t2, -0.5f);
+    pc = fmaf(pc, t2, 1.0f);
+    const bool big = u > 0.25f;
+    const float sn = big ? pc : ps, cs = big ? ps : pc;
+    fc = cs * cs;
+    dfc = -pi_over_rc * sn * cs;
+}
+
+// Stage the records of centre i (slot order = key order: grouped by element);
+// rr[n] = (r, f_c, f_c', 0) for the pair terms.  Returns K.
+template <int NETA, bool ADJ>
+__device__ __forceinline__ int stage_neighbors(int i, const float4 &pi, const BeadInfo &bi, const int32_t *nbr,
+                                               const int32_t *nbr_cnt, const float4 *posu, const DescParams &dp,
+                                               const Recs &rec)
+{
+    const int lane = lane_id();
+    const int K = nbr_cnt[i];
+    const int32_t *row = nbr + (int64_t)i * dp.Kmax;
+    for (int n = lane; n < K; n += kWave) {
+        const int j = row[n] & (int)kRowMask;
+        float3 d;
+        float r, inv_r;
+        displacement(pi, posu[j], bi, d, r, inv_r);
+        const float r2 = r * r;
+        float fc, dfc;
+        cutoff_fn(r * (1.0f / dp.rc), dp.pi_over_rc, fc, dfc);
+        const float g0 = expf(-dp.ang_eta[0] * r2);
+        const float g1 = NETA > 1 ? expf(-dp.ang_eta[1] * r2) : 0.0f;
+        rec.D[n] = make_float4(d.x, d.y, d.z, inv_r);
+        // dE_eta/dr = exp(-eta r^2) (-2 eta r f_c + f_c')
+        rec.E[n] = make_float4(g0 * fc, g1 * fc, ADJ ? g0 * (-2.0f * dp.ang_eta[0] * r * fc + dfc) : 0.0f,
+                               (ADJ && NETA > 1) ? g1 * (-2.0f * dp.ang_eta[1] * r * fc + dfc) : 0.0f);
+        rec.rr[n] = make_float4(r, fc, dfc, 0.0f);
+    }
+    return K;
+}
+
+__device__ __forceinline__ void group_offsets(const int32_t *nbr_grp, int i, int n_el, int (&gcnt)[kMaxElements],
+                                              int (&goff)[kMaxElements])
+{
+    int o = 0;
+    for (int e = 0; e < kMaxElements; ++e) {
+        gcnt[e] = e < n_el ? nbr_grp[(int64_t)i * kMaxElements + e] : 0;
+        goff[e] = o;
+        o += gcnt[e];
     }
 }
 
+// Slot pair t of the triangle of K slots (t = b(b-1)/2 + a, a < b); used by
+// the work counter.
+__device__ __forceinline__ void decode_triangle(int t, int &a, int &b)
+{
+    int bb = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
+    if (bb * (bb - 1) / 2 > t)
+        --bb;
+    if ((bb + 1) * bb / 2 <= t)
+        ++bb;
+    b = bb;
+    a = t - bb * (bb - 1) / 2;
+}
+
 // Walk over the slot pairs of one element-pair block.  Each lane owns one
-// slot b of the "own" group for the whole block and pairs it with partner
-// slot (b + s) mod n_par for a uniform shift s:
+// slot b of the "own" group and pairs it with partner slot (b + s) mod n_par
+// for a uniform shift s:
 //   triangle (e1 = e2, n slots): s = 1 .. n/2, and for even n the shift n/2
 //     only for b < n/2, so every unordered pair appears once;
 //   rectangle (e1 < e2): own = the larger group, s = 0 .. n_par - 1.
-// Lane work is balanced and the lane's own slot changes only between
-// chunks of 64 slots, so its share of the gradient can stay in registers.
 struct BlockWalk {
     bool tri;
     int n_own, n_par, o_own, o_par, s0, s1;
@@ -108,38 +169,73 @@ struct BlockWalk {
     }
 };
 
-// Stage the neighbour records of centre i; returns K.  Also fills grp_off.
-template <int NETA, bool ADJ>
-__device__ __forceinline__ int stage_neighbors(int i, const float4 &pi, const BeadInfo &bi, const int32_t *nbr,
-                                               const int32_t *nbr_cnt, const float4 *posu, const DescParams &dp,
-                                               StagedA *rec, float4 *recd)
+constexpr int kQueue = 128;   // in-range slot pairs waiting per wave (< 64 + one shift's 64)
+
+// Phase 1 of a block: every lane tests its (own, partner) pairs with the
+// cheap r_jk^2 < rc^2 test and appends the pairs in range to the wave's LDS
+// queue; whenever 64 are waiting, `body` runs on them with one pair per lane
+// (phase 2), so the costly triplet terms never run on idle lanes.
+template <typename Body>
+__device__ __forceinline__ void for_each_triplet_in_range(const BlockWalk &bw, const float4 *recD, float rc2,
+                                                          uint32_t *queue, Body &&body)
 {
     const int lane = lane_id();
-    const int K = nbr_cnt[i];
-    const int32_t *row = nbr + (int64_t)i * dp.Kmax;
-    for (int n = lane; n < K; n += kWave) {
-        const int j = row[n] & (int)kRowMask;
-        const float4 pj = posu[j];
-        float3 d;
-        float r, inv_r;
-        displacement(pi, pj, bi, d, r, inv_r);
-        const float r2 = r * r;
-        const float x = r * (1.0f / dp.rc);
-        const float fc = 0.5f * cospif(x) + 0.5f;
-        const float g0 = expf(-dp.ang_eta[0] * r2);
-        const float g1 = NETA > 1 ? expf(-dp.ang_eta[1] * r2) : 0.0f;
-        StagedA s;
-        s.d = make_float4(d.x, d.y, d.z, r);
-        s.e = make_float4(fc, g0 * fc, g1 * fc, inv_r);
-        rec[n] = s;
-        if (ADJ) {
-            // dE_eta/dr = exp(-eta r^2) (-2 eta r fc + fc'),  fc' = -(pi/(2 rc)) sin(pi r/rc)
-            const float dfc = -0.5f * dp.pi_over_rc * sinpif(x);
-            recd[n] = make_float4(g0 * (-2.0f * dp.ang_eta[0] * r * fc + dfc),
-                                  NETA > 1 ? g1 * (-2.0f * dp.ang_eta[1] * r * fc + dfc) : 0.0f, dfc, 0.0f);
+    const uint64_t below = lanes_below_mask();
+    int qn = 0;
+    for (int b0 = 0; b0 < bw.n_own; b0 += kWave) {
+        const int b = b0 + lane;
+        const bool own_ok = b < bw.n_own;
+        const int ia = bw.o_own + (own_ok ? b : 0);
+        const float4 A = recD[ia];
+        const int bm = bw.tri ? b : ((own_ok && bw.n_par > 0) ? b % bw.n_par : 0);
+        for (int s = bw.s0; s <= bw.s1; ++s) {
+            bool inr = false;
+            int ic = 0;
+            if (bw.active(own_ok, b, s)) {
+                int p = bm + s;
+                p -= p >= bw.n_par ? bw.n_par : 0;
+                ic = bw.o_par + p;
+                const float4 C = recD[ic];
+                const float jx = C.x - A.x, jy = C.y - A.y, jz = C.z - A.z;
+                inr = jx * jx + jy * jy + jz * jz < rc2;
+            }
+            const uint64_t m = __ballot(inr);
+            if (inr)
+                queue[qn + __popcll(m & below)] = ((uint32_t)ia << 16) | (uint32_t)ic;
+            qn += __popcll(m);
+            if (qn >= kWave) {
+                wave_sync();
+                const uint32_t q = queue[lane];
+                body(q >> 16, q & 0xFFFFu, true);
+                const int rest = qn - kWave;
+                const uint32_t carry = lane < rest ? queue[kWave + lane] : 0u;
+                wave_sync();
+                if (lane < rest)
+                    queue[lane] = carry;
+                wave_sync();
+                qn = rest;
+            }
         }
     }
-    return K;
+    if (qn > 0) {
+        wave_sync();
+        const uint32_t q = lane < qn ? queue[lane] : 0u;
+        body(q >> 16, q & 0xFFFFu, lane < qn);
+        wave_sync();
+    }
+}
+
+__device__ __forceinline__ float block_scale(int q)
+{
+    const int iz = (q & 7) >> 1;   // 2^(1 - zeta) for zeta = 1, 2, 4, 8
+    return iz == 0 ? 1.0f : (iz == 1 ? 0.5f : (iz == 2 ? 0.125f : 0.0078125f));
+}
+
+// exp(-eta x) for the small arguments of the triplet terms (eta x <= ~1):
+// hardware exp2 of a pre-scaled argument, relative error about 1e-7 there.
+__device__ __forceinline__ float exp_small(float neg_eta_log2e, float x)
+{
+    return __builtin_amdgcn_exp2f(neg_eta_log2e * x);
 }
 
 // ---------------------------------------------------------------------------
@@ -158,25 +254,22 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
     extern __shared__ float4 lds4[];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int Dcap = (dp.D + 3) & ~3;
-    float4 *base = lds4 + w * (2 * dp.Kmax + Dcap / 4);
-    StagedA *rec = reinterpret_cast<StagedA *>(base);
-    float *Gs = reinterpret_cast<float *>(base + 2 * dp.Kmax);
+    float4 *base = lds4 + w * (3 * dp.Kmax + Dcap / 4 + kQueue / 4);
+    const Recs rec{base, base + dp.Kmax, base + 2 * dp.Kmax};
+    const float4 *rr = rec.rr;
+    float *Gs = reinterpret_cast<float *>(base + 3 * dp.Kmax);
+    uint32_t *queue = reinterpret_cast<uint32_t *>(base + 3 * dp.Kmax + Dcap / 4);
     const int Frad = dp.n_el * dp.n_rad;
+    const float nel0 = -dp.ang_eta[0] * 1.4426950408889634f, nel1 = -dp.ang_eta[1] * 1.4426950408889634f;
+    const float inv_rc = 1.0f / dp.rc;
 
     for (int i = blockIdx.x * 4 + w; i < B; i += gridDim.x * 4) {
         const BeadInfo bi = beads[bead_of_ba[i]];
         const float4 pi = posu[i];
         const int zi = __float_as_int(pi.w);
-        stage_neighbors<NETA, false>(i, pi, bi, nbr, nbr_cnt, posu, dp, rec, nullptr);
+        stage_neighbors<NETA, false>(i, pi, bi, nbr, nbr_cnt, posu, dp, rec);
         int gcnt[kMaxElements], goff[kMaxElements];
-        {
-            int o = 0;
-            for (int e = 0; e < kMaxElements; ++e) {
-                gcnt[e] = e < dp.n_el ? nbr_grp[(int64_t)i * kMaxElements + e] : 0;
-                goff[e] = o;
-                o += gcnt[e];
-            }
-        }
+        group_offsets(nbr_grp, i, dp.n_el, gcnt, goff);
         wave_sync();
         // radial: lane -> feature (e, s); the two half-waves split the group
         for (int f0 = 0; f0 < Frad; f0 += 32) {
@@ -189,8 +282,9 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
                 const int a0 = (lane < 32) ? lo : mid, a1 = (lane < 32) ? mid : hi;
                 const float Rs = dp.rad_center[s], eta = dp.rad_eta[s];
                 for (int n = a0; n < a1; ++n) {
-                    const float x = rec[n].d.w - Rs;
-                    acc += expf(-eta * x * x) * rec[n].e.x;
+                    const float4 q = rr[n];
+                    const float x = q.x - Rs;
+                    acc += expf(-eta * x * x) * q.y;
                 }
             }
             acc += __shfl_xor(acc, 32, kWave);
@@ -201,49 +295,40 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
         int pair = 0;
         for (int e1 = 0; e1 < dp.n_el; ++e1)
             for (int e2 = e1; e2 < dp.n_el; ++e2, ++pair) {
-                BlockWalk bw(e1, e2, gcnt, goff);
+                const BlockWalk bw(e1, e2, gcnt, goff);
                 float acc[8 * NETA];
 #pragma unroll
                 for (int q = 0; q < 8 * NETA; ++q)
                     acc[q] = 0.0f;
-                for (int b0 = 0; b0 < bw.n_own; b0 += kWave) {
-                    const int b = b0 + lane;
-                    const bool own_ok = b < bw.n_own;
-                    const StagedA A = rec[bw.o_own + (own_ok ? b : 0)];
-                    const int bm = bw.tri ? b : ((own_ok && bw.n_par > 0) ? b % bw.n_par : 0);
-                    for (int s = bw.s0; s <= bw.s1; ++s) {
-                        if (!bw.active(own_ok, b, s))
-                            continue;
-                        int p = bm + s;
-                        p -= p >= bw.n_par ? bw.n_par : 0;
-                        const StagedA C = rec[bw.o_par + p];
-                        const float jx = C.d.x - A.d.x, jy = C.d.y - A.d.y, jz = C.d.z - A.d.z;
-                        const float r2jk = jx * jx + jy * jy + jz * jz;
-                        if (r2jk < dp.rc2) {
-                            const float rjk = sqrtf(r2jk);
-                            const float fcjk = 0.5f * cospif(rjk * (1.0f / dp.rc)) + 0.5f;
-                            const float cs = (A.d.x * C.d.x + A.d.y * C.d.y + A.d.z * C.d.z) * (A.e.w * C.e.w);
-                            const float p1 = 1.0f + cs, m1 = 1.0f - cs;
-                            const float p2 = p1 * p1, m2 = m1 * m1;
-                            const float p4 = p2 * p2, m4 = m2 * m2;
-                            const float p8 = p4 * p4, m8 = m4 * m4;
+                for_each_triplet_in_range(bw, rec.D, dp.rc2, queue, [&](uint32_t ia, uint32_t ic, bool ok) {
+                    if (!ok)
+                        return;
+                    const float4 Ad = rec.D[ia], Cd = rec.D[ic], Ae = rec.E[ia], Ce = rec.E[ic];
+                    const float jx = Cd.x - Ad.x, jy = Cd.y - Ad.y, jz = Cd.z - Ad.z;
+                    const float r2jk = jx * jx + jy * jy + jz * jz;
+                    const float rjk = __builtin_amdgcn_sqrtf(r2jk);
+                    float fcjk, dfcjk;
+                    cutoff_fn(rjk * inv_rc, dp.pi_over_rc, fcjk, dfcjk);
+                    const float cs = (Ad.x * Cd.x + Ad.y * Cd.y + Ad.z * Cd.z) * (Ad.w * Cd.w);
+                    const float p1 = 1.0f + cs, m1 = 1.0f - cs;
+                    const float p2 = p1 * p1, m2 = m1 * m1;
+                    const float p4 = p2 * p2, m4 = m2 * m2;
+                    const float p8 = p4 * p4, m8 = m4 * m4;
 #pragma unroll
-                            for (int ie = 0; ie < NETA; ++ie) {
-                                const float Ea = ie == 0 ? A.e.y : A.e.z;
-                                const float Eb = ie == 0 ? C.e.y : C.e.z;
-                                const float R = Ea * Eb * expf(-dp.ang_eta[ie] * r2jk) * fcjk;
-                                acc[ie * 8 + 0] += p1 * R;
-                                acc[ie * 8 + 1] += m1 * R;
-                                acc[ie * 8 + 2] += p2 * R;
-                                acc[ie * 8 + 3] += m2 * R;
-                                acc[ie * 8 + 4] += p4 * R;
-                                acc[ie * 8 + 5] += m4 * R;
-                                acc[ie * 8 + 6] += p8 * R;
-                                acc[ie * 8 + 7] += m8 * R;
-                            }
-                        }
+                    for (int ie = 0; ie < NETA; ++ie) {
+                        const float Ea = ie == 0 ? Ae.x : Ae.y;
+                        const float Eb = ie == 0 ? Ce.x : Ce.y;
+                        const float R = Ea * Eb * exp_small(ie == 0 ? nel0 : nel1, r2jk) * fcjk;
+                        acc[ie * 8 + 0] += p1 * R;
+                        acc[ie * 8 + 1] += m1 * R;
+                        acc[ie * 8 + 2] += p2 * R;
+                        acc[ie * 8 + 3] += m2 * R;
+                        acc[ie * 8 + 4] += p4 * R;
+                        acc[ie * 8 + 5] += m4 * R;
+                        acc[ie * 8 + 6] += p8 * R;
+                        acc[ie * 8 + 7] += m8 * R;
                     }
-                }
+                });
                 float mine = 0.0f;
 #pragma unroll
                 for (int q = 0; q < 8 * NETA; ++q) {
@@ -251,11 +336,8 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
                     if (lane == q)
                         mine = v;
                 }
-                if (lane < 8 * NETA) {
-                    const int iz = (lane & 7) >> 1;
-                    const float scale = iz == 0 ? 1.0f : (iz == 1 ? 0.5f : (iz == 2 ? 0.125f : 0.0078125f));
-                    Gs[Frad + pair * dp.n_ang + lane] = mine * scale;
-                }
+                if (lane < 8 * NETA)
+                    Gs[Frad + pair * dp.n_ang + lane] = mine * block_scale(lane);
             }
         wave_sync();
         const float *shift = norm + (int64_t)zi * 2 * dp.D;
@@ -281,127 +363,105 @@ __global__ __launch_bounds__(256) void k_adjoint(const float4 *__restrict__ posu
     extern __shared__ float4 lds4[];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int Dcap = (dp.D + 3) & ~3;
-    float4 *base = lds4 + w * (4 * dp.Kmax + Dcap / 4);
-    StagedA *rec = reinterpret_cast<StagedA *>(base);
-    float4 *recd = base + 2 * dp.Kmax;
-    float4 *vacc = base + 3 * dp.Kmax;
-    float *gl = reinterpret_cast<float *>(base + 4 * dp.Kmax);
+    float4 *base = lds4 + w * (5 * dp.Kmax + Dcap / 4 + kQueue / 4);
+    const Recs rec{base, base + dp.Kmax, base + 2 * dp.Kmax};
+    const float4 *rr = rec.rr;
+    // slot accumulators: three FP64 arrays (one per component, so gathers by
+    // slot spread over the banks); each slot sums ~K mixed-sign triplet terms
+    double *vx = reinterpret_cast<double *>(base + 3 * dp.Kmax);
+    double *vy = vx + dp.Kmax;
+    double *vz = vy + dp.Kmax;
+    float *gl = reinterpret_cast<float *>(base + 5 * dp.Kmax);
+    uint32_t *queue = reinterpret_cast<uint32_t *>(base + 5 * dp.Kmax + Dcap / 4);
     const int Frad = dp.n_el * dp.n_rad;
+    const float nel0 = -dp.ang_eta[0] * 1.4426950408889634f, nel1 = -dp.ang_eta[1] * 1.4426950408889634f;
+    const float inv_rc = 1.0f / dp.rc;
 
     for (int i = blockIdx.x * 4 + w; i < B; i += gridDim.x * 4) {
         const BeadInfo bi = beads[bead_of_ba[i]];
         const float4 pi = posu[i];
-        const int K = stage_neighbors<NETA, true>(i, pi, bi, nbr, nbr_cnt, posu, dp, rec, recd);
+        const int K = stage_neighbors<NETA, true>(i, pi, bi, nbr, nbr_cnt, posu, dp, rec);
         for (int f = lane; f < dp.D; f += kWave)
             gl[f] = dEdG[(int64_t)i * dp.D + f];
         int gcnt[kMaxElements], goff[kMaxElements];
-        {
-            int o = 0;
-            for (int e = 0; e < kMaxElements; ++e) {
-                gcnt[e] = e < dp.n_el ? nbr_grp[(int64_t)i * kMaxElements + e] : 0;
-                goff[e] = o;
-                o += gcnt[e];
-            }
-        }
+        group_offsets(nbr_grp, i, dp.n_el, gcnt, goff);
         const int32_t *row = nbr + (int64_t)i * dp.Kmax;
         wave_sync();
         // radial part of every slot: sum_s g[e,s] dG2/dr * d/r
         for (int n = lane; n < K; n += kWave) {
             const int e = row[n] >> kKeyShift;
-            const StagedA s = rec[n];
-            const float r = s.d.w, fc = s.e.x, dfc = recd[n].z;
+            const float4 q = rr[n];
+            const float4 dn = rec.D[n];
+            const float r = q.x, fc = q.y, dfc = q.z;
             float acc = 0.0f;
-            for (int q = 0; q < dp.n_rad; ++q) {
-                const float x = r - dp.rad_center[q];
-                const float eta = dp.rad_eta[q];
-                acc += gl[e * dp.n_rad + q] * expf(-eta * x * x) * (-2.0f * eta * x * fc + dfc);
+            for (int t = 0; t < dp.n_rad; ++t) {
+                const float x = r - dp.rad_center[t];
+                const float eta = dp.rad_eta[t];
+                acc += gl[e * dp.n_rad + t] * expf(-eta * x * x) * (-2.0f * eta * x * fc + dfc);
             }
-            const float c = acc * s.e.w;
-            vacc[n] = make_float4(c * s.d.x, c * s.d.y, c * s.d.z, 0.0f);
+            const float c = acc * dn.w;
+            vx[n] = (double)(c * dn.x);
+            vy[n] = (double)(c * dn.y);
+            vz[n] = (double)(c * dn.z);
         }
         wave_sync();
         int pair = 0;
         for (int e1 = 0; e1 < dp.n_el; ++e1)
             for (int e2 = e1; e2 < dp.n_el; ++e2, ++pair) {
-                BlockWalk bw(e1, e2, gcnt, goff);
+                const BlockWalk bw(e1, e2, gcnt, goff);
                 // block coefficients with the 2^(1-zeta) factors folded in
                 float gq[8 * NETA];
 #pragma unroll
-                for (int q = 0; q < 8 * NETA; ++q) {
-                    const int iz = (q & 7) >> 1;
-                    const float scale = iz == 0 ? 1.0f : (iz == 1 ? 0.5f : (iz == 2 ? 0.125f : 0.0078125f));
-                    gq[q] = gl[Frad + pair * dp.n_ang + q] * scale;
-                }
-                for (int b0 = 0; b0 < bw.n_own; b0 += kWave) {
-                    const int b = b0 + lane;
-                    const bool own_ok = b < bw.n_own;
-                    const int ia_slot = bw.o_own + (own_ok ? b : 0);
-                    const StagedA A = rec[ia_slot];
-                    const float4 dA = recd[ia_slot];
-                    const int bm = bw.tri ? b : ((own_ok && bw.n_par > 0) ? b % bw.n_par : 0);
-                    float vx = 0.0f, vy = 0.0f, vz = 0.0f;   // gradient on the lane's own slot
-                    for (int s = bw.s0; s <= bw.s1; ++s) {
-                        if (!bw.active(own_ok, b, s))
-                            continue;
-                        int p = bm + s;
-                        p -= p >= bw.n_par ? bw.n_par : 0;
-                        const int ic = bw.o_par + p;
-                        const StagedA C = rec[ic];
-                        const float jx = C.d.x - A.d.x, jy = C.d.y - A.d.y, jz = C.d.z - A.d.z;
-                        const float r2jk = jx * jx + jy * jy + jz * jz;
-                        if (!(r2jk < dp.rc2))
-                            continue;
-                        const float4 dC = recd[ic];
-                        const float rjk = sqrtf(r2jk), inv_rjk = 1.0f / rjk;
-                        const float x = rjk * (1.0f / dp.rc);
-                        const float fcjk = 0.5f * cospif(x) + 0.5f;
-                        const float dfcjk = -0.5f * dp.pi_over_rc * sinpif(x);
-                        const float cs = (A.d.x * C.d.x + A.d.y * C.d.y + A.d.z * C.d.z) * (A.e.w * C.e.w);
-                        const float p1 = 1.0f + cs, m1 = 1.0f - cs;
-                        const float p2 = p1 * p1, m2 = m1 * m1;
-                        const float p3 = p2 * p1, m3 = m2 * m1;
-                        const float p4 = p2 * p2, m4 = m2 * m2;
-                        const float p7 = p4 * p3, m7 = m4 * m3;
-                        const float p8 = p4 * p4, m8 = m4 * m4;
-                        float Pc = 0.0f, Pa = 0.0f, Pb = 0.0f, Pjk = 0.0f;
+                for (int q = 0; q < 8 * NETA; ++q)
+                    gq[q] = gl[Frad + pair * dp.n_ang + q] * block_scale(q);
+                for_each_triplet_in_range(bw, rec.D, dp.rc2, queue, [&](uint32_t ia, uint32_t ic, bool ok) {
+                    if (!ok)
+                        return;
+                    const float4 Ad = rec.D[ia], Cd = rec.D[ic], Ae = rec.E[ia], Ce = rec.E[ic];
+                    const float jx = Cd.x - Ad.x, jy = Cd.y - Ad.y, jz = Cd.z - Ad.z;
+                    const float r2jk = jx * jx + jy * jy + jz * jz;
+                    const float rjk = __builtin_amdgcn_sqrtf(r2jk);
+                    const float inv_rjk = __builtin_amdgcn_rcpf(rjk);
+                    float fcjk, dfcjk;
+                    cutoff_fn(rjk * inv_rc, dp.pi_over_rc, fcjk, dfcjk);
+                    const float cs = (Ad.x * Cd.x + Ad.y * Cd.y + Ad.z * Cd.z) * (Ad.w * Cd.w);
+                    const float p1 = 1.0f + cs, m1 = 1.0f - cs;
+                    const float p2 = p1 * p1, m2 = m1 * m1;
+                    const float p3 = p2 * p1, m3 = m2 * m1;
+                    const float p4 = p2 * p2, m4 = m2 * m2;
+                    const float p7 = p4 * p3, m7 = m4 * m3;
+                    const float p8 = p4 * p4, m8 = m4 * m4;
+                    float Pc = 0.0f, Pa = 0.0f, Pb = 0.0f, Pjk = 0.0f;
 #pragma unroll
-                        for (int ie = 0; ie < NETA; ++ie) {
-                            const float *g = gq + ie * 8;
-                            const float S = g[0] * p1 + g[1] * m1 + g[2] * p2 + g[3] * m2 + g[4] * p4 + g[5] * m4 +
-                                            g[6] * p8 + g[7] * m8;
-                            const float Sd = (g[0] - g[1]) + 2.0f * (g[2] * p1 - g[3] * m1) +
-                                             4.0f * (g[4] * p3 - g[5] * m3) + 8.0f * (g[6] * p7 - g[7] * m7);
-                            const float eta = dp.ang_eta[ie];
-                            const float X = expf(-eta * r2jk);
-                            const float Ea = ie == 0 ? A.e.y : A.e.z, Eb = ie == 0 ? C.e.y : C.e.z;
-                            const float dEa = ie == 0 ? dA.x : dA.y, dEb = ie == 0 ? dC.x : dC.y;
-                            const float Xf = X * fcjk;
-                            const float EaEb = Ea * Eb;
-                            Pc += Sd * EaEb * Xf;
-                            Pa += S * dEa * Eb * Xf;
-                            Pb += S * Ea * dEb * Xf;
-                            Pjk += S * EaEb * X * (-2.0f * eta * rjk * fcjk + dfcjk);
-                        }
-                        const float ia = A.e.w, ib = C.e.w;
-                        const float alpha_a = (Pa - Pc * cs * ia) * ia;
-                        const float alpha_b = (Pb - Pc * cs * ib) * ib;
-                        const float beta = Pc * ia * ib;
-                        const float gam = Pjk * inv_rjk;
-                        vx += alpha_a * A.d.x + beta * C.d.x - gam * jx;
-                        vy += alpha_a * A.d.y + beta * C.d.y - gam * jy;
-                        vz += alpha_a * A.d.z + beta * C.d.z - gam * jz;
-                        // partner slots differ across lanes for triangles; for rectangles at most
-                        // ceil(n_own / n_par) lanes share one
-                        atomicAdd(&vacc[ic].x, alpha_b * C.d.x + beta * A.d.x + gam * jx);
-                        atomicAdd(&vacc[ic].y, alpha_b * C.d.y + beta * A.d.y + gam * jy);
-                        atomicAdd(&vacc[ic].z, alpha_b * C.d.z + beta * A.d.z + gam * jz);
+                    for (int ie = 0; ie < NETA; ++ie) {
+                        const float *g = gq + ie * 8;
+                        const float S = g[0] * p1 + g[1] * m1 + g[2] * p2 + g[3] * m2 + g[4] * p4 + g[5] * m4 +
+                                        g[6] * p8 + g[7] * m8;
+                        const float Sd = (g[0] - g[1]) + 2.0f * (g[2] * p1 - g[3] * m1) +
+                                         4.0f * (g[4] * p3 - g[5] * m3) + 8.0f * (g[6] * p7 - g[7] * m7);
+                        const float eta = dp.ang_eta[ie];
+                        const float X = exp_small(ie == 0 ? nel0 : nel1, r2jk);
+                        const float Ea = ie == 0 ? Ae.x : Ae.y, Eb = ie == 0 ? Ce.x : Ce.y;
+                        const float dEa = ie == 0 ? Ae.z : Ae.w, dEb = ie == 0 ? Ce.z : Ce.w;
+                        const float Xf = X * fcjk;
+                        const float EaEb = Ea * Eb;
+                        Pc += Sd * EaEb * Xf;
+                        Pa += S * dEa * Eb * Xf;
+                        Pb += S * Ea * dEb * Xf;
+                        Pjk += S * EaEb * X * (-2.0f * eta * rjk * fcjk + dfcjk);
                     }
-                    if (own_ok) {
-                        atomicAdd(&vacc[ia_slot].x, vx);
-                        atomicAdd(&vacc[ia_slot].y, vy);
-                        atomicAdd(&vacc[ia_slot].z, vz);
-                    }
-                }
+                    const float ia_ = Ad.w, ib_ = Cd.w;
+                    const float alpha_a = (Pa - Pc * cs * ia_) * ia_;
+                    const float alpha_b = (Pb - Pc * cs * ib_) * ib_;
+                    const float beta = Pc * ia_ * ib_;
+                    const float gam = Pjk * inv_rjk;
+                    atomicAdd(&vx[ia], (double)(alpha_a * Ad.x + beta * Cd.x - gam * jx));
+                    atomicAdd(&vy[ia], (double)(alpha_a * Ad.y + beta * Cd.y - gam * jy));
+                    atomicAdd(&vz[ia], (double)(alpha_a * Ad.z + beta * Cd.z - gam * jz));
+                    atomicAdd(&vx[ic], (double)(alpha_b * Cd.x + beta * Ad.x + gam * jx));
+                    atomicAdd(&vy[ic], (double)(alpha_b * Cd.y + beta * Ad.y + gam * jy));
+                    atomicAdd(&vz[ic], (double)(alpha_b * Cd.z + beta * Ad.z + gam * jz));
+                });
             }
         wave_sync();
         float W[9];
@@ -410,10 +470,10 @@ __global__ __launch_bounds__(256) void k_adjoint(const float4 *__restrict__ posu
             W[q] = 0.0f;
         float4 *out = vslot + (int64_t)i * dp.Kmax;
         for (int n = lane; n < K; n += kWave) {
-            const float4 v = vacc[n];
+            const float4 v = make_float4((float)vx[n], (float)vy[n], (float)vz[n], 0.0f);
             out[n] = v;
-            const float4 d = rec[n].d;
-            const float dd[3] = {d.x, d.y, d.z}, vv[3] = {v.x, v.y, v.z};
+            const float4 dn = rec.D[n];
+            const float dd[3] = {dn.x, dn.y, dn.z}, vv[3] = {v.x, v.y, v.z};
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -542,17 +602,19 @@ __global__ __launch_bounds__(256) void k_work_counts(const float4 *__restrict__ 
 {
     extern __shared__ float4 lds4[];
     const int lane = lane_id(), w = threadIdx.x >> 6;
-    StagedA *rec = reinterpret_cast<StagedA *>(lds4 + w * 2 * dp.Kmax);
+    float4 *base = lds4 + w * 3 * dp.Kmax;
+    const Recs rec{base, base + dp.Kmax, base + 2 * dp.Kmax};
     unsigned long long pairs = 0, trip = 0, trip_in = 0;
     for (int i = blockIdx.x * 4 + w; i < B; i += gridDim.x * 4) {
         const BeadInfo bi = beads[bead_of_ba[i]];
-        const int K = stage_neighbors<1, false>(i, posu[i], bi, nbr, nbr_cnt, posu, dp, rec, nullptr);
+        const int K = stage_neighbors<1, false>(i, posu[i], bi, nbr, nbr_cnt, posu, dp, rec);
         wave_sync();
         const int np = K * (K - 1) / 2;
         for (int t = lane; t < np; t += kWave) {
             int a, b;
-            decode_pair(t, true, 0, 0.0f, a, b);
-            const float jx = rec[b].d.x - rec[a].d.x, jy = rec[b].d.y - rec[a].d.y, jz = rec[b].d.z - rec[a].d.z;
+            decode_triangle(t, a, b);
+            const float4 Da = rec.D[a], Db = rec.D[b];
+            const float jx = Db.x - Da.x, jy = Db.y - Da.y, jz = Db.z - Da.z;
             trip_in += (jx * jx + jy * jy + jz * jz) < dp.rc2 ? 1 : 0;
         }
         if (lane == 0) {
@@ -566,17 +628,20 @@ __global__ __launch_bounds__(256) void k_work_counts(const float4 *__restrict__ 
     atomicAdd(&counts[2], trip_in);
 }
 
+// LDS per workgroup (4 waves), in float4 units per slot: records (2), pair
+// terms (1), the adjoint's FP64 slot accumulators (2); plus the feature row
+// and the pair queue.
 static size_t desc_lds(const DescParams &dp, int records)
 {
     const int Dcap = (dp.D + 3) & ~3;
-    return (size_t)4 * (records * dp.Kmax + Dcap / 4) * sizeof(float4);
+    return (size_t)4 * (records * dp.Kmax + Dcap / 4 + kQueue / 4) * sizeof(float4);
 }
 
-size_t descriptor_lds_bytes(const DescParams &dp, bool adjoint) { return desc_lds(dp, adjoint ? 4 : 2); }
+size_t descriptor_lds_bytes(const DescParams &dp, bool adjoint) { return desc_lds(dp, adjoint ? 5 : 3); }
 
 hipError_t configure_descriptor_lds(const DescParams &dp)
 {
-    const int f = (int)desc_lds(dp, 2), a = (int)desc_lds(dp, 4);
+    const int f = (int)desc_lds(dp, 3), a = (int)desc_lds(dp, 5);
     hipError_t e = hipSuccess;
     if (dp.n_ang_eta == 2) {
         e = hipFuncSetAttribute((const void *)k_descriptors<2>, hipFuncAttributeMaxDynamicSharedMemorySize, f);
@@ -593,7 +658,7 @@ hipError_t configure_descriptor_lds(const DescParams &dp)
 void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &dp, hipStream_t s)
 {
     const int grid = (z.B + 3) / 4;
-    const size_t lds = desc_lds(dp, 2);
+    const size_t lds = desc_lds(dp, 3);
     if (dp.n_ang_eta == 2)
         hipLaunchKernelGGL(k_descriptors<2>, dim3(grid), dim3(256), lds, s, d.posu4, d.beads, d.bead_of_ba, d.nbr,
                            d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, z.B);
@@ -605,7 +670,7 @@ void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &d
 void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, hipStream_t s)
 {
     const int grid = (z.B + 3) / 4;
-    const size_t lds = desc_lds(dp, 4);
+    const size_t lds = desc_lds(dp, 5);
     if (dp.n_ang_eta == 2)
         hipLaunchKernelGGL(k_adjoint<2>, dim3(grid), dim3(256), lds, s, d.posu4, d.beads, d.bead_of_ba, d.nbr,
                            d.nbr_cnt, d.nbr_grp, d.dEdG, dp, d.vslot, d.vir_atom, z.B);
@@ -618,7 +683,7 @@ void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &d
                         hipStream_t s)
 {
     const int grid = (z.B + 3) / 4 < 4096 ? (z.B + 3) / 4 : 4096;
-    hipLaunchKernelGGL(k_work_counts, dim3(grid), dim3(256), (size_t)4 * 2 * dp.Kmax * sizeof(float4), s, d.posu4,
+    hipLaunchKernelGGL(k_work_counts, dim3(grid), dim3(256), (size_t)4 * 3 * dp.Kmax * sizeof(float4), s, d.posu4,
                        d.beads, d.bead_of_ba, d.nbr, d.nbr_cnt, dp, counts, z.B);
 }
 

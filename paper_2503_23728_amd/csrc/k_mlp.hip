@@ -229,7 +229,9 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
 
 // FP64 variant (precision mode 3): the same chain with FP64 operands,
 // activations and accumulation on v_mfma_f64_16x16x4f64, so the MLP adds no
-// error visible next to the FP32 descriptors.
+// error visible next to the FP32 descriptors.  Its A and B operand layouts
+// match the FP32 16x16x4 instruction; its output rows interleave by four
+// (element q of lane (g, l) is row 4q + g, column l).
 __device__ __forceinline__ void gemm16_cols_f64(const double *act, int K, const double *Bt, int ldb, int nct, int w,
                                                 f64x4 (&acc)[2])
 {
@@ -260,6 +262,8 @@ __global__ __launch_bounds__(256) void k_mlp_f64(const int32_t *__restrict__ row
     __shared__ double epart[4][16];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int lr = lane & 15, lg = lane >> 4;
+    // v_mfma_f64_16x16x4f64 returns element q of lane (lg, lr) as C[4 q + lg][lr]
+    auto crow = [lg](int q) { return 4 * q + lg; };
     const MlpTile tile = tiles[blockIdx.x];
     const MlpNet &net = nets.net[tile.e];
     const int32_t *trows = rows + tile.row0;
@@ -290,7 +294,7 @@ __global__ __launch_bounds__(256) void k_mlp_f64(const int32_t *__restrict__ row
                         const double e = exp(-2.0 * fabs(z));
                         const double ope = 1.0 + e;
                         dsave[l][t][q] = 4.0 * e / (ope * ope);
-                        act[(lg * 4 + q) * S + col] = copysign((1.0 - e) / ope, z);
+                        act[crow(q) * S + col] = copysign((1.0 - e) / ope, z);
                     }
                 }
             }
@@ -308,7 +312,7 @@ __global__ __launch_bounds__(256) void k_mlp_f64(const int32_t *__restrict__ row
             const double wo = (double)net.wo[col];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                e_part[q] += act[(lg * 4 + q) * S + col] * wo;
+                e_part[q] += act[crow(q) * S + col] * wo;
         }
     }
 #pragma unroll
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(256) void k_mlp_f64(const int32_t *__restrict__ row
     if (lr == 0)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            epart[w][lg * 4 + q] = e_part[q];
+            epart[w][crow(q)] = e_part[q];
     __syncthreads();
     if (threadIdx.x < 16 && (int)threadIdx.x < nrows)
         E_atom[trows[threadIdx.x]] = (float)(((epart[0][threadIdx.x] + epart[1][threadIdx.x]) +
@@ -336,7 +340,7 @@ __global__ __launch_bounds__(256) void k_mlp_f64(const int32_t *__restrict__ row
                     const double wo = (double)net.wo[col];
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        act[(lg * 4 + q) * S + col] = wo * dsave[l][t][q];
+                        act[crow(q) * S + col] = wo * dsave[l][t][q];
                 }
             }
         }
@@ -355,7 +359,7 @@ __global__ __launch_bounds__(256) void k_mlp_f64(const int32_t *__restrict__ row
                     const int col = ct * 16 + lr;
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        act[(lg * 4 + q) * S + col] = acc[t][q] * dsave[l - 1][t][q];
+                        act[crow(q) * S + col] = acc[t][q] * dsave[l - 1][t][q];
                 }
             }
             __syncthreads();
@@ -372,7 +376,7 @@ __global__ __launch_bounds__(256) void k_mlp_f64(const int32_t *__restrict__ row
                 const double is = (double)net.inv_scale[col];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int r = lg * 4 + q;
+                    const int r = crow(q);
                     if (r < nrows)
                         dEdG[(int64_t)trows[r] * D + col] = (float)(acc[t][q] * is);
                 }
