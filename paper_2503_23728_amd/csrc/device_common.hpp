@@ -38,6 +38,33 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
+// Transposed reduction of N per-lane values (N a power of two, 2..64): each
+// butterfly step exchanges half of the remaining values with the partner
+// lane, so the total shuffle count is N - 1 + log2(64/N) instead of 6N.
+// Afterwards lane l holds the wave total of value (l / (64/N)) and every lane
+// of the same group of 64/N lanes holds the same total.  Fixed order: bitwise
+// reproducible.
+template <int N>
+__device__ __forceinline__ float transpose_reduce(float (&v)[N])
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int half = N / 2, d = 32; half >= 1; half /= 2, d /= 2) {
+        const bool hi = (lane & d) != 0;
+#pragma unroll
+        for (int j = 0; j < half; ++j) {
+            const float keep = hi ? v[j + half] : v[j];
+            const float send = hi ? v[j] : v[j + half];
+            v[j] = keep + __shfl_xor(send, d, kWave);
+        }
+    }
+    float t = v[0];
+#pragma unroll
+    for (int d = 32 / N; d >= 1; d /= 2)
+        t += __shfl_xor(t, d, kWave);
+    return t;
+}
+
 // Sum over the 16 lanes that share lane / 16.
 __device__ __forceinline__ float row16_sum(float v)
 {

@@ -25,7 +25,7 @@ namespace pimd {
 // slot index spread over the LDS banks:
 //   recD[n] = d_ij (x, y, z), 1/r_ij
 //   recE[n] = E_0, E_1 (E_eta = exp(-eta r^2) f_c(r)), dE_0/dr, dE_1/dr
-//   rr[n]   = r, f_c, f_c', 0   (pair terms)
+//   rr[n]   = r, f_c, f_c', r_lo   (pair terms; r + r_lo is r to ~FP64 accuracy)
 struct Recs {
     float4 *D;
     float4 *E;
@@ -38,7 +38,7 @@ struct Recs {
 // itself comes from the float32 test of the neighbour kernel; for |d| < rc <
 // L/2 the minimum image is unique, so both choose the same image.
 __device__ __forceinline__ void displacement(const float4 &pi, const float4 &pj, const BeadInfo &bi, float3 &d,
-                                             float &r, float &inv_r)
+                                             float &r, float &r_lo, float &inv_r)
 {
     double dx = (double)pj.x - (double)pi.x, dy = (double)pj.y - (double)pi.y, dz = (double)pj.z - (double)pi.z;
     if (bi.periodic) {
@@ -49,6 +49,7 @@ __device__ __forceinline__ void displacement(const float4 &pi, const float4 &pj,
     const double r64 = sqrt(dx * dx + dy * dy + dz * dz);
     d = make_float3((float)dx, (float)dy, (float)dz);
     r = (float)r64;
+    r_lo = (float)(r64 - (double)r);
     inv_r = (float)(1.0 / r64);
 }
 
@@ -95,8 +96,8 @@ __device__ __forceinline__ int stage_neighbors(int i, const float4 &pi, const Be
     for (int n = lane; n < K; n += kWave) {
         const int j = row[n] & (int)kRowMask;
         float3 d;
-        float r, inv_r;
-        displacement(pi, posu[j], bi, d, r, inv_r);
+        float r, r_lo, inv_r;
+        displacement(pi, posu[j], bi, d, r, r_lo, inv_r);
         const float r2 = r * r;
         float fc, dfc;
         cutoff_fn(r * (1.0f / dp.rc), dp.pi_over_rc, fc, dfc);
@@ -106,7 +107,7 @@ __device__ __forceinline__ int stage_neighbors(int i, const float4 &pi, const Be
         // dE_eta/dr = exp(-eta r^2) (-2 eta r f_c + f_c')
         rec.E[n] = make_float4(g0 * fc, g1 * fc, ADJ ? g0 * (-2.0f * dp.ang_eta[0] * r * fc + dfc) : 0.0f,
                                (ADJ && NETA > 1) ? g1 * (-2.0f * dp.ang_eta[1] * r * fc + dfc) : 0.0f);
-        rec.rr[n] = make_float4(r, fc, dfc, 0.0f);
+        rec.rr[n] = make_float4(r, fc, dfc, r_lo);
     }
     return K;
 }
@@ -280,10 +281,13 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
                 const int lo = goff[e], hi = goff[e] + gcnt[e];
                 const int mid = (lo + hi) >> 1;
                 const int a0 = (lane < 32) ? lo : mid, a1 = (lane < 32) ? mid : hi;
-                const float Rs = dp.rad_center[s], eta = dp.rad_eta[s];
+                const float Rs = dp.rad_center[s], Rs_lo = dp.rad_center_lo[s], eta = dp.rad_eta[s];
                 for (int n = a0; n < a1; ++n) {
                     const float4 q = rr[n];
-                    const float x = q.x - Rs;
+                    // r - R_s from the two-float r and R_s: the steep Gaussians
+                    // (eta up to ~5/A^2) would turn the float rounding of r into
+                    // 1e-6 relative errors
+                    const float x = (q.x - Rs) + (q.w - Rs_lo);
                     acc += expf(-eta * x * x) * q.y;
                 }
             }
@@ -329,15 +333,13 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
                         acc[ie * 8 + 7] += m8 * R;
                     }
                 });
-                float mine = 0.0f;
-#pragma unroll
-                for (int q = 0; q < 8 * NETA; ++q) {
-                    const float v = wave_sum(acc[q]);
-                    if (lane == q)
-                        mine = v;
+                // lane l ends with the total of feature l / (64 / (8 NETA))
+                const float tot = transpose_reduce<8 * NETA>(acc);
+                constexpr int group = 64 / (8 * NETA);
+                if ((lane & (group - 1)) == 0) {
+                    const int q = lane / group;
+                    Gs[Frad + pair * dp.n_ang + q] = tot * block_scale(q);
                 }
-                if (lane < 8 * NETA)
-                    Gs[Frad + pair * dp.n_ang + lane] = mine * block_scale(lane);
             }
         wave_sync();
         const float *shift = norm + (int64_t)zi * 2 * dp.D;
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const float4 *__restrict__ posu
             const float r = q.x, fc = q.y, dfc = q.z;
             float acc = 0.0f;
             for (int t = 0; t < dp.n_rad; ++t) {
-                const float x = r - dp.rad_center[t];
+                const float x = (r - dp.rad_center[t]) + (q.w - dp.rad_center_lo[t]);
                 const float eta = dp.rad_eta[t];
                 acc += gl[e * dp.n_rad + t] * expf(-eta * x * x) * (-2.0f * eta * x * fc + dfc);
             }
@@ -464,9 +466,9 @@ __global__ __launch_bounds__(256) void k_adjoint(const float4 *__restrict__ posu
                 });
             }
         wave_sync();
-        float W[9];
+        float W[16];
 #pragma unroll
-        for (int q = 0; q < 9; ++q)
+        for (int q = 0; q < 16; ++q)
             W[q] = 0.0f;
         float4 *out = vslot + (int64_t)i * dp.Kmax;
         for (int n = lane; n < K; n += kWave) {
@@ -480,15 +482,10 @@ __global__ __launch_bounds__(256) void k_adjoint(const float4 *__restrict__ posu
                 for (int b = 0; b < 3; ++b)
                     W[a * 3 + b] -= dd[a] * vv[b];
         }
-        float mine = 0.0f;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const float v = wave_sum(W[q]);
-            if (lane == q)
-                mine = v;
-        }
-        if (lane < 9)
-            vir_atom[(int64_t)i * 9 + lane] = mine;
+        // components 9..15 are padding; lane 4q holds the total of component q
+        const float tot = transpose_reduce<16>(W);
+        if ((lane & 3) == 0 && (lane >> 2) < 9)
+            vir_atom[(int64_t)i * 9 + (lane >> 2)] = tot;
         wave_sync();
     }
 }

@@ -155,19 +155,23 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
         a.dke_part[2 * blockIdx.x + (PRE ? 0 : 1)] = tot;
 }
 
-// heat_bath[s] -= (sum of O-step kinetic-energy changes of the step); step += 1
-__global__ void k_finish_step(const SysInfo *__restrict__ sys, const double *__restrict__ dke_part,
-                              double *__restrict__ heat, int64_t *__restrict__ step, int n_sys)
+// heat_bath[s] -= (sum of O-step kinetic-energy changes of the step); step += 1.
+// One workgroup per system; fixed-order tree sum in FP64.
+__global__ __launch_bounds__(256) void k_finish_step(const SysInfo *__restrict__ sys,
+                                                     const double *__restrict__ dke_part, double *__restrict__ heat,
+                                                     int64_t *__restrict__ step)
 {
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n_sys; s += gridDim.x * blockDim.x) {
-        const SysInfo S = sys[s];
-        double d = 0.0;
-        for (int u = S.unit0; u < S.unit0 + S.nunit; ++u)
-            d += dke_part[2 * u] + dke_part[2 * u + 1];
-        heat[s] -= d;
+    __shared__ double red[256];
+    const SysInfo S = sys[blockIdx.x];
+    double d = 0.0;
+    for (int u = S.unit0 + threadIdx.x; u < S.unit0 + S.nunit; u += 256)
+        d += dke_part[2 * u] + dke_part[2 * u + 1];
+    const double tot = block_sum_double(d, red);
+    if (threadIdx.x == 0) {
+        heat[blockIdx.x] -= tot;
+        if (blockIdx.x == 0)
+            step[0] += 1;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        step[0] += 1;
 }
 
 // Estimator terms per column (atom, xyz) of every system:
@@ -306,8 +310,7 @@ void launch_integrate_post(const DevBuffers &d, const Sizes &z, float dt, uint32
 
 void launch_finish_step(const DevBuffers &d, const Sizes &z, hipStream_t s)
 {
-    const int grid = (z.n_sys + 255) / 256;
-    hipLaunchKernelGGL(k_finish_step, dim3(grid), dim3(256), 0, s, d.sys, d.dke_part, d.heat, d.step, z.n_sys);
+    hipLaunchKernelGGL(k_finish_step, dim3(z.n_sys), dim3(256), 0, s, d.sys, d.dke_part, d.heat, d.step);
 }
 
 void launch_estimator_terms(const DevBuffers &d, const Sizes &z, hipStream_t s)

@@ -636,6 +636,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         dp.half_over_rc = (float)(0.5 / m->cutoff_A);
         for (int s = 0; s < m->n_rad; ++s) {
             dp.rad_center[s] = (float)m->rad_center_A[s];
+            dp.rad_center_lo[s] = (float)(m->rad_center_A[s] - (double)dp.rad_center[s]);
             dp.rad_eta[s] = (float)m->rad_eta[s];
         }
         for (int s = 0; s < m->n_ang_eta; ++s)

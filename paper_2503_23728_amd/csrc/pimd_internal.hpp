@@ -44,7 +44,8 @@ struct BeadInfo {
 struct DescParams {
     int32_t n_el, n_rad, n_ang_eta, n_ang, D, Kmax;
     float rc, rc2, pi_over_rc, half_over_rc;  // half_over_rc = 1/(2 rc): cos(pi r/rc) = cos(2 pi (r half_over_rc))
-    float rad_center[kMaxRad];
+    float rad_center[kMaxRad];     // R_s rounded to float ...
+    float rad_center_lo[kMaxRad];  // ... and the remainder R_s - float(R_s)
     float rad_eta[kMaxRad];
     float ang_eta[2];
 };
