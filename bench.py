@@ -26,7 +26,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
+BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X published dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
+
+
+def measured_traffic(workload):
+    """HBM bytes per k_adjoint launch from the committed rocprofv3 counters, when
+    they were taken on this workload and the kernel source has not changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if rec.get("workload") != workload or hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec["hbm_read_bytes"] + rec["hbm_write_bytes"]
+
+
+def mlp_flops_per_row(D, hidden):
+    """Multiply-adds of one row: forward through the hidden layers and the
+    readout, then the input gradient back through every layer (x2 FLOPs)."""
+    sizes = [D] + list(hidden)
+    fwd = sum(a * b for a, b in zip(sizes[:-1], sizes[1:])) + sizes[-1]
+    bwd = sum(a * b for a, b in zip(sizes[:-1], sizes[1:]))
+    return 2 * (fwd + bwd)
 
 
 def flops_model(n_rad, n_eta, pairs, triplets, triplets_in):
@@ -144,6 +169,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-FP32 comparison path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-reps", type=int, default=10)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape (no autotuner)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
@@ -160,6 +186,13 @@ def main():
     eng = Pimd.from_workload(wl, precision=args.precision, device=device)
     q, p = S.initial_state(wl)
     eng.set_state(torch.from_numpy(q).to(device), torch.from_numpy(p).to(device))
+    if args.no_tune:
+        shape, cached = eng.get_tuning(), None
+    else:
+        t0 = time.perf_counter()
+        shape, cached = eng.autotune(n_reps=3)
+        print(f"[bench] launch shape {shape} ({'cached' if cached else 'autotuned'} in "
+              f"{time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     print(f"[bench] {wl.name}: {B} bead-atoms, {len(wl.systems)} systems; warmup {args.warmup}", file=sys.stderr,
           flush=True)
     wall, gpu_s = time_steps(eng, args.steps, args.warmup)
@@ -168,22 +201,33 @@ def main():
     ns_day = args.steps * wl.dt * 1e-6 / wall * 86400.0
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
 
-    # per-stage timing with HIP events on the launch stream (kernels one by one)
+    # per-stage timing with HIP events on the launch stream (kernels one by one,
+    # one integrator step per repetition) and gap-free kernel timing (each force
+    # stage enqueued back to back on the current positions)
     stages = eng.profile_stages(args.profile_reps)
+    kern = eng.time_stages(max(args.profile_reps, 5))
     pairs, trip, trip_in = eng.work_counts()
     m = wl.model
     fwd_flops, adj_flops = flops_model(m.n_rad, len(m.ang_eta), pairs, trip, trip_in)
-    adj_ms = stages["adjoint"]
+    adj_ms = kern["adjoint"]
     achieved = adj_flops / (adj_ms * 1e-3) / 1e12
+    traffic = measured_traffic(wl.name)
+    mlp_flops = B * mlp_flops_per_row(eng.D, m.hidden)
     roofline = {"kernel": "k_adjoint (descriptor adjoint with recomputation)", "bound": "alu",
                 "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,
                 "flops_per_launch": adj_flops, "launch_ms": round(adj_ms, 4),
                 "forward": {"kernel": "k_descriptors", "flops_per_launch": fwd_flops,
-                            "launch_ms": round(stages["descriptors"], 4),
-                            "achieved": round(fwd_flops / (stages["descriptors"] * 1e-3) / 1e12, 3)},
+                            "launch_ms": round(kern["descriptors"], 4),
+                            "achieved": round(fwd_flops / (kern["descriptors"] * 1e-3) / 1e12, 3)},
+                "mlp": {"kernel": "k_mlp", "bound": "mfma", "flops_per_launch": mlp_flops,
+                        "launch_ms": round(kern["mlp"], 4),
+                        "achieved": round(mlp_flops / (kern["mlp"] * 1e-3) / 1e12, 3),
+                        "peak": BF16_MFMA_PEAK_TFLOPS,
+                        "frac": round(mlp_flops / (kern["mlp"] * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4)},
                 "work": {"pairs": pairs, "triplets": trip, "triplets_in_range": trip_in}}
     print(f"[bench] stages {json.dumps({k: round(v, 4) for k, v in stages.items()})}", file=sys.stderr, flush=True)
+    print(f"[bench] kernels {json.dumps({k: round(v, 4) for k, v in kern.items()})}", file=sys.stderr, flush=True)
 
     out = {
         "metric": "bead·atom force evals/s + PIMD ns/day vs plain FP32, at force err vs FP64",
@@ -195,9 +239,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "systems": len(wl.systems), "bead_atoms": B,
                    "beads": sum(s.n_beads for s in wl.systems), "dt_fs": wl.dt, "precision": args.precision,
-                   "launch": "hip graph per step"},
+                   "launch": "hip graph per step", "launch_shape": shape,
+                   "shape_source": {None: "default", True: "tuning cache", False: "autotuner"}[cached]},
         "ns_per_day": ns_day, "gpu_event_s": gpu_s,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
         "roofline": roofline,
     }
     if not args.no_plain:

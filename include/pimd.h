@@ -221,6 +221,46 @@ pimd_status pimd_debug_philox(pimd_ctx *ctx, int64_t step, int32_t half, int64_t
  * captured HIP graph; 0 enqueues every kernel of every step one by one. */
 pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled);
 
+/* Launch shapes of the force kernels.  Many ring polymers and beads run as
+ * one flat batch (the concurrent-trajectory parallelism of Sec. 2.3 and the
+ * multi-trajectory point of Sec. 4); these fields only change how that batch
+ * is cut into workgroups, never the results: each centre atom is one wave and
+ * each MLP row runs the same MFMA chain whatever the shape.
+ *   centre_waves  waves (one centre atom each) per workgroup of the neighbour,
+ *                 descriptor, adjoint and force-assembly kernels: 1, 2 or 4
+ *                 (default 4)
+ *   centre_grid   0 (default): one wave per centre atom; > 0: at most this
+ *                 many workgroups, whose waves stride over the centres
+ *   mlp_rows      rows per MLP workgroup tile: 16 (default), 32 or 64;
+ *                 PIMD_PREC_FP64_MLP takes 16 only
+ *   reserved      must be 0 */
+typedef struct {
+    int32_t centre_waves;
+    int32_t centre_grid;
+    int32_t mlp_rows;
+    int32_t reserved;
+} pimd_tuning;
+
+pimd_status pimd_get_tuning(const pimd_ctx *ctx, pimd_tuning *out);
+
+/* Applies a launch shape (PIMD_E_ARG for a value outside the lists above,
+ * PIMD_E_UNSUPPORTED for mlp_rows != 16 in FP64-MLP mode) and drops the
+ * captured step graph, which the next pimd_step captures again.
+ * Synchronises. */
+pimd_status pimd_set_tuning(pimd_ctx *ctx, const pimd_tuning *t);
+
+/* Autotuner: times the force evaluation of the current positions (n_reps
+ * evaluations per candidate after one untimed one, HIP events on the context
+ * stream) for every centre_waves x centre_grid candidate (centre_grid from 0
+ * and 2, 4, 8, 16 workgroups per compute unit), then for every mlp_rows
+ * candidate with the best centre shape; applies the fastest (a candidate
+ * replaces the current best only when at least 1% faster) and writes it to
+ * best (may be NULL).  The state does not advance; the forces left behind are
+ * those of the current positions.  Needs pimd_set_state first
+ * (PIMD_E_STATE); with the harmonic potential there is nothing to tune and
+ * the current shape is returned.  Synchronises. */
+pimd_status pimd_autotune(pimd_ctx *ctx, int32_t n_reps, pimd_tuning *best);
+
 /* Stage timing: runs n_reps integrator steps with the kernels enqueued one
  * by one, records HIP events between the stages on the context stream and
  * writes the mean milliseconds per step of each stage to
@@ -230,6 +270,18 @@ pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled);
  * bookkeeping.  Advances the state by n_reps steps.  Synchronises. */
 #define PIMD_N_STAGES 7
 pimd_status pimd_profile_stages(pimd_ctx *ctx, int32_t n_reps, double *ms_host);
+
+/* Kernel timing without launch gaps (neural potential only): for each force
+ * stage in the order neighbour search (wrap, cells, lists), descriptors,
+ * MLP, adjoint, force assembly with bead sums, enqueues the stage n_reps
+ * times back to back between two HIP events on the context stream and writes
+ * the mean milliseconds of one run to ms_host[PIMD_N_FORCE_STAGES].  Each
+ * stage rereads what the stage before it wrote for the current positions,
+ * so the state does not advance and the forces left behind are those of the
+ * current positions.  PIMD_E_STATE before pimd_set_state or with the
+ * harmonic potential.  Synchronises. */
+#define PIMD_N_FORCE_STAGES 5
+pimd_status pimd_time_stages(pimd_ctx *ctx, int32_t n_reps, double *ms_host);
 
 /* Work of the last force evaluation (BPNN): neighbour pairs (i, j), j<k
  * neighbour pairs of every centre (triplets) and the triplets with

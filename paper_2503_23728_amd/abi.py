@@ -35,6 +35,10 @@ class pimd_config(ctypes.Structure):
                 ("harmonic_omega_per_fs", c_double), ("max_neighbors", c_int32)]
 
 
+class pimd_tuning(ctypes.Structure):
+    _fields_ = [("centre_waves", c_int32), ("centre_grid", c_int32), ("mlp_rows", c_int32), ("reserved", c_int32)]
+
+
 class pimd_estimates(ctypes.Structure):
     _fields_ = [(n, c_double) for n in ("V_bar", "K_prim", "K_cv", "E_spring", "K_beads", "T_beads",
                                         "H_conserved", "heat_bath")]
@@ -55,7 +59,11 @@ _SIGNATURES = {
     "pimd_debug_copy": (c_int32, [c_void_p, c_int32, c_void_p, c_size_t]),
     "pimd_debug_philox": (c_int32, [c_void_p, c_int64, c_int32, c_int64, c_void_p]),
     "pimd_set_graph": (c_int32, [c_void_p, c_int32]),
+    "pimd_get_tuning": (c_int32, [c_void_p, POINTER(pimd_tuning)]),
+    "pimd_set_tuning": (c_int32, [c_void_p, POINTER(pimd_tuning)]),
+    "pimd_autotune": (c_int32, [c_void_p, c_int32, POINTER(pimd_tuning)]),
     "pimd_profile_stages": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
+    "pimd_time_stages": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "pimd_work_counts": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
     "pimd_sizes": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32)]),
     "pimd_last_error": (ctypes.c_char_p, [c_void_p]),
@@ -172,9 +180,35 @@ def pimd_set_graph(ctx, enabled):
     return lib().pimd_set_graph(c_void_p(ctx), 1 if enabled else 0)
 
 
+def pimd_get_tuning(ctx):
+    t = pimd_tuning()
+    st = lib().pimd_get_tuning(c_void_p(ctx), ctypes.byref(t))
+    return st, t
+
+
+def pimd_set_tuning(ctx, t):
+    return lib().pimd_set_tuning(c_void_p(ctx), ctypes.byref(t))
+
+
+def pimd_autotune(ctx, n_reps):
+    t = pimd_tuning()
+    st = lib().pimd_autotune(c_void_p(ctx), n_reps, ctypes.byref(t))
+    return st, t
+
+
 def pimd_profile_stages(ctx, n_reps):
     ms = (c_double * PIMD_N_STAGES)()
     st = lib().pimd_profile_stages(c_void_p(ctx), n_reps, ms)
+    return st, list(ms)
+
+
+PIMD_N_FORCE_STAGES = 5
+FORCE_STAGE_NAMES = ("neighbors", "descriptors", "mlp", "adjoint", "forces")
+
+
+def pimd_time_stages(ctx, n_reps):
+    ms = (c_double * PIMD_N_FORCE_STAGES)()
+    st = lib().pimd_time_stages(c_void_p(ctx), n_reps, ms)
     return st, list(ms)
 
 

@@ -50,11 +50,14 @@ __device__ __forceinline__ float transpose_reduce(float (&v)[N])
     const int lane = lane_id();
 #pragma unroll
     for (int half = N / 2, d = 32; half >= 1; half /= 2, d /= 2) {
-        const bool hi = (lane & d) != 0;
+        // bit select (not a ?: on two array elements, which the compiler may
+        // turn into a dynamically indexed access and move the array to scratch)
+        const uint32_t m = (lane & d) ? 0xFFFFFFFFu : 0u;
 #pragma unroll
         for (int j = 0; j < half; ++j) {
-            const float keep = hi ? v[j + half] : v[j];
-            const float send = hi ? v[j] : v[j + half];
+            const uint32_t a = __float_as_uint(v[j]), b = __float_as_uint(v[j + half]);
+            const float keep = __uint_as_float((a & ~m) | (b & m));
+            const float send = __uint_as_float((b & ~m) | (a & m));
             v[j] = keep + __shfl_xor(send, d, kWave);
         }
     }

@@ -83,18 +83,20 @@ __device__ __forceinline__ void cutoff_fn(float x, float pi_over_rc, float &fc, 
     dfc = -pi_over_rc * sn * cs;
 }
 
-// Stage the records of centre i (slot order = key order: grouped by element);
-// rr[n] = (r, f_c, f_c', 0) for the pair terms.  Returns K.
-template <int NETA, bool ADJ>
+// Stage the records of centre i (slot order = key order: grouped by element)
+// and hand each slot's pair terms to per_slot(n, element, d, r, r_lo, inv_r,
+// f_c, f_c') in the lane that computed them.  Returns K.
+template <int NETA, bool ADJ, typename PerSlot>
 __device__ __forceinline__ int stage_neighbors(int i, const float4 &pi, const BeadInfo &bi, const int32_t *nbr,
                                                const int32_t *nbr_cnt, const float4 *posu, const DescParams &dp,
-                                               const Recs &rec)
+                                               const Recs &rec, PerSlot &&per_slot)
 {
     const int lane = lane_id();
     const int K = nbr_cnt[i];
     const int32_t *row = nbr + (int64_t)i * dp.Kmax;
     for (int n = lane; n < K; n += kWave) {
-        const int j = row[n] & (int)kRowMask;
+        const int key = row[n];
+        const int j = key & (int)kRowMask;
         float3 d;
         float r, r_lo, inv_r;
         displacement(pi, posu[j], bi, d, r, r_lo, inv_r);
@@ -107,7 +109,7 @@ __device__ __forceinline__ int stage_neighbors(int i, const float4 &pi, const Be
         // dE_eta/dr = exp(-eta r^2) (-2 eta r f_c + f_c')
         rec.E[n] = make_float4(g0 * fc, g1 * fc, ADJ ? g0 * (-2.0f * dp.ang_eta[0] * r * fc + dfc) : 0.0f,
                                (ADJ && NETA > 1) ? g1 * (-2.0f * dp.ang_eta[1] * r * fc + dfc) : 0.0f);
-        rec.rr[n] = make_float4(r, fc, dfc, r_lo);
+        per_slot(n, key >> kKeyShift, d, r, r_lo, inv_r, fc, dfc);
     }
     return K;
 }
@@ -239,6 +241,17 @@ __device__ __forceinline__ float exp_small(float neg_eta_log2e, float x)
     return __builtin_amdgcn_exp2f(neg_eta_log2e * x);
 }
 
+// LDS per wave of the adjoint kernel: records D and E (16 B each per slot),
+// the FP64 slot accumulators (24 B per slot), the dE/dG row and the pair
+// queue, rounded up to 16 bytes.  The pair terms of the radial part never
+// leave registers.
+__host__ __device__ inline size_t adjoint_wave_bytes(const DescParams &dp)
+{
+    const int Dcap = (dp.D + 3) & ~3;
+    const size_t b = (size_t)56 * dp.Kmax + 4 * (size_t)Dcap + 4 * (size_t)kQueue;
+    return (b + 15) & ~(size_t)15;
+}
+
 // ---------------------------------------------------------------------------
 // forward: normalised descriptors xhat[i][D]
 // ---------------------------------------------------------------------------
@@ -253,7 +266,7 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
                                                      float *__restrict__ xhat, int B)
 {
     extern __shared__ float4 lds4[];
-    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int lane = lane_id(), w = threadIdx.x >> 6, wpg = blockDim.x >> 6;
     const int Dcap = (dp.D + 3) & ~3;
     float4 *base = lds4 + w * (3 * dp.Kmax + Dcap / 4 + kQueue / 4);
     const Recs rec{base, base + dp.Kmax, base + 2 * dp.Kmax};
@@ -264,11 +277,14 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
     const float nel0 = -dp.ang_eta[0] * 1.4426950408889634f, nel1 = -dp.ang_eta[1] * 1.4426950408889634f;
     const float inv_rc = 1.0f / dp.rc;
 
-    for (int i = blockIdx.x * 4 + w; i < B; i += gridDim.x * 4) {
+    for (int i = blockIdx.x * wpg + w; i < B; i += gridDim.x * wpg) {
         const BeadInfo bi = beads[bead_of_ba[i]];
         const float4 pi = posu[i];
         const int zi = __float_as_int(pi.w);
-        stage_neighbors<NETA, false>(i, pi, bi, nbr, nbr_cnt, posu, dp, rec);
+        stage_neighbors<NETA, false>(i, pi, bi, nbr, nbr_cnt, posu, dp, rec,
+                                     [&](int n, int, const float3 &, float r, float r_lo, float, float fc, float dfc) {
+                                         rec.rr[n] = make_float4(r, fc, dfc, r_lo);
+                                     });
         int gcnt[kMaxElements], goff[kMaxElements];
         group_offsets(nbr_grp, i, dp.n_el, gcnt, goff);
         wave_sync();
@@ -354,7 +370,7 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
 // adjoint: v[i][slot] = dE/d d_{i, slot}; per-atom virial -sum d (x) v
 // ---------------------------------------------------------------------------
 template <int NETA>
-__global__ __launch_bounds__(256) void k_adjoint(const float4 *__restrict__ posu, const BeadInfo *__restrict__ beads,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adjoint(const float4 *__restrict__ posu, const BeadInfo *__restrict__ beads,
                                                  const int32_t *__restrict__ bead_of_ba,
                                                  const int32_t *__restrict__ nbr,
                                                  const int32_t *__restrict__ nbr_cnt,
@@ -363,49 +379,45 @@ __global__ __launch_bounds__(256) void k_adjoint(const float4 *__restrict__ posu
                                                  float4 *__restrict__ vslot, float *__restrict__ vir_atom, int B)
 {
     extern __shared__ float4 lds4[];
-    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int lane = lane_id(), w = threadIdx.x >> 6, wpg = blockDim.x >> 6;
     const int Dcap = (dp.D + 3) & ~3;
-    float4 *base = lds4 + w * (5 * dp.Kmax + Dcap / 4 + kQueue / 4);
-    const Recs rec{base, base + dp.Kmax, base + 2 * dp.Kmax};
-    const float4 *rr = rec.rr;
+    char *base = reinterpret_cast<char *>(lds4) + w * adjoint_wave_bytes(dp);
+    const Recs rec{reinterpret_cast<float4 *>(base), reinterpret_cast<float4 *>(base) + dp.Kmax, nullptr};
     // slot accumulators: three FP64 arrays (one per component, so gathers by
     // slot spread over the banks); each slot sums ~K mixed-sign triplet terms
-    double *vx = reinterpret_cast<double *>(base + 3 * dp.Kmax);
+    double *vx = reinterpret_cast<double *>(base + 32 * dp.Kmax);
     double *vy = vx + dp.Kmax;
     double *vz = vy + dp.Kmax;
-    float *gl = reinterpret_cast<float *>(base + 5 * dp.Kmax);
-    uint32_t *queue = reinterpret_cast<uint32_t *>(base + 5 * dp.Kmax + Dcap / 4);
+    float *gl = reinterpret_cast<float *>(base + 56 * dp.Kmax);
+    uint32_t *queue = reinterpret_cast<uint32_t *>(gl + Dcap);
     const int Frad = dp.n_el * dp.n_rad;
     const float nel0 = -dp.ang_eta[0] * 1.4426950408889634f, nel1 = -dp.ang_eta[1] * 1.4426950408889634f;
     const float inv_rc = 1.0f / dp.rc;
 
-    for (int i = blockIdx.x * 4 + w; i < B; i += gridDim.x * 4) {
+    for (int i = blockIdx.x * wpg + w; i < B; i += gridDim.x * wpg) {
         const BeadInfo bi = beads[bead_of_ba[i]];
         const float4 pi = posu[i];
-        const int K = stage_neighbors<NETA, true>(i, pi, bi, nbr, nbr_cnt, posu, dp, rec);
         for (int f = lane; f < dp.D; f += kWave)
             gl[f] = dEdG[(int64_t)i * dp.D + f];
+        wave_sync();
+        // staging, and the radial part of every slot in the lane that staged
+        // it: v = sum_s g[e,s] dG2/dr * d/r
+        const int K = stage_neighbors<NETA, true>(
+            i, pi, bi, nbr, nbr_cnt, posu, dp, rec,
+            [&](int n, int e, const float3 &d, float r, float r_lo, float inv_r, float fc, float dfc) {
+                float acc = 0.0f;
+                for (int t = 0; t < dp.n_rad; ++t) {
+                    const float x = (r - dp.rad_center[t]) + (r_lo - dp.rad_center_lo[t]);
+                    const float eta = dp.rad_eta[t];
+                    acc += gl[e * dp.n_rad + t] * expf(-eta * x * x) * (-2.0f * eta * x * fc + dfc);
+                }
+                const float c = acc * inv_r;
+                vx[n] = (double)(c * d.x);
+                vy[n] = (double)(c * d.y);
+                vz[n] = (double)(c * d.z);
+            });
         int gcnt[kMaxElements], goff[kMaxElements];
         group_offsets(nbr_grp, i, dp.n_el, gcnt, goff);
-        const int32_t *row = nbr + (int64_t)i * dp.Kmax;
-        wave_sync();
-        // radial part of every slot: sum_s g[e,s] dG2/dr * d/r
-        for (int n = lane; n < K; n += kWave) {
-            const int e = row[n] >> kKeyShift;
-            const float4 q = rr[n];
-            const float4 dn = rec.D[n];
-            const float r = q.x, fc = q.y, dfc = q.z;
-            float acc = 0.0f;
-            for (int t = 0; t < dp.n_rad; ++t) {
-                const float x = (r - dp.rad_center[t]) + (q.w - dp.rad_center_lo[t]);
-                const float eta = dp.rad_eta[t];
-                acc += gl[e * dp.n_rad + t] * expf(-eta * x * x) * (-2.0f * eta * x * fc + dfc);
-            }
-            const float c = acc * dn.w;
-            vx[n] = (double)(c * dn.x);
-            vy[n] = (double)(c * dn.y);
-            vz[n] = (double)(c * dn.z);
-        }
         wave_sync();
         int pair = 0;
         for (int e1 = 0; e1 < dp.n_el; ++e1)
@@ -501,8 +513,8 @@ __global__ __launch_bounds__(256) void k_assemble_forces(const float4 *__restric
                                                          const float4 *__restrict__ vslot, int Kmax,
                                                          float *__restrict__ F, uint32_t *__restrict__ status, int B)
 {
-    const int lane = lane_id(), w = threadIdx.x >> 6;
-    for (int i = blockIdx.x * 4 + w; i < B; i += gridDim.x * 4) {
+    const int lane = lane_id(), w = threadIdx.x >> 6, wpg = blockDim.x >> 6;
+    for (int i = blockIdx.x * wpg + w; i < B; i += gridDim.x * wpg) {
         const int K = nbr_cnt[i];
         const int key_i = (__float_as_int(pos4[i].w) << kKeyShift) | i;
         const int32_t *row = nbr + (int64_t)i * Kmax;
@@ -598,13 +610,14 @@ __global__ __launch_bounds__(256) void k_work_counts(const float4 *__restrict__ 
                                                      unsigned long long *__restrict__ counts, int B)
 {
     extern __shared__ float4 lds4[];
-    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int lane = lane_id(), w = threadIdx.x >> 6, wpg = blockDim.x >> 6;
     float4 *base = lds4 + w * 3 * dp.Kmax;
     const Recs rec{base, base + dp.Kmax, base + 2 * dp.Kmax};
     unsigned long long pairs = 0, trip = 0, trip_in = 0;
-    for (int i = blockIdx.x * 4 + w; i < B; i += gridDim.x * 4) {
+    for (int i = blockIdx.x * wpg + w; i < B; i += gridDim.x * wpg) {
         const BeadInfo bi = beads[bead_of_ba[i]];
-        const int K = stage_neighbors<1, false>(i, posu[i], bi, nbr, nbr_cnt, posu, dp, rec);
+        const int K = stage_neighbors<1, false>(i, posu[i], bi, nbr, nbr_cnt, posu, dp, rec,
+                                                [](int, int, const float3 &, float, float, float, float, float) {});
         wave_sync();
         const int np = K * (K - 1) / 2;
         for (int t = lane; t < np; t += kWave) {
@@ -625,20 +638,23 @@ __global__ __launch_bounds__(256) void k_work_counts(const float4 *__restrict__ 
     atomicAdd(&counts[2], trip_in);
 }
 
-// LDS per workgroup (4 waves), in float4 units per slot: records (2), pair
-// terms (1), the adjoint's FP64 slot accumulators (2); plus the feature row
-// and the pair queue.
-static size_t desc_lds(const DescParams &dp, int records)
+// LDS per wave of the forward kernel: records D, E and the pair terms (16 B
+// each per slot), the feature row and the pair queue.
+static size_t forward_wave_bytes(const DescParams &dp)
 {
     const int Dcap = (dp.D + 3) & ~3;
-    return (size_t)4 * (records * dp.Kmax + Dcap / 4 + kQueue / 4) * sizeof(float4);
+    return (size_t)(3 * dp.Kmax + Dcap / 4 + kQueue / 4) * sizeof(float4);
 }
 
-size_t descriptor_lds_bytes(const DescParams &dp, bool adjoint) { return desc_lds(dp, adjoint ? 5 : 3); }
+size_t descriptor_lds_bytes(const DescParams &dp, bool adjoint)
+{
+    return 4 * (adjoint ? adjoint_wave_bytes(dp) : forward_wave_bytes(dp));
+}
 
+// the attribute is the largest workgroup's (four waves); smaller ones use less
 hipError_t configure_descriptor_lds(const DescParams &dp)
 {
-    const int f = (int)desc_lds(dp, 3), a = (int)desc_lds(dp, 5);
+    const int f = (int)descriptor_lds_bytes(dp, false), a = (int)descriptor_lds_bytes(dp, true);
     hipError_t e = hipSuccess;
     if (dp.n_ang_eta == 2) {
         e = hipFuncSetAttribute((const void *)k_descriptors<2>, hipFuncAttributeMaxDynamicSharedMemorySize, f);
@@ -652,28 +668,28 @@ hipError_t configure_descriptor_lds(const DescParams &dp)
     return e;
 }
 
-void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &dp, hipStream_t s)
+void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s)
 {
-    const int grid = (z.B + 3) / 4;
-    const size_t lds = desc_lds(dp, 3);
+    const int wpg = tn.centre_waves, grid = centre_grid(z.B, tn);
+    const size_t lds = wpg * forward_wave_bytes(dp);
     if (dp.n_ang_eta == 2)
-        hipLaunchKernelGGL(k_descriptors<2>, dim3(grid), dim3(256), lds, s, d.posu4, d.beads, d.bead_of_ba, d.nbr,
-                           d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, z.B);
+        hipLaunchKernelGGL(k_descriptors<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
+                           d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, z.B);
     else
-        hipLaunchKernelGGL(k_descriptors<1>, dim3(grid), dim3(256), lds, s, d.posu4, d.beads, d.bead_of_ba, d.nbr,
-                           d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, z.B);
+        hipLaunchKernelGGL(k_descriptors<1>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
+                           d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, z.B);
 }
 
-void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, hipStream_t s)
+void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s)
 {
-    const int grid = (z.B + 3) / 4;
-    const size_t lds = desc_lds(dp, 5);
+    const int wpg = tn.centre_waves, grid = centre_grid(z.B, tn);
+    const size_t lds = wpg * adjoint_wave_bytes(dp);
     if (dp.n_ang_eta == 2)
-        hipLaunchKernelGGL(k_adjoint<2>, dim3(grid), dim3(256), lds, s, d.posu4, d.beads, d.bead_of_ba, d.nbr,
-                           d.nbr_cnt, d.nbr_grp, d.dEdG, dp, d.vslot, d.vir_atom, z.B);
+        hipLaunchKernelGGL(k_adjoint<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
+                           d.nbr, d.nbr_cnt, d.nbr_grp, d.dEdG, dp, d.vslot, d.vir_atom, z.B);
     else
-        hipLaunchKernelGGL(k_adjoint<1>, dim3(grid), dim3(256), lds, s, d.posu4, d.beads, d.bead_of_ba, d.nbr,
-                           d.nbr_cnt, d.nbr_grp, d.dEdG, dp, d.vslot, d.vir_atom, z.B);
+        hipLaunchKernelGGL(k_adjoint<1>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
+                           d.nbr, d.nbr_cnt, d.nbr_grp, d.dEdG, dp, d.vslot, d.vir_atom, z.B);
 }
 
 void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &dp, unsigned long long *counts,
@@ -684,11 +700,10 @@ void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &d
                        d.beads, d.bead_of_ba, d.nbr, d.nbr_cnt, dp, counts, z.B);
 }
 
-void launch_assemble_forces(const DevBuffers &d, const Sizes &z, float *F, hipStream_t s)
+void launch_assemble_forces(const DevBuffers &d, const Sizes &z, float *F, const Tuning &tn, hipStream_t s)
 {
-    const int grid = (z.B + 3) / 4;
-    hipLaunchKernelGGL(k_assemble_forces, dim3(grid), dim3(256), 0, s, d.pos4, d.nbr, d.nbr_cnt, d.vslot, z.Kmax, F,
-                       d.status, z.B);
+    hipLaunchKernelGGL(k_assemble_forces, dim3(centre_grid(z.B, tn)), dim3(kWave * tn.centre_waves), 0, s, d.pos4,
+                       d.nbr, d.nbr_cnt, d.vslot, z.Kmax, F, d.status, z.B);
 }
 
 void launch_bead_sums(const DevBuffers &d, const Sizes &z, float *E_bead, float *W_bead, bool virial, hipStream_t s)

@@ -1,12 +1,12 @@
 // Per-element MLP of the Behler-Parrinello potential on MFMA, fused:
 // forward through the hidden tanh layers, the energy readout, and the input
 // gradient dE/dx by the transposed chain, divided by the feature scale
-// (dE/dG), for one 16-row tile per workgroup.
+// (dE/dG), for one tile of 16, 32 or 64 rows per workgroup.
 //
 //   h_l = tanh(W_l h_{l-1} + b_l),  E = w_o . h_L + b_o
 //   g_L = w_o * (1 - h_L^2),  g_{l-1} = (W_l^T g_l) * (1 - h_{l-1}^2),  dE/dx = W_1^T g_1
 //
-// Each GEMM is rows(16) x K times K x N with the 16x16 MFMA tiles of gfx950,
+// Each GEMM is rows x K times K x N with the 16x16 MFMA tiles of gfx950,
 // accumulating in FP32; the operand precision modes are listed at MlpCfg.  Activations pass between layers through a per-wave
 // LDS tile; (1 - h^2) of every hidden layer stays in registers in the MFMA
 // output layout, which is also the layout of the backward GEMM outputs.
@@ -35,39 +35,52 @@ struct MlpCfg {
 
 __device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// acc[t] = A[16][K] * B[K][16 ct ...] for the column tiles ct = w + 4t < nct,
-// with B[k][n] = Bt[n][k] (row-major Bt[N][ldb]); A is the LDS tile.
-template <int MODE>
+// acc[r][t] = A[16 r .. 16 r + 15][K] * B[K][16 ct ...] for the row blocks
+// r < RT of the tile and the column tiles ct = w + 4t < nct, with
+// B[k][n] = Bt[n][k] (row-major Bt[N][ldb]); A is the LDS tile.  Each B
+// fragment read from memory feeds RT MFMAs.
+template <int MODE, int RT>
 __device__ __forceinline__ void gemm16_cols(const float *act, int K, const float *Bt, const uint16_t *Btb,
-                                            const uint16_t *Btb_lo, int ldb, int nct, int w, f32x4 (&acc)[8])
+                                            const uint16_t *Btb_lo, int ldb, int nct, int w, f32x4 (&acc)[RT][2])
 {
     constexpr int S = MlpCfg<MODE>::S;
     const int lane = lane_id();
     const int lr = lane & 15, lg = lane >> 4;
-    acc[0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    acc[1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        acc[r][0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        acc[r][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
     if (MODE == 0) {
         for (int k0 = 0; k0 < K; k0 += 4) {
-            const float a = act[lr * S + k0 + lg];
+            float a[RT];
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+                a[r] = act[(16 * r + lr) * S + k0 + lg];
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 const int ct = w + 4 * t;
                 if (ct < nct) {
                     const float b = Bt[(ct * 16 + lr) * ldb + k0 + lg];
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < RT; ++r)
+                        acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b, acc[r][t], 0, 0, 0);
                 }
             }
         }
     } else {
         for (int k0 = 0; k0 < K; k0 += 16) {
-            const float4 av = *reinterpret_cast<const float4 *>(act + lr * S + k0 + lg * 4);
-            const float af[4] = {av.x, av.y, av.z, av.w};
-            i16x4 ahi, alo;
+            i16x4 ahi[RT], alo[RT];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint16_t h = f32_to_bf16(af[u]);
-                ahi[u] = (short)h;
-                alo[u] = (short)f32_to_bf16(af[u] - bf16_value(h));
+            for (int r = 0; r < RT; ++r) {
+                const float4 av = *reinterpret_cast<const float4 *>(act + (16 * r + lr) * S + k0 + lg * 4);
+                const float af[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint16_t h = f32_to_bf16(af[u]);
+                    ahi[r][u] = (short)h;
+                    alo[r][u] = (short)f32_to_bf16(af[u] - bf16_value(h));
+                }
             }
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
@@ -75,11 +88,16 @@ __device__ __forceinline__ void gemm16_cols(const float *act, int K, const float
                 if (ct < nct) {
                     const int64_t o = (int64_t)(ct * 16 + lr) * ldb + k0 + lg * 4;
                     const i16x4 bhi = *reinterpret_cast<const i16x4 *>(Btb + o);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc[t], 0, 0, 0);
-                    if (MODE == 1) {
-                        const i16x4 blo = *reinterpret_cast<const i16x4 *>(Btb_lo + o);
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc[t], 0, 0, 0);
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc[t], 0, 0, 0);
+                    i16x4 blo;
+                    if (MODE == 1)
+                        blo = *reinterpret_cast<const i16x4 *>(Btb_lo + o);
+#pragma unroll
+                    for (int r = 0; r < RT; ++r) {
+                        acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[r], bhi, acc[r][t], 0, 0, 0);
+                        if (MODE == 1) {
+                            acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[r], bhi, acc[r][t], 0, 0, 0);
+                            acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[r], blo, acc[r][t], 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -87,17 +105,20 @@ __device__ __forceinline__ void gemm16_cols(const float *act, int K, const float
     }
 }
 
-// One workgroup per 16-row tile (tiles of all elements in one launch); the
-// four waves split the output columns of every GEMM (column tiles w and w+4),
-// and the activations of the tile live in LDS between layers.
-template <int MODE>
+// One workgroup per tile of 16 RT rows (tiles of all elements in one
+// launch); the four waves split the output columns of every GEMM (column
+// tiles w and w+4) and run all RT row blocks of the tile, and the activations
+// of the tile live in LDS between layers.  Row r's arithmetic is the same for
+// every RT.
+template <int MODE, int RT>
 __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, const MlpTile *__restrict__ tiles,
                                              const float *__restrict__ xhat, int D, int Dp, MlpNets nets,
                                              float *__restrict__ E_atom, float *__restrict__ dEdG)
 {
     constexpr int S = MlpCfg<MODE>::S;
-    __shared__ __attribute__((aligned(16))) float act[16 * S];
-    __shared__ float epart[4][16];
+    constexpr int MT = 16 * RT;
+    __shared__ __attribute__((aligned(16))) float act[MT * S];
+    __shared__ float epart[4][MT];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int lr = lane & 15, lg = lane >> 4;
     const MlpTile tile = tiles[blockIdx.x];
@@ -105,20 +126,20 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
     const int32_t *trows = rows + tile.row0;
     const int nrows = tile.nrows;
 
-    for (int idx = threadIdx.x; idx < 16 * Dp; idx += 256) {
+    for (int idx = threadIdx.x; idx < MT * Dp; idx += 256) {
         const int r = idx / Dp, c = idx - r * Dp;
         act[r * S + c] = (r < nrows && c < D) ? xhat[(int64_t)trows[r] * D + c] : 0.0f;
     }
     __syncthreads();
 
-    f32x4 dsave[3][2];
-    f32x4 acc[8];
+    f32x4 dsave[3][RT][2];
+    f32x4 acc[RT][2];
     int K = Dp;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         if (l < net.n_hidden) {
             const MlpLayer L = net.layer[l];
-            gemm16_cols<MODE>(act, K, L.W, L.Wb, L.Wb_lo, L.in_pad, L.out / 16, w, acc);
+            gemm16_cols<MODE, RT>(act, K, L.W, L.Wb, L.Wb_lo, L.in_pad, L.out / 16, w, acc);
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
@@ -127,15 +148,17 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
                     const int col = ct * 16 + lr;
                     const float bias = L.b[col];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        // tanh and 1 - tanh^2 = sech^2 from e = exp(-2|z|): tanh = sign(z)(1 - e)/(1 + e),
-                        // sech^2 = 4e/(1 + e)^2, free of the cancellation in 1 - h^2 for saturated units
-                        const float z = acc[t][q] + bias;
-                        const float e = expf(-2.0f * fabsf(z));
-                        const float ope = 1.0f + e;
-                        dsave[l][t][q] = 4.0f * e / (ope * ope);
-                        act[(lg * 4 + q) * S + col] = copysignf((1.0f - e) / ope, z);
-                    }
+                    for (int r = 0; r < RT; ++r)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            // tanh and 1 - tanh^2 = sech^2 from e = exp(-2|z|): tanh = sign(z)(1 - e)/(1 + e),
+                            // sech^2 = 4e/(1 + e)^2, free of the cancellation in 1 - h^2 for saturated units
+                            const float z = acc[r][t][q] + bias;
+                            const float e = expf(-2.0f * fabsf(z));
+                            const float ope = 1.0f + e;
+                            dsave[l][r][t][q] = 4.0f * e / (ope * ope);
+                            act[(16 * r + lg * 4 + q) * S + col] = copysignf((1.0f - e) / ope, z);
+                        }
                 }
             }
             __syncthreads();
@@ -144,7 +167,12 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
     }
     // energy readout (FP32 on the VALU in every mode); waves hold column slices
     const int nlast = K / 16;
-    float e_part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float e_part[RT][4];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            e_part[r][q] = 0.0f;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const int ct = w + 4 * t;
@@ -152,19 +180,25 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
             const int col = ct * 16 + lr;
             const float wo = net.wo[col];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                e_part[q] += act[(lg * 4 + q) * S + col] * wo;
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    e_part[r][q] += act[(16 * r + lg * 4 + q) * S + col] * wo;
         }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        e_part[q] = row16_sum(e_part[q]);
-    if (lr == 0)
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            epart[w][lg * 4 + q] = e_part[q];
+            e_part[r][q] = row16_sum(e_part[r][q]);
+    if (lr == 0)
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                epart[w][16 * r + lg * 4 + q] = e_part[r][q];
     __syncthreads();
-    if (threadIdx.x < 16 && (int)threadIdx.x < nrows)
+    if (threadIdx.x < MT && (int)threadIdx.x < nrows)
         E_atom[trows[threadIdx.x]] = ((epart[0][threadIdx.x] + epart[1][threadIdx.x]) +
                                       (epart[2][threadIdx.x] + epart[3][threadIdx.x])) + net.bo;
     // g_L = w_o * (1 - h_L^2)
@@ -179,8 +213,10 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
                     const int col = ct * 16 + lr;
                     const float wo = net.wo[col];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        act[(lg * 4 + q) * S + col] = wo * dsave[l][t][q];
+                    for (int r = 0; r < RT; ++r)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            act[(16 * r + lg * 4 + q) * S + col] = wo * dsave[l][r][t][q];
                 }
             }
         }
@@ -191,7 +227,7 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
     for (int l = 2; l >= 1; --l) {
         if (l < nh) {
             const MlpLayer L = net.layer[l];
-            gemm16_cols<MODE>(act, L.out, L.WT, L.WTb, L.WTb_lo, L.out, L.in_pad / 16, w, acc);
+            gemm16_cols<MODE, RT>(act, L.out, L.WT, L.WTb, L.WTb_lo, L.out, L.in_pad / 16, w, acc);
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
@@ -199,8 +235,10 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
                 if (ct < L.in_pad / 16) {
                     const int col = ct * 16 + lr;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        act[(lg * 4 + q) * S + col] = acc[t][q] * dsave[l - 1][t][q];
+                    for (int r = 0; r < RT; ++r)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            act[(16 * r + lg * 4 + q) * S + col] = acc[r][t][q] * dsave[l - 1][r][t][q];
                 }
             }
             __syncthreads();
@@ -208,7 +246,7 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
     }
     // dE/dx = W_1^T g_1 and dE/dG = dE/dx / scale
     const MlpLayer L0 = net.layer[0];
-    gemm16_cols<MODE>(act, L0.out, L0.WT, L0.WTb, L0.WTb_lo, L0.out, Dp / 16, w, acc);
+    gemm16_cols<MODE, RT>(act, L0.out, L0.WT, L0.WTb, L0.WTb_lo, L0.out, Dp / 16, w, acc);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const int ct = w + 4 * t;
@@ -217,11 +255,13 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
             if (col < D) {
                 const float is = net.inv_scale[col];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = lg * 4 + q;
-                    if (r < nrows)
-                        dEdG[(int64_t)trows[r] * D + col] = acc[t][q] * is;
-                }
+                for (int r = 0; r < RT; ++r)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = 16 * r + lg * 4 + q;
+                        if (row < nrows)
+                            dEdG[(int64_t)trows[row] * D + col] = acc[r][t][q] * is;
+                    }
             }
         }
     }
@@ -385,7 +425,23 @@ __global__ __launch_bounds__(256) void k_mlp_f64(const int32_t *__restrict__ row
     }
 }
 
-void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int mlp_mode, hipStream_t s)
+template <int MODE>
+static void launch_mlp_mode(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int rows,
+                            hipStream_t s)
+{
+    if (rows == 64)
+        hipLaunchKernelGGL((k_mlp<MODE, 4>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp,
+                           nets, d.E_atom, d.dEdG);
+    else if (rows == 32)
+        hipLaunchKernelGGL((k_mlp<MODE, 2>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp,
+                           nets, d.E_atom, d.dEdG);
+    else
+        hipLaunchKernelGGL((k_mlp<MODE, 1>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp,
+                           nets, d.E_atom, d.dEdG);
+}
+
+void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int mlp_mode, int rows,
+                hipStream_t s)
 {
     if (n_tiles <= 0)
         return;
@@ -393,14 +449,11 @@ void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, in
         hipLaunchKernelGGL(k_mlp_f64, dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp, nets,
                            d.E_atom, d.dEdG);
     else if (mlp_mode == 1)
-        hipLaunchKernelGGL(k_mlp<1>, dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp, nets,
-                           d.E_atom, d.dEdG);
+        launch_mlp_mode<1>(d, nets, n_tiles, D, Dp, rows, s);
     else if (mlp_mode == 2)
-        hipLaunchKernelGGL(k_mlp<2>, dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp, nets,
-                           d.E_atom, d.dEdG);
+        launch_mlp_mode<2>(d, nets, n_tiles, D, Dp, rows, s);
     else
-        hipLaunchKernelGGL(k_mlp<0>, dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp, nets,
-                           d.E_atom, d.dEdG);
+        launch_mlp_mode<0>(d, nets, n_tiles, D, Dp, rows, s);
 }
 
 }  // namespace pimd

@@ -113,6 +113,16 @@ __global__ __launch_bounds__(256) void k_cell_fill(const BeadInfo *__restrict__ 
     cell_atoms[bi.ba0 + cell_start[atom_cell[ba]] + atom_slot[ba]] = ba;
 }
 
+// Keys buffered per wave: up to Kmax + 63 candidates (a pass may overshoot
+// Kmax) and room for the sort's padding to a power of two.
+__host__ __device__ inline int nl_buffer(int Kmax)
+{
+    int n = 1;
+    while (n < Kmax)
+        n <<= 1;
+    return n > Kmax + kWave ? n : Kmax + kWave;
+}
+
 __device__ __forceinline__ bool within_cutoff(const float4 &pi, const float4 &pj, const BeadInfo &bi, float rc2)
 {
     float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
@@ -143,10 +153,10 @@ __global__ __launch_bounds__(256) void k_neighbors(const float4 *__restrict__ po
 {
     extern __shared__ int32_t nl_lds[];
     const int lane = lane_id();
-    const int w = threadIdx.x >> 6;
-    int32_t *buf = nl_lds + w * (Kmax + kWave);
+    const int w = threadIdx.x >> 6, wpg = blockDim.x >> 6;
+    int32_t *buf = nl_lds + w * nl_buffer(Kmax);
     const uint64_t below = lanes_below_mask();
-    for (int i = blockIdx.x * 4 + w; i < B; i += gridDim.x * 4) {
+    for (int i = blockIdx.x * wpg + w; i < B; i += gridDim.x * wpg) {
         const BeadInfo bi = beads[bead_of_ba[i]];
         const float4 pi = pos4[i];
         int count = 0;
@@ -166,36 +176,43 @@ __global__ __launch_bounds__(256) void k_neighbors(const float4 *__restrict__ po
             count += __popcll(m);
         };
         if (bi.periodic) {
+            // the (deduplicated) stencil cells, one per lane: lane c < n_cells
+            // holds cell c's first slot and its end in the flattened candidate
+            // index space, so each pass tests 64 candidates of any cells
             const int cx = cell_of(pi.x, bi.cell_scale[0], bi.nc[0]);
             const int cy = cell_of(pi.y, bi.cell_scale[1], bi.nc[1]);
             const int cz = cell_of(pi.z, bi.cell_scale[2], bi.nc[2]);
-            int ax[3][3], an[3];
-            const int cc[3] = {cx, cy, cz};
-            for (int d = 0; d < 3; ++d) {
-                const int nc = bi.nc[d];
-                if (nc < 3) {
-                    an[d] = nc;
-                    for (int t = 0; t < nc; ++t)
-                        ax[d][t] = t;
-                } else {
-                    an[d] = 3;
-                    ax[d][0] = (cc[d] + nc - 1) % nc;
-                    ax[d][1] = cc[d];
-                    ax[d][2] = (cc[d] + 1) % nc;
-                }
+            const int an0 = bi.nc[0] < 3 ? bi.nc[0] : 3, an1 = bi.nc[1] < 3 ? bi.nc[1] : 3;
+            const int an2 = bi.nc[2] < 3 ? bi.nc[2] : 3;
+            const int n_cells = an0 * an1 * an2;
+            int first = 0, cnt = 0;
+            if (lane < n_cells) {
+                const int c = lane % an2, b = (lane / an2) % an1, a = lane / (an1 * an2);
+                // axis offsets -1, 0, +1 (or every cell of an axis with fewer than 3)
+                const int ux = bi.nc[0] < 3 ? a : (cx + bi.nc[0] - 1 + a) % bi.nc[0];
+                const int uy = bi.nc[1] < 3 ? b : (cy + bi.nc[1] - 1 + b) % bi.nc[1];
+                const int uz = bi.nc[2] < 3 ? c : (cz + bi.nc[2] - 1 + c) % bi.nc[2];
+                const int cell = bi.cell0 + (ux * bi.nc[1] + uy) * bi.nc[2] + uz;
+                first = cell_start[cell];
+                cnt = cell_count[cell];
             }
-            for (int a = 0; a < an[0]; ++a)
-                for (int b = 0; b < an[1]; ++b)
-                    for (int c = 0; c < an[2]; ++c) {
-                        const int cell = bi.cell0 + (ax[0][a] * bi.nc[1] + ax[1][b]) * bi.nc[2] + ax[2][c];
-                        const int st = cell_start[cell], ct = cell_count[cell];
-                        for (int t0 = 0; t0 < ct; t0 += kWave) {
-                            const int t = t0 + lane;
-                            const bool valid = t < ct;
-                            const int j = valid ? cell_atoms[bi.ba0 + st + t] : 0;
-                            consider(j, valid);
-                        }
-                    }
+            int end = cnt;   // inclusive prefix sum of the counts over the lanes
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int t = __shfl_up(end, o, kWave);
+                end += lane >= o ? t : 0;
+            }
+            const int total = __shfl(end, kWave - 1, kWave);
+            const int base = first - (end - cnt);   // slot of candidate t in cell c: base_c + t
+            for (int t0 = 0; t0 < total; t0 += kWave) {
+                const int t = t0 + lane;
+                const bool valid = t < total;
+                int k = 0;   // the cell holding candidate t: number of cell ends <= t
+                for (int c = 0; c < n_cells; ++c)
+                    k += t >= __shfl(end, c, kWave) ? 1 : 0;
+                const int bk = __shfl(base, k < n_cells ? k : 0, kWave);
+                const int j = valid ? cell_atoms[bi.ba0 + bk + t] : 0;
+                consider(j, valid);
+            }
         } else {
             for (int t0 = 0; t0 < bi.n; t0 += kWave) {
                 const int t = t0 + lane;
@@ -206,20 +223,44 @@ __global__ __launch_bounds__(256) void k_neighbors(const float4 *__restrict__ po
         if (count > Kmax && lane == 0)
             atomicOr(status, kStatusOverflow);
         const int K = count < Kmax ? count : Kmax;
+        // bitonic sort of the K keys (distinct) in the wave's buffer, padded
+        // with INT_MAX to a power of two; then the sorted keys go out
+        // coalesced and the element groups are counted from them
+        int n = 1;
+        while (n < K)
+            n <<= 1;
+        for (int t = K + lane; t < n; t += kWave)
+            buf[t] = 0x7FFFFFFF;
+        wave_sync();
+        for (int size = 2; size <= n; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int p = lane; p < (n >> 1); p += kWave) {
+                    const int lo = ((p & ~(stride - 1)) << 1) | (p & (stride - 1)), hi = lo + stride;
+                    const int a = buf[lo], b = buf[hi];
+                    if ((a > b) == ((lo & size) == 0)) {
+                        buf[lo] = b;
+                        buf[hi] = a;
+                    }
+                }
+                wave_sync();
+            }
         int32_t *out = nbr + (int64_t)i * Kmax;
-        for (int s = lane; s < K; s += kWave) {
-            const int v = buf[s];
-            int rank = 0;
-            for (int u = 0; u < K; ++u)
-                rank += buf[u] < v;
-            out[rank] = v;
+        int grp[kMaxElements] = {0, 0, 0, 0};
+        for (int t0 = 0; t0 < K; t0 += kWave) {
+            const int t = t0 + lane;
+            const int v = t < K ? buf[t] : -1;
+            if (t < K)
+                out[t] = v;
+#pragma unroll
+            for (int e = 0; e < kMaxElements; ++e)
+                grp[e] += __popcll(__ballot(t < K && (v >> kKeyShift) == e));
         }
-        if (lane < kMaxElements) {
-            int c = 0;
-            for (int u = 0; u < K; ++u)
-                c += (buf[u] >> kKeyShift) == lane;
-            if (lane < n_el)
-                nbr_grp[(int64_t)i * kMaxElements + lane] = c;
+        if (lane < n_el) {
+            int c = grp[0];
+#pragma unroll
+            for (int e = 1; e < kMaxElements; ++e)
+                c = lane == e ? grp[e] : c;
+            nbr_grp[(int64_t)i * kMaxElements + lane] = c;
         }
         if (lane == 0)
             nbr_cnt[i] = K;
@@ -258,12 +299,13 @@ void launch_cell_fill(const DevBuffers &d, const Sizes &z, hipStream_t s)
                        d.atom_slot, d.cell_start, d.cell_atoms, z.B);
 }
 
-void launch_neighbors(const DevBuffers &d, const Sizes &z, float rc2, int n_el, hipStream_t s)
+void launch_neighbors(const DevBuffers &d, const Sizes &z, float rc2, int n_el, const Tuning &tn, hipStream_t s)
 {
-    const size_t lds = (size_t)4 * (z.Kmax + kWave) * sizeof(int32_t);
-    const int grid = (z.B + 3) / 4;
-    hipLaunchKernelGGL(k_neighbors, dim3(grid), dim3(256), lds, s, d.pos4, d.beads, d.bead_of_ba, d.cell_count,
-                       d.cell_start, d.cell_atoms, rc2, z.Kmax, n_el, d.nbr, d.nbr_cnt, d.nbr_grp, d.status, z.B);
+    const int wpg = tn.centre_waves;
+    const size_t lds = (size_t)wpg * nl_buffer(z.Kmax) * sizeof(int32_t);
+    hipLaunchKernelGGL(k_neighbors, dim3(centre_grid(z.B, tn)), dim3(kWave * wpg), lds, s, d.pos4, d.beads,
+                       d.bead_of_ba, d.cell_count, d.cell_start, d.cell_atoms, rc2, z.Kmax, n_el, d.nbr, d.nbr_cnt,
+                       d.nbr_grp, d.status, z.B);
 }
 
 }  // namespace pimd

@@ -253,6 +253,17 @@ uint16_t bf16_bits(float f)
     return (uint16_t)(u >> 16);
 }
 
+// Tiles of at most `rows` rows over the element-grouped MLP rows (an element's
+// rows never share a tile).
+std::vector<MlpTile> mlp_tiles(const std::vector<int32_t> &elem_row0, int rows)
+{
+    std::vector<MlpTile> tiles;
+    for (int e = 0; e + 1 < (int)elem_row0.size(); ++e)
+        for (int t = elem_row0[e]; t < elem_row0[e + 1]; t += rows)
+            tiles.push_back(MlpTile{e, t, std::min(rows, elem_row0[e + 1] - t), 0});
+    return tiles;
+}
+
 }  // namespace
 
 struct pimd_ctx {
@@ -262,6 +273,9 @@ struct pimd_ctx {
     DescParams dp{};
     MlpNets nets{};
     int n_mlp_tiles = 0;
+    std::vector<int32_t> elem_row0;   // [n_el + 1] first MLP row of each element in elem_rows
+    Tuning tn{4, 0, 16, 0};
+    pimd_tuning last_tuning_out{};     // sink for pimd_autotune(best = NULL)
     std::vector<SysInfo> sys_host;
     std::vector<double> temperature, masses_el;
     std::vector<int> species;
@@ -299,6 +313,42 @@ namespace {
         }                                                                                       \
     } while (0)
 
+// The force path of the neural potential in five stages (each reads only
+// what the earlier ones wrote, so any stage can be re-run on its own):
+// 0 neighbour search, 1 descriptors, 2 MLP, 3 adjoint, 4 forces and bead sums.
+void launch_force_stage(pimd_ctx *c, int stage, const float *q, float *E_out, float *F_out, float *W_out)
+{
+    const DevBuffers &d = c->d;
+    const Sizes &z = c->z;
+    hipStream_t s = c->stream;
+    switch (stage) {
+    case 0:
+        if (z.any_periodic)
+            launch_zero_i32(d.cell_count, z.total_cells, s);
+        launch_wrap_bin(q, d, z, s);
+        if (z.any_periodic) {
+            launch_cell_scan(d, z, s);
+            launch_cell_fill(d, z, s);
+        }
+        launch_neighbors(d, z, c->dp.rc2, c->pl.n_el, c->tn, s);
+        break;
+    case 1:
+        launch_descriptors(d, z, c->dp, c->tn, s);
+        break;
+    case 2:
+        launch_mlp(d, c->nets, c->n_mlp_tiles, c->pl.D, c->pl.Dp, c->precision, c->tn.mlp_rows, s);
+        break;
+    case 3:
+        if (F_out || W_out)
+            launch_adjoint(d, z, c->dp, c->tn, s);
+        break;
+    default:
+        if (F_out)
+            launch_assemble_forces(d, z, F_out, c->tn, s);
+        launch_bead_sums(d, z, E_out, W_out, W_out != nullptr, s);
+    }
+}
+
 pimd_status run_forces(pimd_ctx *c, const float *q, float *E_out, float *F_out, float *W_out)
 {
     const DevBuffers &d = c->d;
@@ -316,28 +366,11 @@ pimd_status run_forces(pimd_ctx *c, const float *q, float *E_out, float *F_out, 
         CHECK_LAUNCH(c);
         return PIMD_OK;
     }
-    if (z.any_periodic)
-        launch_zero_i32(d.cell_count, z.total_cells, s);
-    launch_wrap_bin(q, d, z, s);
-    if (z.any_periodic) {
-        launch_cell_scan(d, z, s);
-        launch_cell_fill(d, z, s);
+    for (int k = 0; k < 5; ++k) {
+        launch_force_stage(c, k, q, E_out, F_out, W_out);
+        if (k < 4)
+            mark(k + 2);
     }
-    launch_neighbors(d, z, c->dp.rc2, c->pl.n_el, s);
-    mark(2);
-    launch_descriptors(d, z, c->dp, s);
-    mark(3);
-    launch_mlp(d, c->nets, c->n_mlp_tiles, c->pl.D, c->pl.Dp, c->precision, s);
-    mark(4);
-    if (F_out || W_out) {
-        launch_adjoint(d, z, c->dp, s);
-        mark(5);
-        if (F_out)
-            launch_assemble_forces(d, z, F_out, s);
-    } else {
-        mark(5);
-    }
-    launch_bead_sums(d, z, E_out, W_out, W_out != nullptr, s);
     mark(6);
     CHECK_LAUNCH(c);
     return PIMD_OK;
@@ -641,11 +674,10 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         }
         for (int s = 0; s < m->n_ang_eta; ++s)
             dp.ang_eta[s] = (float)m->ang_eta[s];
-        // rows grouped by element for the MLP gather, cut into 16-row tiles
+        // rows grouped by element for the MLP gather, cut into tiles of tn.mlp_rows
         std::vector<int32_t> rows;
-        std::vector<MlpTile> tiles;
+        c->elem_row0.assign(1, 0);
         for (int e = 0; e < pl.n_el; ++e) {
-            const int r0 = (int)rows.size();
             for (int s = 0; s < pl.n_sys; ++s) {
                 const SysInfo &si = c->sys_host[s];
                 for (int k = 0; k < si.P; ++k)
@@ -653,9 +685,9 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
                         if (cfg->species[si.atom0 + i] == e)
                             rows.push_back(si.ba0 + k * si.N + i);
             }
-            for (int t = r0; t < (int)rows.size(); t += 16)
-                tiles.push_back(MlpTile{e, t, std::min(16, (int)rows.size() - t), 0});
+            c->elem_row0.push_back((int32_t)rows.size());
         }
+        const std::vector<MlpTile> tiles = mlp_tiles(c->elem_row0, c->tn.mlp_rows);
         c->n_mlp_tiles = (int)tiles.size();
         push(d.elem_rows, rows.data(), rows.size() * 4);
         push(d.mlp_tiles, tiles.data(), tiles.size() * sizeof(MlpTile));
@@ -1079,6 +1111,194 @@ pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled)
         return PIMD_E_ARG;
     ctx->use_graph = enabled != 0;
     return PIMD_OK;
+}
+
+pimd_status pimd_get_tuning(const pimd_ctx *ctx, pimd_tuning *out)
+{
+    if (!ctx || !out)
+        return PIMD_E_ARG;
+    *out = pimd_tuning{ctx->tn.centre_waves, ctx->tn.centre_grid, ctx->tn.mlp_rows, 0};
+    return PIMD_OK;
+}
+
+static pimd_status apply_tuning(pimd_ctx *ctx, const Tuning &tn)
+{
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->pl.bpnn && tn.mlp_rows != ctx->tn.mlp_rows) {
+        const std::vector<MlpTile> tiles = mlp_tiles(ctx->elem_row0, tn.mlp_rows);
+        HIPCHK(ctx, hipMemcpyAsync(ctx->d.mlp_tiles, tiles.data(), tiles.size() * sizeof(MlpTile),
+                                   hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        ctx->n_mlp_tiles = (int)tiles.size();
+    }
+    ctx->tn = tn;
+    if (ctx->gexec) {
+        (void)hipGraphExecDestroy(ctx->gexec);
+        ctx->gexec = nullptr;
+    }
+    if (ctx->graph) {
+        (void)hipGraphDestroy(ctx->graph);
+        ctx->graph = nullptr;
+    }
+    return PIMD_OK;
+}
+
+pimd_status pimd_set_tuning(pimd_ctx *ctx, const pimd_tuning *t)
+{
+    if (!ctx || !t)
+        return PIMD_E_ARG;
+    const bool waves_ok = t->centre_waves == 1 || t->centre_waves == 2 || t->centre_waves == 4;
+    const bool rows_ok = t->mlp_rows == 16 || t->mlp_rows == 32 || t->mlp_rows == 64;
+    if (!waves_ok || !rows_ok || t->centre_grid < 0 || t->reserved != 0) {
+        ctx->err = "tuning: centre_waves in {1, 2, 4}, centre_grid >= 0, mlp_rows in {16, 32, 64}, reserved 0";
+        return PIMD_E_ARG;
+    }
+    if (ctx->precision == PIMD_PREC_FP64_MLP && t->mlp_rows != 16) {
+        ctx->err = "the FP64 MLP runs 16-row tiles only";
+        return PIMD_E_UNSUPPORTED;
+    }
+    return apply_tuning(ctx, Tuning{t->centre_waves, t->centre_grid, t->mlp_rows, 0});
+}
+
+// Mean milliseconds of one force evaluation of the current positions.
+static pimd_status time_forces(pimd_ctx *ctx, int n_reps, double &ms)
+{
+    pimd_status st = run_forces(ctx, ctx->d.q, ctx->d.E_bead, ctx->d.F, nullptr);
+    if (st != PIMD_OK)
+        return st;
+    hipEvent_t ev[2];
+    HIPCHK(ctx, hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        ctx->err = "hipEventCreate failed";
+        return PIMD_E_DEVICE;
+    }
+    (void)hipEventRecord(ev[0], ctx->stream);
+    for (int r = 0; r < n_reps && st == PIMD_OK; ++r)
+        st = run_forces(ctx, ctx->d.q, ctx->d.E_bead, ctx->d.F, nullptr);
+    (void)hipEventRecord(ev[1], ctx->stream);
+    hipError_t e = hipEventSynchronize(ev[1]);
+    float t = 0.0f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&t, ev[0], ev[1]);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (st != PIMD_OK)
+        return st;
+    if (e != hipSuccess) {
+        ctx->err = std::string("timing events: ") + hipGetErrorString(e);
+        return PIMD_E_DEVICE;
+    }
+    ms = (double)t / n_reps;
+    return read_status(ctx);
+}
+
+pimd_status pimd_autotune(pimd_ctx *ctx, int32_t n_reps, pimd_tuning *best)
+{
+    if (!ctx || n_reps < 1)
+        return PIMD_E_ARG;
+    if (!ctx->state_set) {
+        ctx->err = "pimd_set_state must come before pimd_autotune";
+        return PIMD_E_STATE;
+    }
+    if (ctx->pl.bpnn) {
+        int n_cu = 0;
+        HIPCHK(ctx, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        Tuning cur = ctx->tn, top = cur;
+        double top_ms = 0.0;
+        pimd_status st = time_forces(ctx, n_reps, top_ms);
+        if (st != PIMD_OK)
+            return st;
+        auto consider = [&](const Tuning &cand) -> pimd_status {
+            pimd_status s2 = apply_tuning(ctx, cand);
+            double ms = 0.0;
+            if (s2 == PIMD_OK)
+                s2 = time_forces(ctx, n_reps, ms);
+            if (s2 != PIMD_OK)
+                return s2;
+            if (ms < 0.99 * top_ms) {
+                top = cand;
+                top_ms = ms;
+            }
+            return PIMD_OK;
+        };
+        for (int waves : {4, 2, 1})
+            for (int per_cu : {0, 2, 4, 8, 16}) {
+                Tuning cand = top;
+                cand.centre_waves = waves;
+                cand.centre_grid = per_cu * n_cu;
+                if (cand.centre_grid >= centre_grid(ctx->z.B, Tuning{waves, 0, 16, 0}))
+                    continue;   // no fewer workgroups than one wave per centre gives
+                if (cand.centre_waves == cur.centre_waves && cand.centre_grid == cur.centre_grid)
+                    continue;
+                if ((st = consider(cand)) != PIMD_OK)
+                    return st;
+            }
+        if (ctx->precision != PIMD_PREC_FP64_MLP)
+            for (int rows : {16, 32, 64}) {
+                if (rows == top.mlp_rows)
+                    continue;
+                Tuning cand = top;
+                cand.mlp_rows = rows;
+                if ((st = consider(cand)) != PIMD_OK)
+                    return st;
+            }
+        if ((st = apply_tuning(ctx, top)) != PIMD_OK)
+            return st;
+        // leave the forces of the current positions under the chosen shape
+        if ((st = run_forces(ctx, ctx->d.q, ctx->d.E_bead, ctx->d.F, nullptr)) != PIMD_OK)
+            return st;
+        ctx->forces_valid = true;
+        if ((st = read_status(ctx)) != PIMD_OK)
+            return st;
+    }
+    return pimd_get_tuning(ctx, best ? best : &ctx->last_tuning_out);
+}
+
+pimd_status pimd_time_stages(pimd_ctx *ctx, int32_t n_reps, double *ms_host)
+{
+    if (!ctx || !ms_host || n_reps < 1)
+        return PIMD_E_ARG;
+    if (!ctx->state_set) {
+        ctx->err = "state not set";
+        return PIMD_E_STATE;
+    }
+    if (ctx->potential != PIMD_POT_BPNN) {
+        ctx->err = "stage timing needs the neural potential";
+        return PIMD_E_STATE;
+    }
+    DevBuffers &d = ctx->d;
+    pimd_status st = run_forces(ctx, d.q, d.E_bead, d.F, nullptr);
+    if (st != PIMD_OK)
+        return st;
+    ctx->forces_valid = true;
+    hipEvent_t ev[2];
+    HIPCHK(ctx, hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        ctx->err = "hipEventCreate failed";
+        return PIMD_E_DEVICE;
+    }
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < PIMD_N_FORCE_STAGES && e == hipSuccess; ++k) {
+        (void)hipEventRecord(ev[0], ctx->stream);
+        for (int r = 0; r < n_reps; ++r)
+            launch_force_stage(ctx, k, d.q, d.E_bead, d.F, nullptr);
+        (void)hipEventRecord(ev[1], ctx->stream);
+        e = hipEventSynchronize(ev[1]);
+        float ms = 0.0f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        ms_host[k] = (double)ms / n_reps;
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (e != hipSuccess) {
+        ctx->err = std::string("stage timing: ") + hipGetErrorString(e);
+        return PIMD_E_DEVICE;
+    }
+    CHECK_LAUNCH(ctx);
+    return read_status(ctx);
 }
 
 pimd_status pimd_profile_stages(pimd_ctx *ctx, int32_t n_reps, double *ms_host)

@@ -77,7 +77,7 @@ struct MlpNets {
     MlpNet net[kMaxElements];
 };
 
-// 16-row tile of one element's rows for the MLP kernel.
+// Tile of up to 16, 32 or 64 rows of one element for the MLP kernel.
 struct MlpTile {
     int32_t e, row0, nrows, pad;
 };
@@ -127,7 +127,7 @@ struct DevBuffers {
     int32_t *bead_of_ba;
     int32_t *species_atom;         // [sum N]
     int32_t *elem_rows;            // rows grouped by element (MLP gather)
-    MlpTile *mlp_tiles;            // 16-row tiles over all elements
+    MlpTile *mlp_tiles;            // row tiles over all elements
     float *mass_atom;              // [sum N]
     SysInfo *sys;
     ModeInfo *modes;
@@ -140,6 +140,22 @@ struct DevBuffers {
     float *norm;                   // [n_el][2][D] shift, 1/scale
 };
 
+// Launch shapes chosen by the tuner (results do not depend on them: every
+// centre atom is still one wave, every MLP row the same MFMA chain).
+struct Tuning {
+    int32_t centre_waves;  // waves (centre atoms in flight) per workgroup of the per-centre kernels: 1, 2 or 4
+    int32_t centre_grid;   // 0: one wave per centre; > 0: at most this many workgroups, waves stride over centres
+    int32_t mlp_rows;      // rows per MLP workgroup tile: 16, 32 or 64
+    int32_t pad;
+};
+
+// Workgroups of a per-centre launch over B centres.
+inline int centre_grid(int B, const Tuning &tn)
+{
+    const int full = (B + tn.centre_waves - 1) / tn.centre_waves;
+    return tn.centre_grid > 0 && tn.centre_grid < full ? tn.centre_grid : (full > 0 ? full : 1);
+}
+
 // ---------------------------------------------------------------- launchers
 struct Sizes {
     int32_t n_sys, B, n_beads_total, n_atoms_total, ncol, total_cells, n_units, D, Kmax;
@@ -150,12 +166,14 @@ void launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
 void launch_wrap_bin(const float *q, const DevBuffers &d, const Sizes &z, hipStream_t s);
 void launch_cell_scan(const DevBuffers &d, const Sizes &z, hipStream_t s);
 void launch_cell_fill(const DevBuffers &d, const Sizes &z, hipStream_t s);
-void launch_neighbors(const DevBuffers &d, const Sizes &z, float rc2, int n_el, hipStream_t s);
-void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &dp, hipStream_t s);
+void launch_neighbors(const DevBuffers &d, const Sizes &z, float rc2, int n_el, const Tuning &tn, hipStream_t s);
+void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s);
 // mlp_mode: 0 FP32 operands; 1 BF16 operands, three-term split; 2 BF16 operands, one term; 3 FP64
-void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int mlp_mode, hipStream_t s);
-void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, hipStream_t s);
-void launch_assemble_forces(const DevBuffers &d, const Sizes &z, float *F, hipStream_t s);
+// rows: rows per tile of d.mlp_tiles (16, 32 or 64; mode 3 takes 16 only)
+void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int mlp_mode, int rows,
+                hipStream_t s);
+void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s);
+void launch_assemble_forces(const DevBuffers &d, const Sizes &z, float *F, const Tuning &tn, hipStream_t s);
 void launch_bead_sums(const DevBuffers &d, const Sizes &z, float *E_bead, float *W_bead, bool virial,
                       hipStream_t s);
 void launch_harmonic(const float *q, const DevBuffers &d, const Sizes &z, float k_over_m,

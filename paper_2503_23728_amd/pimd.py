@@ -16,7 +16,7 @@ import ctypes
 import numpy as np
 import torch
 
-from . import abi
+from . import abi, tuning
 
 
 def _check(st, ctx=None):
@@ -105,6 +105,7 @@ class Pimd:
                  omega=0.0, max_neighbors=0, masses=None, device="cuda:0", stream=None):
         self.device = torch.device(device)
         self.systems = list(systems)
+        self.model, self.precision, self.max_neighbors = model, precision, max_neighbors
         self.cfg, self._keep = make_config(self.systems, model, dt, tau0, pile_lambda, seed, precision,
                                            potential, omega, max_neighbors, masses)
         st, nbytes = abi.pimd_workspace_size(self.cfg)
@@ -185,11 +186,56 @@ class Pimd:
     def set_graph(self, enabled):
         _check(abi.pimd_set_graph(self.ctx, enabled), self.ctx)
 
+    def get_tuning(self):
+        """The launch shape of the force kernels: {centre_waves, centre_grid, mlp_rows}."""
+        st, t = abi.pimd_get_tuning(self.ctx)
+        _check(st, self.ctx)
+        return {f: getattr(t, f) for f in tuning.FIELDS}
+
+    def set_tuning(self, **shape):
+        cur = self.get_tuning()
+        cur.update(shape)
+        t = abi.pimd_tuning(cur["centre_waves"], cur["centre_grid"], cur["mlp_rows"], 0)
+        _check(abi.pimd_set_tuning(self.ctx, t), self.ctx)
+
+    def tuning_key(self):
+        props = torch.cuda.get_device_properties(self.device)
+        arch = getattr(props, "gcnArchName", props.name)
+        return tuning.config_key(arch, props.multi_processor_count, self.systems, self.model, self.precision,
+                                 self.max_neighbors)
+
+    def autotune(self, n_reps=5, cache=True):
+        """Pick the fastest launch shape for this batch (needs the state set).
+
+        With cache=True a shape stored for the same GPU and configuration is
+        applied without timing; otherwise pimd_autotune sweeps the candidates
+        on the current positions and the winner is stored.  Returns the shape
+        and whether it came from the cache."""
+        key = self.tuning_key()
+        if cache:
+            hit = tuning.load(key)
+            if hit is not None:
+                self.set_tuning(**hit)
+                return hit, True
+        st, t = abi.pimd_autotune(self.ctx, int(n_reps))
+        _check(st, self.ctx)
+        shape = {f: getattr(t, f) for f in tuning.FIELDS}
+        if cache:
+            tuning.store(key, shape)
+        return shape, False
+
     def profile_stages(self, n_reps):
         """Mean ms per step of each stage (abi.STAGE_NAMES), HIP events on the context stream."""
         st, ms = abi.pimd_profile_stages(self.ctx, int(n_reps))
         _check(st, self.ctx)
         return dict(zip(abi.STAGE_NAMES, ms))
+
+    def time_stages(self, n_reps):
+        """Mean ms of one run of each force stage (abi.FORCE_STAGE_NAMES), each stage
+        enqueued n_reps times back to back between HIP events; the state does not move."""
+        st, ms = abi.pimd_time_stages(self.ctx, int(n_reps))
+        _check(st, self.ctx)
+        return dict(zip(abi.FORCE_STAGE_NAMES, ms))
 
     def work_counts(self):
         """(pairs, triplets, triplets with r_jk < cutoff) of the last force evaluation."""

@@ -234,6 +234,12 @@ def test_stage_profile_and_eager_steps_match_graph_steps():
     assert set(ms) == {"integrate_pre", "neighbors", "descriptors", "mlp", "adjoint", "forces", "integrate_post"}
     assert all(v >= 0 for v in ms.values())
     assert a.get_state()[3] == 5
+    # gap-free kernel timing leaves the state and the forces of the positions alone
+    q5, p5, F5, _ = a.get_state()
+    kt = a.time_stages(3)
+    assert set(kt) == {"neighbors", "descriptors", "mlp", "adjoint", "forces"} and all(v > 0 for v in kt.values())
+    q6, p6, F6, s6 = a.get_state()
+    assert s6 == 5 and torch.equal(q5, q6) and torch.equal(p5, p6) and torch.equal(F5, F6)
 
 
 def test_forces_are_bitwise_deterministic():
@@ -351,3 +357,66 @@ def test_step_before_state_is_an_order_error():
     with pytest.raises(PimdError) as e:
         eng.step(1)
     assert e.value.status == PIMD_E_STATE
+
+
+# ---------------------------------------------------------------- launch shapes / autotuner
+
+@pytest.mark.parametrize("name", ["water64-P32", "fad-P4"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_every_launch_shape_gives_bitwise_identical_results(name, prec):
+    wl = WORKLOADS[name]()
+    say(f"launch shapes {name} {prec}")
+    eng = _engine(wl, precision=prec)
+    q = torch.from_numpy(_q(wl, seed=9)).cuda()
+    E0, F0, W0 = eng.energy_forces(q, virial=True)
+    x0 = eng.debug_descriptors()
+    for waves in (1, 2, 4):
+        for grid in (0, 7, 300):
+            for rows in (16, 32, 64):
+                eng.set_tuning(centre_waves=waves, centre_grid=grid, mlp_rows=rows)
+                E, F, W = eng.energy_forces(q, virial=True)
+                assert torch.equal(E, E0) and torch.equal(F, F0) and torch.equal(W, W0), (waves, grid, rows)
+                assert torch.equal(eng.debug_descriptors(), x0), (waves, grid, rows)
+
+
+def test_autotune_picks_a_valid_shape_and_the_cache_reapplies_it(tmp_path, monkeypatch):
+    from paper_2503_23728_amd import tuning
+    monkeypatch.setenv("PIMD_TUNING_CACHE", str(tmp_path / "tuning.json"))
+    wl = WORKLOADS["water64-P32"]()
+    say("autotune")
+    q0, p0 = S.initial_state(wl)
+    a = _engine(wl, precision="bf16")
+    a.set_state(torch.from_numpy(q0).cuda(), torch.from_numpy(p0).cuda())
+    _, _, F_before, step0 = a.get_state()
+    shape, cached = a.autotune(n_reps=2)
+    assert not cached
+    assert shape["centre_waves"] in (1, 2, 4) and shape["mlp_rows"] in (16, 32, 64) and shape["centre_grid"] >= 0
+    # the state does not move and the forces are those of the same positions
+    _, _, F_after, step1 = a.get_state()
+    assert step1 == step0 and torch.equal(F_before, F_after)
+    assert tuning.load(a.tuning_key()) == shape
+    b = _engine(wl, precision="bf16")
+    b.set_state(torch.from_numpy(q0).cuda(), torch.from_numpy(p0).cuda())
+    shape_b, cached_b = b.autotune(n_reps=2)
+    assert cached_b and shape_b == shape and b.get_tuning() == shape
+    # tuned and untuned contexts step identically
+    a.step(3)
+    b.set_tuning(centre_waves=4, centre_grid=0, mlp_rows=16)
+    b.step(3)
+    assert torch.equal(a.get_state()[0], b.get_state()[0])
+
+
+def test_bad_launch_shapes_are_rejected():
+    from paper_2503_23728_amd.abi import PimdError, PIMD_E_ARG, PIMD_E_UNSUPPORTED
+    wl = WORKLOADS["fad-P4"]()
+    eng = _engine(wl)
+    for bad in ({"centre_waves": 3}, {"centre_waves": 8}, {"mlp_rows": 48}, {"centre_grid": -1}):
+        with pytest.raises(PimdError) as ei:
+            eng.set_tuning(**bad)
+        assert ei.value.status == PIMD_E_ARG
+    f64 = _engine(wl, precision="fp64-mlp")
+    with pytest.raises(PimdError) as ei:
+        f64.set_tuning(mlp_rows=32)
+    assert ei.value.status == PIMD_E_UNSUPPORTED
+    with pytest.raises(PimdError):
+        eng.autotune(n_reps=1, cache=False)     # no state yet
