@@ -93,8 +93,10 @@ def time_steps(eng, steps, warmup):
     return wall, start.elapsed_time(stop) / 1e3
 
 
-def plain_fp32(wl, steps, warmup, device):
-    """The comparison path: FP32 MLP, no graph, one context per system."""
+def plain_fp32(wl, steps, warmup, device, shape=None):
+    """The comparison path: FP32 MLP, no graph, one context per system (with the
+    launch shape of the timed path, so the two differ only in MLP precision,
+    batching and graph replay)."""
     import torch
     from paper_2503_23728_amd import synthetic as S
     from paper_2503_23728_amd.pimd import Pimd
@@ -106,6 +108,8 @@ def plain_fp32(wl, steps, warmup, device):
         e = Pimd(
             [s], wl.model, wl.dt, wl.tau0, wl.pile_lambda, wl.philox_seed, precision="fp32", device=device)
         e.set_graph(False)
+        if shape is not None:
+            e.set_tuning(**shape)
         e.set_state(torch.from_numpy(q[off:off + n]).to(device), torch.from_numpy(p[off:off + n]).to(device))
         engines.append(e)
         off += n
@@ -248,7 +252,7 @@ def main():
     }
     if not args.no_plain:
         psteps = max(1, min(args.steps, 50 if len(wl.systems) > 1 else args.steps))
-        pwall = plain_fp32(wl, psteps, min(args.warmup, 5), device)
+        pwall = plain_fp32(wl, psteps, min(args.warmup, 5), device, shape)
         pval = B * psteps / pwall
         out["plain_fp32"] = {"value": pval, "steps": psteps, "ms_per_step": 1e3 * pwall / psteps,
                              "launch": "eager, one context per system"}

@@ -125,4 +125,32 @@ __device__ __forceinline__ float thermostat_normal(uint32_t k0, uint32_t k1, int
     return comp == 1 ? r * sn : r * cs;
 }
 
+// Centres of one wave in the per-centre kernels.  Workgroups are dispatched
+// round-robin over the 8 XCDs of the chip, each with its own L2; the logical
+// block index gives XCD x the contiguous block range it serves, and each wave
+// takes a contiguous run of the centre order (cell order, so consecutive
+// centres share their neighbourhoods).  A bijection of [0, G) for any G.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_block(int b, int G)
+{
+    const int x = b % kXcds, k = b / kXcds, q = G / kXcds, r = G % kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
+struct CentreRange {
+    int begin, end;
+};
+
+__device__ __forceinline__ CentreRange centre_range(int B)
+{
+    const int wpg = blockDim.x >> 6, w = threadIdx.x >> 6;
+    const int nw = gridDim.x * wpg;
+    const int v = xcd_block(blockIdx.x, gridDim.x) * wpg + w;
+    const int per = (B + nw - 1) / nw;
+    const int b0 = v * per;
+    return CentreRange{b0 < B ? b0 : B, b0 + per < B ? b0 + per : B};
+}
+
 }  // namespace pimd
+

@@ -166,10 +166,6 @@ struct BlockWalk {
             s1 = n_par - 1;
         }
     }
-    __device__ bool active(bool own_ok, int b, int s) const
-    {
-        return own_ok && (!tri || 2 * s != n_own || b < s);
-    }
 };
 
 constexpr int kQueue = 128;   // in-range slot pairs waiting per wave (< 64 + one shift's 64)
@@ -182,30 +178,36 @@ template <typename Body>
 __device__ __forceinline__ void for_each_triplet_in_range(const BlockWalk &bw, const float4 *recD, float rc2,
                                                           uint32_t *queue, Body &&body)
 {
+    if (bw.s1 < bw.s0)
+        return;   // fewer than two slots in a triangle, or an empty partner group
     const int lane = lane_id();
-    const uint64_t below = lanes_below_mask();
+    // the half shift of an even triangle pairs only the own slots b < s
+    const int s_half = (bw.tri && 2 * bw.s1 == bw.n_own) ? bw.s1 : -1;
     int qn = 0;
     for (int b0 = 0; b0 < bw.n_own; b0 += kWave) {
         const int b = b0 + lane;
         const bool own_ok = b < bw.n_own;
-        const int ia = bw.o_own + (own_ok ? b : 0);
+        const int bb = own_ok ? b : 0;
+        const int ia = bw.o_own + bb;
         const float4 A = recD[ia];
-        const int bm = bw.tri ? b : ((own_ok && bw.n_par > 0) ? b % bw.n_par : 0);
+        // partner slot p = (b + s) mod n_par, advanced by one per shift
+        int p = (bw.tri ? bb : bb % bw.n_par) + bw.s0;
+        p -= p >= bw.n_par ? bw.n_par : 0;
         for (int s = bw.s0; s <= bw.s1; ++s) {
-            bool inr = false;
-            int ic = 0;
-            if (bw.active(own_ok, b, s)) {
-                int p = bm + s;
-                p -= p >= bw.n_par ? bw.n_par : 0;
-                ic = bw.o_par + p;
-                const float4 C = recD[ic];
-                const float jx = C.x - A.x, jy = C.y - A.y, jz = C.z - A.z;
-                inr = jx * jx + jy * jy + jz * jz < rc2;
-            }
+            const int ic = bw.o_par + p;
+            const float4 C = recD[ic];
+            const float jx = C.x - A.x, jy = C.y - A.y, jz = C.z - A.z;
+            // bitwise (not short-circuit) so the test stays branch-free
+            const bool inr = own_ok & ((s != s_half) | (b < s)) & (jx * jx + jy * jy + jz * jz < rc2);
             const uint64_t m = __ballot(inr);
-            if (inr)
-                queue[qn + __popcll(m & below)] = ((uint32_t)ia << 16) | (uint32_t)ic;
-            qn += __popcll(m);
+            if (inr) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                queue[qn + (int)below] = ((uint32_t)ia << 16) | (uint32_t)ic;
+            }
+            qn = __builtin_amdgcn_readfirstlane(qn + (int)__popcll(m));   // uniform: a scalar branch below
+            ++p;
+            p -= p >= bw.n_par ? bw.n_par : 0;
             if (qn >= kWave) {
                 wave_sync();
                 const uint32_t q = queue[lane];
@@ -259,6 +261,7 @@ template <int NETA>
 __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ posu,
                                                      const BeadInfo *__restrict__ beads,
                                                      const int32_t *__restrict__ bead_of_ba,
+                                                     const int32_t *__restrict__ order,
                                                      const int32_t *__restrict__ nbr,
                                                      const int32_t *__restrict__ nbr_cnt,
                                                      const int32_t *__restrict__ nbr_grp,
@@ -266,7 +269,7 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
                                                      float *__restrict__ xhat, int B)
 {
     extern __shared__ float4 lds4[];
-    const int lane = lane_id(), w = threadIdx.x >> 6, wpg = blockDim.x >> 6;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
     const int Dcap = (dp.D + 3) & ~3;
     float4 *base = lds4 + w * (3 * dp.Kmax + Dcap / 4 + kQueue / 4);
     const Recs rec{base, base + dp.Kmax, base + 2 * dp.Kmax};
@@ -277,7 +280,10 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
     const float nel0 = -dp.ang_eta[0] * 1.4426950408889634f, nel1 = -dp.ang_eta[1] * 1.4426950408889634f;
     const float inv_rc = 1.0f / dp.rc;
 
-    for (int i = blockIdx.x * wpg + w; i < B; i += gridDim.x * wpg) {
+    const CentreRange cr = centre_range(B);
+    for (int ci = cr.begin; ci < cr.end; ++ci) {
+        // wave-uniform: the per-centre values below live in scalar registers
+        const int i = __builtin_amdgcn_readfirstlane(order ? order[ci] : ci);
         const BeadInfo bi = beads[bead_of_ba[i]];
         const float4 pi = posu[i];
         const int zi = __float_as_int(pi.w);
@@ -371,7 +377,7 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
 // ---------------------------------------------------------------------------
 template <int NETA>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adjoint(const float4 *__restrict__ posu, const BeadInfo *__restrict__ beads,
-                                                 const int32_t *__restrict__ bead_of_ba,
+                                                 const int32_t *__restrict__ bead_of_ba, const int32_t *__restrict__ order,
                                                  const int32_t *__restrict__ nbr,
                                                  const int32_t *__restrict__ nbr_cnt,
                                                  const int32_t *__restrict__ nbr_grp,
@@ -379,7 +385,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                                                  float4 *__restrict__ vslot, float *__restrict__ vir_atom, int B)
 {
     extern __shared__ float4 lds4[];
-    const int lane = lane_id(), w = threadIdx.x >> 6, wpg = blockDim.x >> 6;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
     const int Dcap = (dp.D + 3) & ~3;
     char *base = reinterpret_cast<char *>(lds4) + w * adjoint_wave_bytes(dp);
     const Recs rec{reinterpret_cast<float4 *>(base), reinterpret_cast<float4 *>(base) + dp.Kmax, nullptr};
@@ -394,7 +400,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const float nel0 = -dp.ang_eta[0] * 1.4426950408889634f, nel1 = -dp.ang_eta[1] * 1.4426950408889634f;
     const float inv_rc = 1.0f / dp.rc;
 
-    for (int i = blockIdx.x * wpg + w; i < B; i += gridDim.x * wpg) {
+    const CentreRange cr = centre_range(B);
+    for (int ci = cr.begin; ci < cr.end; ++ci) {
+        // wave-uniform: the per-centre values below live in scalar registers
+        const int i = __builtin_amdgcn_readfirstlane(order ? order[ci] : ci);
         const BeadInfo bi = beads[bead_of_ba[i]];
         const float4 pi = posu[i];
         for (int f = lane; f < dp.D; f += kWave)
@@ -508,13 +517,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 // i's key in j's sorted list); no atomics, fixed summation order.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_assemble_forces(const float4 *__restrict__ pos4,
+                                                         const int32_t *__restrict__ order,
                                                          const int32_t *__restrict__ nbr,
                                                          const int32_t *__restrict__ nbr_cnt,
                                                          const float4 *__restrict__ vslot, int Kmax,
                                                          float *__restrict__ F, uint32_t *__restrict__ status, int B)
 {
-    const int lane = lane_id(), w = threadIdx.x >> 6, wpg = blockDim.x >> 6;
-    for (int i = blockIdx.x * wpg + w; i < B; i += gridDim.x * wpg) {
+    const int lane = lane_id();
+    const CentreRange cr = centre_range(B);
+    for (int ci = cr.begin; ci < cr.end; ++ci) {
+        // wave-uniform: the per-centre values below live in scalar registers
+        const int i = __builtin_amdgcn_readfirstlane(order ? order[ci] : ci);
         const int K = nbr_cnt[i];
         const int key_i = (__float_as_int(pos4[i].w) << kKeyShift) | i;
         const int32_t *row = nbr + (int64_t)i * Kmax;
@@ -609,12 +622,16 @@ __global__ __launch_bounds__(256) void k_work_counts(const float4 *__restrict__ 
                                                      const int32_t *__restrict__ nbr_cnt, DescParams dp,
                                                      unsigned long long *__restrict__ counts, int B)
 {
+    const int32_t *order = nullptr;   // counts do not depend on the centre order
     extern __shared__ float4 lds4[];
-    const int lane = lane_id(), w = threadIdx.x >> 6, wpg = blockDim.x >> 6;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
     float4 *base = lds4 + w * 3 * dp.Kmax;
     const Recs rec{base, base + dp.Kmax, base + 2 * dp.Kmax};
     unsigned long long pairs = 0, trip = 0, trip_in = 0;
-    for (int i = blockIdx.x * wpg + w; i < B; i += gridDim.x * wpg) {
+    const CentreRange cr = centre_range(B);
+    for (int ci = cr.begin; ci < cr.end; ++ci) {
+        // wave-uniform: the per-centre values below live in scalar registers
+        const int i = __builtin_amdgcn_readfirstlane(order ? order[ci] : ci);
         const BeadInfo bi = beads[bead_of_ba[i]];
         const int K = stage_neighbors<1, false>(i, posu[i], bi, nbr, nbr_cnt, posu, dp, rec,
                                                 [](int, int, const float3 &, float, float, float, float, float) {});
@@ -674,10 +691,10 @@ void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &d
     const size_t lds = wpg * forward_wave_bytes(dp);
     if (dp.n_ang_eta == 2)
         hipLaunchKernelGGL(k_descriptors<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, z.B);
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, z.B);
     else
         hipLaunchKernelGGL(k_descriptors<1>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, z.B);
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, z.B);
 }
 
 void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s)
@@ -686,10 +703,10 @@ void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, c
     const size_t lds = wpg * adjoint_wave_bytes(dp);
     if (dp.n_ang_eta == 2)
         hipLaunchKernelGGL(k_adjoint<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           d.nbr, d.nbr_cnt, d.nbr_grp, d.dEdG, dp, d.vslot, d.vir_atom, z.B);
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_grp, d.dEdG, dp, d.vslot, d.vir_atom, z.B);
     else
         hipLaunchKernelGGL(k_adjoint<1>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           d.nbr, d.nbr_cnt, d.nbr_grp, d.dEdG, dp, d.vslot, d.vir_atom, z.B);
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_grp, d.dEdG, dp, d.vslot, d.vir_atom, z.B);
 }
 
 void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &dp, unsigned long long *counts,
@@ -703,7 +720,7 @@ void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &d
 void launch_assemble_forces(const DevBuffers &d, const Sizes &z, float *F, const Tuning &tn, hipStream_t s)
 {
     hipLaunchKernelGGL(k_assemble_forces, dim3(centre_grid(z.B, tn)), dim3(kWave * tn.centre_waves), 0, s, d.pos4,
-                       d.nbr, d.nbr_cnt, d.vslot, z.Kmax, F, d.status, z.B);
+                       centre_order(d, z), d.nbr, d.nbr_cnt, d.vslot, z.Kmax, F, d.status, z.B);
 }
 
 void launch_bead_sums(const DevBuffers &d, const Sizes &z, float *E_bead, float *W_bead, bool virial, hipStream_t s)

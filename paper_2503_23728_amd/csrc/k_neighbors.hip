@@ -108,9 +108,9 @@ __global__ __launch_bounds__(256) void k_cell_fill(const BeadInfo *__restrict__ 
     if (ba >= B)
         return;
     const BeadInfo bi = beads[bead_of_ba[ba]];
-    if (!bi.periodic)
-        return;
-    cell_atoms[bi.ba0 + cell_start[atom_cell[ba]] + atom_slot[ba]] = ba;
+    // rows of a bead in cell order (the centre order of the per-centre
+    // kernels); a bead without a box keeps its own row order
+    cell_atoms[bi.periodic ? bi.ba0 + cell_start[atom_cell[ba]] + atom_slot[ba] : ba] = ba;
 }
 
 // Keys buffered per wave: up to Kmax + 63 candidates (a pass may overshoot
@@ -147,16 +147,20 @@ __global__ __launch_bounds__(256) void k_neighbors(const float4 *__restrict__ po
                                                    const int32_t *__restrict__ bead_of_ba,
                                                    const int32_t *__restrict__ cell_count,
                                                    const int32_t *__restrict__ cell_start,
-                                                   const int32_t *__restrict__ cell_atoms, float rc2, int Kmax,
+                                                   const int32_t *__restrict__ cell_atoms,
+                                                   const int32_t *__restrict__ order, float rc2, int Kmax,
                                                    int n_el, int32_t *__restrict__ nbr, int32_t *__restrict__ nbr_cnt,
                                                    int32_t *__restrict__ nbr_grp, uint32_t *__restrict__ status, int B)
 {
     extern __shared__ int32_t nl_lds[];
     const int lane = lane_id();
-    const int w = threadIdx.x >> 6, wpg = blockDim.x >> 6;
+    const int w = threadIdx.x >> 6;
     int32_t *buf = nl_lds + w * nl_buffer(Kmax);
     const uint64_t below = lanes_below_mask();
-    for (int i = blockIdx.x * wpg + w; i < B; i += gridDim.x * wpg) {
+    const CentreRange cr = centre_range(B);
+    for (int ci = cr.begin; ci < cr.end; ++ci) {
+        // wave-uniform: the per-centre values below live in scalar registers
+        const int i = __builtin_amdgcn_readfirstlane(order ? order[ci] : ci);
         const BeadInfo bi = beads[bead_of_ba[i]];
         const float4 pi = pos4[i];
         int count = 0;
@@ -304,7 +308,8 @@ void launch_neighbors(const DevBuffers &d, const Sizes &z, float rc2, int n_el, 
     const int wpg = tn.centre_waves;
     const size_t lds = (size_t)wpg * nl_buffer(z.Kmax) * sizeof(int32_t);
     hipLaunchKernelGGL(k_neighbors, dim3(centre_grid(z.B, tn)), dim3(kWave * wpg), lds, s, d.pos4, d.beads,
-                       d.bead_of_ba, d.cell_count, d.cell_start, d.cell_atoms, rc2, z.Kmax, n_el, d.nbr, d.nbr_cnt,
+                       d.bead_of_ba, d.cell_count, d.cell_start, d.cell_atoms, centre_order(d, z), rc2, z.Kmax, n_el,
+                       d.nbr, d.nbr_cnt,
                        d.nbr_grp, d.status, z.B);
 }
 

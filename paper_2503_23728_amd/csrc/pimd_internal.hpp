@@ -162,6 +162,14 @@ struct Sizes {
     int32_t any_periodic;
 };
 
+// Order in which the per-centre kernels visit the rows: cell order within
+// every bead (written by the cell fill) when any system has a box, else the
+// row order itself (null).
+inline const int32_t *centre_order(const DevBuffers &d, const Sizes &z)
+{
+    return z.any_periodic ? d.cell_atoms : nullptr;
+}
+
 void launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
 void launch_wrap_bin(const float *q, const DevBuffers &d, const Sizes &z, hipStream_t s);
 void launch_cell_scan(const DevBuffers &d, const Sizes &z, hipStream_t s);
