@@ -130,7 +130,7 @@ typedef struct {
     int32_t potential;                 /* PIMD_POT_* */
     const pimd_bpnn_model *model;      /* PIMD_POT_BPNN: the model; HARMONIC: masses only */
     double harmonic_omega_per_fs;      /* PIMD_POT_HARMONIC: V = sum 1/2 m w^2 |q|^2 */
-    int32_t max_neighbors;             /* neighbour slots per atom, 0 => 128; <= 256 */
+    int32_t max_neighbors;             /* neighbour slots per atom: 0 => 128; a multiple of 16, <= 256 */
 } pimd_config;
 
 /* Finite-P estimators of one system (Sec. 2.1; virial kinetic energy of
@@ -233,12 +233,15 @@ pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled);
  *                 many workgroups, whose waves stride over the centres
  *   mlp_rows      rows per MLP workgroup tile: 16 (default), 32 or 64;
  *                 PIMD_PREC_FP64_MLP takes 16 only
- *   reserved      must be 0 */
+ *   neighbor_cells  periodic neighbour search: 0 = one wave per centre
+ *                 gathering its stencil from global memory, 1 = one workgroup
+ *                 per cell with the stencil staged in LDS once for all of the
+ *                 cell's centres (default 1 from 4096 cells on, else 0) */
 typedef struct {
     int32_t centre_waves;
     int32_t centre_grid;
     int32_t mlp_rows;
-    int32_t reserved;
+    int32_t neighbor_cells;
 } pimd_tuning;
 
 pimd_status pimd_get_tuning(const pimd_ctx *ctx, pimd_tuning *out);
@@ -253,7 +256,8 @@ pimd_status pimd_set_tuning(pimd_ctx *ctx, const pimd_tuning *t);
  * evaluations per candidate after one untimed one, HIP events on the context
  * stream) for every centre_waves x centre_grid candidate (centre_grid from 0
  * and 2, 4, 8, 16 workgroups per compute unit), then for every mlp_rows
- * candidate with the best centre shape; applies the fastest (a candidate
+ * candidate with the best centre shape, then for the other neighbor_cells
+ * value (systems with a box); applies the fastest (a candidate
  * replaces the current best only when at least 1% faster) and writes it to
  * best (may be NULL).  The state does not advance; the forces left behind are
  * those of the current positions.  Needs pimd_set_state first

@@ -432,11 +432,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         for (int e1 = 0; e1 < dp.n_el; ++e1)
             for (int e2 = e1; e2 < dp.n_el; ++e2, ++pair) {
                 const BlockWalk bw(e1, e2, gcnt, goff);
-                // block coefficients with the 2^(1-zeta) factors folded in
-                float gq[8 * NETA];
+                // block coefficients with the 2^(1-zeta) factors folded in, and
+                // those of dS/dcos (d/dc (1 +- c)^zeta = +-zeta (1 +- c)^(zeta-1))
+                float gq[8 * NETA], gd[8 * NETA];
 #pragma unroll
                 for (int q = 0; q < 8 * NETA; ++q)
                     gq[q] = gl[Frad + pair * dp.n_ang + q] * block_scale(q);
+#pragma unroll
+                for (int ie = 0; ie < NETA; ++ie) {
+                    const float *g = gq + 8 * ie;
+                    float *h = gd + 8 * ie;
+                    h[0] = g[0] - g[1];
+                    h[1] = 2.0f * g[2];
+                    h[2] = 2.0f * g[3];
+                    h[3] = 4.0f * g[4];
+                    h[4] = 4.0f * g[5];
+                    h[5] = 8.0f * g[6];
+                    h[6] = 8.0f * g[7];
+                    h[7] = 0.0f;
+                }
                 for_each_triplet_in_range(bw, rec.D, dp.rc2, queue, [&](uint32_t ia, uint32_t ic, bool ok) {
                     if (!ok)
                         return;
@@ -447,43 +461,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     const float inv_rjk = __builtin_amdgcn_rcpf(rjk);
                     float fcjk, dfcjk;
                     cutoff_fn(rjk * inv_rc, dp.pi_over_rc, fcjk, dfcjk);
-                    const float cs = (Ad.x * Cd.x + Ad.y * Cd.y + Ad.z * Cd.z) * (Ad.w * Cd.w);
+                    const float iab = Ad.w * Cd.w;
+                    const float cs = (Ad.x * Cd.x + Ad.y * Cd.y + Ad.z * Cd.z) * iab;
                     const float p1 = 1.0f + cs, m1 = 1.0f - cs;
                     const float p2 = p1 * p1, m2 = m1 * m1;
                     const float p3 = p2 * p1, m3 = m2 * m1;
                     const float p4 = p2 * p2, m4 = m2 * m2;
                     const float p7 = p4 * p3, m7 = m4 * m3;
                     const float p8 = p4 * p4, m8 = m4 * m4;
+                    // per eta, with Y = exp(-eta r_jk^2) f_c(r_jk):
+                    //   dE/dcos:  Sd Ea Eb Y;  dE/dr_ij: S dEa Eb Y;  dE/dr_ik: S Ea dEb Y
+                    //   dE/dr_jk: S Ea Eb exp(-eta r_jk^2) (f_c' - 2 eta r_jk f_c)
                     float Pc = 0.0f, Pa = 0.0f, Pb = 0.0f, Pjk = 0.0f;
 #pragma unroll
                     for (int ie = 0; ie < NETA; ++ie) {
                         const float *g = gq + ie * 8;
+                        const float *h = gd + ie * 8;
                         const float S = g[0] * p1 + g[1] * m1 + g[2] * p2 + g[3] * m2 + g[4] * p4 + g[5] * m4 +
                                         g[6] * p8 + g[7] * m8;
-                        const float Sd = (g[0] - g[1]) + 2.0f * (g[2] * p1 - g[3] * m1) +
-                                         4.0f * (g[4] * p3 - g[5] * m3) + 8.0f * (g[6] * p7 - g[7] * m7);
-                        const float eta = dp.ang_eta[ie];
+                        const float Sd = h[0] + h[1] * p1 - h[2] * m1 + h[3] * p3 - h[4] * m3 + h[5] * p7 - h[6] * m7;
                         const float X = exp_small(ie == 0 ? nel0 : nel1, r2jk);
                         const float Ea = ie == 0 ? Ae.x : Ae.y, Eb = ie == 0 ? Ce.x : Ce.y;
                         const float dEa = ie == 0 ? Ae.z : Ae.w, dEb = ie == 0 ? Ce.z : Ce.w;
-                        const float Xf = X * fcjk;
+                        const float Y = X * fcjk;
+                        const float SY = S * Y;
                         const float EaEb = Ea * Eb;
-                        Pc += Sd * EaEb * Xf;
-                        Pa += S * dEa * Eb * Xf;
-                        Pb += S * Ea * dEb * Xf;
-                        Pjk += S * EaEb * X * (-2.0f * eta * rjk * fcjk + dfcjk);
+                        Pa = fmaf(dEa, Eb * SY, Pa);
+                        Pb = fmaf(dEb, Ea * SY, Pb);
+                        Pc = fmaf(Sd, EaEb * Y, Pc);
+                        const float gjk = fmaf(-2.0f * dp.ang_eta[ie] * rjk, fcjk, dfcjk);
+                        Pjk = fmaf(S * EaEb, X * gjk, Pjk);
                     }
+                    // dE/d d_ij = alpha_a d_ij + beta d_ik - gam d_jk and
+                    // dE/d d_ik = alpha_b d_ik + beta d_ij + gam d_jk with
+                    // d_jk = d_ik - d_ij, regrouped onto d_ij and d_ik
                     const float ia_ = Ad.w, ib_ = Cd.w;
-                    const float alpha_a = (Pa - Pc * cs * ia_) * ia_;
-                    const float alpha_b = (Pb - Pc * cs * ib_) * ib_;
-                    const float beta = Pc * ia_ * ib_;
+                    const float Pcs = Pc * cs;
                     const float gam = Pjk * inv_rjk;
-                    atomicAdd(&vx[ia], (double)(alpha_a * Ad.x + beta * Cd.x - gam * jx));
-                    atomicAdd(&vy[ia], (double)(alpha_a * Ad.y + beta * Cd.y - gam * jy));
-                    atomicAdd(&vz[ia], (double)(alpha_a * Ad.z + beta * Cd.z - gam * jz));
-                    atomicAdd(&vx[ic], (double)(alpha_b * Cd.x + beta * Ad.x + gam * jx));
-                    atomicAdd(&vy[ic], (double)(alpha_b * Cd.y + beta * Ad.y + gam * jy));
-                    atomicAdd(&vz[ic], (double)(alpha_b * Cd.z + beta * Ad.z + gam * jz));
+                    const float ka = (Pa - Pcs * ia_) * ia_ + gam;
+                    const float kc = (Pb - Pcs * ib_) * ib_ + gam;
+                    const float kb = Pc * iab - gam;
+                    atomicAdd(&vx[ia], (double)(ka * Ad.x + kb * Cd.x));
+                    atomicAdd(&vy[ia], (double)(ka * Ad.y + kb * Cd.y));
+                    atomicAdd(&vz[ia], (double)(ka * Ad.z + kb * Cd.z));
+                    atomicAdd(&vx[ic], (double)(kc * Cd.x + kb * Ad.x));
+                    atomicAdd(&vy[ic], (double)(kc * Cd.y + kb * Ad.y));
+                    atomicAdd(&vz[ic], (double)(kc * Cd.z + kb * Ad.z));
                 });
             }
         wave_sync();
@@ -513,13 +536,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 
 // ---------------------------------------------------------------------------
 // forces: F_i = sum_slots v[i][n] - sum_slots v[j][slot of i in j's list]
-// (the list is symmetric, so the reverse slot is found by binary search of
-// i's key in j's sorted list); no atomics, fixed summation order.
+// (the list is symmetric, so the reverse slot is the rank of i's key in j's
+// sorted list: two dependent 64-byte reads, j's fence row and one 16-key
+// segment, instead of a binary search); no atomics, fixed summation order.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_assemble_forces(const float4 *__restrict__ pos4,
                                                          const int32_t *__restrict__ order,
                                                          const int32_t *__restrict__ nbr,
                                                          const int32_t *__restrict__ nbr_cnt,
+                                                         const int32_t *__restrict__ fence,
                                                          const float4 *__restrict__ vslot, int Kmax,
                                                          float *__restrict__ F, uint32_t *__restrict__ status, int B)
 {
@@ -536,25 +561,36 @@ __global__ __launch_bounds__(256) void k_assemble_forces(const float4 *__restric
         for (int n = lane; n < K; n += kWave) {
             const float4 v = vslot[(int64_t)i * Kmax + n];
             const int j = row[n] & (int)kRowMask;
-            const int32_t *rj = nbr + (int64_t)j * Kmax;
-            int lo = 0, hi = nbr_cnt[j] - 1, m = -1;
-            while (lo <= hi) {
-                const int mid = (lo + hi) >> 1;
-                const int kv = rj[mid];
-                if (kv == key_i) {
-                    m = mid;
-                    break;
+            // reverse slot of i in j's sorted list: j's fence row (its count
+            // and every 16th key) picks the 16-key segment, the segment the slot
+            const int4 *fj = reinterpret_cast<const int4 *>(fence + (int64_t)j * kFence);
+            int seg = 0, Kj = 0;
+#pragma unroll
+            for (int c = 0; c < kFence / 4; ++c) {
+                const int4 f = fj[c];
+                Kj = c == 0 ? f.x : Kj;
+                seg += (c > 0 && f.x <= key_i) + (f.y <= key_i) + (f.z <= key_i) + (f.w <= key_i);
+            }
+            const int4 *sj = reinterpret_cast<const int4 *>(nbr + (int64_t)j * Kmax + 16 * seg);
+            int m = 16 * seg, hit = -1;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int4 kv = 16 * seg + 4 * c < Kj ? sj[c] : make_int4(0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF,
+                                                                            0x7FFFFFFF);
+                const int kk[4] = {kv.x, kv.y, kv.z, kv.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int pos = 16 * seg + 4 * c + e;
+                    const bool in = pos < Kj;
+                    m += (in && kk[e] < key_i) ? 1 : 0;
+                    hit = (in && kk[e] == key_i) ? pos : hit;
                 }
-                if (kv < key_i)
-                    lo = mid + 1;
-                else
-                    hi = mid - 1;
             }
             fx += (double)v.x;
             fy += (double)v.y;
             fz += (double)v.z;
-            if (m >= 0) {
-                const float4 u = vslot[(int64_t)j * Kmax + m];
+            if (hit >= 0 && hit == m) {
+                const float4 u = vslot[(int64_t)j * Kmax + hit];
                 fx -= (double)u.x;
                 fy -= (double)u.y;
                 fz -= (double)u.z;
@@ -720,7 +756,7 @@ void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &d
 void launch_assemble_forces(const DevBuffers &d, const Sizes &z, float *F, const Tuning &tn, hipStream_t s)
 {
     hipLaunchKernelGGL(k_assemble_forces, dim3(centre_grid(z.B, tn)), dim3(kWave * tn.centre_waves), 0, s, d.pos4,
-                       centre_order(d, z), d.nbr, d.nbr_cnt, d.vslot, z.Kmax, F, d.status, z.B);
+                       centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_fence, d.vslot, z.Kmax, F, d.status, z.B);
 }
 
 void launch_bead_sums(const DevBuffers &d, const Sizes &z, float *E_bead, float *W_bead, bool virial, hipStream_t s)

@@ -9,7 +9,11 @@
 // the O/B/A updates of that mode, and the inverse transform is the same dot
 // product with row j of C.  For P <= 128 this dense form costs about as much as
 // a real FFT and needs no bit reversal; HBM traffic (q, p, F once each) bounds
-// the kernel either way.
+// the kernel either way.  The state is float32 in memory; the transforms, the
+// O/B/A updates and their coefficients are FP64 in registers, because float32
+// coefficients (C not orthogonal, cos^2 + sin^2 != 1 at the 1e-7 level) change
+// the ring-polymer energy by a fixed amount every step, a drift that grows as
+// dt shrinks.
 //
 //   O: p~_k <- c1_k p~_k + sqrt(m) sig_T c2_k xi,   (kinetic-energy change -> heat bath)
 //   B: p~_k <- p~_k + dt/2 F~_k / MVV2E
@@ -26,7 +30,7 @@ struct IntegArgs {
     const SysInfo *sys;
     const ModeInfo *modes;
     const IntegUnit *units;
-    const float *cmat;
+    const double *cmat;
     const float *mass_atom;
     const int64_t *step;
     double *dke_part;
@@ -55,19 +59,19 @@ __device__ double block_sum_double(double v, double *red)
     return red[0];
 }
 
-// LDS: CT[P][P+1] | s0[256] | s1[256] | s2[256] | red[256] doubles
+// LDS (doubles): CT[P][P+1] | s0[256] | s1[256] | s2[256] | red[256]
 template <bool PRE>
 __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
 {
-    extern __shared__ float ism[];
+    extern __shared__ double ism[];
     const IntegUnit u = a.units[blockIdx.x];
     const SysInfo S = a.sys[u.sys];
     const int P = S.P, N = S.N;
-    float *CT = ism;
-    float *s0 = CT + P * (P + 1);
-    float *s1 = s0 + 256;
-    float *s2 = s1 + 256;
-    double *red = reinterpret_cast<double *>(s2 + 256);
+    double *CT = ism;
+    double *s0 = CT + P * (P + 1);
+    double *s1 = s0 + 256;
+    double *s2 = s1 + 256;
+    double *red = s2 + 256;
     const int tid = threadIdx.x;
     for (int idx = tid; idx < P * P; idx += 256) {
         const int j = idx / P, k = idx - j * P;
@@ -79,43 +83,43 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
     const int atom = col / 3, cc = col - 3 * (col / 3);
     const int64_t row = (int64_t)S.ba0 + (int64_t)kk * N + atom;   // bead kk (loads) = mode kk (noise)
     const int64_t step = *a.step;
-    float m = 1.0f;
+    double m = 1.0;
     if (valid) {
-        m = a.mass_atom[S.atom0 + atom];
-        s0[tid] = a.p[row * 3 + cc];
-        s1[tid] = a.F[row * 3 + cc];
+        m = (double)a.mass_atom[S.atom0 + atom];
+        s0[tid] = (double)a.p[row * 3 + cc];
+        s1[tid] = (double)a.F[row * 3 + cc];
         if (PRE)
-            s2[tid] = a.q[row * 3 + cc];
+            s2[tid] = (double)a.q[row * 3 + cc];
     }
     __syncthreads();
-    const float kick = 0.5f * a.dt / (float)kMvv2e;
-    float dke = 0.0f;
-    float pt = 0.0f, qt = 0.0f;
+    const double kick = 0.5 * (double)a.dt / kMvv2e;
+    double dke = 0.0;
+    double pt = 0.0, qt = 0.0;
     if (valid) {
-        const float *ct = CT + kk * (P + 1);
-        const float *sp = s0 + cl * P, *sf = s1 + cl * P, *sq = s2 + cl * P;
+        const double *ct = CT + kk * (P + 1);
+        const double *sp = s0 + cl * P, *sf = s1 + cl * P, *sq = s2 + cl * P;
         const ModeInfo M = a.modes[S.mode0 + kk];
-        const float sig = sqrtf(m) * S.sig_T;
+        const double sig = sqrt(m) * (double)S.sig_T;
         if (PRE) {
-            float Ft = 0.0f;
+            double Ft = 0.0;
             for (int j = 0; j < P; ++j) {
-                const float c = ct[j];
+                const double c = ct[j];
                 pt += c * sp[j];
                 Ft += c * sf[j];
                 qt += c * sq[j];
             }
             // O(dt/2), half 0
-            const float xi = noise_value(a, 0, row, cc, step);
-            const float pn = M.c1 * pt + sig * M.c2 * xi;
-            dke = 0.5f * (pn * pn - pt * pt) / m * (float)kMvv2e;
+            const double xi = (double)noise_value(a, 0, row, cc, step);
+            const double pn = M.c1 * pt + sig * M.c2 * xi;
+            dke = 0.5 * (pn * pn - pt * pt) / m * kMvv2e;
             pt = pn + kick * Ft;  // B(dt/2)
             // A(dt)
             if (kk == 0) {
-                qt += a.dt * pt / m;
+                qt += (double)a.dt * pt / m;
             } else {
-                const float mw = m * M.w;
-                const float qn = M.sw * pt / mw + M.cw * qt;
-                const float pn2 = M.cw * pt - mw * M.sw * qt;
+                const double mw = m * M.w;
+                const double qn = M.sw * pt / mw + M.cw * qt;
+                const double pn2 = M.cw * pt - mw * M.sw * qt;
                 qt = qn;
                 pt = pn2;
             }
@@ -123,9 +127,9 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
             // B(dt/2) in bead space, then to modes
             for (int j = 0; j < P; ++j)
                 pt += ct[j] * (sp[j] + kick * sf[j]);
-            const float xi = noise_value(a, 1, row, cc, step);
-            const float pn = M.c1 * pt + sig * M.c2 * xi;
-            dke = 0.5f * (pn * pn - pt * pt) / m * (float)kMvv2e;
+            const double xi = (double)noise_value(a, 1, row, cc, step);
+            const double pn = M.c1 * pt + sig * M.c2 * xi;
+            dke = 0.5 * (pn * pn - pt * pt) / m * kMvv2e;
             pt = pn;
         }
     }
@@ -138,19 +142,19 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
     __syncthreads();
     if (valid) {
         // back to beads: x_j = sum_k C[j][k] x~_k, with j = kk
-        float pj = 0.0f, qj = 0.0f;
-        const float *sp = s0 + cl * P, *sq = s2 + cl * P;
+        double pj = 0.0, qj = 0.0;
+        const double *sp = s0 + cl * P, *sq = s2 + cl * P;
         for (int k = 0; k < P; ++k) {
-            const float c = CT[k * (P + 1) + kk];
+            const double c = CT[k * (P + 1) + kk];
             pj += c * sp[k];
             if (PRE)
                 qj += c * sq[k];
         }
-        a.p[row * 3 + cc] = pj;
+        a.p[row * 3 + cc] = (float)pj;
         if (PRE)
-            a.q[row * 3 + cc] = qj;
+            a.q[row * 3 + cc] = (float)qj;
     }
-    const double tot = block_sum_double((double)dke, red);
+    const double tot = block_sum_double(dke, red);
     if (tid == 0)
         a.dke_part[2 * blockIdx.x + (PRE ? 0 : 1)] = tot;
 }
@@ -280,7 +284,7 @@ static IntegArgs integ_args(const DevBuffers &d, const Sizes &z, float dt, uint3
 
 static size_t integ_lds(int max_P)
 {
-    return (size_t)max_P * (max_P + 1) * sizeof(float) + 3 * 256 * sizeof(float) + 256 * sizeof(double);
+    return ((size_t)max_P * (max_P + 1) + 4 * 256) * sizeof(double);
 }
 
 size_t integrator_lds_bytes(int max_P) { return integ_lds(max_P); }

@@ -7,9 +7,10 @@
 //   g_L = w_o * (1 - h_L^2),  g_{l-1} = (W_l^T g_l) * (1 - h_{l-1}^2),  dE/dx = W_1^T g_1
 //
 // Each GEMM is rows x K times K x N with the 16x16 MFMA tiles of gfx950,
-// accumulating in FP32; the operand precision modes are listed at MlpCfg.  Activations pass between layers through a per-wave
-// LDS tile; (1 - h^2) of every hidden layer stays in registers in the MFMA
-// output layout, which is also the layout of the backward GEMM outputs.
+// accumulating in FP32; the operand precision modes are listed below.
+// Activations pass between layers through the workgroup's LDS tile;
+// (1 - h^2) of every hidden layer stays in registers in the MFMA output
+// layout, which is also the layout of the backward GEMM outputs.
 // Weights are read from global memory (L2-resident, shared by all waves):
 // W[out][in] serves the forward B operand and its transpose WT[in][out] the
 // backward one, so each lane reads contiguous k.
@@ -21,16 +22,13 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef short i16x4 __attribute__((ext_vector_type(4)));
 
-// MODE 0: FP32 operands (v_mfma_f32_16x16x4f32).
-// MODE 1: BF16 operands, three-term split: with a = a_hi + a_lo and
-//         b = b_hi + b_lo (each part bfloat16), acc += a_hi b_hi + a_lo b_hi + a_hi b_lo
-//         (v_mfma_f32_16x16x16bf16_1k, FP32 accumulation); the dropped a_lo b_lo term is
-//         below 2^-16 of the product.
-// MODE 2: BF16 operands, one term: acc += bf16(a) bf16(b).
-// (Mode 3, FP64 operands and activations, is the separate kernel k_mlp_f64.)
-template <int MODE>
+// Operand precision modes: 0 FP32 operands (v_mfma_f32_16x16x4f32, this
+// kernel); 1 BF16 operands in a three-term split, with a = a_hi + a_lo and
+// b = b_hi + b_lo (each part bfloat16), acc += a_hi b_hi + a_lo b_hi + a_hi b_lo
+// (the dropped a_lo b_lo term is below 2^-16 of the product); 2 BF16 operands,
+// one term (modes 1 and 2: k_mlp_bf16); 3 FP64 (k_mlp_f64).
 struct MlpCfg {
-    static constexpr int S = MODE == 0 ? 130 : 136;  // LDS row stride (floats)
+    static constexpr int S = 130;  // LDS row stride of the FP32 tile (floats)
 };
 
 __device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -39,11 +37,11 @@ __device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float
 // r < RT of the tile and the column tiles ct = w + 4t < nct, with
 // B[k][n] = Bt[n][k] (row-major Bt[N][ldb]); A is the LDS tile.  Each B
 // fragment read from memory feeds RT MFMAs.
-template <int MODE, int RT>
-__device__ __forceinline__ void gemm16_cols(const float *act, int K, const float *Bt, const uint16_t *Btb,
-                                            const uint16_t *Btb_lo, int ldb, int nct, int w, f32x4 (&acc)[RT][2])
+template <int RT>
+__device__ __forceinline__ void gemm16_cols(const float *act, int K, const float *Bt, int ldb, int nct, int w,
+                                            f32x4 (&acc)[RT][2])
 {
-    constexpr int S = MlpCfg<MODE>::S;
+    constexpr int S = MlpCfg::S;
     const int lane = lane_id();
     const int lr = lane & 15, lg = lane >> 4;
 #pragma unroll
@@ -51,55 +49,19 @@ __device__ __forceinline__ void gemm16_cols(const float *act, int K, const float
         acc[r][0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         acc[r][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     }
-    if (MODE == 0) {
-        for (int k0 = 0; k0 < K; k0 += 4) {
-            float a[RT];
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        float a[RT];
 #pragma unroll
-            for (int r = 0; r < RT; ++r)
-                a[r] = act[(16 * r + lr) * S + k0 + lg];
+        for (int r = 0; r < RT; ++r)
+            a[r] = act[(16 * r + lr) * S + k0 + lg];
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int ct = w + 4 * t;
-                if (ct < nct) {
-                    const float b = Bt[(ct * 16 + lr) * ldb + k0 + lg];
+        for (int t = 0; t < 2; ++t) {
+            const int ct = w + 4 * t;
+            if (ct < nct) {
+                const float b = Bt[(ct * 16 + lr) * ldb + k0 + lg];
 #pragma unroll
-                    for (int r = 0; r < RT; ++r)
-                        acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b, acc[r][t], 0, 0, 0);
-                }
-            }
-        }
-    } else {
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            i16x4 ahi[RT], alo[RT];
-#pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                const float4 av = *reinterpret_cast<const float4 *>(act + (16 * r + lr) * S + k0 + lg * 4);
-                const float af[4] = {av.x, av.y, av.z, av.w};
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint16_t h = f32_to_bf16(af[u]);
-                    ahi[r][u] = (short)h;
-                    alo[r][u] = (short)f32_to_bf16(af[u] - bf16_value(h));
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int ct = w + 4 * t;
-                if (ct < nct) {
-                    const int64_t o = (int64_t)(ct * 16 + lr) * ldb + k0 + lg * 4;
-                    const i16x4 bhi = *reinterpret_cast<const i16x4 *>(Btb + o);
-                    i16x4 blo;
-                    if (MODE == 1)
-                        blo = *reinterpret_cast<const i16x4 *>(Btb_lo + o);
-#pragma unroll
-                    for (int r = 0; r < RT; ++r) {
-                        acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[r], bhi, acc[r][t], 0, 0, 0);
-                        if (MODE == 1) {
-                            acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[r], bhi, acc[r][t], 0, 0, 0);
-                            acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[r], blo, acc[r][t], 0, 0, 0);
-                        }
-                    }
-                }
+                for (int r = 0; r < RT; ++r)
+                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b, acc[r][t], 0, 0, 0);
             }
         }
     }
@@ -110,12 +72,12 @@ __device__ __forceinline__ void gemm16_cols(const float *act, int K, const float
 // tiles w and w+4) and run all RT row blocks of the tile, and the activations
 // of the tile live in LDS between layers.  Row r's arithmetic is the same for
 // every RT.
-template <int MODE, int RT>
+template <int RT>
 __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, const MlpTile *__restrict__ tiles,
                                              const float *__restrict__ xhat, int D, int Dp, MlpNets nets,
                                              float *__restrict__ E_atom, float *__restrict__ dEdG)
 {
-    constexpr int S = MlpCfg<MODE>::S;
+    constexpr int S = MlpCfg::S;
     constexpr int MT = 16 * RT;
     __shared__ __attribute__((aligned(16))) float act[MT * S];
     __shared__ float epart[4][MT];
@@ -139,7 +101,7 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
     for (int l = 0; l < 3; ++l) {
         if (l < net.n_hidden) {
             const MlpLayer L = net.layer[l];
-            gemm16_cols<MODE, RT>(act, K, L.W, L.Wb, L.Wb_lo, L.in_pad, L.out / 16, w, acc);
+            gemm16_cols<RT>(act, K, L.W, L.in_pad, L.out / 16, w, acc);
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
@@ -227,7 +189,7 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
     for (int l = 2; l >= 1; --l) {
         if (l < nh) {
             const MlpLayer L = net.layer[l];
-            gemm16_cols<MODE, RT>(act, L.out, L.WT, L.WTb, L.WTb_lo, L.out, L.in_pad / 16, w, acc);
+            gemm16_cols<RT>(act, L.out, L.WT, L.out, L.in_pad / 16, w, acc);
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
@@ -246,7 +208,260 @@ __global__ __launch_bounds__(256) void k_mlp(const int32_t *__restrict__ rows, c
     }
     // dE/dx = W_1^T g_1 and dE/dG = dE/dx / scale
     const MlpLayer L0 = net.layer[0];
-    gemm16_cols<MODE, RT>(act, L0.out, L0.WT, L0.WTb, L0.WTb_lo, L0.out, Dp / 16, w, acc);
+    gemm16_cols<RT>(act, L0.out, L0.WT, L0.out, Dp / 16, w, acc);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int ct = w + 4 * t;
+        if (ct < Dp / 16) {
+            const int col = ct * 16 + lr;
+            if (col < D) {
+                const float is = net.inv_scale[col];
+#pragma unroll
+                for (int r = 0; r < RT; ++r)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = 16 * r + lg * 4 + q;
+                        if (row < nrows)
+                            dEdG[(int64_t)trows[row] * D + col] = acc[r][t][q] * is;
+                    }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 operand modes (1: three-term split, 2: one term).  The activations of
+// the tile are kept in LDS as bfloat16 parts (hi, and lo = bf16(v - hi) in
+// the split mode), converted once when a layer's outputs are written instead
+// of once per GEMM k-step in every wave; 32-deep k-steps use
+// v_mfma_f32_16x16x32_bf16 (each lane holds eight consecutive k of its row or
+// column), a 16-deep remainder v_mfma_f32_16x16x16bf16_1k.
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBfStride = 136;   // LDS row stride of the bf16 tiles (elements): 272-byte rows
+
+__device__ __forceinline__ f32x4 mfma_k32(const i16x8 &a, const i16x8 &b, const f32x4 &c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
+template <int MODE>
+__device__ __forceinline__ void store_bf16(uint16_t *hi, uint16_t *lo, int idx, float v)
+{
+    const uint16_t h = f32_to_bf16(v);
+    hi[idx] = h;
+    if (MODE == 1)
+        lo[idx] = f32_to_bf16(v - bf16_value(h));
+}
+
+// acc[r][t] = A[16 r .. 16 r + 15][K] * B[K][16 ct ...] (ct = w + 4t < nct),
+// B[k][n] = Bt[n][k] with Bt row-major [N][ldb] in bfloat16 parts.
+template <int MODE, int RT>
+__device__ __forceinline__ void gemm_bf16(const uint16_t *ahi, const uint16_t *alo, int K, const uint16_t *Bh,
+                                          const uint16_t *Bl, int ldb, int nct, int w, f32x4 (&acc)[RT][2])
+{
+    constexpr int SB = kBfStride;
+    const int lane = lane_id();
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        acc[r][0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        acc[r][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    int k0 = 0;
+    for (; k0 + 32 <= K; k0 += 32) {
+        i16x8 ah[RT], al[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            const int o = (16 * r + lr) * SB + k0 + 8 * lg;
+            ah[r] = *reinterpret_cast<const i16x8 *>(ahi + o);
+            if (MODE == 1)
+                al[r] = *reinterpret_cast<const i16x8 *>(alo + o);
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int ct = w + 4 * t;
+            if (ct < nct) {
+                const int64_t o = (int64_t)(ct * 16 + lr) * ldb + k0 + 8 * lg;
+                const i16x8 bh = *reinterpret_cast<const i16x8 *>(Bh + o);
+                i16x8 bl;
+                if (MODE == 1)
+                    bl = *reinterpret_cast<const i16x8 *>(Bl + o);
+#pragma unroll
+                for (int r = 0; r < RT; ++r) {
+                    acc[r][t] = mfma_k32(ah[r], bh, acc[r][t]);
+                    if (MODE == 1) {
+                        acc[r][t] = mfma_k32(al[r], bh, acc[r][t]);
+                        acc[r][t] = mfma_k32(ah[r], bl, acc[r][t]);
+                    }
+                }
+            }
+        }
+    }
+    if (k0 < K) {   // K is a multiple of 16: one 16-deep step remains
+        i16x4 ah[RT], al[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            const int o = (16 * r + lr) * SB + k0 + 4 * lg;
+            ah[r] = *reinterpret_cast<const i16x4 *>(ahi + o);
+            if (MODE == 1)
+                al[r] = *reinterpret_cast<const i16x4 *>(alo + o);
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int ct = w + 4 * t;
+            if (ct < nct) {
+                const int64_t o = (int64_t)(ct * 16 + lr) * ldb + k0 + 4 * lg;
+                const i16x4 bh = *reinterpret_cast<const i16x4 *>(Bh + o);
+                i16x4 bl;
+                if (MODE == 1)
+                    bl = *reinterpret_cast<const i16x4 *>(Bl + o);
+#pragma unroll
+                for (int r = 0; r < RT; ++r) {
+                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[r], bh, acc[r][t], 0, 0, 0);
+                    if (MODE == 1) {
+                        acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[r], bh, acc[r][t], 0, 0, 0);
+                        acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[r], bl, acc[r][t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// One workgroup per tile of 16 RT rows of one element, as k_mlp; the energy
+// readout is taken from the last layer's FP32 tanh values in registers.
+template <int MODE, int RT>
+__global__ __launch_bounds__(256) void k_mlp_bf16(const int32_t *__restrict__ rows,
+                                                  const MlpTile *__restrict__ tiles,
+                                                  const float *__restrict__ xhat, int D, int Dp, MlpNets nets,
+                                                  float *__restrict__ E_atom, float *__restrict__ dEdG)
+{
+    constexpr int SB = kBfStride;
+    constexpr int MT = 16 * RT;
+    __shared__ __attribute__((aligned(16))) uint16_t ahi[MT * SB];
+    __shared__ __attribute__((aligned(16))) uint16_t alo[MODE == 1 ? MT * SB : 8];
+    __shared__ float epart[4][MT];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const MlpTile tile = tiles[blockIdx.x];
+    const MlpNet &net = nets.net[tile.e];
+    const int32_t *trows = rows + tile.row0;
+    const int nrows = tile.nrows;
+
+    for (int idx = threadIdx.x; idx < MT * Dp; idx += 256) {
+        const int r = idx / Dp, c = idx - r * Dp;
+        store_bf16<MODE>(ahi, alo, r * SB + c, (r < nrows && c < D) ? xhat[(int64_t)trows[r] * D + c] : 0.0f);
+    }
+    __syncthreads();
+
+    f32x4 dsave[3][RT][2];
+    f32x4 acc[RT][2];
+    float e_part[RT][4];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            e_part[r][q] = 0.0f;
+    const int nh = net.n_hidden;
+    int K = Dp;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (l < nh) {
+            const MlpLayer L = net.layer[l];
+            gemm_bf16<MODE, RT>(ahi, alo, K, L.Wb, L.Wb_lo, L.in_pad, L.out / 16, w, acc);
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ct = w + 4 * t;
+                if (ct < L.out / 16) {
+                    const int col = ct * 16 + lr;
+                    const float bias = L.b[col];
+                    const float wo = l == nh - 1 ? net.wo[col] : 0.0f;
+#pragma unroll
+                    for (int r = 0; r < RT; ++r)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            // tanh and sech^2 from e = exp(-2|z|), as in k_mlp
+                            const float z = acc[r][t][q] + bias;
+                            const float e = expf(-2.0f * fabsf(z));
+                            const float ope = 1.0f + e;
+                            const float h = copysignf((1.0f - e) / ope, z);
+                            dsave[l][r][t][q] = 4.0f * e / (ope * ope);
+                            store_bf16<MODE>(ahi, alo, (16 * r + lg * 4 + q) * SB + col, h);
+                            if (l == nh - 1)
+                                e_part[r][q] += h * wo;
+                        }
+                }
+            }
+            __syncthreads();
+            K = L.out;
+        }
+    }
+    // energy readout: the column slices of the four waves
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            e_part[r][q] = row16_sum(e_part[r][q]);
+    if (lr == 0)
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                epart[w][16 * r + lg * 4 + q] = e_part[r][q];
+    // g_L = w_o * (1 - h_L^2)
+    const int nlast = K / 16;
+#pragma unroll
+    for (int l = 2; l >= 0; --l) {
+        if (l == nh - 1) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ct = w + 4 * t;
+                if (ct < nlast) {
+                    const int col = ct * 16 + lr;
+                    const float wo = net.wo[col];
+#pragma unroll
+                    for (int r = 0; r < RT; ++r)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            store_bf16<MODE>(ahi, alo, (16 * r + lg * 4 + q) * SB + col, wo * dsave[l][r][t][q]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < MT && (int)threadIdx.x < nrows)
+        E_atom[trows[threadIdx.x]] = ((epart[0][threadIdx.x] + epart[1][threadIdx.x]) +
+                                      (epart[2][threadIdx.x] + epart[3][threadIdx.x])) + net.bo;
+    // g_{l-1} = (W_l^T g_l) * (1 - h_{l-1}^2)
+#pragma unroll
+    for (int l = 2; l >= 1; --l) {
+        if (l < nh) {
+            const MlpLayer L = net.layer[l];
+            gemm_bf16<MODE, RT>(ahi, alo, L.out, L.WTb, L.WTb_lo, L.out, L.in_pad / 16, w, acc);
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ct = w + 4 * t;
+                if (ct < L.in_pad / 16) {
+                    const int col = ct * 16 + lr;
+#pragma unroll
+                    for (int r = 0; r < RT; ++r)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            store_bf16<MODE>(ahi, alo, (16 * r + lg * 4 + q) * SB + col,
+                                             acc[r][t][q] * dsave[l - 1][r][t][q]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // dE/dx = W_1^T g_1 and dE/dG = dE/dx / scale
+    const MlpLayer L0 = net.layer[0];
+    gemm_bf16<MODE, RT>(ahi, alo, L0.out, L0.WTb, L0.WTb_lo, L0.out, Dp / 16, w, acc);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const int ct = w + 4 * t;
@@ -425,19 +640,33 @@ __global__ __launch_bounds__(256) void k_mlp_f64(const int32_t *__restrict__ row
     }
 }
 
-template <int MODE>
-static void launch_mlp_mode(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int rows,
+static void launch_mlp_fp32(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int rows,
                             hipStream_t s)
 {
     if (rows == 64)
-        hipLaunchKernelGGL((k_mlp<MODE, 4>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp,
+        hipLaunchKernelGGL((k_mlp<4>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp,
                            nets, d.E_atom, d.dEdG);
     else if (rows == 32)
-        hipLaunchKernelGGL((k_mlp<MODE, 2>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp,
+        hipLaunchKernelGGL((k_mlp<2>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp,
                            nets, d.E_atom, d.dEdG);
     else
-        hipLaunchKernelGGL((k_mlp<MODE, 1>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp,
+        hipLaunchKernelGGL((k_mlp<1>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp,
                            nets, d.E_atom, d.dEdG);
+}
+
+template <int MODE>
+static void launch_mlp_bf16(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int rows,
+                            hipStream_t s)
+{
+    if (rows == 64)
+        hipLaunchKernelGGL((k_mlp_bf16<MODE, 4>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat,
+                           D, Dp, nets, d.E_atom, d.dEdG);
+    else if (rows == 32)
+        hipLaunchKernelGGL((k_mlp_bf16<MODE, 2>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat,
+                           D, Dp, nets, d.E_atom, d.dEdG);
+    else
+        hipLaunchKernelGGL((k_mlp_bf16<MODE, 1>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat,
+                           D, Dp, nets, d.E_atom, d.dEdG);
 }
 
 void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int mlp_mode, int rows,
@@ -449,11 +678,11 @@ void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, in
         hipLaunchKernelGGL(k_mlp_f64, dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp, nets,
                            d.E_atom, d.dEdG);
     else if (mlp_mode == 1)
-        launch_mlp_mode<1>(d, nets, n_tiles, D, Dp, rows, s);
+        launch_mlp_bf16<1>(d, nets, n_tiles, D, Dp, rows, s);
     else if (mlp_mode == 2)
-        launch_mlp_mode<2>(d, nets, n_tiles, D, Dp, rows, s);
+        launch_mlp_bf16<2>(d, nets, n_tiles, D, Dp, rows, s);
     else
-        launch_mlp_mode<0>(d, nets, n_tiles, D, Dp, rows, s);
+        launch_mlp_fp32(d, nets, n_tiles, D, Dp, rows, s);
 }
 
 }  // namespace pimd

@@ -120,7 +120,8 @@ __host__ __device__ inline int nl_buffer(int Kmax)
     int n = 1;
     while (n < Kmax)
         n <<= 1;
-    return n > Kmax + kWave ? n : Kmax + kWave;
+    const int b = n > Kmax + kWave ? n : Kmax + kWave;
+    return (b + 3) & ~3;
 }
 
 __device__ __forceinline__ bool within_cutoff(const float4 &pi, const float4 &pj, const BeadInfo &bi, float rc2)
@@ -139,9 +140,126 @@ __device__ __forceinline__ bool within_cutoff(const float4 &pi, const float4 &pj
     return r2 < rc2;
 }
 
-// One wave per centre row.  Candidates come from the (deduplicated) 27-cell
-// stencil, or every atom of the bead when the system is not periodic;
-// accepted keys are compacted into LDS and rank-sorted.
+// The (deduplicated) stencil of cell (cx, cy, cz), one cell per lane: lane
+// c < n_cells holds cell c's first slot in the bead's cell-sorted atoms and
+// the inclusive end of its candidates in a flat index space over all stencil
+// cells (lanes past n_cells hold the total), so a pass tests 64 candidates
+// drawn from any cells.
+struct Stencil {
+    int n_cells, end, base, total;   // candidate t of cell c sits at slot base_c + t
+};
+
+__device__ __forceinline__ Stencil stencil_of(const BeadInfo &bi, int cx, int cy, int cz,
+                                              const int32_t *cell_start, const int32_t *cell_count)
+{
+    const int lane = lane_id();
+    const int an0 = bi.nc[0] < 3 ? bi.nc[0] : 3, an1 = bi.nc[1] < 3 ? bi.nc[1] : 3;
+    const int an2 = bi.nc[2] < 3 ? bi.nc[2] : 3;
+    Stencil st;
+    st.n_cells = an0 * an1 * an2;
+    int first = 0, cnt = 0;
+    if (lane < st.n_cells) {
+        const int c = lane % an2, b = (lane / an2) % an1, a = lane / (an1 * an2);
+        // axis offsets -1, 0, +1 (or every cell of an axis with fewer than 3)
+        const int ux = bi.nc[0] < 3 ? a : (cx + bi.nc[0] - 1 + a) % bi.nc[0];
+        const int uy = bi.nc[1] < 3 ? b : (cy + bi.nc[1] - 1 + b) % bi.nc[1];
+        const int uz = bi.nc[2] < 3 ? c : (cz + bi.nc[2] - 1 + c) % bi.nc[2];
+        const int cell = bi.cell0 + (ux * bi.nc[1] + uy) * bi.nc[2] + uz;
+        first = cell_start[cell];
+        cnt = cell_count[cell];
+    }
+    int end = cnt;   // inclusive prefix sum of the counts over the lanes
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(end, o, kWave);
+        end += lane >= o ? t : 0;
+    }
+    st.end = end;
+    st.total = __shfl(end, kWave - 1, kWave);
+    st.base = first - (end - cnt);
+    return st;
+}
+
+// Slot (in the bead's cell-sorted atoms) of flat candidate t.
+__device__ __forceinline__ int stencil_slot(const Stencil &st, int t)
+{
+    int k = 0;   // the cell holding candidate t: number of cell ends <= t
+    for (int c = 0; c < st.n_cells; ++c)
+        k += t >= __shfl(st.end, c, kWave) ? 1 : 0;
+    return __shfl(st.base, k < st.n_cells ? k : 0, kWave) + t;
+}
+
+// Appends the accepted keys of one pass to the wave's buffer.
+__device__ __forceinline__ void append_keys(bool acc, int key, int Kmax, int32_t *buf, int &count)
+{
+    const uint64_t m = __ballot(acc);
+    const int pos = count + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (acc && pos < Kmax)
+        buf[pos] = key;
+    count += __popcll(m);
+}
+
+// Sorts the wave's `count` keys (distinct) and writes list, count and
+// element groups of centre i: a bitonic network in the buffer, padded with
+// INT_MAX to a power of two; the element groups are counted with ballots
+// over the sorted keys.
+__device__ __forceinline__ void finish_list(int32_t *buf, int count, int i, int Kmax, int n_el,
+                                            int32_t *__restrict__ nbr, int32_t *__restrict__ nbr_cnt,
+                                            int32_t *__restrict__ nbr_grp, int32_t *__restrict__ fence,
+                                            uint32_t *__restrict__ status)
+{
+    const int lane = lane_id();
+    wave_sync();
+    if (count > Kmax && lane == 0)
+        atomicOr(status, kStatusOverflow);
+    const int K = count < Kmax ? count : Kmax;
+    int n = 1;
+    while (n < K)
+        n <<= 1;
+    for (int t = K + lane; t < n; t += kWave)
+        buf[t] = 0x7FFFFFFF;
+    wave_sync();
+    for (int size = 2; size <= n; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int p = lane; p < (n >> 1); p += kWave) {
+                const int lo = ((p & ~(stride - 1)) << 1) | (p & (stride - 1)), hi = lo + stride;
+                const int a = buf[lo], b = buf[hi];
+                if ((a > b) == ((lo & size) == 0)) {
+                    buf[lo] = b;
+                    buf[hi] = a;
+                }
+            }
+            wave_sync();
+        }
+    int32_t *out = nbr + (int64_t)i * Kmax;
+    int grp[kMaxElements] = {0, 0, 0, 0};
+    for (int t0 = 0; t0 < K; t0 += kWave) {
+        const int t = t0 + lane;
+        const int v = t < K ? buf[t] : -1;
+        if (t < K)
+            out[t] = v;
+#pragma unroll
+        for (int e = 0; e < kMaxElements; ++e)
+            grp[e] += __popcll(__ballot(t < K && (v >> kKeyShift) == e));
+    }
+    if (lane < n_el) {
+        int c = grp[0];
+#pragma unroll
+        for (int e = 1; e < kMaxElements; ++e)
+            c = lane == e ? grp[e] : c;
+        nbr_grp[(int64_t)i * kMaxElements + lane] = c;
+    }
+    if (lane == 0)
+        nbr_cnt[i] = K;
+    // fence row: the count, then every 16th key (INT_MAX past the end)
+    if (lane < kFence)
+        fence[(int64_t)i * kFence + lane] = lane == 0 ? K : (16 * lane < K ? buf[16 * lane] : 0x7FFFFFFF);
+    wave_sync();
+}
+
+// One wave per centre row, candidates read from global memory: the stencil
+// cells of a periodic bead, or every atom of a bead without a box.  With
+// skip_periodic the periodic centres are left to k_neighbors_cells.
 __global__ __launch_bounds__(256) void k_neighbors(const float4 *__restrict__ pos4,
                                                    const BeadInfo *__restrict__ beads,
                                                    const int32_t *__restrict__ bead_of_ba,
@@ -149,73 +267,42 @@ __global__ __launch_bounds__(256) void k_neighbors(const float4 *__restrict__ po
                                                    const int32_t *__restrict__ cell_start,
                                                    const int32_t *__restrict__ cell_atoms,
                                                    const int32_t *__restrict__ order, float rc2, int Kmax,
-                                                   int n_el, int32_t *__restrict__ nbr, int32_t *__restrict__ nbr_cnt,
-                                                   int32_t *__restrict__ nbr_grp, uint32_t *__restrict__ status, int B)
+                                                   int n_el, int skip_periodic, int32_t *__restrict__ nbr,
+                                                   int32_t *__restrict__ nbr_cnt, int32_t *__restrict__ nbr_grp,
+                                                   int32_t *__restrict__ fence, uint32_t *__restrict__ status,
+                                                   int B)
 {
     extern __shared__ int32_t nl_lds[];
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
     int32_t *buf = nl_lds + w * nl_buffer(Kmax);
-    const uint64_t below = lanes_below_mask();
     const CentreRange cr = centre_range(B);
     for (int ci = cr.begin; ci < cr.end; ++ci) {
         // wave-uniform: the per-centre values below live in scalar registers
         const int i = __builtin_amdgcn_readfirstlane(order ? order[ci] : ci);
         const BeadInfo bi = beads[bead_of_ba[i]];
+        if (bi.periodic && skip_periodic)
+            continue;
         const float4 pi = pos4[i];
         int count = 0;
         auto consider = [&](int j, bool valid) {
             bool acc = false;
-            float4 pj;
+            float4 pj = pi;
             if (valid && j != i) {
                 pj = pos4[j];
                 acc = within_cutoff(pi, pj, bi, rc2);
             }
-            const uint64_t m = __ballot(acc);
-            const int pos = count + __popcll(m & below);
-            if (acc && pos < Kmax) {
-                const int z = __float_as_int(pj.w);
-                buf[pos] = (z << kKeyShift) | j;
-            }
-            count += __popcll(m);
+            append_keys(acc, (__float_as_int(pj.w) << kKeyShift) | j, Kmax, buf, count);
         };
         if (bi.periodic) {
-            // the (deduplicated) stencil cells, one per lane: lane c < n_cells
-            // holds cell c's first slot and its end in the flattened candidate
-            // index space, so each pass tests 64 candidates of any cells
-            const int cx = cell_of(pi.x, bi.cell_scale[0], bi.nc[0]);
-            const int cy = cell_of(pi.y, bi.cell_scale[1], bi.nc[1]);
-            const int cz = cell_of(pi.z, bi.cell_scale[2], bi.nc[2]);
-            const int an0 = bi.nc[0] < 3 ? bi.nc[0] : 3, an1 = bi.nc[1] < 3 ? bi.nc[1] : 3;
-            const int an2 = bi.nc[2] < 3 ? bi.nc[2] : 3;
-            const int n_cells = an0 * an1 * an2;
-            int first = 0, cnt = 0;
-            if (lane < n_cells) {
-                const int c = lane % an2, b = (lane / an2) % an1, a = lane / (an1 * an2);
-                // axis offsets -1, 0, +1 (or every cell of an axis with fewer than 3)
-                const int ux = bi.nc[0] < 3 ? a : (cx + bi.nc[0] - 1 + a) % bi.nc[0];
-                const int uy = bi.nc[1] < 3 ? b : (cy + bi.nc[1] - 1 + b) % bi.nc[1];
-                const int uz = bi.nc[2] < 3 ? c : (cz + bi.nc[2] - 1 + c) % bi.nc[2];
-                const int cell = bi.cell0 + (ux * bi.nc[1] + uy) * bi.nc[2] + uz;
-                first = cell_start[cell];
-                cnt = cell_count[cell];
-            }
-            int end = cnt;   // inclusive prefix sum of the counts over the lanes
-            for (int o = 1; o < kWave; o <<= 1) {
-                const int t = __shfl_up(end, o, kWave);
-                end += lane >= o ? t : 0;
-            }
-            const int total = __shfl(end, kWave - 1, kWave);
-            const int base = first - (end - cnt);   // slot of candidate t in cell c: base_c + t
-            for (int t0 = 0; t0 < total; t0 += kWave) {
+            const Stencil st = stencil_of(bi, cell_of(pi.x, bi.cell_scale[0], bi.nc[0]),
+                                          cell_of(pi.y, bi.cell_scale[1], bi.nc[1]),
+                                          cell_of(pi.z, bi.cell_scale[2], bi.nc[2]), cell_start, cell_count);
+            for (int t0 = 0; t0 < st.total; t0 += kWave) {
                 const int t = t0 + lane;
-                const bool valid = t < total;
-                int k = 0;   // the cell holding candidate t: number of cell ends <= t
-                for (int c = 0; c < n_cells; ++c)
-                    k += t >= __shfl(end, c, kWave) ? 1 : 0;
-                const int bk = __shfl(base, k < n_cells ? k : 0, kWave);
-                const int j = valid ? cell_atoms[bi.ba0 + bk + t] : 0;
-                consider(j, valid);
+                const bool valid = t < st.total;
+                const int slot = stencil_slot(st, t);
+                consider(valid ? cell_atoms[bi.ba0 + slot] : 0, valid);
             }
         } else {
             for (int t0 = 0; t0 < bi.n; t0 += kWave) {
@@ -223,52 +310,75 @@ __global__ __launch_bounds__(256) void k_neighbors(const float4 *__restrict__ po
                 consider(bi.ba0 + t, t < bi.n);
             }
         }
-        wave_sync();
-        if (count > Kmax && lane == 0)
-            atomicOr(status, kStatusOverflow);
-        const int K = count < Kmax ? count : Kmax;
-        // bitonic sort of the K keys (distinct) in the wave's buffer, padded
-        // with INT_MAX to a power of two; then the sorted keys go out
-        // coalesced and the element groups are counted from them
-        int n = 1;
-        while (n < K)
-            n <<= 1;
-        for (int t = K + lane; t < n; t += kWave)
-            buf[t] = 0x7FFFFFFF;
-        wave_sync();
-        for (int size = 2; size <= n; size <<= 1)
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int p = lane; p < (n >> 1); p += kWave) {
-                    const int lo = ((p & ~(stride - 1)) << 1) | (p & (stride - 1)), hi = lo + stride;
-                    const int a = buf[lo], b = buf[hi];
-                    if ((a > b) == ((lo & size) == 0)) {
-                        buf[lo] = b;
-                        buf[hi] = a;
-                    }
-                }
-                wave_sync();
+        finish_list(buf, count, i, Kmax, n_el, nbr, nbr_cnt, nbr_grp, fence, status);
+    }
+}
+
+// One workgroup per cell of a periodic bead: the atoms of the cell's stencil
+// are staged in LDS once (rows and positions) and every centre of the cell,
+// a wave each, tests them from there instead of gathering them from global
+// memory centre by centre.  A stencil with more than max_cand atoms is read
+// from global memory as in k_neighbors.  The lists are the same.
+__global__ __launch_bounds__(256) void k_neighbors_cells(const float4 *__restrict__ pos4,
+                                                         const BeadInfo *__restrict__ beads,
+                                                         const int32_t *__restrict__ cell_bead,
+                                                         const int32_t *__restrict__ cell_count,
+                                                         const int32_t *__restrict__ cell_start,
+                                                         const int32_t *__restrict__ cell_atoms, float rc2,
+                                                         int Kmax, int n_el, int max_cand,
+                                                         int32_t *__restrict__ nbr, int32_t *__restrict__ nbr_cnt,
+                                                         int32_t *__restrict__ nbr_grp, int32_t *__restrict__ fence,
+                                                         uint32_t *__restrict__ status)
+{
+    extern __shared__ int32_t nl_lds[];
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6, wpg = blockDim.x >> 6;
+    const int nlb = nl_buffer(Kmax);
+    int32_t *buf = nl_lds + w * nlb;
+    int32_t *crow = nl_lds + wpg * nlb;
+    float4 *cpos = reinterpret_cast<float4 *>(crow + max_cand);   // max_cand and nlb are multiples of 4
+    const int cell = xcd_block(blockIdx.x, gridDim.x);
+    const BeadInfo bi = beads[cell_bead[cell]];
+    const int home_n = cell_count[cell], home_first = cell_start[cell];
+    if (home_n == 0)
+        return;
+    const int local = cell - bi.cell0;
+    const int cz = local % bi.nc[2], cy = (local / bi.nc[2]) % bi.nc[1], cx = local / (bi.nc[1] * bi.nc[2]);
+    const Stencil st = stencil_of(bi, cx, cy, cz, cell_start, cell_count);
+    const bool staged = st.total <= max_cand;
+    if (staged) {
+        for (int t0 = 0; t0 < st.total; t0 += blockDim.x) {
+            const int t = t0 + (int)threadIdx.x;
+            const int slot = stencil_slot(st, t);
+            if (t < st.total) {
+                const int j = cell_atoms[bi.ba0 + slot];
+                crow[t] = j;
+                cpos[t] = pos4[j];
             }
-        int32_t *out = nbr + (int64_t)i * Kmax;
-        int grp[kMaxElements] = {0, 0, 0, 0};
-        for (int t0 = 0; t0 < K; t0 += kWave) {
+        }
+        __syncthreads();
+    }
+    for (int s = w; s < home_n; s += wpg) {
+        const int i = __builtin_amdgcn_readfirstlane(cell_atoms[bi.ba0 + home_first + s]);
+        const float4 pi = pos4[i];
+        int count = 0;
+        for (int t0 = 0; t0 < st.total; t0 += kWave) {
             const int t = t0 + lane;
-            const int v = t < K ? buf[t] : -1;
-            if (t < K)
-                out[t] = v;
-#pragma unroll
-            for (int e = 0; e < kMaxElements; ++e)
-                grp[e] += __popcll(__ballot(t < K && (v >> kKeyShift) == e));
+            const bool valid = t < st.total;
+            int j;
+            float4 pj;
+            if (staged) {
+                j = valid ? crow[t] : i;
+                pj = valid ? cpos[t] : pi;
+            } else {
+                const int slot = stencil_slot(st, t);
+                j = valid ? cell_atoms[bi.ba0 + slot] : i;
+                pj = pos4[j];
+            }
+            const bool acc = j != i && within_cutoff(pi, pj, bi, rc2);
+            append_keys(acc, (__float_as_int(pj.w) << kKeyShift) | j, Kmax, buf, count);
         }
-        if (lane < n_el) {
-            int c = grp[0];
-#pragma unroll
-            for (int e = 1; e < kMaxElements; ++e)
-                c = lane == e ? grp[e] : c;
-            nbr_grp[(int64_t)i * kMaxElements + lane] = c;
-        }
-        if (lane == 0)
-            nbr_cnt[i] = K;
-        wave_sync();
+        finish_list(buf, count, i, Kmax, n_el, nbr, nbr_cnt, nbr_grp, fence, status);
     }
 }
 
@@ -303,14 +413,31 @@ void launch_cell_fill(const DevBuffers &d, const Sizes &z, hipStream_t s)
                        d.atom_slot, d.cell_start, d.cell_atoms, z.B);
 }
 
+// Candidates staged per cell: up to kMaxCand stencil atoms (27 cells of ~30).
+constexpr int kMaxCand = 1536;
+
+size_t neighbors_cells_lds(int Kmax) { return (size_t)4 * nl_buffer(Kmax) * 4 + (size_t)kMaxCand * 20; }
+
+hipError_t configure_neighbor_lds(int Kmax)
+{
+    return hipFuncSetAttribute((const void *)k_neighbors_cells, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)neighbors_cells_lds(Kmax));
+}
+
 void launch_neighbors(const DevBuffers &d, const Sizes &z, float rc2, int n_el, const Tuning &tn, hipStream_t s)
 {
-    const int wpg = tn.centre_waves;
-    const size_t lds = (size_t)wpg * nl_buffer(z.Kmax) * sizeof(int32_t);
-    hipLaunchKernelGGL(k_neighbors, dim3(centre_grid(z.B, tn)), dim3(kWave * wpg), lds, s, d.pos4, d.beads,
-                       d.bead_of_ba, d.cell_count, d.cell_start, d.cell_atoms, centre_order(d, z), rc2, z.Kmax, n_el,
-                       d.nbr, d.nbr_cnt,
-                       d.nbr_grp, d.status, z.B);
+    const bool cells = z.any_periodic && tn.nl_cells;
+    if (cells)
+        hipLaunchKernelGGL(k_neighbors_cells, dim3(z.total_cells), dim3(256), neighbors_cells_lds(z.Kmax), s, d.pos4,
+                           d.beads, d.cell_bead, d.cell_count, d.cell_start, d.cell_atoms, rc2, z.Kmax, n_el, kMaxCand,
+                           d.nbr, d.nbr_cnt, d.nbr_grp, d.nbr_fence, d.status);
+    if (!cells || z.any_open) {
+        const int wpg = tn.centre_waves;
+        const size_t lds = (size_t)wpg * nl_buffer(z.Kmax) * sizeof(int32_t);
+        hipLaunchKernelGGL(k_neighbors, dim3(centre_grid(z.B, tn)), dim3(kWave * wpg), lds, s, d.pos4, d.beads,
+                           d.bead_of_ba, d.cell_count, d.cell_start, d.cell_atoms, centre_order(d, z), rc2, z.Kmax,
+                           n_el, cells ? 1 : 0, d.nbr, d.nbr_cnt, d.nbr_grp, d.nbr_fence, d.status, z.B);
+    }
 }
 
 }  // namespace pimd

@@ -38,10 +38,10 @@ struct Layout {
 struct Plan {
     int n_sys = 0, n_el = 0, B = 0, n_beads = 0, n_atoms = 0, ncol = 0, total_cells = 0, n_units = 0;
     int D = 0, Dp = 0, Kmax = 0, max_P = 1, n_rad = 0, n_ang_eta = 0;
-    bool any_periodic = false, bpnn = false;
+    bool any_periodic = false, any_open = false, bpnn = false;
     std::vector<int> cells_per_sys;            // cells per bead of each system
     std::vector<std::array<int, 3>> nc;
-    size_t mlp_f32_floats = 0, mlp_bf16_elems = 0, mlp_f64_elems = 0, cmat_floats = 0, modes = 0;
+    size_t mlp_f32_floats = 0, mlp_bf16_elems = 0, mlp_f64_elems = 0, cmat_elems = 0, modes = 0;
     std::vector<int> distinct_P;
 };
 
@@ -76,6 +76,8 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
         return fail(err, PIMD_E_ARG, "unknown potential");
     if (cfg->max_neighbors < 0 || cfg->max_neighbors > kMaxNeighbors)
         return fail(err, PIMD_E_UNSUPPORTED, "max_neighbors must be in [0, 256]");
+    if (cfg->max_neighbors % 16)
+        return fail(err, PIMD_E_ARG, "max_neighbors must be a multiple of 16");
     const pimd_bpnn_model *m = cfg->model;
     if (!m)
         return fail(err, PIMD_E_ARG, "model is NULL (it carries the element masses)");
@@ -150,6 +152,8 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
                     nc[d] = std::max(1, (int)std::floor(L[d] / (m->cutoff_A + 1e-4)));
                 pl.any_periodic = true;
             }
+        } else {
+            pl.any_open = true;
         }
         pl.nc.push_back(nc);
         const int per_bead = zero || !pl.bpnn ? 0 : nc[0] * nc[1] * nc[2];
@@ -176,7 +180,7 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
     pl.ncol = 3 * (int)na;
     pl.total_cells = (int)cells;
     for (int P : pl.distinct_P)
-        pl.cmat_floats += (size_t)P * P;
+        pl.cmat_elems += (size_t)P * P;
     if (pl.bpnn) {
         int in = pl.Dp;
         for (int e = 0; e < pl.n_el; ++e) {
@@ -214,9 +218,11 @@ Layout make_layout(const Plan &pl)
         L.add("cell_count", (size_t)pl.total_cells * 4);
         L.add("cell_start", (size_t)pl.total_cells * 4);
         L.add("cell_atoms", B * 4);
+        L.add("cell_bead", (size_t)pl.total_cells * 4);
         L.add("nbr", B * K * 4);
         L.add("nbr_cnt", B * 4);
         L.add("nbr_grp", B * kMaxElements * 4);
+        L.add("nbr_fence", B * kFence * 4);
         L.add("xhat", B * D * 4);
         L.add("dEdG", B * D * 4);
         L.add("vslot", B * K * 16);
@@ -239,7 +245,7 @@ Layout make_layout(const Plan &pl)
     L.add("sys", (size_t)pl.n_sys * sizeof(SysInfo));
     L.add("modes", pl.modes * sizeof(ModeInfo));
     L.add("units", (size_t)pl.n_units * sizeof(IntegUnit));
-    L.add("cmat", pl.cmat_floats * 4);
+    L.add("cmat", pl.cmat_elems * 8);
     L.add("col_sys", (size_t)pl.ncol * 4);
     L.add("end", 0);
     return L;
@@ -274,7 +280,7 @@ struct pimd_ctx {
     MlpNets nets{};
     int n_mlp_tiles = 0;
     std::vector<int32_t> elem_row0;   // [n_el + 1] first MLP row of each element in elem_rows
-    Tuning tn{4, 0, 16, 0};
+    Tuning tn{4, 0, 16, 0};         // nl_cells is set from the cell count at init
     pimd_tuning last_tuning_out{};     // sink for pimd_autotune(best = NULL)
     std::vector<SysInfo> sys_host;
     std::vector<double> temperature, masses_el;
@@ -502,9 +508,11 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     d.cell_count = (int32_t *)at("cell_count");
     d.cell_start = (int32_t *)at("cell_start");
     d.cell_atoms = (int32_t *)at("cell_atoms");
+    d.cell_bead = (int32_t *)at("cell_bead");
     d.nbr = (int32_t *)at("nbr");
     d.nbr_cnt = (int32_t *)at("nbr_cnt");
     d.nbr_grp = (int32_t *)at("nbr_grp");
+    d.nbr_fence = (int32_t *)at("nbr_fence");
     d.xhat = (float *)at("xhat");
     d.dEdG = (float *)at("dEdG");
     d.vslot = (float4 *)at("vslot");
@@ -526,7 +534,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     d.sys = (SysInfo *)at("sys");
     d.modes = (ModeInfo *)at("modes");
     d.units = (IntegUnit *)at("units");
-    d.cmat = (float *)at("cmat");
+    d.cmat = (double *)at("cmat");
     d.col_sys = (int32_t *)at("col_sys");
 
     Sizes &z = c->z;
@@ -540,6 +548,8 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     z.D = pl.D;
     z.Kmax = pl.Kmax;
     z.any_periodic = pl.any_periodic ? 1 : 0;
+    c->tn.nl_cells = pl.total_cells >= 4096 ? 1 : 0;
+    z.any_open = pl.any_open ? 1 : 0;
 
     // ---- host tables
     std::vector<BeadInfo> beads;
@@ -547,7 +557,8 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     std::vector<float> mass_atom(pl.n_atoms);
     std::vector<ModeInfo> modes;
     std::vector<IntegUnit> units;
-    std::vector<float> cmat;
+    std::vector<double> cmat;
+    std::vector<int32_t> cell_bead;
     std::map<int, int> cmat_off;
     for (int P : pl.distinct_P) {
         cmat_off[P] = (int)cmat.size();
@@ -564,7 +575,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
                     v = ((j & 1) ? -1.0 : 1.0) / std::sqrt((double)P);
                 else
                     v = std::sqrt(2.0 / P) * std::sin(2.0 * kPi * j * k / P);
-                cmat.push_back((float)v);
+                cmat.push_back(v);
             }
     }
     int ba0 = 0, atom0 = 0, cell0 = 0, mode0 = 0;
@@ -600,11 +611,11 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
                 gamma = k == 0 ? 1.0 / c->tau0 : 2.0 * c->lam * w;
             const double c1 = std::exp(-0.5 * gamma * c->dt);
             ModeInfo mi{};
-            mi.c1 = (float)c1;
-            mi.c2 = (float)std::sqrt(std::max(0.0, 1.0 - c1 * c1));
-            mi.cw = (float)std::cos(w * c->dt);
-            mi.sw = (float)std::sin(w * c->dt);
-            mi.w = (float)w;
+            mi.c1 = c1;
+            mi.c2 = std::sqrt(std::max(0.0, 1.0 - c1 * c1));
+            mi.cw = std::cos(w * c->dt);
+            mi.sw = std::sin(w * c->dt);
+            mi.w = w;
             modes.push_back(mi);
         }
         for (int k = 0; k < P; ++k) {
@@ -622,6 +633,8 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
                 bi.invL64[dd] = periodic ? 1.0 / Lb[dd] : 0.0;
             }
             bi.cell0 = cell0;
+            for (int cc = 0; cc < pl.cells_per_sys[s]; ++cc)
+                cell_bead.push_back((int32_t)beads.size());
             cell0 += pl.cells_per_sys[s];
             for (int i = 0; i < N; ++i)
                 bead_of_ba[bi.ba0 + i] = (int)beads.size();
@@ -652,7 +665,9 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     push(d.sys, c->sys_host.data(), c->sys_host.size() * sizeof(SysInfo));
     push(d.modes, modes.data(), modes.size() * sizeof(ModeInfo));
     push(d.units, units.data(), units.size() * sizeof(IntegUnit));
-    push(d.cmat, cmat.data(), cmat.size() * 4);
+    push(d.cmat, cmat.data(), cmat.size() * 8);
+    if (pl.bpnn)
+        push(d.cell_bead, cell_bead.data(), cell_bead.size() * 4);
     push(d.col_sys, col_sys.data(), col_sys.size() * 4);
 
     if (pl.bpnn) {
@@ -801,6 +816,9 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         e = configure_descriptor_lds(c->dp);
         if (e != hipSuccess)
             return bail(PIMD_E_DEVICE, std::string("descriptor LDS: ") + hipGetErrorString(e));
+        e = configure_neighbor_lds(pl.Kmax);
+        if (e != hipSuccess)
+            return bail(PIMD_E_DEVICE, std::string("neighbour LDS: ") + hipGetErrorString(e));
     }
     e = configure_integrator_lds(pl.max_P);
     if (e != hipSuccess)
@@ -1117,7 +1135,7 @@ pimd_status pimd_get_tuning(const pimd_ctx *ctx, pimd_tuning *out)
 {
     if (!ctx || !out)
         return PIMD_E_ARG;
-    *out = pimd_tuning{ctx->tn.centre_waves, ctx->tn.centre_grid, ctx->tn.mlp_rows, 0};
+    *out = pimd_tuning{ctx->tn.centre_waves, ctx->tn.centre_grid, ctx->tn.mlp_rows, ctx->tn.nl_cells};
     return PIMD_OK;
 }
 
@@ -1149,15 +1167,16 @@ pimd_status pimd_set_tuning(pimd_ctx *ctx, const pimd_tuning *t)
         return PIMD_E_ARG;
     const bool waves_ok = t->centre_waves == 1 || t->centre_waves == 2 || t->centre_waves == 4;
     const bool rows_ok = t->mlp_rows == 16 || t->mlp_rows == 32 || t->mlp_rows == 64;
-    if (!waves_ok || !rows_ok || t->centre_grid < 0 || t->reserved != 0) {
-        ctx->err = "tuning: centre_waves in {1, 2, 4}, centre_grid >= 0, mlp_rows in {16, 32, 64}, reserved 0";
+    if (!waves_ok || !rows_ok || t->centre_grid < 0 || (t->neighbor_cells != 0 && t->neighbor_cells != 1)) {
+        ctx->err = "tuning: centre_waves in {1, 2, 4}, centre_grid >= 0, mlp_rows in {16, 32, 64}, "
+                   "neighbor_cells in {0, 1}";
         return PIMD_E_ARG;
     }
     if (ctx->precision == PIMD_PREC_FP64_MLP && t->mlp_rows != 16) {
         ctx->err = "the FP64 MLP runs 16-row tiles only";
         return PIMD_E_UNSUPPORTED;
     }
-    return apply_tuning(ctx, Tuning{t->centre_waves, t->centre_grid, t->mlp_rows, 0});
+    return apply_tuning(ctx, Tuning{t->centre_waves, t->centre_grid, t->mlp_rows, t->neighbor_cells});
 }
 
 // Mean milliseconds of one force evaluation of the current positions.
@@ -1243,6 +1262,12 @@ pimd_status pimd_autotune(pimd_ctx *ctx, int32_t n_reps, pimd_tuning *best)
                 if ((st = consider(cand)) != PIMD_OK)
                     return st;
             }
+        if (ctx->z.any_periodic) {
+            Tuning cand = top;
+            cand.nl_cells = 1 - top.nl_cells;
+            if ((st = consider(cand)) != PIMD_OK)
+                return st;
+        }
         if ((st = apply_tuning(ctx, top)) != PIMD_OK)
             return st;
         // leave the forces of the current positions under the chosen shape

@@ -13,6 +13,7 @@ constexpr int kMaxRad = 32;
 constexpr int kMaxBeads = 128;
 constexpr int kMaxNeighbors = 256;
 constexpr int kKeyShift = 27;                 // neighbour key = (element << 27) | row
+constexpr int kFence = 16;                    // fence row per list: count, then the keys at slots 16, 32, ...
 constexpr uint32_t kRowMask = (1u << kKeyShift) - 1u;
 
 // device status word bits
@@ -99,11 +100,14 @@ struct SysInfo {
     float pad[3];
 };
 
+// Coefficients in FP64: a rotation whose float32 cos and sin miss
+// cos^2 + sin^2 = 1 by ~1e-7 changes every mode's energy by that factor each
+// step, a drift per step that does not shrink with dt.
 struct ModeInfo {
-    float c1, c2;       // O step: exp(-gamma dt/2), sqrt(1 - c1^2)
-    float cw, sw;       // cos(w dt), sin(w dt)
-    float w;            // mode frequency (1/fs)
-    float pad[3];
+    double c1, c2;      // O step: exp(-gamma dt/2), sqrt(1 - c1^2)
+    double cw, sw;      // cos(w dt), sin(w dt)
+    double w;           // mode frequency (1/fs)
+    double pad[3];
 };
 
 // Everything a step needs on the device, carved from the workspace.
@@ -114,7 +118,9 @@ struct DevBuffers {
     float4 *posu4;                 // unwrapped positions + species bits (displacements)
     int32_t *atom_cell, *atom_slot;
     int32_t *cell_count, *cell_start, *cell_atoms;
+    int32_t *cell_bead;            // bead of every cell (periodic beads)
     int32_t *nbr, *nbr_cnt, *nbr_grp;
+    int32_t *nbr_fence;            // [B][kFence]: list count, then every 16th key (reverse-slot search)
     float *xhat, *dEdG, *E_atom;
     float4 *vslot;
     float *vir_atom, *W_bead;
@@ -132,7 +138,7 @@ struct DevBuffers {
     SysInfo *sys;
     ModeInfo *modes;
     IntegUnit *units;
-    float *cmat;                   // normal-mode matrices, C[j][k] row-major per distinct P
+    double *cmat;                  // normal-mode matrices, C[j][k] row-major per distinct P (FP64)
     int32_t *col_sys;              // [ncol] system of each column
     float *mlp_f32;                // packed f32 weights (W, WT, b, wo per element)
     uint16_t *mlp_bf16;            // packed bf16 weights (W, WT per element)
@@ -146,7 +152,7 @@ struct Tuning {
     int32_t centre_waves;  // waves (centre atoms in flight) per workgroup of the per-centre kernels: 1, 2 or 4
     int32_t centre_grid;   // 0: one wave per centre; > 0: at most this many workgroups, waves stride over centres
     int32_t mlp_rows;      // rows per MLP workgroup tile: 16, 32 or 64
-    int32_t pad;
+    int32_t nl_cells;      // periodic neighbour search per cell with the stencil in LDS (1) or per centre (0)
 };
 
 // Workgroups of a per-centre launch over B centres.
@@ -159,7 +165,8 @@ inline int centre_grid(int B, const Tuning &tn)
 // ---------------------------------------------------------------- launchers
 struct Sizes {
     int32_t n_sys, B, n_beads_total, n_atoms_total, ncol, total_cells, n_units, D, Kmax;
-    int32_t any_periodic;
+    int32_t any_periodic;   // some system has a box (cell lists)
+    int32_t any_open;       // some system has none (all-pairs lists)
 };
 
 // Order in which the per-centre kernels visit the rows: cell order within
@@ -202,6 +209,7 @@ void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &d
 // Raise the dynamic-LDS limit of kernels whose LDS grows with Kmax or P.
 hipError_t configure_descriptor_lds(const DescParams &dp);
 hipError_t configure_integrator_lds(int max_P);
+hipError_t configure_neighbor_lds(int Kmax);
 size_t descriptor_lds_bytes(const DescParams &dp, bool adjoint);
 size_t integrator_lds_bytes(int max_P);
 

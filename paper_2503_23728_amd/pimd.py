@@ -187,7 +187,7 @@ class Pimd:
         _check(abi.pimd_set_graph(self.ctx, enabled), self.ctx)
 
     def get_tuning(self):
-        """The launch shape of the force kernels: {centre_waves, centre_grid, mlp_rows}."""
+        """The launch shape of the force kernels: {centre_waves, centre_grid, mlp_rows, neighbor_cells}."""
         st, t = abi.pimd_get_tuning(self.ctx)
         _check(st, self.ctx)
         return {f: getattr(t, f) for f in tuning.FIELDS}
@@ -195,7 +195,7 @@ class Pimd:
     def set_tuning(self, **shape):
         cur = self.get_tuning()
         cur.update(shape)
-        t = abi.pimd_tuning(cur["centre_waves"], cur["centre_grid"], cur["mlp_rows"], 0)
+        t = abi.pimd_tuning(*(cur[f] for f in tuning.FIELDS))
         _check(abi.pimd_set_tuning(self.ctx, t), self.ctx)
 
     def tuning_key(self):

@@ -12,7 +12,7 @@ import hashlib
 import json
 import os
 
-FIELDS = ("centre_waves", "centre_grid", "mlp_rows")
+FIELDS = ("centre_waves", "centre_grid", "mlp_rows", "neighbor_cells")
 
 
 def cache_path():

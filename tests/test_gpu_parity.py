@@ -76,11 +76,15 @@ def test_philox_integer_stream_matches_oracle():
 
 # ---------------------------------------------------------------- neighbours
 
+@pytest.mark.parametrize("cells", [0, 1])
 @pytest.mark.parametrize("name", list(WORKLOADS))
-def test_neighbor_lists_bit_exact(name):
+def test_neighbor_lists_bit_exact(name, cells):
+    # both periodic search kernels: per centre (0) and per cell with the
+    # stencil staged in LDS (1)
     wl = WORKLOADS[name]()
-    say(f"neighbours {name}")
+    say(f"neighbours {name} cells={cells}")
     eng = _engine(wl)
+    eng.set_tuning(neighbor_cells=cells)
     q = _q(wl, seed=2, amp=0.3)
     q[::7] += np.float32(25.0)    # unwrapped positions far outside the box
     eng.energy_forces(torch.from_numpy(q).cuda(), forces=False)
@@ -373,10 +377,12 @@ def test_every_launch_shape_gives_bitwise_identical_results(name, prec):
     for waves in (1, 2, 4):
         for grid in (0, 7, 300):
             for rows in (16, 32, 64):
-                eng.set_tuning(centre_waves=waves, centre_grid=grid, mlp_rows=rows)
+                cells = (waves + rows // 16) % 2
+                eng.set_tuning(centre_waves=waves, centre_grid=grid, mlp_rows=rows, neighbor_cells=cells)
                 E, F, W = eng.energy_forces(q, virial=True)
-                assert torch.equal(E, E0) and torch.equal(F, F0) and torch.equal(W, W0), (waves, grid, rows)
-                assert torch.equal(eng.debug_descriptors(), x0), (waves, grid, rows)
+                shape = (waves, grid, rows, cells)
+                assert torch.equal(E, E0) and torch.equal(F, F0) and torch.equal(W, W0), shape
+                assert torch.equal(eng.debug_descriptors(), x0), shape
 
 
 def test_autotune_picks_a_valid_shape_and_the_cache_reapplies_it(tmp_path, monkeypatch):
@@ -391,6 +397,7 @@ def test_autotune_picks_a_valid_shape_and_the_cache_reapplies_it(tmp_path, monke
     shape, cached = a.autotune(n_reps=2)
     assert not cached
     assert shape["centre_waves"] in (1, 2, 4) and shape["mlp_rows"] in (16, 32, 64) and shape["centre_grid"] >= 0
+    assert shape["neighbor_cells"] in (0, 1)
     # the state does not move and the forces are those of the same positions
     _, _, F_after, step1 = a.get_state()
     assert step1 == step0 and torch.equal(F_before, F_after)
@@ -410,7 +417,7 @@ def test_bad_launch_shapes_are_rejected():
     from paper_2503_23728_amd.abi import PimdError, PIMD_E_ARG, PIMD_E_UNSUPPORTED
     wl = WORKLOADS["fad-P4"]()
     eng = _engine(wl)
-    for bad in ({"centre_waves": 3}, {"centre_waves": 8}, {"mlp_rows": 48}, {"centre_grid": -1}):
+    for bad in ({"centre_waves": 3}, {"centre_waves": 8}, {"mlp_rows": 48}, {"centre_grid": -1}, {"neighbor_cells": 2}):
         with pytest.raises(PimdError) as ei:
             eng.set_tuning(**bad)
         assert ei.value.status == PIMD_E_ARG
