@@ -162,6 +162,79 @@ def make_model(elements, n_rad, n_ang, hidden, seed, rad_scale=1.0, ang_scale=1.
                  feat_shift=shift, feat_scale=scale)
 
 
+@dataclass
+class GfnModel:
+    """Random weights of a direct-force head in the form of the paper's graph
+    field network (node and edge representations exchanging messages, forces
+    read out per edge).  Shapes (float32; hidden width H, L layers):
+      node_embed [n_el, H], pair_embed [n_el, n_el, H] (symmetric), edge_in [H, n_rad]
+      per layer: msg = (W1 [H, H], b1 [H], W2 [H, H], b2 [H]),
+                 node = (W1 [H, 2H], b1, W2 [H, H], b2), edge = (W1 [H, H], b1, W2 [H, H], b2)
+      force = (W1 [H, H], b1 [H], w2 [H], b2 scalar)
+    The radial basis of an edge uses the grid rad_center / rad_eta."""
+    elements: list
+    masses: np.ndarray
+    cutoff: float
+    rad_center: np.ndarray
+    rad_eta: np.ndarray
+    width: int
+    node_embed: np.ndarray
+    pair_embed: np.ndarray
+    edge_in: np.ndarray
+    layers: list            # [(msg, node, edge)] per layer, each a (W1, b1, W2, b2) tuple
+    force: tuple
+
+    @property
+    def n_elements(self):
+        return len(self.elements)
+
+    @property
+    def n_rad(self):
+        return len(self.rad_center)
+
+    @property
+    def n_layers(self):
+        return len(self.layers)
+
+
+def make_gfn_model(elements, n_rad, width, n_layers, seed):
+    """Weights ~ N(0, 1/fan_in), embeddings ~ N(0, 1) (pair embeddings
+    symmetrised), zero biases."""
+    rng = np.random.default_rng(seed)
+    rc, re = radial_grid(n_rad)
+    n_el, H = len(elements), width
+
+    def lin(n_out, n_in):
+        return (rng.normal(0.0, 1.0 / math.sqrt(n_in), size=(n_out, n_in)).astype(np.float32),
+                np.zeros(n_out, dtype=np.float32))
+
+    def mlp(n_in):
+        W1, b1 = lin(H, n_in)
+        W2, b2 = lin(H, H)
+        return (W1, b1, W2, b2)
+
+    node_embed = rng.normal(0.0, 1.0, size=(n_el, H)).astype(np.float32)
+    pe = rng.normal(0.0, 1.0, size=(n_el, n_el, H))
+    pair_embed = (0.5 * (pe + pe.transpose(1, 0, 2))).astype(np.float32)
+    edge_in = lin(H, n_rad)[0]
+    layers = [(mlp(H), mlp(2 * H), mlp(H)) for _ in range(n_layers)]
+    W1, b1 = lin(H, H)
+    w2 = rng.normal(0.0, 1.0 / math.sqrt(H), size=H).astype(np.float32)
+    return GfnModel(elements=list(elements), masses=np.array([ELEMENT_MASS[e] for e in elements]),
+                    cutoff=CUTOFF_A, rad_center=rc, rad_eta=re, width=H, node_embed=node_embed,
+                    pair_embed=pair_embed, edge_in=edge_in, layers=layers,
+                    force=(W1, b1, w2, np.float32(0.0)))
+
+
+def gfn_workload(c, width=16, n_layers=2, seed_offset=0):
+    """Workload c with the direct-force head in place of the energy network
+    (same systems, seeds shifted by 500 for the head's weights)."""
+    wl = workload(c, seed_offset)
+    head = make_gfn_model(wl.model.elements, wl.model.n_rad, width, n_layers, 2500 + c + seed_offset)
+    return Workload(wl.name + "-gfn", wl.systems, head, wl.dt, wl.tau0, wl.pile_lambda, wl.n_steps,
+                    wl.philox_seed, wl.momentum_seed)
+
+
 # ----------------------------------------------------------------------------
 # geometries
 # ----------------------------------------------------------------------------
