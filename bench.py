@@ -78,6 +78,20 @@ def flops_model(n_rad, n_eta, pairs, triplets, triplets_in):
     return fwd, adj
 
 
+def gfn_flops_per_edge(n_rad, H, L):
+    """Algorithmic FLOPs of the direct-force head per directed edge, counted
+    from its definition (one FLOP per add, multiply, exp or divide; tanh 5):
+    radial basis 6 n_rad and e^(0) 2 H n_rad; an H->H->H MLP 4 H^2 + 7 H;
+    layer l rebuilds e^(l) (l edge MLPs on n_i + n_j, H adds each) and applies
+    the message MLP (+H to accumulate); the readout rebuilds e^(L) and applies
+    phi_f (2 H^2 + 7 H) and the edge force (6).  Returns (layers, readout)."""
+    basis = 6 * n_rad + 2 * H * n_rad
+    mlp = 4 * H * H + 7 * H
+    layers = sum(basis + l * (mlp + 2 * H) + mlp + H for l in range(L))
+    readout = basis + L * (mlp + 2 * H) + 2 * H * H + 7 * H + 6
+    return layers, readout
+
+
 def time_steps(eng, steps, warmup):
     import torch
     eng.step(warmup)
@@ -105,8 +119,8 @@ def plain_fp32(wl, steps, warmup, device, shape=None):
     off = 0
     for s in wl.systems:
         n = s.n_atoms * s.n_beads
-        e = Pimd(
-            [s], wl.model, wl.dt, wl.tau0, wl.pile_lambda, wl.philox_seed, precision="fp32", device=device)
+        e = Pimd([s], wl.model, wl.dt, wl.tau0, wl.pile_lambda, wl.philox_seed, precision="fp32", device=device,
+                 potential="gfn" if hasattr(wl.model, "width") else "bpnn")
         e.set_graph(False)
         if shape is not None:
             e.set_tuning(**shape)
@@ -130,7 +144,7 @@ def cpu_baseline(wl, budget_s=20.0):
     until about budget_s seconds have passed."""
     import numpy as np
     from paper_2503_23728_amd import synthetic as S
-    from oracle import bpnn, ring
+    from oracle import bpnn, gfn, ring
     q, p = S.initial_state(wl)
     systems, rows, n_sys = [], 0, 0
     for s in wl.systems:
@@ -143,6 +157,8 @@ def cpu_baseline(wl, budget_s=20.0):
                      wl.momentum_seed)
 
     def fn(qq):
+        if hasattr(wl.model, "width"):
+            return np.zeros(sum(s.n_beads for s in systems)), gfn.forces(sub, qq.astype(np.float32))
         E, F, _ = bpnn.energy_forces(sub, qq.astype(np.float32))
         return E, F
     rp = ring.RingPolymers([(s.n_atoms, s.n_beads, s.temperature, wl.model.masses[s.species]) for s in systems],
@@ -174,6 +190,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-reps", type=int, default=10)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape (no autotuner)")
+    ap.add_argument("--potential", default="bpnn", choices=["bpnn", "gfn"],
+                    help="energy model with adjoint forces, or the direct-force head")
+    ap.add_argument("--gfn-width", type=int, default=16)
+    ap.add_argument("--gfn-layers", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
@@ -185,9 +205,10 @@ def main():
     from paper_2503_23728_amd.pimd import Pimd
 
     device = "cuda:0"
-    wl = S.workload(args.config)
+    gfn_mode = args.potential == "gfn"
+    wl = S.gfn_workload(args.config, args.gfn_width, args.gfn_layers) if gfn_mode else S.workload(args.config)
     B = wl.bead_atoms
-    eng = Pimd.from_workload(wl, precision=args.precision, device=device)
+    eng = Pimd.from_workload(wl, precision="fp32" if gfn_mode else args.precision, device=device)
     q, p = S.initial_state(wl)
     eng.set_state(torch.from_numpy(q).to(device), torch.from_numpy(p).to(device))
     if args.no_tune:
@@ -212,24 +233,37 @@ def main():
     kern = eng.time_stages(max(args.profile_reps, 5))
     pairs, trip, trip_in = eng.work_counts()
     m = wl.model
-    fwd_flops, adj_flops = flops_model(m.n_rad, len(m.ang_eta), pairs, trip, trip_in)
-    adj_ms = kern["adjoint"]
-    achieved = adj_flops / (adj_ms * 1e-3) / 1e12
-    traffic = measured_traffic(wl.name)
-    mlp_flops = B * mlp_flops_per_row(eng.D, m.hidden)
-    roofline = {"kernel": "k_adjoint (descriptor adjoint with recomputation)", "bound": "alu",
-                "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,
-                "flops_per_launch": adj_flops, "launch_ms": round(adj_ms, 4),
-                "forward": {"kernel": "k_descriptors", "flops_per_launch": fwd_flops,
-                            "launch_ms": round(kern["descriptors"], 4),
-                            "achieved": round(fwd_flops / (kern["descriptors"] * 1e-3) / 1e12, 3)},
-                "mlp": {"kernel": "k_mlp", "bound": "mfma", "flops_per_launch": mlp_flops,
-                        "launch_ms": round(kern["mlp"], 4),
-                        "achieved": round(mlp_flops / (kern["mlp"] * 1e-3) / 1e12, 3),
-                        "peak": BF16_MFMA_PEAK_TFLOPS,
-                        "frac": round(mlp_flops / (kern["mlp"] * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4)},
-                "work": {"pairs": pairs, "triplets": trip, "triplets_in_range": trip_in}}
+    if gfn_mode:
+        kern = {"neighbors": kern["neighbors"], "gfn_layers": kern["descriptors"], "gfn_readout": kern["adjoint"],
+                "bead_sums": kern["forces"]}
+        lf, rf = gfn_flops_per_edge(m.n_rad, m.width, m.n_layers)
+        flops = pairs * (lf + rf) + B * m.n_layers * (6 * m.width * m.width + 7 * m.width)
+        head_ms = kern["gfn_layers"] + kern["gfn_readout"]
+        achieved = flops / (head_ms * 1e-3) / 1e12
+        roofline = {"kernel": "k_gfn_layer + k_gfn_forces (direct-force head)", "bound": "alu",
+                    "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                    "flops_per_launch": flops, "launch_ms": round(head_ms, 4),
+                    "work": {"pairs": pairs, "width": m.width, "layers": m.n_layers}}
+    else:
+        fwd_flops, adj_flops = flops_model(m.n_rad, len(m.ang_eta), pairs, trip, trip_in)
+        adj_ms = kern["adjoint"]
+        achieved = adj_flops / (adj_ms * 1e-3) / 1e12
+        traffic = measured_traffic(wl.name)
+        mlp_flops = B * mlp_flops_per_row(eng.D, m.hidden)
+        roofline = {"kernel": "k_adjoint (descriptor adjoint with recomputation)", "bound": "alu",
+                    "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,
+                    "flops_per_launch": adj_flops, "launch_ms": round(adj_ms, 4),
+                    "forward": {"kernel": "k_descriptors", "flops_per_launch": fwd_flops,
+                                "launch_ms": round(kern["descriptors"], 4),
+                                "achieved": round(fwd_flops / (kern["descriptors"] * 1e-3) / 1e12, 3)},
+                    "mlp": {"kernel": "k_mlp", "bound": "mfma", "flops_per_launch": mlp_flops,
+                            "launch_ms": round(kern["mlp"], 4),
+                            "achieved": round(mlp_flops / (kern["mlp"] * 1e-3) / 1e12, 3),
+                            "peak": BF16_MFMA_PEAK_TFLOPS,
+                            "frac": round(mlp_flops / (kern["mlp"] * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4)},
+                    "work": {"pairs": pairs, "triplets": trip, "triplets_in_range": trip_in}}
     print(f"[bench] stages {json.dumps({k: round(v, 4) for k, v in stages.items()})}", file=sys.stderr, flush=True)
     print(f"[bench] kernels {json.dumps({k: round(v, 4) for k, v in kern.items()})}", file=sys.stderr, flush=True)
 
@@ -238,11 +272,12 @@ def main():
         "value": value, "unit": "bead-atom force evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "f32 (MLP GEMM operands bf16 x3 split)",
-                  "bf16-plain": "f32 (MLP GEMM operands bf16)"}[args.precision],
+        "dtype": "f32" if gfn_mode else {"fp32": "f32", "bf16": "f32 (MLP GEMM operands bf16 x3 split)",
+                                         "bf16-plain": "f32 (MLP GEMM operands bf16)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": wl.name, "systems": len(wl.systems), "bead_atoms": B,
-                   "beads": sum(s.n_beads for s in wl.systems), "dt_fs": wl.dt, "precision": args.precision,
+                   "beads": sum(s.n_beads for s in wl.systems), "dt_fs": wl.dt,
+                   "precision": "fp32" if gfn_mode else args.precision, "potential": args.potential,
                    "launch": "hip graph per step", "launch_shape": shape,
                    "shape_source": {None: "default", True: "tuning cache", False: "autotuner"}[cached]},
         "ns_per_day": ns_day, "gpu_event_s": gpu_s,
@@ -258,6 +293,18 @@ def main():
                              "launch": "eager, one context per system"}
         out["vs_plain_fp32"] = value / pval
         print(f"[bench] plain fp32: {1e3 * pwall / psteps:.3f} ms/step", file=sys.stderr, flush=True)
+    if gfn_mode:
+        # the energy model with adjoint forces on the same systems (BF16-split MLP, its own tuned shape)
+        ewl = S.workload(args.config)
+        eeng = Pimd.from_workload(ewl, precision="bf16", device=device)
+        eq, ep = S.initial_state(ewl)
+        eeng.set_state(torch.from_numpy(eq).to(device), torch.from_numpy(ep).to(device))
+        if not args.no_tune:
+            eeng.autotune(n_reps=3)
+        ewall, _ = time_steps(eeng, args.steps, args.warmup)
+        out["energy_model_ms_per_step"] = 1e3 * ewall / args.steps
+        out["head_speedup_vs_energy_model"] = ewall / wall
+        print(f"[bench] energy model: {1e3 * ewall / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

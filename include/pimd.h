@@ -65,7 +65,7 @@ typedef enum {
  *   FP64_MLP    FP64 operands, activations and accumulation (FP64 MFMA).
  * Descriptors, adjoint and integrator are FP32 in every mode. */
 enum { PIMD_PREC_FP32 = 0, PIMD_PREC_BF16_MLP = 1, PIMD_PREC_BF16_PLAIN = 2, PIMD_PREC_FP64_MLP = 3 };
-enum { PIMD_POT_BPNN = 0, PIMD_POT_HARMONIC = 1 };
+enum { PIMD_POT_BPNN = 0, PIMD_POT_HARMONIC = 1, PIMD_POT_GFN = 2 };
 
 /*
  * Behler-Parrinello model.  Symmetry functions of centre atom i with
@@ -101,6 +101,37 @@ typedef struct {
 } pimd_bpnn_model;
 
 /*
+ * Direct-force head in the form of the graph field network of Sec. 2.2:
+ * forces are an edge property, read out from edge representations that
+ * exchange messages with node representations; there is no energy (bead
+ * energies and V_bar are reported as 0, the virial as 0).  Width H (16 or
+ * 32), L = n_layers (1..3), tanh activations, phi(x) = W2 tanh(W1 x + b1) + b2:
+ *   rho_s(r)   = exp(-rad_eta_s (r - rad_center_s)^2) f_c(r),  f_c = (cos(pi r/rc) + 1)/2
+ *   n_i^(0)    = node_embed[Z_i]
+ *   e_ij^(0)   = edge_in rho(r_ij) + pair_embed[Z_i][Z_j]          (pair_embed symmetric)
+ *   m_i^(l)    = sum_{j in N(i)} phi_msg^(l)(e_ij^(l))
+ *   n_i^(l+1)  = n_i^(l) + phi_node^(l)([n_i^(l); m_i^(l)])
+ *   e_ij^(l+1) = e_ij^(l) + phi_edge^(l)(n_i^(l) + n_j^(l))
+ *   F_i        = sum_{j in N(i)} f_c(r_ij) (q_j - q_i)/r_ij (w2 . tanh(W1 e_ij^(L) + b1) + b2)
+ * params, float32 row-major, in this order: node_embed [n_el][H],
+ * pair_embed [n_el][n_el][H], edge_in [H][n_rad]; per layer phi_msg (W1 [H][H],
+ * b1 [H], W2 [H][H], b2 [H]), phi_node (W1 [H][2H], b1, W2 [H][H], b2), phi_edge
+ * (W1 [H][H], b1, W2, b2); then the readout W1 [H][H], b1 [H], w2 [H], b2 [1].
+ * The neighbour lists are those of the energy model (same cutoff rules).
+ */
+typedef struct {
+    int32_t n_elements;          /* 1..4 */
+    const double *mass_amu;      /* [n_elements] */
+    double cutoff_A;             /* < half of every box length */
+    int32_t n_rad;               /* 1..32 */
+    const double *rad_center_A;  /* [n_rad] */
+    const double *rad_eta;       /* [n_rad] 1/A^2 */
+    int32_t width;               /* H: 16 or 32 */
+    int32_t n_layers;            /* 1..3 */
+    const float *params;         /* packed weights, see above */
+} pimd_gfn_model;
+
+/*
  * Ring polymers.  n_systems independent systems, each with its own atom
  * count, bead count (1 or even, <= 128), temperature and orthorhombic box.
  * Integrator: normal-mode PIMD with the PILE-L thermostat in the splitting
@@ -131,6 +162,7 @@ typedef struct {
     const pimd_bpnn_model *model;      /* PIMD_POT_BPNN: the model; HARMONIC: masses only */
     double harmonic_omega_per_fs;      /* PIMD_POT_HARMONIC: V = sum 1/2 m w^2 |q|^2 */
     int32_t max_neighbors;             /* neighbour slots per atom: 0 => 128; a multiple of 16, <= 256 */
+    const pimd_gfn_model *gfn;         /* PIMD_POT_GFN: the direct-force head (precision is ignored: FP32) */
 } pimd_config;
 
 /* Finite-P estimators of one system (Sec. 2.1; virial kinetic energy of

@@ -16,7 +16,7 @@ HEADER = os.path.join(HERE, "..", "include", "pimd.h")
 PIMD_OK, PIMD_E_ARG, PIMD_E_UNSUPPORTED, PIMD_E_DEVICE, PIMD_E_OOM, PIMD_E_CAPACITY, PIMD_E_NONFINITE, \
     PIMD_E_STATE = range(8)
 PIMD_PREC_FP32, PIMD_PREC_BF16_MLP, PIMD_PREC_BF16_PLAIN, PIMD_PREC_FP64_MLP = 0, 1, 2, 3
-PIMD_POT_BPNN, PIMD_POT_HARMONIC = 0, 1
+PIMD_POT_BPNN, PIMD_POT_HARMONIC, PIMD_POT_GFN = 0, 1, 2
 
 
 class pimd_bpnn_model(ctypes.Structure):
@@ -27,12 +27,19 @@ class pimd_bpnn_model(ctypes.Structure):
                 ("params", POINTER(c_float)), ("feat_shift", POINTER(c_float)), ("feat_scale", POINTER(c_float))]
 
 
+class pimd_gfn_model(ctypes.Structure):
+    _fields_ = [("n_elements", c_int32), ("mass_amu", POINTER(c_double)), ("cutoff_A", c_double),
+                ("n_rad", c_int32), ("rad_center_A", POINTER(c_double)), ("rad_eta", POINTER(c_double)),
+                ("width", c_int32), ("n_layers", c_int32), ("params", POINTER(c_float))]
+
+
 class pimd_config(ctypes.Structure):
     _fields_ = [("n_systems", c_int32), ("n_atoms", POINTER(c_int32)), ("n_beads", POINTER(c_int32)),
                 ("temperature_K", POINTER(c_double)), ("box_A", POINTER(c_double)), ("species", POINTER(c_int32)),
                 ("dt_fs", c_double), ("tau0_fs", c_double), ("pile_lambda", c_double), ("seed", c_uint64),
                 ("precision", c_int32), ("potential", c_int32), ("model", POINTER(pimd_bpnn_model)),
-                ("harmonic_omega_per_fs", c_double), ("max_neighbors", c_int32)]
+                ("harmonic_omega_per_fs", c_double), ("max_neighbors", c_int32),
+                ("gfn", POINTER(pimd_gfn_model))]
 
 
 class pimd_tuning(ctypes.Structure):

@@ -17,6 +17,7 @@
 // (displacement, r, f_c, exp(-eta r^2) f_c and their r-derivatives) are staged
 // once in LDS and shared by all triplets of the centre.
 #include "device_common.hpp"
+#include "pair_terms.hpp"
 
 namespace pimd {
 
@@ -31,57 +32,6 @@ struct Recs {
     float4 *E;
     float4 *rr;
 };
-
-// Displacement d_ij = q_j - q_i (minimum image) of the unwrapped float32
-// positions, formed in FP64 with the FP64 box and rounded once to float32, so
-// it carries no rounding from wrapping large coordinates.  The neighbour set
-// itself comes from the float32 test of the neighbour kernel; for |d| < rc <
-// L/2 the minimum image is unique, so both choose the same image.
-__device__ __forceinline__ void displacement(const float4 &pi, const float4 &pj, const BeadInfo &bi, float3 &d,
-                                             float &r, float &r_lo, float &inv_r)
-{
-    double dx = (double)pj.x - (double)pi.x, dy = (double)pj.y - (double)pi.y, dz = (double)pj.z - (double)pi.z;
-    if (bi.periodic) {
-        dx -= bi.L64[0] * rint(dx * bi.invL64[0]);
-        dy -= bi.L64[1] * rint(dy * bi.invL64[1]);
-        dz -= bi.L64[2] * rint(dz * bi.invL64[2]);
-    }
-    const double r64 = sqrt(dx * dx + dy * dy + dz * dz);
-    d = make_float3((float)dx, (float)dy, (float)dz);
-    r = (float)r64;
-    r_lo = (float)(r64 - (double)r);
-    inv_r = (float)(1.0 / r64);
-}
-
-// Cutoff function and derivative from x = r/rc in [0, 1):
-//   f_c = (cos(pi x) + 1)/2 = cos^2(pi x/2),  f_c' = -(pi/rc) sin(pi x/2) cos(pi x/2).
-// sin and cos of pi u (u = x/2) come from their Taylor series on the reduced
-// argument w = min(u, 1/2 - u) <= 1/4 (five and six terms: truncation below
-// 3e-8); the reflection keeps both relative-accurate, so f_c has no
-// cancellation near the cutoff.
-__device__ __forceinline__ void cutoff_fn(float x, float pi_over_rc, float &fc, float &dfc)
-{
-    const float u = 0.5f * x;
-    const float w = fminf(u, 0.5f - u);
-    const float t = 3.14159265358979f * w;
-    const float t2 = t * t;
-    float ps = 2.7557319224e-06f;
-    ps = fmaf(ps, t2, -1.9841269841e-04f);
-    ps = fmaf(ps, t2, 8.3333333333e-03f);
-    ps = fmaf(ps, t2, -1.6666666667e-01f);
-    ps = fmaf(ps, t2, 1.0f);
-    ps *= t;
-    float pc = -2.7557319224e-07f;
-    pc = fmaf(pc, t2, 2.4801587302e-05f);
-    pc = fmaf(pc, t2, -1.3888888889e-03f);
-    pc = fmaf(pc, t2, 4.1666666667e-02f);
-    pc = fmaf(pc, t2, -0.5f);
-    pc = fmaf(pc, t2, 1.0f);
-    const bool big = u > 0.25f;
-    const float sn = big ? pc : ps, cs = big ? ps : pc;
-    fc = cs * cs;
-    dfc = -pi_over_rc * sn * cs;
-}
 
 // Stage the records of centre i (slot order = key order: grouped by element)
 // and hand each slot's pair terms to per_slot(n, element, d, r, r_lo, inv_r,

@@ -38,7 +38,10 @@ struct Layout {
 struct Plan {
     int n_sys = 0, n_el = 0, B = 0, n_beads = 0, n_atoms = 0, ncol = 0, total_cells = 0, n_units = 0;
     int D = 0, Dp = 0, Kmax = 0, max_P = 1, n_rad = 0, n_ang_eta = 0;
-    bool any_periodic = false, any_open = false, bpnn = false;
+    bool any_periodic = false, any_open = false, bpnn = false, gfn = false;
+    bool nl = false;                           // neighbour lists (the energy model or the direct-force head)
+    int gfn_H = 0, gfn_L = 0;
+    size_t gfn_floats = 0;                     // packed weights of the direct-force head
     std::vector<int> cells_per_sys;            // cells per bead of each system
     std::vector<std::array<int, 3>> nc;
     size_t mlp_f32_floats = 0, mlp_bf16_elems = 0, mlp_f64_elems = 0, cmat_elems = 0, modes = 0;
@@ -52,6 +55,28 @@ pimd_status fail(std::string *err, pimd_status s, const std::string &msg)
     if (err)
         *err = msg;
     return s;
+}
+
+// The fields every potential provides: elements, masses, cutoff and radial grid.
+struct ModelView {
+    int n_el = 0;
+    const double *mass = nullptr;
+    double cutoff = 0.0;
+    int n_rad = 0;
+    const double *rad_center = nullptr, *rad_eta = nullptr;
+};
+
+ModelView model_view(const pimd_config *cfg)
+{
+    ModelView v;
+    if (cfg->potential == PIMD_POT_GFN) {
+        const pimd_gfn_model *g = cfg->gfn;
+        v = ModelView{g->n_elements, g->mass_amu, g->cutoff_A, g->n_rad, g->rad_center_A, g->rad_eta};
+    } else {
+        const pimd_bpnn_model *m = cfg->model;
+        v = ModelView{m->n_elements, m->mass_amu, m->cutoff_A, m->n_rad, m->rad_center_A, m->rad_eta};
+    }
+    return v;
 }
 
 // All checks are on host data only.
@@ -72,25 +97,51 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
     if (cfg->precision != PIMD_PREC_FP32 && cfg->precision != PIMD_PREC_BF16_MLP &&
         cfg->precision != PIMD_PREC_BF16_PLAIN && cfg->precision != PIMD_PREC_FP64_MLP)
         return fail(err, PIMD_E_ARG, "unknown precision");
-    if (cfg->potential != PIMD_POT_BPNN && cfg->potential != PIMD_POT_HARMONIC)
+    if (cfg->potential != PIMD_POT_BPNN && cfg->potential != PIMD_POT_HARMONIC && cfg->potential != PIMD_POT_GFN)
         return fail(err, PIMD_E_ARG, "unknown potential");
     if (cfg->max_neighbors < 0 || cfg->max_neighbors > kMaxNeighbors)
         return fail(err, PIMD_E_UNSUPPORTED, "max_neighbors must be in [0, 256]");
     if (cfg->max_neighbors % 16)
         return fail(err, PIMD_E_ARG, "max_neighbors must be a multiple of 16");
-    const pimd_bpnn_model *m = cfg->model;
-    if (!m)
-        return fail(err, PIMD_E_ARG, "model is NULL (it carries the element masses)");
-    if (m->n_elements < 1 || m->n_elements > kMaxElements)
-        return fail(err, PIMD_E_UNSUPPORTED, "n_elements must be in [1, 4]");
-    if (!m->mass_amu)
-        return fail(err, PIMD_E_ARG, "mass_amu is NULL");
-    for (int e = 0; e < m->n_elements; ++e)
-        if (!(m->mass_amu[e] > 0.0) || !std::isfinite(m->mass_amu[e]))
-            return fail(err, PIMD_E_ARG, "masses must be positive");
     pl.bpnn = cfg->potential == PIMD_POT_BPNN;
-    pl.n_el = m->n_elements;
-    if (pl.bpnn) {
+    pl.gfn = cfg->potential == PIMD_POT_GFN;
+    pl.nl = pl.bpnn || pl.gfn;
+    const pimd_bpnn_model *m = cfg->model;
+    const pimd_gfn_model *g = cfg->gfn;
+    if (pl.gfn ? !g : !m)
+        return fail(err, PIMD_E_ARG, "model is NULL (it carries the element masses)");
+    const ModelView mv = model_view(cfg);
+    if (mv.n_el < 1 || mv.n_el > kMaxElements)
+        return fail(err, PIMD_E_UNSUPPORTED, "n_elements must be in [1, 4]");
+    if (!mv.mass)
+        return fail(err, PIMD_E_ARG, "mass_amu is NULL");
+    for (int e = 0; e < mv.n_el; ++e)
+        if (!(mv.mass[e] > 0.0) || !std::isfinite(mv.mass[e]))
+            return fail(err, PIMD_E_ARG, "masses must be positive");
+    pl.n_el = mv.n_el;
+    if (pl.gfn) {
+        if (!(g->cutoff_A > 0.0) || !std::isfinite(g->cutoff_A))
+            return fail(err, PIMD_E_ARG, "cutoff must be positive");
+        if (g->n_rad < 1 || g->n_rad > kMaxRad)
+            return fail(err, PIMD_E_UNSUPPORTED, "n_rad must be in [1, 32]");
+        if (g->width != 16 && g->width != 32)
+            return fail(err, PIMD_E_UNSUPPORTED, "the head's width must be 16 or 32");
+        if (g->n_layers < 1 || g->n_layers > 3)
+            return fail(err, PIMD_E_UNSUPPORTED, "n_layers must be in [1, 3]");
+        if (!g->rad_center_A || !g->rad_eta || !g->params)
+            return fail(err, PIMD_E_ARG, "a model array is NULL");
+        for (int s2 = 0; s2 < g->n_rad; ++s2)
+            if (!std::isfinite(g->rad_center_A[s2]) || !(g->rad_eta[s2] >= 0.0))
+                return fail(err, PIMD_E_ARG, "bad radial grid");
+        pl.n_rad = g->n_rad;
+        pl.gfn_H = g->width;
+        pl.gfn_L = g->n_layers;
+        const size_t H = g->width, ne = g->n_elements;
+        pl.gfn_floats = ne * H + ne * ne * H + H * g->n_rad +
+                        (size_t)g->n_layers * ((H * H + 2 * H + H * H) + (2 * H * H + 2 * H + H * H) +
+                                               (H * H + 2 * H + H * H)) +
+                        H * H + 2 * H + 1;
+    } else if (pl.bpnn) {
         if (!(m->cutoff_A > 0.0) || !std::isfinite(m->cutoff_A))
             return fail(err, PIMD_E_ARG, "cutoff must be positive");
         if (m->n_rad < 1 || m->n_rad > kMaxRad || m->n_elements * m->n_rad > 64)
@@ -144,19 +195,19 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
             for (int d = 0; d < 3; ++d)
                 if (!(L[d] > 0.0) || !std::isfinite(L[d]))
                     return fail(err, PIMD_E_ARG, "box lengths must be all positive or all zero");
-            if (pl.bpnn) {
+            if (pl.nl) {
                 for (int d = 0; d < 3; ++d)
-                    if (!(m->cutoff_A < 0.5 * L[d]))
+                    if (!(mv.cutoff < 0.5 * L[d]))
                         return fail(err, PIMD_E_UNSUPPORTED, "cutoff must be below half of every box length");
                 for (int d = 0; d < 3; ++d)
-                    nc[d] = std::max(1, (int)std::floor(L[d] / (m->cutoff_A + 1e-4)));
+                    nc[d] = std::max(1, (int)std::floor(L[d] / (mv.cutoff + 1e-4)));
                 pl.any_periodic = true;
             }
         } else {
             pl.any_open = true;
         }
         pl.nc.push_back(nc);
-        const int per_bead = zero || !pl.bpnn ? 0 : nc[0] * nc[1] * nc[2];
+        const int per_bead = zero || !pl.nl ? 0 : nc[0] * nc[1] * nc[2];
         pl.cells_per_sys.push_back(per_bead);
         cells += (int64_t)per_bead * P;
         B += (int64_t)N * P;
@@ -172,7 +223,7 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
     if (B >= (int64_t)kRowMask || cells > (int64_t)1 << 30)
         return fail(err, PIMD_E_UNSUPPORTED, "too many bead-atoms (limit 2^27)");
     for (int64_t a = 0; a < na; ++a)
-        if (cfg->species[a] < 0 || cfg->species[a] >= m->n_elements)
+        if (cfg->species[a] < 0 || cfg->species[a] >= mv.n_el)
             return fail(err, PIMD_E_ARG, "species index out of range");
     pl.B = (int)B;
     pl.n_beads = (int)nb;
@@ -212,7 +263,7 @@ Layout make_layout(const Plan &pl)
     L.add("posu4", B * 16);
     L.add("E_atom", B * 4);
     L.add("vir_atom", B * 36);
-    if (pl.bpnn) {
+    if (pl.nl) {
         L.add("atom_cell", B * 4);
         L.add("atom_slot", B * 4);
         L.add("cell_count", (size_t)pl.total_cells * 4);
@@ -223,6 +274,12 @@ Layout make_layout(const Plan &pl)
         L.add("nbr_cnt", B * 4);
         L.add("nbr_grp", B * kMaxElements * 4);
         L.add("nbr_fence", B * kFence * 4);
+    }
+    if (pl.gfn) {
+        L.add("gfn_params", pl.gfn_floats * 4);
+        L.add("gfn_nodes", (size_t)(pl.gfn_L + 1) * B * pl.gfn_H * 4);
+    }
+    if (pl.bpnn) {
         L.add("xhat", B * D * 4);
         L.add("dEdG", B * D * 4);
         L.add("vslot", B * K * 16);
@@ -277,6 +334,7 @@ struct pimd_ctx {
     Sizes z{};
     DevBuffers d{};
     DescParams dp{};
+    GfnParams gp{};
     MlpNets nets{};
     int n_mlp_tiles = 0;
     std::vector<int32_t> elem_row0;   // [n_el + 1] first MLP row of each element in elem_rows
@@ -339,17 +397,30 @@ void launch_force_stage(pimd_ctx *c, int stage, const float *q, float *E_out, fl
         launch_neighbors(d, z, c->dp.rc2, c->pl.n_el, c->tn, s);
         break;
     case 1:
-        launch_descriptors(d, z, c->dp, c->tn, s);
+        if (c->pl.gfn)
+            launch_gfn_layers(d, z, c->dp, c->gp, c->tn, s);
+        else
+            launch_descriptors(d, z, c->dp, c->tn, s);
         break;
     case 2:
-        launch_mlp(d, c->nets, c->n_mlp_tiles, c->pl.D, c->pl.Dp, c->precision, c->tn.mlp_rows, s);
+        if (c->pl.bpnn)
+            launch_mlp(d, c->nets, c->n_mlp_tiles, c->pl.D, c->pl.Dp, c->precision, c->tn.mlp_rows, s);
         break;
     case 3:
-        if (F_out || W_out)
+        if (c->pl.gfn) {
+            // the head has no energy: atomic energies and virials are zero
+            if (F_out) {
+                launch_gfn_forces(d, z, c->dp, c->gp, c->tn, F_out, s);
+            } else {
+                launch_zero_i32(reinterpret_cast<int32_t *>(d.E_atom), z.B, s);
+                launch_zero_i32(reinterpret_cast<int32_t *>(d.vir_atom), (int64_t)z.B * 9, s);
+            }
+        } else if (F_out || W_out) {
             launch_adjoint(d, z, c->dp, c->tn, s);
+        }
         break;
     default:
-        if (F_out)
+        if (F_out && c->pl.bpnn)
             launch_assemble_forces(d, z, F_out, c->tn, s);
         launch_bead_sums(d, z, E_out, W_out, W_out != nullptr, s);
     }
@@ -483,7 +554,8 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     c->potential = cfg->potential;
     c->omega = cfg->harmonic_omega_per_fs;
     const pimd_bpnn_model *m = cfg->model;
-    c->masses_el.assign(m->mass_amu, m->mass_amu + m->n_elements);
+    const ModelView mv = model_view(cfg);
+    c->masses_el.assign(mv.mass, mv.mass + mv.n_el);
     c->species.assign(cfg->species, cfg->species + pl.n_atoms);
     c->temperature.assign(cfg->temperature_K, cfg->temperature_K + pl.n_sys);
 
@@ -513,6 +585,8 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     d.nbr_cnt = (int32_t *)at("nbr_cnt");
     d.nbr_grp = (int32_t *)at("nbr_grp");
     d.nbr_fence = (int32_t *)at("nbr_fence");
+    d.gfn_params = (float *)at("gfn_params");
+    d.gfn_nodes = (float *)at("gfn_nodes");
     d.xhat = (float *)at("xhat");
     d.dEdG = (float *)at("dEdG");
     d.vslot = (float4 *)at("vslot");
@@ -583,7 +657,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         const int N = cfg->n_atoms[s], P = cfg->n_beads[s];
         const double T = cfg->temperature_K[s];
         const double *Lb = cfg->box_A + 3 * s;
-        const bool periodic = pl.bpnn && (Lb[0] != 0.0 || Lb[1] != 0.0 || Lb[2] != 0.0);
+        const bool periodic = pl.nl && (Lb[0] != 0.0 || Lb[1] != 0.0 || Lb[2] != 0.0);
         SysInfo si{};
         si.N = N;
         si.P = P;
@@ -641,7 +715,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
             beads.push_back(bi);
         }
         for (int i = 0; i < N; ++i) {
-            mass_atom[atom0 + i] = (float)m->mass_amu[cfg->species[atom0 + i]];
+            mass_atom[atom0 + i] = (float)mv.mass[cfg->species[atom0 + i]];
             for (int cc = 0; cc < 3; ++cc)
                 col_sys[3 * (atom0 + i) + cc] = s;
         }
@@ -666,27 +740,61 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     push(d.modes, modes.data(), modes.size() * sizeof(ModeInfo));
     push(d.units, units.data(), units.size() * sizeof(IntegUnit));
     push(d.cmat, cmat.data(), cmat.size() * 8);
-    if (pl.bpnn)
+    if (pl.nl)
         push(d.cell_bead, cell_bead.data(), cell_bead.size() * 4);
     push(d.col_sys, col_sys.data(), col_sys.size() * 4);
 
+    if (pl.nl) {
+        // cutoff and radial grid (both neural potentials)
+        DescParams &dp = c->dp;
+        dp.n_el = mv.n_el;
+        dp.n_rad = mv.n_rad;
+        dp.Kmax = pl.Kmax;
+        dp.rc = (float)mv.cutoff;
+        dp.rc2 = (float)(mv.cutoff * mv.cutoff);
+        dp.pi_over_rc = (float)(kPi / mv.cutoff);
+        dp.half_over_rc = (float)(0.5 / mv.cutoff);
+        for (int s = 0; s < mv.n_rad; ++s) {
+            dp.rad_center[s] = (float)mv.rad_center[s];
+            dp.rad_center_lo[s] = (float)(mv.rad_center[s] - (double)dp.rad_center[s]);
+            dp.rad_eta[s] = (float)mv.rad_eta[s];
+        }
+    }
+    if (pl.gfn) {
+        // packed weights go to the device as they are; the head's tables point into them
+        const pimd_gfn_model *g = cfg->gfn;
+        push(d.gfn_params, g->params, pl.gfn_floats * 4);
+        const int H = g->width, ne = g->n_elements;
+        const float *p0 = d.gfn_params;
+        size_t o = 0;
+        auto take = [&](size_t n) {
+            const float *q = p0 + o;
+            o += n;
+            return q;
+        };
+        GfnParams &gp = c->gp;
+        gp.H = H;
+        gp.L = g->n_layers;
+        gp.node_embed = take((size_t)ne * H);
+        gp.pair_embed = take((size_t)ne * ne * H);
+        gp.edge_in = take((size_t)H * g->n_rad);
+        for (int l = 0; l < g->n_layers; ++l) {
+            const size_t HH = (size_t)H * H;
+            gp.msg[l] = GfnMlp{take(HH), take(H), take(HH), take(H)};
+            gp.node[l] = GfnMlp{take(2 * HH), take(H), take(HH), take(H)};
+            gp.edge[l] = GfnMlp{take(HH), take(H), take(HH), take(H)};
+        }
+        gp.fW1 = take((size_t)H * H);
+        gp.fb1 = take(H);
+        gp.fw2 = take(H);
+        gp.fb2 = g->params[o];
+        (void)take(1);
+    }
     if (pl.bpnn) {
         DescParams &dp = c->dp;
-        dp.n_el = m->n_elements;
-        dp.n_rad = m->n_rad;
         dp.n_ang_eta = m->n_ang_eta;
         dp.n_ang = 8 * m->n_ang_eta;
         dp.D = pl.D;
-        dp.Kmax = pl.Kmax;
-        dp.rc = (float)m->cutoff_A;
-        dp.rc2 = (float)(m->cutoff_A * m->cutoff_A);
-        dp.pi_over_rc = (float)(kPi / m->cutoff_A);
-        dp.half_over_rc = (float)(0.5 / m->cutoff_A);
-        for (int s = 0; s < m->n_rad; ++s) {
-            dp.rad_center[s] = (float)m->rad_center_A[s];
-            dp.rad_center_lo[s] = (float)(m->rad_center_A[s] - (double)dp.rad_center[s]);
-            dp.rad_eta[s] = (float)m->rad_eta[s];
-        }
         for (int s = 0; s < m->n_ang_eta; ++s)
             dp.ang_eta[s] = (float)m->ang_eta[s];
         // rows grouped by element for the MLP gather, cut into tiles of tn.mlp_rows
@@ -816,6 +924,8 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         e = configure_descriptor_lds(c->dp);
         if (e != hipSuccess)
             return bail(PIMD_E_DEVICE, std::string("descriptor LDS: ") + hipGetErrorString(e));
+    }
+    if (pl.nl) {
         e = configure_neighbor_lds(pl.Kmax);
         if (e != hipSuccess)
             return bail(PIMD_E_DEVICE, std::string("neighbour LDS: ") + hipGetErrorString(e));
@@ -1031,7 +1141,7 @@ pimd_status pimd_debug_neighbors(pimd_ctx *ctx, int32_t bead, int32_t *ij_host, 
 {
     if (!ctx || !count)
         return PIMD_E_ARG;
-    if (ctx->potential != PIMD_POT_BPNN) {
+    if (!ctx->pl.nl) {
         ctx->err = "no neighbour list for this potential";
         return PIMD_E_STATE;
     }
@@ -1089,7 +1199,8 @@ pimd_status pimd_debug_copy(pimd_ctx *ctx, int32_t buffer, void *dst_dev, size_t
 {
     if (!ctx || !dst_dev)
         return PIMD_E_ARG;
-    if (ctx->potential != PIMD_POT_BPNN && buffer != PIMD_BUF_EATOM) {
+    const bool lists = buffer == PIMD_BUF_NBR || buffer == PIMD_BUF_NCOUNT;
+    if (buffer != PIMD_BUF_EATOM && !(lists ? ctx->pl.nl : ctx->pl.bpnn)) {
         ctx->err = "buffer not used by this potential";
         return PIMD_E_STATE;
     }
@@ -1220,7 +1331,7 @@ pimd_status pimd_autotune(pimd_ctx *ctx, int32_t n_reps, pimd_tuning *best)
         ctx->err = "pimd_set_state must come before pimd_autotune";
         return PIMD_E_STATE;
     }
-    if (ctx->pl.bpnn) {
+    if (ctx->pl.nl) {
         int n_cu = 0;
         HIPCHK(ctx, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
         Tuning cur = ctx->tn, top = cur;
@@ -1253,7 +1364,7 @@ pimd_status pimd_autotune(pimd_ctx *ctx, int32_t n_reps, pimd_tuning *best)
                 if ((st = consider(cand)) != PIMD_OK)
                     return st;
             }
-        if (ctx->precision != PIMD_PREC_FP64_MLP)
+        if (ctx->pl.bpnn && ctx->precision != PIMD_PREC_FP64_MLP)
             for (int rows : {16, 32, 64}) {
                 if (rows == top.mlp_rows)
                     continue;
@@ -1288,8 +1399,8 @@ pimd_status pimd_time_stages(pimd_ctx *ctx, int32_t n_reps, double *ms_host)
         ctx->err = "state not set";
         return PIMD_E_STATE;
     }
-    if (ctx->potential != PIMD_POT_BPNN) {
-        ctx->err = "stage timing needs the neural potential";
+    if (!ctx->pl.nl) {
+        ctx->err = "stage timing needs a neural potential";
         return PIMD_E_STATE;
     }
     DevBuffers &d = ctx->d;
@@ -1376,7 +1487,7 @@ pimd_status pimd_work_counts(pimd_ctx *ctx, int64_t *pairs, int64_t *triplets, i
 {
     if (!ctx || !pairs || !triplets || !triplets_in_range)
         return PIMD_E_ARG;
-    if (ctx->potential != PIMD_POT_BPNN) {
+    if (!ctx->pl.nl) {
         ctx->err = "no neighbour list for this potential";
         return PIMD_E_STATE;
     }

@@ -110,6 +110,22 @@ struct ModeInfo {
     double pad[3];
 };
 
+// Direct-force head: one small MLP y = W2 tanh(W1 x + b1) + b2 and the whole head
+// (pointers into the packed float32 weights in device memory).
+struct GfnMlp {
+    const float *W1, *b1, *W2, *b2;
+};
+
+struct GfnParams {
+    const float *node_embed;   // [n_el][H]
+    const float *pair_embed;   // [n_el][n_el][H]
+    const float *edge_in;      // [H][n_rad]
+    GfnMlp msg[3], node[3], edge[3];
+    const float *fW1, *fb1, *fw2;
+    float fb2;
+    int32_t H, L;
+};
+
 // Everything a step needs on the device, carved from the workspace.
 struct DevBuffers {
     float *q, *p, *F, *E_bead;     // integrator state, forces of q, bead energies
@@ -144,6 +160,8 @@ struct DevBuffers {
     uint16_t *mlp_bf16;            // packed bf16 weights (W, WT per element)
     double *mlp_f64;               // packed f64 weights (W, WT per element)
     float *norm;                   // [n_el][2][D] shift, 1/scale
+    float *gfn_params;             // direct-force head: packed weights
+    float *gfn_nodes;              // direct-force head: node states n^(0..L) [L+1][B][H]
 };
 
 // Launch shapes chosen by the tuner (results do not depend on them: every
@@ -188,6 +206,10 @@ void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &d
 void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int mlp_mode, int rows,
                 hipStream_t s);
 void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s);
+void launch_gfn_layers(const DevBuffers &d, const Sizes &z, const DescParams &dp, const GfnParams &gp,
+                       const Tuning &tn, hipStream_t s);
+void launch_gfn_forces(const DevBuffers &d, const Sizes &z, const DescParams &dp, const GfnParams &gp,
+                       const Tuning &tn, float *F, hipStream_t s);
 void launch_assemble_forces(const DevBuffers &d, const Sizes &z, float *F, const Tuning &tn, hipStream_t s);
 void launch_bead_sums(const DevBuffers &d, const Sizes &z, float *E_bead, float *W_bead, bool virial,
                       hipStream_t s);

@@ -50,15 +50,40 @@ class _Keep:
         return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
+def pack_gfn_params(head):
+    """The direct-force head's weights in the order include/pimd.h gives."""
+    parts = [head.node_embed, head.pair_embed, head.edge_in]
+    for msg, node, edge in head.layers:
+        for W1, b1, W2, b2 in (msg, node, edge):
+            parts += [W1, b1, W2, b2]
+    W1, b1, w2, b2 = head.force
+    parts += [W1, b1, w2, np.array([b2])]
+    return np.concatenate([np.ascontiguousarray(a, dtype=np.float32).ravel() for a in parts])
+
+
 def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
                 omega=0.0, max_neighbors=0, masses=None):
     """Build the pimd_config (and the storage it points into).
 
     systems: sequence with n_atoms, n_beads, temperature, box, species.
-    model: a synthetic.Model (BPNN) or None with `masses` (harmonic)."""
+    model: a synthetic.Model (BPNN), a synthetic.GfnModel (direct-force head,
+    potential "gfn"), or None with `masses` (harmonic)."""
     keep = _Keep()
     m = abi.pimd_bpnn_model()
-    if model is not None:
+    g = None
+    if potential == "gfn":
+        g = abi.pimd_gfn_model()
+        g.n_elements = model.n_elements
+        g.mass_amu = keep.arr(model.masses, np.float64, ctypes.c_double)
+        g.cutoff_A = float(model.cutoff)
+        g.n_rad = model.n_rad
+        g.rad_center_A = keep.arr(model.rad_center, np.float64, ctypes.c_double)
+        g.rad_eta = keep.arr(model.rad_eta, np.float64, ctypes.c_double)
+        g.width = model.width
+        g.n_layers = model.n_layers
+        g.params = keep.arr(pack_gfn_params(model), np.float32, ctypes.c_float)
+        keep.items.append(g)
+    elif model is not None:
         m.n_elements = model.n_elements
         m.mass_amu = keep.arr(model.masses, np.float64, ctypes.c_double)
         m.cutoff_A = float(model.cutoff)
@@ -91,8 +116,10 @@ def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", p
     cfg.seed = seed
     cfg.precision = {"fp32": abi.PIMD_PREC_FP32, "bf16": abi.PIMD_PREC_BF16_MLP,
                      "bf16-plain": abi.PIMD_PREC_BF16_PLAIN, "fp64-mlp": abi.PIMD_PREC_FP64_MLP}[precision]
-    cfg.potential = {"bpnn": abi.PIMD_POT_BPNN, "harmonic": abi.PIMD_POT_HARMONIC}[potential]
+    cfg.potential = {"bpnn": abi.PIMD_POT_BPNN, "harmonic": abi.PIMD_POT_HARMONIC,
+                     "gfn": abi.PIMD_POT_GFN}[potential]
     cfg.model = ctypes.pointer(m)
+    cfg.gfn = ctypes.pointer(g) if g is not None else None
     cfg.harmonic_omega_per_fs = omega
     cfg.max_neighbors = max_neighbors
     return cfg, keep
@@ -129,6 +156,10 @@ class Pimd:
 
     @classmethod
     def from_workload(cls, wl, **kw):
+        """A context for a synthetic workload; a workload whose model is the
+        direct-force head selects potential "gfn"."""
+        if type(wl.model).__name__ == "GfnModel":
+            kw.setdefault("potential", "gfn")
         return cls(wl.systems, wl.model, wl.dt, wl.tau0, wl.pile_lambda, wl.philox_seed, **kw)
 
     def close(self):

@@ -28,7 +28,10 @@ def config_key(arch, n_cu, systems, model, precision, max_neighbors):
         "arch": arch, "cu": int(n_cu), "precision": precision, "kmax": int(max_neighbors),
         "systems": sorted([int(s.n_atoms), int(s.n_beads), [round(float(b), 4) for b in s.box]] for s in systems),
     }
-    if model is not None:
+    if model is not None and hasattr(model, "width"):      # direct-force head
+        desc["model"] = {"head": "gfn", "elements": int(model.n_elements), "n_rad": int(model.n_rad),
+                         "width": int(model.width), "layers": int(model.n_layers), "cutoff": float(model.cutoff)}
+    elif model is not None:
         desc["model"] = {"elements": int(model.n_elements), "n_rad": int(model.n_rad),
                          "n_ang_eta": len(model.ang_eta), "hidden": [int(h) for h in model.hidden],
                          "cutoff": float(model.cutoff)}

@@ -51,3 +51,12 @@ def test_corrupt_or_partial_entries_are_ignored(tmp_path):
     assert tuning.load("k", str(path)) is None
     assert tuning.store("k", {"centre_waves": 1, "centre_grid": 0, "mlp_rows": 64, "neighbor_cells": 0}, str(path))
     assert tuning.load("k", str(path))["centre_waves"] == 1
+
+
+def test_key_of_the_direct_force_head_differs_from_the_energy_model():
+    wl = S.workload(2)
+    head = S.gfn_workload(2)
+    a = tuning.config_key("gfx950", 256, wl.systems, wl.model, "fp32", 0)
+    b = tuning.config_key("gfx950", 256, head.systems, head.model, "fp32", 0)
+    c = tuning.config_key("gfx950", 256, head.systems, S.gfn_workload(2, width=32).model, "fp32", 0)
+    assert len({a, b, c}) == 3
