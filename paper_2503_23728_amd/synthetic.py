@@ -199,7 +199,10 @@ class GfnModel:
 
 def make_gfn_model(elements, n_rad, width, n_layers, seed):
     """Weights ~ N(0, 1/fan_in), embeddings ~ N(0, 1) (pair embeddings
-    symmetrised), zero biases."""
+    symmetrised), zero biases; the readout vector w2 ~ N(0, 0.09/H), which
+    puts the rms force of the water workloads near 0.3 eV/A, the scale of the
+    energy network's forces (a head without an energy is not conservative, so
+    larger random forces heat the ring polymer quickly)."""
     rng = np.random.default_rng(seed)
     rc, re = radial_grid(n_rad)
     n_el, H = len(elements), width
@@ -219,7 +222,7 @@ def make_gfn_model(elements, n_rad, width, n_layers, seed):
     edge_in = lin(H, n_rad)[0]
     layers = [(mlp(H), mlp(2 * H), mlp(H)) for _ in range(n_layers)]
     W1, b1 = lin(H, H)
-    w2 = rng.normal(0.0, 1.0 / math.sqrt(H), size=H).astype(np.float32)
+    w2 = rng.normal(0.0, 0.3 / math.sqrt(H), size=H).astype(np.float32)
     return GfnModel(elements=list(elements), masses=np.array([ELEMENT_MASS[e] for e in elements]),
                     cutoff=CUTOFF_A, rad_center=rc, rad_eta=re, width=H, node_embed=node_embed,
                     pair_embed=pair_embed, edge_in=edge_in, layers=layers,
@@ -514,3 +517,78 @@ def perturbed_beads(wl, amplitude=0.05, seed=11):
         q = s.q0[None] + rng.uniform(-amplitude, amplitude, size=(s.n_beads, s.n_atoms, 3))
         qs.append(q.reshape(-1, 3))
     return np.concatenate(qs).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# well-tempered metadynamics settings (Sec. 2.5; S2 and S3 sampling paragraphs)
+# ----------------------------------------------------------------------------
+
+# 1 eV = 96.48533212 kJ/mol (CODATA 2018 Faraday constant).
+KJ_PER_MOL_IN_EV = 1.0 / 96.48533212
+
+# X-ray atomic scattering factors as four-Gaussian fits,
+# f(s) = sum_i a_i exp(-b_i s^2) + c with s = sin(theta)/lambda = Q/(4 pi)
+# (Cromer-Mann coefficients as tabulated in International Tables for
+# Crystallography Vol. C, Table 6.1.1.4); only f at one Q enters a run.
+_CROMER_MANN = {
+    "H": ((0.489918, 0.262003, 0.196767, 0.049879), (20.6593, 7.74039, 49.5519, 2.20159), 0.001305),
+    "C": ((2.31, 1.02, 1.5886, 0.865), (20.8439, 10.2075, 0.5687, 51.6512), 0.2156),
+    "O": ((3.0485, 2.2868, 1.5463, 0.867), (13.2771, 5.7011, 0.3239, 32.9089), 0.2508),
+}
+
+
+def scattering_factor(element, Q):
+    """X-ray form factor of an element at scattering vector Q (1/A)."""
+    a, b, c = _CROMER_MANN[element]
+    s2 = (Q / (4.0 * math.pi)) ** 2
+    return float(sum(ai * math.exp(-bi * s2) for ai, bi in zip(a, b)) + c)
+
+
+def scattering_vector(theta_deg, wavelength_A):
+    """Q = 4 pi sin(theta) / lambda (1/A)."""
+    return 4.0 * math.pi * math.sin(math.radians(theta_deg)) / wavelength_A
+
+
+# Double proton transfer in the dimer (Sec. 3.1): with the atom order of
+# formic_acid_dimer(), H(1) = 4 is bound to O(1) = 2 (monomer A hydroxyl) and
+# points at O(2) = 6 (monomer B carbonyl); H(2) = 9 is bound to O(4) = 7 and
+# points at O(3) = 1.  s = d(O1,H1) - d(O2,H1) + d(O4,H2) - d(O3,H2) is
+# -1.48 A in the reactant geometry and +1.48 A after both protons moved.
+FAD_DPT_ATOMS = np.array([[2, 4], [6, 4], [7, 9], [1, 9]], dtype=np.int32)
+FAD_DPT_COEF = np.array([1.0, -1.0, 1.0, -1.0])
+
+
+@dataclass
+class MetadSpec:
+    """Collective variable and well-tempered deposition settings.
+
+    cv "distances": s = sum_m coef[m] |r_atoms[m,0] - r_atoms[m,1]| (A);
+    cv "xrd": S = (1/N) sum_ij f_i f_j sinc(Q R_ij) with form_factor[element].
+    height0 in eV, sigma in CV units, stride in steps, max_hills per bead."""
+    cv: str
+    atoms: np.ndarray = None
+    coef: np.ndarray = None
+    q_scatter: float = 0.0
+    form_factor: np.ndarray = None
+    height0: float = 1.0 * KJ_PER_MOL_IN_EV
+    sigma: float = 0.05
+    gamma: float = 10.0
+    stride: int = 100
+    max_hills: int = 1024
+
+
+def metad_spec(wl, stride=None, max_hills=1024):
+    """The sampling settings of the paper's two studies for a workload:
+    dimer systems use s_dimer (S2: hill every 100 steps, 1 kJ/mol, bias
+    factor 10); water and ice use the XRD CV at theta = 11.95 deg,
+    lambda = 1.54 A (S3: hill every 0.05 ps, 1 kJ/mol, bias factor 60).
+    The widths are not given in the paper: 0.05 A for s_dimer and 0.05
+    (electrons^2) for S, small against each CV's spread over the beads of a
+    thermal ring polymer."""
+    if "C" in wl.model.elements:
+        return MetadSpec("distances", atoms=FAD_DPT_ATOMS.copy(), coef=FAD_DPT_COEF.copy(), sigma=0.05,
+                         gamma=10.0, stride=stride or 100, max_hills=max_hills)
+    Q = scattering_vector(11.95, 1.54)
+    f = np.array([scattering_factor(e, Q) for e in wl.model.elements])
+    return MetadSpec("xrd", q_scatter=Q, form_factor=f, sigma=0.05, gamma=60.0,
+                     stride=stride or int(round(50.0 / wl.dt)), max_hills=max_hills)
