@@ -12,6 +12,8 @@ the definition or the algorithm step it follows:
   bpnn         symmetry-function descriptors, per-element MLP, analytic forces
   ring         normal modes, PILE-L OBABO integrator, estimators, harmonic V
   qho          quantum-harmonic-oscillator closed forms
+  gfn          direct-force head in the graph-field-network form
+  metad        well-tempered metadynamics on bead CVs (s_dimer, XRD)
 
 The FP64 C core (bpnn_core.c) holds the triplet sums; oracle.build compiles
 it with gcc.
