@@ -132,6 +132,46 @@ typedef struct {
 } pimd_gfn_model;
 
 /*
+ * Well-tempered metadynamics on bead collective variables (Sec. 2.5; the CVs
+ * of Sec. 3.1 and Sec. 3.2).  Every bead k of every system carries its own
+ * bias, a sum of Gaussian hills deposited at that bead's own CV values:
+ *   V^(k)(s) = sum_h height_h exp(-(s - center_h)^2 / (2 sigma^2)),
+ * added to that bead's potential (bias force -dV^(k)/ds * ds/dq on the bead's
+ * atoms, added to the forces the integrator uses; bead energies stay the
+ * potential's).  After every `stride` completed steps each bead deposits a
+ * hill at its current CV s^(k) with height
+ *   height0 * exp(-V^(k)(s^(k)) / (k_B T (bias_factor - 1)))
+ * (T the system's temperature, V^(k) before the new hill; the forces of that
+ * step use the bias before the hill).  The free-energy surface of a system
+ * is the path-integral reweighting over its beads (pimd_metad_fes).
+ * Collective variables of one bead (the same definition for every system):
+ *   PIMD_CV_DISTANCES  s = sum_m coef[m] |q_atoms[2m] - q_atoms[2m+1]|  (A;
+ *                      minimum image in a box; atom indices within the bead,
+ *                      below every system's atom count), e.g. the double
+ *                      proton transfer coordinate of Sec. 3.1
+ *   PIMD_CV_XRD        S = (1/N) sum_i sum_j f_i f_j sin(Q R_ij) / (Q R_ij),
+ *                      over all ordered pairs including i = j (term 1),
+ *                      R_ij the minimum-image distance in a box, f_i =
+ *                      form_factor[element of i] (the X-ray intensity CV of
+ *                      Sec. 3.2)
+ * All arrays are host pointers, copied during pimd_init.
+ */
+enum { PIMD_CV_DISTANCES = 1, PIMD_CV_XRD = 2 };
+typedef struct {
+    int32_t cv;                  /* PIMD_CV_* */
+    int32_t n_terms;             /* DISTANCES: 1..64 */
+    const int32_t *atoms;        /* DISTANCES: [n_terms][2] */
+    const double *coef;          /* DISTANCES: [n_terms] */
+    double q_scatter;            /* XRD: Q > 0 (1/A) */
+    const double *form_factor;   /* XRD: [n_elements] */
+    double height0_eV;           /* >= 0 */
+    double sigma;                /* > 0, CV units */
+    double bias_factor;          /* > 1; infinity: every hill has height0 */
+    int32_t stride;              /* >= 1 steps between depositions */
+    int32_t max_hills;           /* >= 1 hills kept per bead; pimd_step refuses to pass it */
+} pimd_metad;
+
+/*
  * Ring polymers.  n_systems independent systems, each with its own atom
  * count, bead count (1 or even, <= 128), temperature and orthorhombic box.
  * Integrator: normal-mode PIMD with the PILE-L thermostat in the splitting
@@ -163,6 +203,7 @@ typedef struct {
     double harmonic_omega_per_fs;      /* PIMD_POT_HARMONIC: V = sum 1/2 m w^2 |q|^2 */
     int32_t max_neighbors;             /* neighbour slots per atom: 0 => 128; a multiple of 16, <= 256 */
     const pimd_gfn_model *gfn;         /* PIMD_POT_GFN: the direct-force head (precision is ignored: FP32) */
+    const pimd_metad *metad;           /* well-tempered metadynamics bias, or NULL for none */
 } pimd_config;
 
 /* Finite-P estimators of one system (Sec. 2.1; virial kinetic energy of
@@ -173,9 +214,12 @@ typedef struct {
  *   K_cv   = 3N/(2 beta) - 1/(2P) sum_k sum_i (q_i^k - qbar_i) . F_i^k
  *   K_beads = sum |p|^2 / (2m),  T_beads = 2 K_beads / (3 N P k_B)  (-> P T)
  *   heat_bath = -(sum of kinetic-energy changes made by every O step)
- *   H_conserved = K_beads + E_spring + sum_k V(q^k) + heat_bath */
+ *   H_conserved = K_beads + E_spring + sum_k V(q^k) + heat_bath
+ * With a metadynamics bias the forces, and so K_cv, are those of the biased
+ * ring; H_conserved leaves the (time-dependent) bias out. */
 typedef struct {
     double V_bar, K_prim, K_cv, E_spring, K_beads, T_beads, H_conserved, heat_bath;
+    double V_bias;   /* sum_k V^(k)(s^(k)) / P, the metadynamics bias (0 without one) */
 } pimd_estimates;
 
 /* Bytes of device workspace a context needs for cfg.  No GPU needed. */
@@ -211,12 +255,49 @@ pimd_status pimd_energy_forces(pimd_ctx *ctx, const float *q_dev, float *energy_
 
 /* Advance every system by n_steps full integrator steps (one force
  * evaluation each).  After the first step the step is replayed as a captured
- * HIP graph.  Asynchronous. */
+ * HIP graph.  With metadynamics, PIMD_E_CAPACITY (nothing run) when the
+ * steps would deposit more than max_hills hills per bead.  Asynchronous. */
 pimd_status pimd_step(pimd_ctx *ctx, int32_t n_steps);
 
 /* Estimators of the current state for every system (out_host[n_systems]).
  * Synchronises; returns a latched device fault, if any. */
 pimd_status pimd_estimators(pimd_ctx *ctx, pimd_estimates *out_host);
+
+/* Metadynamics (pimd_config.metad non-NULL; else PIMD_E_STATE).
+ *
+ * pimd_bias_forces: CV (cv_dev[sum P_s], double), bias energy (bias_dev
+ *   [sum P_s], double, eV) and bias forces (forces_dev [B][3] float32, eV/A,
+ *   overwritten) of every bead at positions q_dev with the current hills;
+ *   any output may be NULL.  No deposition, the state is not touched.
+ *   Asynchronous.
+ * pimd_metad_cv: CV and bias energy of every bead at the current state
+ *   (cv_host, bias_host [sum P_s], either may be NULL), as the last force
+ *   evaluation of the state saw them.  Synchronises.
+ * pimd_metad_hills: hills deposited so far per bead (*n_hills of them):
+ *   center_host, height_host [sum P_s][*n_hills] (either may be NULL to
+ *   query the count).  Synchronises.
+ * pimd_metad_set_hills: replaces every bead's hills (restart):
+ *   center_host, height_host [sum P_s][n_hills], 0 <= n_hills <= max_hills.
+ *   The forces of the state are re-evaluated at the next step.  Synchronises.
+ * pimd_metad_fes: quantum free-energy surface of system `system` on a grid
+ *   s_host[n_grid] (Sec. 2.5 reweighting): F^(k)(s) = -(gamma/(gamma-1)) V^(k)(s),
+ *   F(s) = -k_B T ln[(1/P) sum_k exp(-F^(k)(s) / k_B T)] -> fes_host[n_grid]
+ *   (eV).  Synchronises. */
+pimd_status pimd_bias_forces(pimd_ctx *ctx, const float *q_dev, float *forces_dev, double *cv_dev,
+                             double *bias_dev);
+pimd_status pimd_metad_cv(pimd_ctx *ctx, double *cv_host, double *bias_host);
+pimd_status pimd_metad_hills(pimd_ctx *ctx, double *center_host, double *height_host, int32_t *n_hills);
+pimd_status pimd_metad_set_hills(pimd_ctx *ctx, int32_t n_hills, const double *center_host,
+                                 const double *height_host);
+pimd_status pimd_metad_fes(pimd_ctx *ctx, int32_t system, int32_t n_grid, const double *s_host,
+                           double *fes_host);
+
+/* Timing of the bias pass (CV kernels, bias, bias forces; no deposition) at
+ * the current positions: n_reps passes back to back between two HIP events
+ * on the context stream after one untimed pass; *ms_host = mean milliseconds
+ * per pass.  The forces of the state are re-evaluated at the next step.
+ * Synchronises. */
+pimd_status pimd_time_bias(pimd_ctx *ctx, int32_t n_reps, double *ms_host);
 
 /* Test hook: the next pimd_step uses xi_dev ([2][B][3] float32 normals:
  * half 0 then half 1, rows indexed like the Philox counter) instead of

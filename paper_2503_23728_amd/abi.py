@@ -17,6 +17,7 @@ PIMD_OK, PIMD_E_ARG, PIMD_E_UNSUPPORTED, PIMD_E_DEVICE, PIMD_E_OOM, PIMD_E_CAPAC
     PIMD_E_STATE = range(8)
 PIMD_PREC_FP32, PIMD_PREC_BF16_MLP, PIMD_PREC_BF16_PLAIN, PIMD_PREC_FP64_MLP = 0, 1, 2, 3
 PIMD_POT_BPNN, PIMD_POT_HARMONIC, PIMD_POT_GFN = 0, 1, 2
+PIMD_CV_DISTANCES, PIMD_CV_XRD = 1, 2
 
 
 class pimd_bpnn_model(ctypes.Structure):
@@ -33,13 +34,19 @@ class pimd_gfn_model(ctypes.Structure):
                 ("width", c_int32), ("n_layers", c_int32), ("params", POINTER(c_float))]
 
 
+class pimd_metad(ctypes.Structure):
+    _fields_ = [("cv", c_int32), ("n_terms", c_int32), ("atoms", POINTER(c_int32)), ("coef", POINTER(c_double)),
+                ("q_scatter", c_double), ("form_factor", POINTER(c_double)), ("height0_eV", c_double),
+                ("sigma", c_double), ("bias_factor", c_double), ("stride", c_int32), ("max_hills", c_int32)]
+
+
 class pimd_config(ctypes.Structure):
     _fields_ = [("n_systems", c_int32), ("n_atoms", POINTER(c_int32)), ("n_beads", POINTER(c_int32)),
                 ("temperature_K", POINTER(c_double)), ("box_A", POINTER(c_double)), ("species", POINTER(c_int32)),
                 ("dt_fs", c_double), ("tau0_fs", c_double), ("pile_lambda", c_double), ("seed", c_uint64),
                 ("precision", c_int32), ("potential", c_int32), ("model", POINTER(pimd_bpnn_model)),
                 ("harmonic_omega_per_fs", c_double), ("max_neighbors", c_int32),
-                ("gfn", POINTER(pimd_gfn_model))]
+                ("gfn", POINTER(pimd_gfn_model)), ("metad", POINTER(pimd_metad))]
 
 
 class pimd_tuning(ctypes.Structure):
@@ -49,7 +56,7 @@ class pimd_tuning(ctypes.Structure):
 
 class pimd_estimates(ctypes.Structure):
     _fields_ = [(n, c_double) for n in ("V_bar", "K_prim", "K_cv", "E_spring", "K_beads", "T_beads",
-                                        "H_conserved", "heat_bath")]
+                                        "H_conserved", "heat_bath", "V_bias")]
 
 
 _SIGNATURES = {
@@ -62,6 +69,12 @@ _SIGNATURES = {
     "pimd_step": (c_int32, [c_void_p, c_int32]),
     "pimd_estimators": (c_int32, [c_void_p, POINTER(pimd_estimates)]),
     "pimd_inject_noise": (c_int32, [c_void_p, c_void_p]),
+    "pimd_bias_forces": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pimd_metad_cv": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double)]),
+    "pimd_metad_hills": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_int32)]),
+    "pimd_metad_set_hills": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double)]),
+    "pimd_metad_fes": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double), POINTER(c_double)]),
+    "pimd_time_bias": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "pimd_debug_neighbors": (c_int32, [c_void_p, c_int32, POINTER(c_int32), c_int64, POINTER(c_int64)]),
     "pimd_debug_descriptors": (c_int32, [c_void_p, c_void_p]),
     "pimd_debug_copy": (c_int32, [c_void_p, c_int32, c_void_p, c_size_t]),
@@ -218,6 +231,40 @@ def pimd_time_stages(ctx, n_reps):
     ms = (c_double * PIMD_N_FORCE_STAGES)()
     st = lib().pimd_time_stages(c_void_p(ctx), n_reps, ms)
     return st, list(ms)
+
+
+def pimd_bias_forces(ctx, q_ptr, f_ptr, cv_ptr, v_ptr):
+    return lib().pimd_bias_forces(c_void_p(ctx), c_void_p(q_ptr), c_void_p(f_ptr), c_void_p(cv_ptr),
+                                  c_void_p(v_ptr))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(POINTER(c_double)) if a is not None else None
+
+
+def pimd_metad_cv(ctx, cv_out, v_out):
+    """cv_out, v_out: float64 numpy arrays [beads] (or None)."""
+    return lib().pimd_metad_cv(c_void_p(ctx), _dptr(cv_out), _dptr(v_out))
+
+
+def pimd_metad_hills(ctx, centers=None, heights=None):
+    n = c_int32(0)
+    st = lib().pimd_metad_hills(c_void_p(ctx), _dptr(centers), _dptr(heights), ctypes.byref(n))
+    return st, n.value
+
+
+def pimd_metad_set_hills(ctx, n_hills, centers, heights):
+    return lib().pimd_metad_set_hills(c_void_p(ctx), n_hills, _dptr(centers), _dptr(heights))
+
+
+def pimd_metad_fes(ctx, system, grid, out):
+    return lib().pimd_metad_fes(c_void_p(ctx), system, len(grid), _dptr(grid), _dptr(out))
+
+
+def pimd_time_bias(ctx, n_reps):
+    ms = c_double(0.0)
+    st = lib().pimd_time_bias(c_void_p(ctx), n_reps, ctypes.byref(ms))
+    return st, ms.value
 
 
 def pimd_work_counts(ctx):

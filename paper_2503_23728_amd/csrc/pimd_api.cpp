@@ -46,7 +46,12 @@ struct Plan {
     std::vector<std::array<int, 3>> nc;
     size_t mlp_f32_floats = 0, mlp_bf16_elems = 0, mlp_f64_elems = 0, cmat_elems = 0, modes = 0;
     std::vector<int> distinct_P;
+    bool any_box = false;                      // some system has a box (metadynamics minimum image)
+    bool metad = false;                        // well-tempered metadynamics bias
+    int cv = 0, n_terms = 0, max_hills = 0, n_xrd_tiles = 0;
 };
+
+constexpr int kFesChunk = 4096;                // grid points per pimd_metad_fes launch
 
 int n_features(int n_el, int n_rad, int n_ang_eta) { return n_el * n_rad + n_el * (n_el + 1) / 2 * n_ang_eta * 8; }
 
@@ -203,6 +208,7 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
                     nc[d] = std::max(1, (int)std::floor(L[d] / (mv.cutoff + 1e-4)));
                 pl.any_periodic = true;
             }
+            pl.any_box = true;
         } else {
             pl.any_open = true;
         }
@@ -245,6 +251,51 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
             }
             pl.mlp_f32_floats += in;
         }
+    }
+    if (cfg->metad) {
+        const pimd_metad *md = cfg->metad;
+        if (md->cv != PIMD_CV_DISTANCES && md->cv != PIMD_CV_XRD)
+            return fail(err, PIMD_E_ARG, "unknown collective variable");
+        if (!(md->sigma > 0.0) || !std::isfinite(md->sigma))
+            return fail(err, PIMD_E_ARG, "metadynamics sigma must be positive");
+        if (!(md->height0_eV >= 0.0) || !std::isfinite(md->height0_eV))
+            return fail(err, PIMD_E_ARG, "metadynamics height0 must be >= 0");
+        if (!(md->bias_factor > 1.0))
+            return fail(err, PIMD_E_ARG, "metadynamics bias_factor must be > 1");
+        if (md->stride < 1)
+            return fail(err, PIMD_E_ARG, "metadynamics stride must be >= 1");
+        if (md->max_hills < 1 || (int64_t)md->max_hills * pl.n_beads > ((int64_t)1 << 31))
+            return fail(err, PIMD_E_ARG, "max_hills must be >= 1 (and max_hills * beads below 2^31)");
+        int min_n = cfg->n_atoms[0];
+        for (int s = 1; s < cfg->n_systems; ++s)
+            min_n = std::min(min_n, cfg->n_atoms[s]);
+        if (md->cv == PIMD_CV_DISTANCES) {
+            if (md->n_terms < 1 || md->n_terms > kMaxCvTerms)
+                return fail(err, PIMD_E_ARG, "n_terms must be in [1, 64]");
+            if (!md->atoms || !md->coef)
+                return fail(err, PIMD_E_ARG, "CV atoms or coef is NULL");
+            for (int t = 0; t < md->n_terms; ++t) {
+                const int a = md->atoms[2 * t], b = md->atoms[2 * t + 1];
+                if (a < 0 || b < 0 || a >= min_n || b >= min_n || a == b)
+                    return fail(err, PIMD_E_ARG, "CV atom index out of range (or a term pairs an atom with itself)");
+                if (!std::isfinite(md->coef[t]))
+                    return fail(err, PIMD_E_ARG, "CV coefficients must be finite");
+            }
+        } else {
+            if (!(md->q_scatter > 0.0) || !std::isfinite(md->q_scatter))
+                return fail(err, PIMD_E_ARG, "q_scatter must be positive");
+            if (!md->form_factor)
+                return fail(err, PIMD_E_ARG, "form_factor is NULL");
+            for (int e = 0; e < pl.n_el; ++e)
+                if (!std::isfinite(md->form_factor[e]))
+                    return fail(err, PIMD_E_ARG, "form factors must be finite");
+            for (int s = 0; s < cfg->n_systems; ++s)
+                pl.n_xrd_tiles += cfg->n_beads[s] * ((cfg->n_atoms[s] + 255) / 256);
+        }
+        pl.metad = true;
+        pl.cv = md->cv;
+        pl.n_terms = md->cv == PIMD_CV_DISTANCES ? md->n_terms : 0;
+        pl.max_hills = md->max_hills;
     }
     return PIMD_OK;
 }
@@ -304,6 +355,25 @@ Layout make_layout(const Plan &pl)
     L.add("units", (size_t)pl.n_units * sizeof(IntegUnit));
     L.add("cmat", pl.cmat_elems * 8);
     L.add("col_sys", (size_t)pl.ncol * 4);
+    if (pl.metad) {
+        L.add("hills", (size_t)nb * pl.max_hills * 16);
+        L.add("n_hills", 8);
+        L.add("cv_bead", nb * 8);
+        L.add("vbias_bead", nb * 8);
+        L.add("cv_eval", nb * 8);
+        L.add("vbias_eval", nb * 8);
+        L.add("wt_scale", (size_t)pl.n_sys * 8);
+        L.add("fes_grid", (size_t)kFesChunk * 8);
+        L.add("fes_out", (size_t)kFesChunk * 8);
+        if (pl.cv == PIMD_CV_XRD) {
+            L.add("xrd_row", B * 8);
+            L.add("xrd_grad", B * 12);
+            L.add("xrd_tiles", (size_t)pl.n_xrd_tiles * 8);
+        } else {
+            L.add("cv_atoms", (size_t)pl.n_terms * 8);
+            L.add("cv_coef", (size_t)pl.n_terms * 8);
+        }
+    }
     L.add("end", 0);
     return L;
 }
@@ -353,6 +423,14 @@ struct pimd_ctx {
     bool state_set = false, forces_valid = false, noise_pending = false, use_graph = true;
     // stage timing: events recorded after each stage when non-null
     hipEvent_t *stage_ev = nullptr;
+    // metadynamics: parameters, host mirrors of the step and hill counters
+    // (the capacity check of pimd_step), deposition switch of the force pass
+    MetadParams mp{};
+    double bias_factor = 0.0;
+    double *fes_grid = nullptr, *fes_out = nullptr;
+    int64_t host_step = 0;
+    int host_hills = 0;
+    bool deposit_now = false;
     int device = 0;
     std::string err;
 };
@@ -435,9 +513,15 @@ pimd_status run_forces(pimd_ctx *c, const float *q, float *E_out, float *F_out, 
         if (c->stage_ev)
             (void)hipEventRecord(c->stage_ev[k], s);
     };
+    // the metadynamics bias joins the forces the integrator uses (never the
+    // caller's arrays of pimd_energy_forces)
+    const bool bias = c->pl.metad && F_out == d.F;
     if (c->potential == PIMD_POT_HARMONIC) {
         launch_harmonic(q, d, z, (float)(c->omega * c->omega * kMvv2e), F_out, s);
         launch_bead_sums(d, z, E_out, W_out, W_out != nullptr, s);
+        if (bias)
+            launch_metad(q, d, z, c->mp, c->pl.n_xrd_tiles, F_out, 1, c->deposit_now ? 1 : 0, d.cv_bead,
+                         d.vbias_bead, s);
         for (int k = 2; k <= 6; ++k)
             mark(k);
         CHECK_LAUNCH(c);
@@ -448,6 +532,9 @@ pimd_status run_forces(pimd_ctx *c, const float *q, float *E_out, float *F_out, 
         if (k < 4)
             mark(k + 2);
     }
+    if (bias)
+        launch_metad(q, d, z, c->mp, c->pl.n_xrd_tiles, F_out, 1, c->deposit_now ? 1 : 0, d.cv_bead, d.vbias_bead,
+                     s);
     mark(6);
     CHECK_LAUNCH(c);
     return PIMD_OK;
@@ -463,7 +550,11 @@ pimd_status run_step(pimd_ctx *c, hipStream_t s, const float *xi)
     launch_integrate_pre(c->d, c->z, (float)c->dt, k0, k1, xi, c->pl.max_P, s);
     if (c->stage_ev)
         (void)hipEventRecord(c->stage_ev[1], s);
+    c->deposit_now = true;
     pimd_status st = run_forces(c, c->d.q, c->d.E_bead, c->d.F, nullptr);
+    c->deposit_now = false;
+    if (c->pl.metad)
+        launch_metad_advance(c->d, c->mp, s);
     launch_integrate_post(c->d, c->z, (float)c->dt, k0, k1, xi, c->pl.max_P, s);
     launch_finish_step(c->d, c->z, s);
     if (c->stage_ev)
@@ -485,12 +576,34 @@ pimd_status read_status(pimd_ctx *c)
     const uint32_t zero = 0;
     HIPCHK(c, hipMemcpyAsync(c->d.status, &zero, 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (st & kStatusHills) {
+        c->err = "a deposition found the hill store full (max_hills)";
+        return PIMD_E_CAPACITY;
+    }
     if (st & kStatusOverflow) {
         c->err = "an atom has more neighbours than max_neighbors (" + std::to_string(c->pl.Kmax) + ")";
         return PIMD_E_CAPACITY;
     }
     c->err = "non-finite energy, force or state value";
     return PIMD_E_NONFINITE;
+}
+
+// Hills the next n steps deposit per bead (every bead deposits together),
+// checked against the store before anything runs, then booked.
+pimd_status reserve_steps(pimd_ctx *c, int64_t n)
+{
+    if (c->pl.metad) {
+        const int64_t stride = c->mp.stride;
+        const int64_t dep = (c->host_step + n) / stride - c->host_step / stride;
+        if (c->host_hills + dep > c->mp.max_hills) {
+            c->err = "these steps would deposit " + std::to_string(dep) + " hills per bead, " +
+                     std::to_string(c->mp.max_hills - c->host_hills) + " left (max_hills)";
+            return PIMD_E_CAPACITY;
+        }
+        c->host_hills += (int)dep;
+    }
+    c->host_step += n;
+    return PIMD_OK;
 }
 
 }  // namespace
@@ -624,6 +737,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     z.any_periodic = pl.any_periodic ? 1 : 0;
     c->tn.nl_cells = pl.total_cells >= 4096 ? 1 : 0;
     z.any_open = pl.any_open ? 1 : 0;
+    z.any_box = pl.any_box ? 1 : 0;
 
     // ---- host tables
     std::vector<BeadInfo> beads;
@@ -657,7 +771,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         const int N = cfg->n_atoms[s], P = cfg->n_beads[s];
         const double T = cfg->temperature_K[s];
         const double *Lb = cfg->box_A + 3 * s;
-        const bool periodic = pl.nl && (Lb[0] != 0.0 || Lb[1] != 0.0 || Lb[2] != 0.0);
+        const bool periodic = Lb[0] != 0.0 || Lb[1] != 0.0 || Lb[2] != 0.0;
         SysInfo si{};
         si.N = N;
         si.P = P;
@@ -701,8 +815,8 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
             for (int dd = 0; dd < 3; ++dd) {
                 bi.L[dd] = (float)Lb[dd];
                 bi.invL[dd] = periodic ? (float)(1.0 / Lb[dd]) : 0.0f;
-                bi.nc[dd] = periodic ? pl.nc[s][dd] : 1;
-                bi.cell_scale[dd] = periodic ? (float)(pl.nc[s][dd] / Lb[dd]) : 0.0f;
+                bi.nc[dd] = periodic && pl.nl ? pl.nc[s][dd] : 1;
+                bi.cell_scale[dd] = periodic && pl.nl ? (float)(pl.nc[s][dd] / Lb[dd]) : 0.0f;
                 bi.L64[dd] = Lb[dd];
                 bi.invL64[dd] = periodic ? 1.0 / Lb[dd] : 0.0;
             }
@@ -897,6 +1011,54 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         push(d.mlp_bf16, wb.data(), wb.size() * 2);
         push(d.mlp_f64, w64.data(), w64.size() * 8);
     }
+    if (pl.metad) {
+        const pimd_metad *md = cfg->metad;
+        d.hills = (double2 *)at("hills");
+        d.n_hills = (int32_t *)at("n_hills");
+        d.cv_bead = (double *)at("cv_bead");
+        d.vbias_bead = (double *)at("vbias_bead");
+        d.cv_eval = (double *)at("cv_eval");
+        d.vbias_eval = (double *)at("vbias_eval");
+        d.wt_scale = (double *)at("wt_scale");
+        d.xrd_row = (double *)at("xrd_row");
+        d.xrd_grad = (float *)at("xrd_grad");
+        d.xrd_tiles = (int2 *)at("xrd_tiles");
+        d.cv_atoms = (int32_t *)at("cv_atoms");
+        d.cv_coef = (double *)at("cv_coef");
+        c->fes_grid = (double *)at("fes_grid");
+        c->fes_out = (double *)at("fes_out");
+        MetadParams &mp = c->mp;
+        mp.cv = md->cv;
+        mp.n_terms = pl.n_terms;
+        mp.stride = md->stride;
+        mp.max_hills = md->max_hills;
+        mp.q_scatter = md->q_scatter;
+        mp.sigma = md->sigma;
+        mp.inv_sigma = 1.0 / md->sigma;
+        mp.height0 = md->height0_eV;
+        for (int e = 0; e < pl.n_el; ++e)
+            mp.form_factor[e] = md->cv == PIMD_CV_XRD ? md->form_factor[e] : 0.0;
+        c->bias_factor = md->bias_factor;
+        std::vector<double> wt(pl.n_sys);
+        for (int s = 0; s < pl.n_sys; ++s)
+            wt[s] = std::isinf(md->bias_factor) ? 0.0 : 1.0 / (kKB * cfg->temperature_K[s] * (md->bias_factor - 1.0));
+        push(d.wt_scale, wt.data(), wt.size() * 8);
+        if (md->cv == PIMD_CV_XRD) {
+            std::vector<int2> tiles;
+            for (int b = 0; b < (int)beads.size(); ++b)
+                for (int r = 0; r < beads[b].n; r += 256)
+                    tiles.push_back(make_int2(b, r));
+            push(d.xrd_tiles, tiles.data(), tiles.size() * 8);
+        } else {
+            push(d.cv_atoms, md->atoms, (size_t)pl.n_terms * 8);
+            push(d.cv_coef, md->coef, (size_t)pl.n_terms * 8);
+        }
+        const int64_t zero = 0;
+        push(d.n_hills, &zero, 8);
+        std::vector<double> zb(pl.n_beads, 0.0);
+        push(d.cv_bead, zb.data(), zb.size() * 8);
+        push(d.vbias_bead, zb.data(), zb.size() * 8);
+    }
     std::vector<double> zeros_d(pl.n_sys, 0.0);
     push(d.heat, zeros_d.data(), zeros_d.size() * 8);
     const int64_t zero64 = 0;
@@ -969,6 +1131,7 @@ pimd_status pimd_set_state(pimd_ctx *ctx, const float *q_dev, const float *p_dev
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     ctx->state_set = true;
     ctx->forces_valid = false;
+    ctx->host_step = step;
     return PIMD_OK;
 }
 
@@ -1030,6 +1193,11 @@ pimd_status pimd_step(pimd_ctx *ctx, int32_t n_steps)
     }
     if (n_steps == 0)
         return PIMD_OK;
+    {
+        pimd_status st = reserve_steps(ctx, n_steps);
+        if (st != PIMD_OK)
+            return st;
+    }
     if (!ctx->forces_valid) {
         pimd_status st = run_forces(ctx, ctx->d.q, ctx->d.E_bead, ctx->d.F, nullptr);
         if (st != PIMD_OK)
@@ -1091,7 +1259,9 @@ pimd_status pimd_estimators(pimd_ctx *ctx, pimd_estimates *out_host)
     launch_estimator_terms(ctx->d, ctx->z, ctx->stream);
     CHECK_LAUNCH(ctx);
     std::vector<float> cols((size_t)ctx->z.ncol * 3), E(ctx->z.n_beads_total);
-    std::vector<double> heat(ctx->z.n_sys);
+    std::vector<double> heat(ctx->z.n_sys), vb(ctx->pl.metad ? ctx->z.n_beads_total : 0);
+    if (ctx->pl.metad)
+        HIPCHK(ctx, hipMemcpyAsync(vb.data(), ctx->d.vbias_bead, vb.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(cols.data(), ctx->d.est_cols, cols.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(E.data(), ctx->d.E_bead, E.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(heat.data(), ctx->d.heat, heat.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
@@ -1108,10 +1278,15 @@ pimd_status pimd_estimators(pimd_ctx *ctx, pimd_estimates *out_host)
             cv += cols[3 * (size_t)col + 1];
             ke += cols[3 * (size_t)col + 2];
         }
-        for (int k = 0; k < si.P; ++k)
+        double vbias = 0;
+        for (int k = 0; k < si.P; ++k) {
             V += E[bead0 + k];
+            if (ctx->pl.metad)
+                vbias += vb[bead0 + k];
+        }
         bead0 += si.P;
         pimd_estimates &o = out_host[s];
+        o.V_bias = vbias / si.P;
         o.E_spring = si.P > 1 ? 0.5 * wP * wP * kMvv2e * spring : 0.0;
         o.V_bar = V / si.P;
         o.K_prim = 3.0 * si.N * si.P / (2.0 * beta) - o.E_spring / si.P;
@@ -1121,6 +1296,191 @@ pimd_status pimd_estimators(pimd_ctx *ctx, pimd_estimates *out_host)
         o.heat_bath = heat[s];
         o.H_conserved = o.K_beads + o.E_spring + V + heat[s];
     }
+    return read_status(ctx);
+}
+
+static pimd_status need_metad(pimd_ctx *ctx)
+{
+    if (!ctx)
+        return PIMD_E_ARG;
+    if (!ctx->pl.metad) {
+        ctx->err = "the context has no metadynamics bias";
+        return PIMD_E_STATE;
+    }
+    return PIMD_OK;
+}
+
+pimd_status pimd_bias_forces(pimd_ctx *ctx, const float *q_dev, float *forces_dev, double *cv_dev,
+                             double *bias_dev)
+{
+    pimd_status st = need_metad(ctx);
+    if (st != PIMD_OK)
+        return st;
+    if (!q_dev) {
+        ctx->err = "q must be non-NULL";
+        return PIMD_E_ARG;
+    }
+    const DevBuffers &d = ctx->d;
+    launch_metad(q_dev, d, ctx->z, ctx->mp, ctx->pl.n_xrd_tiles, forces_dev, 0, 0, d.cv_eval, d.vbias_eval,
+                 ctx->stream);
+    CHECK_LAUNCH(ctx);
+    const size_t nb = (size_t)ctx->z.n_beads_total * 8;
+    if (cv_dev)
+        HIPCHK(ctx, hipMemcpyAsync(cv_dev, d.cv_eval, nb, hipMemcpyDeviceToDevice, ctx->stream));
+    if (bias_dev)
+        HIPCHK(ctx, hipMemcpyAsync(bias_dev, d.vbias_eval, nb, hipMemcpyDeviceToDevice, ctx->stream));
+    return PIMD_OK;
+}
+
+pimd_status pimd_metad_cv(pimd_ctx *ctx, double *cv_host, double *bias_host)
+{
+    pimd_status st = need_metad(ctx);
+    if (st != PIMD_OK)
+        return st;
+    if (!ctx->state_set) {
+        ctx->err = "state not set";
+        return PIMD_E_STATE;
+    }
+    if (!ctx->forces_valid) {
+        if ((st = run_forces(ctx, ctx->d.q, ctx->d.E_bead, ctx->d.F, nullptr)) != PIMD_OK)
+            return st;
+        ctx->forces_valid = true;
+    }
+    const size_t nb = (size_t)ctx->z.n_beads_total * 8;
+    if (cv_host)
+        HIPCHK(ctx, hipMemcpyAsync(cv_host, ctx->d.cv_bead, nb, hipMemcpyDeviceToHost, ctx->stream));
+    if (bias_host)
+        HIPCHK(ctx, hipMemcpyAsync(bias_host, ctx->d.vbias_bead, nb, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return read_status(ctx);
+}
+
+pimd_status pimd_metad_hills(pimd_ctx *ctx, double *center_host, double *height_host, int32_t *n_hills)
+{
+    pimd_status st = need_metad(ctx);
+    if (st != PIMD_OK)
+        return st;
+    int32_t nh = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&nh, ctx->d.n_hills, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (n_hills)
+        *n_hills = nh;
+    if ((center_host || height_host) && nh > 0) {
+        const size_t nb = ctx->z.n_beads_total;
+        std::vector<double2> h(nb * nh);
+        HIPCHK(ctx, hipMemcpy2DAsync(h.data(), (size_t)nh * 16, ctx->d.hills, (size_t)ctx->mp.max_hills * 16,
+                                     (size_t)nh * 16, nb, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        for (size_t t = 0; t < h.size(); ++t) {
+            if (center_host)
+                center_host[t] = h[t].x;
+            if (height_host)
+                height_host[t] = h[t].y;
+        }
+    }
+    return read_status(ctx);
+}
+
+pimd_status pimd_metad_set_hills(pimd_ctx *ctx, int32_t n_hills, const double *center_host,
+                                 const double *height_host)
+{
+    pimd_status st = need_metad(ctx);
+    if (st != PIMD_OK)
+        return st;
+    if (n_hills < 0 || n_hills > ctx->mp.max_hills) {
+        ctx->err = "n_hills must be in [0, max_hills]";
+        return PIMD_E_ARG;
+    }
+    if (n_hills > 0 && (!center_host || !height_host)) {
+        ctx->err = "centers and heights must be non-NULL";
+        return PIMD_E_ARG;
+    }
+    for (size_t t = 0; t < (size_t)ctx->z.n_beads_total * n_hills; ++t)
+        if (!std::isfinite(center_host[t]) || !std::isfinite(height_host[t])) {
+            ctx->err = "hill centers and heights must be finite";
+            return PIMD_E_ARG;
+        }
+    const size_t nb = ctx->z.n_beads_total;
+    if (n_hills > 0) {
+        std::vector<double2> h(nb * n_hills);
+        for (size_t t = 0; t < h.size(); ++t)
+            h[t] = make_double2(center_host[t], height_host[t]);
+        HIPCHK(ctx, hipMemcpy2DAsync(ctx->d.hills, (size_t)ctx->mp.max_hills * 16, h.data(), (size_t)n_hills * 16,
+                                     (size_t)n_hills * 16, nb, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d.n_hills, &n_hills, 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->host_hills = n_hills;
+    ctx->forces_valid = false;
+    return PIMD_OK;
+}
+
+pimd_status pimd_metad_fes(pimd_ctx *ctx, int32_t system, int32_t n_grid, const double *s_host, double *fes_host)
+{
+    pimd_status st = need_metad(ctx);
+    if (st != PIMD_OK)
+        return st;
+    if (system < 0 || system >= ctx->z.n_sys || n_grid < 0 || (n_grid > 0 && (!s_host || !fes_host))) {
+        ctx->err = "bad system index, grid size or NULL grid";
+        return PIMD_E_ARG;
+    }
+    int bead0 = 0;
+    for (int s = 0; s < system; ++s)
+        bead0 += ctx->sys_host[s].P;
+    const double kT = kKB * ctx->temperature[system];
+    const double ratio = std::isinf(ctx->bias_factor) ? 1.0 : ctx->bias_factor / (ctx->bias_factor - 1.0);
+    for (int g0 = 0; g0 < n_grid; g0 += kFesChunk) {
+        const int n = std::min(kFesChunk, n_grid - g0);
+        HIPCHK(ctx, hipMemcpyAsync(ctx->fes_grid, s_host + g0, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream));
+        launch_metad_fes(ctx->d, ctx->mp, bead0, ctx->sys_host[system].P, kT, ratio, ctx->fes_grid, n, ctx->fes_out,
+                         ctx->stream);
+        CHECK_LAUNCH(ctx);
+        HIPCHK(ctx, hipMemcpyAsync(fes_host + g0, ctx->fes_out, (size_t)n * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return PIMD_OK;
+}
+
+pimd_status pimd_time_bias(pimd_ctx *ctx, int32_t n_reps, double *ms_host)
+{
+    pimd_status st = need_metad(ctx);
+    if (st != PIMD_OK)
+        return st;
+    if (!ms_host || n_reps < 1)
+        return PIMD_E_ARG;
+    if (!ctx->state_set) {
+        ctx->err = "state not set";
+        return PIMD_E_STATE;
+    }
+    const DevBuffers &d = ctx->d;
+    hipEvent_t ev[2];
+    HIPCHK(ctx, hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        ctx->err = "hipEventCreate failed";
+        return PIMD_E_DEVICE;
+    }
+    // one untimed pass, then n_reps passes of the CV and bias kernels writing
+    // the bias forces into the force array (which is re-evaluated at the next step)
+    launch_metad(d.q, d, ctx->z, ctx->mp, ctx->pl.n_xrd_tiles, d.F, 0, 0, d.cv_eval, d.vbias_eval, ctx->stream);
+    (void)hipEventRecord(ev[0], ctx->stream);
+    for (int r = 0; r < n_reps; ++r)
+        launch_metad(d.q, d, ctx->z, ctx->mp, ctx->pl.n_xrd_tiles, d.F, 0, 0, d.cv_eval, d.vbias_eval, ctx->stream);
+    (void)hipEventRecord(ev[1], ctx->stream);
+    hipError_t e = hipEventSynchronize(ev[1]);
+    float ms = 0.0f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    ctx->forces_valid = false;
+    if (e != hipSuccess) {
+        ctx->err = std::string("bias timing: ") + hipGetErrorString(e);
+        return PIMD_E_DEVICE;
+    }
+    *ms_host = (double)ms / n_reps;
+    CHECK_LAUNCH(ctx);
     return read_status(ctx);
 }
 
@@ -1429,6 +1789,8 @@ pimd_status pimd_time_stages(pimd_ctx *ctx, int32_t n_reps, double *ms_host)
     }
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
+    if (ctx->pl.metad)
+        ctx->forces_valid = false;   // the stage runs rewrote the forces without the bias
     if (e != hipSuccess) {
         ctx->err = std::string("stage timing: ") + hipGetErrorString(e);
         return PIMD_E_DEVICE;
@@ -1450,6 +1812,11 @@ pimd_status pimd_profile_stages(pimd_ctx *ctx, int32_t n_reps, double *ms_host)
         if (st != PIMD_OK)
             return st;
         ctx->forces_valid = true;
+    }
+    {
+        pimd_status st0 = reserve_steps(ctx, n_reps);
+        if (st0 != PIMD_OK)
+            return st0;
     }
     hipEvent_t ev[8];
     for (int k = 0; k < 8; ++k)

@@ -126,6 +126,19 @@ struct GfnParams {
     int32_t H, L;
 };
 
+// Well-tempered metadynamics on bead CVs, passed by value to its kernels.
+constexpr int kMaxCvTerms = 64;
+constexpr uint32_t kStatusHills = 4u;        // a deposition found the hill store full
+
+struct MetadParams {
+    int32_t cv;              // 1 distances, 2 XRD
+    int32_t n_terms;
+    int32_t stride, max_hills;
+    double q_scatter;        // Q (1/A)
+    double sigma, inv_sigma, height0;
+    double form_factor[kMaxElements];
+};
+
 // Everything a step needs on the device, carved from the workspace.
 struct DevBuffers {
     float *q, *p, *F, *E_bead;     // integrator state, forces of q, bead energies
@@ -162,6 +175,17 @@ struct DevBuffers {
     float *norm;                   // [n_el][2][D] shift, 1/scale
     float *gfn_params;             // direct-force head: packed weights
     float *gfn_nodes;              // direct-force head: node states n^(0..L) [L+1][B][H]
+    // metadynamics
+    double2 *hills;                // [beads][max_hills] (center, height)
+    int32_t *n_hills;              // hills deposited per bead (one counter: all beads deposit together)
+    double *cv_bead, *vbias_bead;  // CV and bias energy of every bead at the last force evaluation
+    double *cv_eval, *vbias_eval;  // the same for pimd_bias_forces
+    double *xrd_row;               // [B] f_i sum_j f_j sinc(Q R_ij)
+    float *xrd_grad;               // [B][3] dS/dq_i
+    int2 *xrd_tiles;               // (bead, first row) of every 256-row tile
+    int32_t *cv_atoms;             // [n_terms][2]
+    double *cv_coef;               // [n_terms]
+    double *wt_scale;              // [n_sys] 1 / (k_B T (gamma - 1)), 0 for gamma = infinity
 };
 
 // Launch shapes chosen by the tuner (results do not depend on them: every
@@ -185,6 +209,7 @@ struct Sizes {
     int32_t n_sys, B, n_beads_total, n_atoms_total, ncol, total_cells, n_units, D, Kmax;
     int32_t any_periodic;   // some system has a box (cell lists)
     int32_t any_open;       // some system has none (all-pairs lists)
+    int32_t any_box;        // some system has a box (minimum image of the metadynamics CVs)
 };
 
 // Order in which the per-centre kernels visit the rows: cell order within
@@ -224,6 +249,15 @@ void launch_estimator_terms(const DevBuffers &d, const Sizes &z, hipStream_t s);
 void launch_philox_words(uint32_t key0, uint32_t key1, int64_t step, int half, int64_t n, uint32_t *out,
                          hipStream_t s);
 void launch_check_finite(const float *a, int64_t n, uint32_t *status, hipStream_t s);
+
+// Metadynamics: CV rows (XRD), then per bead the CV, bias, optional
+// deposition (deposit != 0: when the step that is completing is a multiple of
+// the stride) and the bias forces (add != 0: F += bias force, else F = bias force).
+void launch_metad(const float *q, const DevBuffers &d, const Sizes &z, const MetadParams &mp, int n_xrd_tiles,
+                  float *F, int add, int deposit, double *cv_out, double *v_out, hipStream_t s);
+void launch_metad_advance(const DevBuffers &d, const MetadParams &mp, hipStream_t s);
+void launch_metad_fes(const DevBuffers &d, const MetadParams &mp, int bead0, int P, double kT, double gamma_ratio,
+                      const double *grid, int n_grid, double *out, hipStream_t s);
 
 void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &dp,
                         unsigned long long *counts, hipStream_t s);

@@ -61,8 +61,33 @@ def pack_gfn_params(head):
     return np.concatenate([np.ascontiguousarray(a, dtype=np.float32).ravel() for a in parts])
 
 
+def make_metad(spec, keep):
+    """pimd_metad from a synthetic.MetadSpec (cv "distances" or "xrd")."""
+    md = abi.pimd_metad()
+    if spec.cv == "distances":
+        md.cv = abi.PIMD_CV_DISTANCES
+        if np.asarray(spec.atoms).size != 2 * len(spec.coef):
+            raise ValueError("distance CV: atoms must hold two indices per coefficient")
+        md.n_terms = len(spec.coef)
+        md.atoms = keep.arr(np.asarray(spec.atoms).reshape(-1), np.int32, ctypes.c_int32)
+        md.coef = keep.arr(spec.coef, np.float64, ctypes.c_double)
+    elif spec.cv == "xrd":
+        md.cv = abi.PIMD_CV_XRD
+        md.q_scatter = float(spec.q_scatter)
+        md.form_factor = keep.arr(spec.form_factor, np.float64, ctypes.c_double)
+    else:
+        raise ValueError(f"unknown collective variable {spec.cv!r}")
+    md.height0_eV = float(spec.height0)
+    md.sigma = float(spec.sigma)
+    md.bias_factor = float(spec.gamma)
+    md.stride = int(spec.stride)
+    md.max_hills = int(spec.max_hills)
+    keep.items.append(md)
+    return md
+
+
 def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
-                omega=0.0, max_neighbors=0, masses=None):
+                omega=0.0, max_neighbors=0, masses=None, metad=None):
     """Build the pimd_config (and the storage it points into).
 
     systems: sequence with n_atoms, n_beads, temperature, box, species.
@@ -122,6 +147,7 @@ def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", p
     cfg.gfn = ctypes.pointer(g) if g is not None else None
     cfg.harmonic_omega_per_fs = omega
     cfg.max_neighbors = max_neighbors
+    cfg.metad = ctypes.pointer(make_metad(metad, keep)) if metad is not None else None
     return cfg, keep
 
 
@@ -129,12 +155,13 @@ class Pimd:
     """One library context: state, workspace and stream on one device."""
 
     def __init__(self, systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
-                 omega=0.0, max_neighbors=0, masses=None, device="cuda:0", stream=None):
+                 omega=0.0, max_neighbors=0, masses=None, device="cuda:0", stream=None, metad=None):
         self.device = torch.device(device)
+        self.metad = metad
         self.systems = list(systems)
         self.model, self.precision, self.max_neighbors = model, precision, max_neighbors
         self.cfg, self._keep = make_config(self.systems, model, dt, tau0, pile_lambda, seed, precision,
-                                           potential, omega, max_neighbors, masses)
+                                           potential, omega, max_neighbors, masses, metad)
         st, nbytes = abi.pimd_workspace_size(self.cfg)
         _check(st)
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
@@ -273,6 +300,52 @@ class Pimd:
         st, a, b, c = abi.pimd_work_counts(self.ctx)
         _check(st, self.ctx)
         return a, b, c
+
+    # ---- well-tempered metadynamics (contexts built with metad=MetadSpec)
+    def bias_forces(self, q, forces=True):
+        """(bias forces [B, 3] or None, CV [beads], bias energy [beads]) at q
+        with the current hills; no deposition."""
+        q = self._vec(q, (self.B, 3))
+        F = torch.empty(self.B, 3, device=self.device) if forces else None
+        cv = torch.empty(self.n_beads, dtype=torch.float64, device=self.device)
+        v = torch.empty_like(cv)
+        _check(abi.pimd_bias_forces(self.ctx, q.data_ptr(), _ptr(F), cv.data_ptr(), v.data_ptr()), self.ctx)
+        return F, cv, v
+
+    def metad_cv(self):
+        """(CV, bias energy) per bead at the current state, numpy float64."""
+        cv, v = np.zeros(self.n_beads), np.zeros(self.n_beads)
+        _check(abi.pimd_metad_cv(self.ctx, cv, v), self.ctx)
+        return cv, v
+
+    def metad_hills(self):
+        """(centers, heights) [beads, n_hills] numpy float64."""
+        st, n = abi.pimd_metad_hills(self.ctx)
+        _check(st, self.ctx)
+        c, h = np.zeros((self.n_beads, n)), np.zeros((self.n_beads, n))
+        st, n2 = abi.pimd_metad_hills(self.ctx, c, h)
+        _check(st, self.ctx)
+        return c[:, :n2], h[:, :n2]
+
+    def metad_set_hills(self, centers, heights):
+        c = np.ascontiguousarray(centers, dtype=np.float64).reshape(self.n_beads, -1)
+        h = np.ascontiguousarray(heights, dtype=np.float64).reshape(self.n_beads, -1)
+        if c.shape != h.shape:
+            raise ValueError("centers and heights differ in shape")
+        _check(abi.pimd_metad_set_hills(self.ctx, c.shape[1], c, h), self.ctx)
+
+    def metad_fes(self, system, grid):
+        """Quantum free-energy surface (eV) of one system on a grid."""
+        g = np.ascontiguousarray(grid, dtype=np.float64)
+        out = np.zeros_like(g)
+        _check(abi.pimd_metad_fes(self.ctx, int(system), g, out), self.ctx)
+        return out
+
+    def time_bias(self, n_reps):
+        """Mean ms of one bias pass (CV kernels, bias, bias forces) at the current positions."""
+        st, ms = abi.pimd_time_bias(self.ctx, int(n_reps))
+        _check(st, self.ctx)
+        return ms
 
     def debug_neighbors(self, bead):
         cap = 1 << 22

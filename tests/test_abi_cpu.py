@@ -101,3 +101,46 @@ def test_null_context_calls_are_argument_errors(lib):
     assert lib.pimd_set_state(None, None, None, 0) == abi.PIMD_E_ARG
     assert lib.pimd_energy_forces(None, None, None, None, None) == abi.PIMD_E_ARG
     lib.pimd_destroy(None)
+
+
+def _md_cfg(wl, **over):
+    spec = S.metad_spec(wl)
+    for k, v in over.items():
+        setattr(spec, k, v)
+    return _cfg(wl, metad=spec)
+
+
+def test_metad_configs_size_the_hill_store(lib):
+    for c in (1, 2):
+        wl = S.workload(c)
+        base = abi.pimd_workspace_size(_cfg(wl)[0])[1]
+        st, a = abi.pimd_workspace_size(_md_cfg(wl, max_hills=16)[0])
+        st2, b = abi.pimd_workspace_size(_md_cfg(wl, max_hills=4096)[0])
+        assert st == st2 == abi.PIMD_OK and base < a < b
+        beads = sum(s.n_beads for s in wl.systems)
+        assert b - a >= beads * (4096 - 16) * 16
+
+
+@pytest.mark.parametrize("c,over,status", [
+    (1, dict(sigma=0.0), abi.PIMD_E_ARG),
+    (1, dict(gamma=1.0), abi.PIMD_E_ARG),
+    (1, dict(gamma=float("nan")), abi.PIMD_E_ARG),
+    (1, dict(height0=-1.0), abi.PIMD_E_ARG),
+    (1, dict(stride=0), abi.PIMD_E_ARG),
+    (1, dict(max_hills=0), abi.PIMD_E_ARG),
+    (1, dict(atoms=np.array([[0, 10]]), coef=np.array([1.0])), abi.PIMD_E_ARG),  # atom 10 of 10
+    (1, dict(atoms=np.array([[3, 3]]), coef=np.array([1.0])), abi.PIMD_E_ARG),
+    (2, dict(q_scatter=0.0), abi.PIMD_E_ARG),
+    (2, dict(form_factor=np.array([1.0, np.inf])), abi.PIMD_E_ARG),
+])
+def test_bad_metad_configs_are_rejected_without_a_gpu(lib, c, over, status):
+    cfg, keep = _md_cfg(S.workload(c), **over)
+    assert abi.pimd_workspace_size(cfg)[0] == status
+    assert abi.pimd_last_error(None)
+
+
+def test_metad_calls_need_a_context(lib):
+    assert lib.pimd_bias_forces(None, None, None, None, None) == abi.PIMD_E_ARG
+    assert lib.pimd_metad_cv(None, None, None) == abi.PIMD_E_ARG
+    assert lib.pimd_metad_set_hills(None, 0, None, None) == abi.PIMD_E_ARG
+    assert lib.pimd_metad_fes(None, 0, 0, None, None) == abi.PIMD_E_ARG
