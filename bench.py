@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X published dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X published FP64 vector peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
 
 
@@ -90,6 +91,33 @@ def gfn_flops_per_edge(n_rad, H, L):
     layers = sum(basis + l * (mlp + 2 * H) + mlp + H for l in range(L))
     readout = basis + L * (mlp + 2 * H) + 2 * H * H + 7 * H + 6
     return layers, readout
+
+
+def xrd_flops_per_pair(periodic):
+    """Algorithmic FLOP of one ordered pair of the XRD CV sum and its gradient,
+    one per add, multiply, rounding, sqrt, division, sin or cos: displacement 3,
+    minimum image 3 x 3, r^2 5, r 1, x = Q r 1, sin and cos 2, sinc = sin/x 1,
+    f_j sinc accumulated 2, (cos - sinc)/r^2 2, times f_j 1, gradient
+    accumulated 3 x 2."""
+    return 3 + (9 if periodic else 0) + 5 + 1 + 1 + 2 + 1 + 2 + 2 + 1 + 6
+
+
+def metad_report(eng, wl, spec, n_reps):
+    """Bias-pass timing and, for the XRD CV, the roofline of its all-pairs kernel."""
+    bias_ms = eng.time_bias(n_reps)
+    out = {"cv": spec.cv, "stride": spec.stride, "sigma": spec.sigma, "bias_factor": spec.gamma,
+           "height0_eV": spec.height0, "bias_pass_ms": round(bias_ms, 4)}
+    if spec.cv == "xrd":
+        pairs = sum(s.n_beads * s.n_atoms * s.n_atoms for s in wl.systems)
+        periodic = any(float(b) > 0 for s in wl.systems for b in s.box)
+        flops = pairs * xrd_flops_per_pair(periodic)
+        achieved = flops / (bias_ms * 1e-3) / 1e12
+        out["roofline"] = {"kernel": "k_xrd_rows + k_metad_bias (all-pairs XRD CV, FP64)", "bound": "alu",
+                           "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                           "flops_per_launch": flops, "launch_ms": round(bias_ms, 4),
+                           "work": {"ordered_pairs": pairs, "flops_per_pair": xrd_flops_per_pair(periodic)}}
+    return out
 
 
 def time_steps(eng, steps, warmup, restart=None):
@@ -207,6 +235,8 @@ def main():
                     help="energy model with adjoint forces, or the direct-force head")
     ap.add_argument("--gfn-width", type=int, default=16)
     ap.add_argument("--gfn-layers", type=int, default=2)
+    ap.add_argument("--metad", action="store_true",
+                    help="add the well-tempered metadynamics bias of the workload's study (s_dimer or XRD CV)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
@@ -221,7 +251,8 @@ def main():
     gfn_mode = args.potential == "gfn"
     wl = S.gfn_workload(args.config, args.gfn_width, args.gfn_layers) if gfn_mode else S.workload(args.config)
     B = wl.bead_atoms
-    eng = Pimd.from_workload(wl, precision="fp32" if gfn_mode else args.precision, device=device)
+    spec = S.metad_spec(wl, max_hills=4096) if args.metad else None
+    eng = Pimd.from_workload(wl, precision="fp32" if gfn_mode else args.precision, device=device, metad=spec)
     q, p = S.initial_state(wl)
     eng.set_state(torch.from_numpy(q).to(device), torch.from_numpy(p).to(device))
     if args.no_tune:
@@ -322,6 +353,10 @@ def main():
         out["energy_model_ms_per_step"] = 1e3 * ewall / args.steps
         out["head_speedup_vs_energy_model"] = ewall / wall
         print(f"[bench] energy model: {1e3 * ewall / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    if spec is not None:
+        out["metad"] = metad_report(eng, wl, spec, max(args.profile_reps, 5))
+        out["config"]["workload"] += f"+wt-metad({spec.cv})"
+        print(f"[bench] metad {json.dumps(out['metad'])}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -1,10 +1,11 @@
 // Well-tempered metadynamics on bead collective variables (Sec. 2.5).
 //
 // Every bead carries its own hills; per force evaluation:
-//   k_xrd_rows     (XRD CV only) one workgroup per 256-row tile of a bead:
-//                  row sums f_i sum_j f_j sinc(Q R_ij) and gradients dS/dq_i,
-//                  every ordered pair of the bead (the all-pairs sum of the
-//                  Sec. 3.2 CV), j staged through LDS 256 rows at a time
+//   k_xrd_pairs    (XRD CV only) the all-pairs sum of the Sec. 3.2 CV, one
+//                  workgroup per pair of row tiles of a bead, each pair of
+//                  atoms evaluated once for both of its rows
+//   k_xrd_reduce   row sums f_i sum_j f_j sinc(Q R_ij) and gradients dS/dq_i
+//                  from the per-tile partials, in a fixed order
 //   k_metad_bias   one workgroup per bead: the CV (row sums reduced, or the
 //                  distance terms), the bias and its slope from the bead's
 //                  hills, the deposition of a new hill, the bias forces
@@ -23,7 +24,6 @@
 namespace pimd {
 namespace {
 
-constexpr int kXrdBlock = 256;
 
 // sin and cos of t, |t| <= pi/4, in FP64 (Taylor series to t^17 and t^18:
 // truncation below 2e-17).
@@ -69,96 +69,177 @@ __device__ __forceinline__ void sincos_phase(double x, double &sn, double &cs)
     cs = ((k + 1) & 2) ? -c0 : c0;
 }
 
-// Positions of one staged partner: FP64 coordinates and its form factor.
-struct Partner {
-    double x, y, z, f;
-};
-
+// One pair (i, j) of the XRD sum: sinc(Q r_ij) and base = (cos x - sinc x) / r^2
+// (the gradient term of row i is f_j base d, of row j -f_i base d, with
+// d = q_i - q_j; sinc'(x) Q / r = (cos x - sinc x) / r^2).  i = j (or
+// coincident atoms): sinc = 1 and the arithmetic runs on r^2 = 1 so it stays
+// finite (d = 0 carries no gradient).
 template <bool PERIODIC>
-__global__ __launch_bounds__(256) void k_xrd_rows(const float *__restrict__ q, const BeadInfo *__restrict__ beads,
-                                                  const SysInfo *__restrict__ sys,
-                                                  const int32_t *__restrict__ species_atom,
-                                                  const int2 *__restrict__ tiles, MetadParams mp,
-                                                  double *__restrict__ row_out, float *__restrict__ grad_out)
+__device__ __forceinline__ void xrd_pair(double xi, double yi, double zi, double xj, double yj, double zj,
+                                         const BeadInfo &bi, double Q, double invQ, double &sc, double &base,
+                                         double &dx, double &dy, double &dz)
 {
-    __shared__ Partner part[kXrdBlock];
-    const int2 tile = tiles[blockIdx.x];
-    const BeadInfo bi = beads[tile.x];
-    const int n = bi.n;
+    dx = xi - xj;
+    dy = yi - yj;
+    dz = zi - zj;
+    if (PERIODIC && bi.periodic) {
+        dx -= bi.L64[0] * rint(dx * bi.invL64[0]);
+        dy -= bi.L64[1] * rint(dy * bi.invL64[1]);
+        dz -= bi.L64[2] * rint(dz * bi.invL64[2]);
+    }
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const bool self = r2 == 0.0;
+    const double r2s = self ? 1.0 : r2;
+    // 1/r: float32 estimate (hardware reciprocal square root; r2 is a normal
+    // number) and two Newton steps (relative error ~1e-16)
+    double y = (double)__builtin_amdgcn_rsqf((float)r2s);
+    y = y * fma(-0.5 * r2s, y * y, 1.5);
+    y = y * fma(-0.5 * r2s, y * y, 1.5);
+    const double x = Q * (r2s * y);
+    double sn, cs;
+    sincos_phase(x, sn, cs);
+    sc = self ? 1.0 : sn * (y * invQ);
+    base = (cs - sc) * (y * y);
+}
+
+// Pair sum over tiles of T = 64 W rows: one workgroup per work item (bead,
+// tiles I <= J).  I = J: every ordered pair of the tile, into the rows.
+// I < J: every pair once; row i of tile I accumulates in registers, row j of
+// tile J in LDS.  In phase ph, wave w owns the 64 columns of block
+// (w + ph) mod W, and at step k lane l takes column (l + k) mod 64 of it, so
+// no two lanes (or waves) touch one column accumulator at a time.  Each item
+// writes one partial (sum_j f_j sinc, gradient sum) per row and partner tile:
+// part[part0 + partner * n + row].
+template <int W, bool PERIODIC>
+__global__ __launch_bounds__(64 * W) void k_xrd_pairs(const float *__restrict__ q,
+                                                      const BeadInfo *__restrict__ beads,
+                                                      const SysInfo *__restrict__ sys,
+                                                      const int32_t *__restrict__ species_atom,
+                                                      const int4 *__restrict__ items, MetadParams mp,
+                                                      double4 *__restrict__ part)
+{
+    constexpr int T = 64 * W;
+    __shared__ double cx[T], cy[T], cz[T], cf[T];
+    __shared__ double aS[T], ax[T], ay[T], az[T];
+    const int4 it = items[blockIdx.x];
+    const BeadInfo bi = beads[it.x];
+    const int n = bi.n, I = it.y, J = it.z;
+    const int64_t p0 = it.w;
     const int atom0 = sys[bi.sys].atom0;
-    const int li = tile.y + (int)threadIdx.x;
-    const bool active = li < n;
+    const int tid = threadIdx.x;
+    const int li = I * T + tid, lj = J * T + tid;
     double xi = 0, yi = 0, zi = 0, fi = 0;
-    if (active) {
+    if (li < n) {
         const int64_t r = (int64_t)bi.ba0 + li;
         xi = q[3 * r + 0];
         yi = q[3 * r + 1];
         zi = q[3 * r + 2];
         fi = mp.form_factor[species_atom[atom0 + li]];
     }
-    const double Q = mp.q_scatter;
-    const double invQ = 1.0 / Q;
-    double S = 0, gx = 0, gy = 0, gz = 0;
-    for (int j0 = 0; j0 < n; j0 += kXrdBlock) {
-        __syncthreads();
-        const int lj = j0 + (int)threadIdx.x;
+    {
+        // rows past the end stage as f = 0 at the origin: their pairs add nothing
+        double x = 0, y = 0, z = 0, f = 0;
         if (lj < n) {
             const int64_t r = (int64_t)bi.ba0 + lj;
-            Partner pj;
-            pj.x = q[3 * r + 0];
-            pj.y = q[3 * r + 1];
-            pj.z = q[3 * r + 2];
-            pj.f = mp.form_factor[species_atom[atom0 + lj]];
-            part[threadIdx.x] = pj;
+            x = q[3 * r + 0];
+            y = q[3 * r + 1];
+            z = q[3 * r + 2];
+            f = mp.form_factor[species_atom[atom0 + lj]];
         }
-        __syncthreads();
-        const int nj = min(kXrdBlock, n - j0);
-        for (int jj = 0; jj < nj; ++jj) {
-            const Partner pj = part[jj];
-            double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
-            if (PERIODIC && bi.periodic) {
-                dx -= bi.L64[0] * rint(dx * bi.invL64[0]);
-                dy -= bi.L64[1] * rint(dy * bi.invL64[1]);
-                dz -= bi.L64[2] * rint(dz * bi.invL64[2]);
+        cx[tid] = x;
+        cy[tid] = y;
+        cz[tid] = z;
+        cf[tid] = f;
+        aS[tid] = 0.0;
+        ax[tid] = 0.0;
+        ay[tid] = 0.0;
+        az[tid] = 0.0;
+    }
+    __syncthreads();
+    const double Q = mp.q_scatter, invQ = 1.0 / Q;
+    double S = 0, gx = 0, gy = 0, gz = 0;
+    double sc, base, dx, dy, dz;
+    if (I == J) {
+        for (int jj = 0; jj < T; ++jj) {
+            const double fj = cf[jj];
+            xrd_pair<PERIODIC>(xi, yi, zi, cx[jj], cy[jj], cz[jj], bi, Q, invQ, sc, base, dx, dy, dz);
+            S = fma(fj, sc, S);
+            const double wj = fj * base;
+            gx = fma(wj, dx, gx);
+            gy = fma(wj, dy, gy);
+            gz = fma(wj, dz, gz);
+        }
+    } else {
+        const int w = tid >> 6, lane = tid & 63;
+        for (int ph = 0; ph < W; ++ph) {
+            const int blk = ((w + ph) % W) * 64;
+            for (int k = 0; k < 64; ++k) {
+                const int jj = blk + ((lane + k) & 63);
+                const double fj = cf[jj];
+                xrd_pair<PERIODIC>(xi, yi, zi, cx[jj], cy[jj], cz[jj], bi, Q, invQ, sc, base, dx, dy, dz);
+                S = fma(fj, sc, S);
+                const double wj = fj * base;
+                gx = fma(wj, dx, gx);
+                gy = fma(wj, dy, gy);
+                gz = fma(wj, dz, gz);
+                const double wi = -fi * base;
+                aS[jj] = fma(fi, sc, aS[jj]);
+                ax[jj] = fma(wi, dx, ax[jj]);
+                ay[jj] = fma(wi, dy, ay[jj]);
+                az[jj] = fma(wi, dz, az[jj]);
+                wave_sync();    // the next step's lanes read what this step wrote
             }
-            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            // i = j (or coincident atoms): sinc(0) = 1 and no gradient; the
-            // arithmetic below runs on r2 = 1 so it stays finite.
-            const bool self = r2 == 0.0;
-            const double r2s = self ? 1.0 : r2;
-            // 1/r: float32 estimate (hardware reciprocal square root; r2 is a
-            // normal number) and two Newton steps (relative error ~1e-16)
-            double y = (double)__builtin_amdgcn_rsqf((float)r2s);
-            y = y * fma(-0.5 * r2s, y * y, 1.5);
-            y = y * fma(-0.5 * r2s, y * y, 1.5);
-            const double x = Q * (r2s * y);
-            double sn, cs;
-            sincos_phase(x, sn, cs);
-            const double f = pj.f;
-            const double sc = self ? 1.0 : sn * (y * invQ);
-            // dS/dq_i term: f_j Q sinc'(x) d/r with sinc'(x) = (cos x - sinc x)/x,
-            // i.e. f_j (cos x - sinc x) d / r^2
-            S = fma(f, sc, S);
-            const double w = f * (cs - sc) * (y * y);
-            gx = fma(w, dx, gx);
-            gy = fma(w, dy, gy);
-            gz = fma(w, dz, gz);
+            __syncthreads();    // the next phase hands this block to another wave
         }
     }
-    if (active) {
-        const int64_t r = (int64_t)bi.ba0 + li;
-        row_out[r] = fi * S;
-        const double c = 2.0 * fi / (double)n;
-        grad_out[3 * r + 0] = (float)(c * gx);
-        grad_out[3 * r + 1] = (float)(c * gy);
-        grad_out[3 * r + 2] = (float)(c * gz);
-    }
+    if (li < n)
+        part[p0 + (int64_t)J * n + li] = make_double4(S, gx, gy, gz);
+    if (I != J && lj < n)
+        part[p0 + (int64_t)I * n + lj] = make_double4(aS[tid], ax[tid], ay[tid], az[tid]);
 }
 
-// Deterministic sum over the 256 threads of a workgroup (fixed tree).
+// Row totals in fixed partner order: row_out = f_i sum_j f_j sinc(Q r_ij),
+// grad_out = dS/dq_i = (2 f_i / n) sum_j f_j base_ij d_ij.
+__global__ __launch_bounds__(256) void k_xrd_reduce(const BeadInfo *__restrict__ beads,
+                                                    const int32_t *__restrict__ bead_of_ba,
+                                                    const SysInfo *__restrict__ sys,
+                                                    const int32_t *__restrict__ species_atom,
+                                                    const int32_t *__restrict__ part0, int T, MetadParams mp,
+                                                    const double4 *__restrict__ part, double *__restrict__ row_out,
+                                                    float *__restrict__ grad_out, int B)
+{
+    const int ba = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ba >= B)
+        return;
+    const int bead = bead_of_ba[ba];
+    const BeadInfo bi = beads[bead];
+    const int a = ba - bi.ba0, n = bi.n;
+    const int nt = (n + T - 1) / T;
+    const double4 *pp = part + part0[bead] + a;
+    double S = 0, gx = 0, gy = 0, gz = 0;
+    for (int p = 0; p < nt; ++p) {
+        const double4 v = pp[(int64_t)p * n];
+        S += v.x;
+        gx += v.y;
+        gy += v.z;
+        gz += v.w;
+    }
+    const double f = mp.form_factor[species_atom[sys[bi.sys].atom0 + a]];
+    row_out[ba] = f * S;
+    const double c = 2.0 * f / (double)n;
+    grad_out[3 * (int64_t)ba + 0] = (float)(c * gx);
+    grad_out[3 * (int64_t)ba + 1] = (float)(c * gy);
+    grad_out[3 * (int64_t)ba + 2] = (float)(c * gz);
+}
+
+// Deterministic sum over the NT threads of a workgroup (fixed tree; one wave:
+// the butterfly alone).
+template <int NT>
 __device__ __forceinline__ double block_sum(double v, double *red)
 {
     v = wave_sum_f64(v);
+    if (NT == kWave)
+        return v;
     const int w = threadIdx.x / kWave;
     __syncthreads();
     if (lane_id() == 0)
@@ -176,7 +257,8 @@ __device__ __forceinline__ void min_image(double &dx, double &dy, double &dz, co
     }
 }
 
-__global__ __launch_bounds__(256) void k_metad_bias(const float *__restrict__ q, const BeadInfo *__restrict__ beads,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_metad_bias(const float *__restrict__ q, const BeadInfo *__restrict__ beads,
                                                     const double *__restrict__ xrd_row,
                                                     const float *__restrict__ xrd_grad,
                                                     const int32_t *__restrict__ cv_atoms,
@@ -196,7 +278,7 @@ __global__ __launch_bounds__(256) void k_metad_bias(const float *__restrict__ q,
     // 1. the CV of the bead
     double part = 0.0;
     if (mp.cv == 2) {
-        for (int i = tid; i < n; i += 256)
+        for (int i = tid; i < n; i += NT)
             part += xrd_row[(int64_t)bi.ba0 + i];
     } else if (tid < mp.n_terms) {
         const int64_t a = (int64_t)bi.ba0 + cv_atoms[2 * tid], b = (int64_t)bi.ba0 + cv_atoms[2 * tid + 1];
@@ -205,22 +287,22 @@ __global__ __launch_bounds__(256) void k_metad_bias(const float *__restrict__ q,
         min_image(dx, dy, dz, bi);
         part = cv_coef[tid] * sqrt(dx * dx + dy * dy + dz * dz);
     }
-    double s = block_sum(part, red);
+    double s = block_sum<NT>(part, red);
     if (mp.cv == 2)
         s /= (double)n;
     // 2. bias and slope from the bead's hills
     const int nh = *n_hills_p;
     const double2 *hb = hills + (int64_t)bead * mp.max_hills;
     double v = 0.0, dv = 0.0;
-    for (int h = tid; h < nh; h += 256) {
+    for (int h = tid; h < nh; h += NT) {
         const double2 c = hb[h];
         const double x = (s - c.x) * mp.inv_sigma;
         const double g = c.y * exp(-0.5 * x * x);
         v += g;
         dv -= g * x;
     }
-    v = block_sum(v, red);
-    dv = block_sum(dv, red) * mp.inv_sigma;
+    v = block_sum<NT>(v, red);
+    dv = block_sum<NT>(dv, red) * mp.inv_sigma;
     if (tid == 0) {
         if (cv_out)
             cv_out[bead] = s;
@@ -240,7 +322,7 @@ __global__ __launch_bounds__(256) void k_metad_bias(const float *__restrict__ q,
         return;
     const int64_t r0 = bi.ba0;
     if (mp.cv == 2) {
-        for (int i = tid; i < n; i += 256) {
+        for (int i = tid; i < n; i += NT) {
             const int64_t r = r0 + i;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -251,7 +333,7 @@ __global__ __launch_bounds__(256) void k_metad_bias(const float *__restrict__ q,
         return;
     }
     if (!add) {
-        for (int i = tid; i < 3 * n; i += 256)
+        for (int i = tid; i < 3 * n; i += NT)
             F[3 * r0 + i] = 0.f;
     }
     __syncthreads();
@@ -318,20 +400,39 @@ __global__ __launch_bounds__(256) void k_metad_fes(const double2 *__restrict__ h
 
 }  // namespace
 
-void launch_metad(const float *q, const DevBuffers &d, const Sizes &z, const MetadParams &mp, int n_xrd_tiles,
+void launch_metad(const float *q, const DevBuffers &d, const Sizes &z, const MetadParams &mp, int n_xrd_items,
                   float *F, int add, int deposit, double *cv_out, double *v_out, hipStream_t s)
 {
     if (mp.cv == 2) {
-        if (z.any_box)
-            hipLaunchKernelGGL(k_xrd_rows<true>, dim3(n_xrd_tiles), dim3(256), 0, s, q, d.beads, d.sys,
-                               d.species_atom, d.xrd_tiles, mp, d.xrd_row, d.xrd_grad);
-        else
-            hipLaunchKernelGGL(k_xrd_rows<false>, dim3(n_xrd_tiles), dim3(256), 0, s, q, d.beads, d.sys,
-                               d.species_atom, d.xrd_tiles, mp, d.xrd_row, d.xrd_grad);
+        const dim3 g(n_xrd_items);
+        if (mp.xrd_tile == 256) {
+            if (z.any_box)
+                hipLaunchKernelGGL((k_xrd_pairs<4, true>), g, dim3(256), 0, s, q, d.beads, d.sys, d.species_atom,
+                                   d.xrd_items, mp, d.xrd_part);
+            else
+                hipLaunchKernelGGL((k_xrd_pairs<4, false>), g, dim3(256), 0, s, q, d.beads, d.sys, d.species_atom,
+                                   d.xrd_items, mp, d.xrd_part);
+        } else {
+            if (z.any_box)
+                hipLaunchKernelGGL((k_xrd_pairs<1, true>), g, dim3(64), 0, s, q, d.beads, d.sys, d.species_atom,
+                                   d.xrd_items, mp, d.xrd_part);
+            else
+                hipLaunchKernelGGL((k_xrd_pairs<1, false>), g, dim3(64), 0, s, q, d.beads, d.sys, d.species_atom,
+                                   d.xrd_items, mp, d.xrd_part);
+        }
+        hipLaunchKernelGGL(k_xrd_reduce, dim3((z.B + 255) / 256), dim3(256), 0, s, d.beads, d.bead_of_ba, d.sys,
+                           d.species_atom, d.xrd_part0, mp.xrd_tile, mp, d.xrd_part, d.xrd_row, d.xrd_grad, z.B);
     }
-    hipLaunchKernelGGL(k_metad_bias, dim3(z.n_beads_total), dim3(256), 0, s, q, d.beads, d.xrd_row, d.xrd_grad,
-                       d.cv_atoms, d.cv_coef, d.wt_scale, mp, d.hills, d.n_hills, d.step, deposit, cv_out, v_out, F,
-                       add, d.status);
+    // the XRD CV reduces a bead's rows with 256 threads; a distance CV (<= 64
+    // terms) needs one wave per bead
+    if (mp.cv == 2)
+        hipLaunchKernelGGL(k_metad_bias<256>, dim3(z.n_beads_total), dim3(256), 0, s, q, d.beads, d.xrd_row,
+                           d.xrd_grad, d.cv_atoms, d.cv_coef, d.wt_scale, mp, d.hills, d.n_hills, d.step, deposit,
+                           cv_out, v_out, F, add, d.status);
+    else
+        hipLaunchKernelGGL(k_metad_bias<64>, dim3(z.n_beads_total), dim3(64), 0, s, q, d.beads, d.xrd_row,
+                           d.xrd_grad, d.cv_atoms, d.cv_coef, d.wt_scale, mp, d.hills, d.n_hills, d.step, deposit,
+                           cv_out, v_out, F, add, d.status);
 }
 
 void launch_metad_advance(const DevBuffers &d, const MetadParams &mp, hipStream_t s)

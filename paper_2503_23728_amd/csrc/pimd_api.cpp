@@ -48,7 +48,9 @@ struct Plan {
     std::vector<int> distinct_P;
     bool any_box = false;                      // some system has a box (metadynamics minimum image)
     bool metad = false;                        // well-tempered metadynamics bias
-    int cv = 0, n_terms = 0, max_hills = 0, n_xrd_tiles = 0;
+    int cv = 0, n_terms = 0, max_hills = 0;
+    int xrd_tile = 64, n_xrd_items = 0;          // XRD pair sum: rows per tile, work items
+    int64_t n_xrd_part = 0;                    // per-tile partials of the XRD pair sum
 };
 
 constexpr int kFesChunk = 4096;                // grid points per pimd_metad_fes launch
@@ -289,8 +291,17 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
             for (int e = 0; e < pl.n_el; ++e)
                 if (!std::isfinite(md->form_factor[e]))
                     return fail(err, PIMD_E_ARG, "form factors must be finite");
+            int max_n = 0;
             for (int s = 0; s < cfg->n_systems; ++s)
-                pl.n_xrd_tiles += cfg->n_beads[s] * ((cfg->n_atoms[s] + 255) / 256);
+                max_n = std::max(max_n, cfg->n_atoms[s]);
+            pl.xrd_tile = max_n > 1024 ? 256 : 64;
+            for (int s = 0; s < cfg->n_systems; ++s) {
+                const int64_t nt = (cfg->n_atoms[s] + pl.xrd_tile - 1) / pl.xrd_tile;
+                pl.n_xrd_items += (int)(cfg->n_beads[s] * nt * (nt + 1) / 2);
+                pl.n_xrd_part += (int64_t)cfg->n_beads[s] * nt * cfg->n_atoms[s];
+            }
+            if (pl.n_xrd_part >= ((int64_t)1 << 31))
+                return fail(err, PIMD_E_UNSUPPORTED, "XRD pair sum too large (per-tile partials above 2^31)");
         }
         pl.metad = true;
         pl.cv = md->cv;
@@ -368,7 +379,9 @@ Layout make_layout(const Plan &pl)
         if (pl.cv == PIMD_CV_XRD) {
             L.add("xrd_row", B * 8);
             L.add("xrd_grad", B * 12);
-            L.add("xrd_tiles", (size_t)pl.n_xrd_tiles * 8);
+            L.add("xrd_items", (size_t)pl.n_xrd_items * 16);
+            L.add("xrd_part0", nb * 4);
+            L.add("xrd_part", (size_t)pl.n_xrd_part * 32);
         } else {
             L.add("cv_atoms", (size_t)pl.n_terms * 8);
             L.add("cv_coef", (size_t)pl.n_terms * 8);
@@ -520,7 +533,7 @@ pimd_status run_forces(pimd_ctx *c, const float *q, float *E_out, float *F_out, 
         launch_harmonic(q, d, z, (float)(c->omega * c->omega * kMvv2e), F_out, s);
         launch_bead_sums(d, z, E_out, W_out, W_out != nullptr, s);
         if (bias)
-            launch_metad(q, d, z, c->mp, c->pl.n_xrd_tiles, F_out, 1, c->deposit_now ? 1 : 0, d.cv_bead,
+            launch_metad(q, d, z, c->mp, c->pl.n_xrd_items, F_out, 1, c->deposit_now ? 1 : 0, d.cv_bead,
                          d.vbias_bead, s);
         for (int k = 2; k <= 6; ++k)
             mark(k);
@@ -533,7 +546,7 @@ pimd_status run_forces(pimd_ctx *c, const float *q, float *E_out, float *F_out, 
             mark(k + 2);
     }
     if (bias)
-        launch_metad(q, d, z, c->mp, c->pl.n_xrd_tiles, F_out, 1, c->deposit_now ? 1 : 0, d.cv_bead, d.vbias_bead,
+        launch_metad(q, d, z, c->mp, c->pl.n_xrd_items, F_out, 1, c->deposit_now ? 1 : 0, d.cv_bead, d.vbias_bead,
                      s);
     mark(6);
     CHECK_LAUNCH(c);
@@ -1022,7 +1035,9 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         d.wt_scale = (double *)at("wt_scale");
         d.xrd_row = (double *)at("xrd_row");
         d.xrd_grad = (float *)at("xrd_grad");
-        d.xrd_tiles = (int2 *)at("xrd_tiles");
+        d.xrd_items = (int4 *)at("xrd_items");
+        d.xrd_part0 = (int32_t *)at("xrd_part0");
+        d.xrd_part = (double4 *)at("xrd_part");
         d.cv_atoms = (int32_t *)at("cv_atoms");
         d.cv_coef = (double *)at("cv_coef");
         c->fes_grid = (double *)at("fes_grid");
@@ -1043,12 +1058,23 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         for (int s = 0; s < pl.n_sys; ++s)
             wt[s] = std::isinf(md->bias_factor) ? 0.0 : 1.0 / (kKB * cfg->temperature_K[s] * (md->bias_factor - 1.0));
         push(d.wt_scale, wt.data(), wt.size() * 8);
+        mp.xrd_tile = pl.xrd_tile;
         if (md->cv == PIMD_CV_XRD) {
-            std::vector<int2> tiles;
-            for (int b = 0; b < (int)beads.size(); ++b)
-                for (int r = 0; r < beads[b].n; r += 256)
-                    tiles.push_back(make_int2(b, r));
-            push(d.xrd_tiles, tiles.data(), tiles.size() * 8);
+            // work items (bead, I, J >= I, first partial of the bead), partials per
+            // bead laid out [partner tile][row]
+            std::vector<int4> items;
+            std::vector<int32_t> part0(beads.size());
+            int64_t off = 0;
+            for (int b = 0; b < (int)beads.size(); ++b) {
+                const int nt = (beads[b].n + pl.xrd_tile - 1) / pl.xrd_tile;
+                part0[b] = (int32_t)off;
+                for (int I = 0; I < nt; ++I)
+                    for (int J = I; J < nt; ++J)
+                        items.push_back(make_int4(b, I, J, (int32_t)off));
+                off += (int64_t)nt * beads[b].n;
+            }
+            push(d.xrd_items, items.data(), items.size() * 16);
+            push(d.xrd_part0, part0.data(), part0.size() * 4);
         } else {
             push(d.cv_atoms, md->atoms, (size_t)pl.n_terms * 8);
             push(d.cv_coef, md->coef, (size_t)pl.n_terms * 8);
@@ -1321,7 +1347,7 @@ pimd_status pimd_bias_forces(pimd_ctx *ctx, const float *q_dev, float *forces_de
         return PIMD_E_ARG;
     }
     const DevBuffers &d = ctx->d;
-    launch_metad(q_dev, d, ctx->z, ctx->mp, ctx->pl.n_xrd_tiles, forces_dev, 0, 0, d.cv_eval, d.vbias_eval,
+    launch_metad(q_dev, d, ctx->z, ctx->mp, ctx->pl.n_xrd_items, forces_dev, 0, 0, d.cv_eval, d.vbias_eval,
                  ctx->stream);
     CHECK_LAUNCH(ctx);
     const size_t nb = (size_t)ctx->z.n_beads_total * 8;
@@ -1463,10 +1489,10 @@ pimd_status pimd_time_bias(pimd_ctx *ctx, int32_t n_reps, double *ms_host)
     }
     // one untimed pass, then n_reps passes of the CV and bias kernels writing
     // the bias forces into the force array (which is re-evaluated at the next step)
-    launch_metad(d.q, d, ctx->z, ctx->mp, ctx->pl.n_xrd_tiles, d.F, 0, 0, d.cv_eval, d.vbias_eval, ctx->stream);
+    launch_metad(d.q, d, ctx->z, ctx->mp, ctx->pl.n_xrd_items, d.F, 0, 0, d.cv_eval, d.vbias_eval, ctx->stream);
     (void)hipEventRecord(ev[0], ctx->stream);
     for (int r = 0; r < n_reps; ++r)
-        launch_metad(d.q, d, ctx->z, ctx->mp, ctx->pl.n_xrd_tiles, d.F, 0, 0, d.cv_eval, d.vbias_eval, ctx->stream);
+        launch_metad(d.q, d, ctx->z, ctx->mp, ctx->pl.n_xrd_items, d.F, 0, 0, d.cv_eval, d.vbias_eval, ctx->stream);
     (void)hipEventRecord(ev[1], ctx->stream);
     hipError_t e = hipEventSynchronize(ev[1]);
     float ms = 0.0f;

@@ -134,6 +134,8 @@ struct MetadParams {
     int32_t cv;              // 1 distances, 2 XRD
     int32_t n_terms;
     int32_t stride, max_hills;
+    int32_t xrd_tile;        // rows per tile of the XRD pair sum: 64 or 256
+    int32_t pad;
     double q_scatter;        // Q (1/A)
     double sigma, inv_sigma, height0;
     double form_factor[kMaxElements];
@@ -182,7 +184,9 @@ struct DevBuffers {
     double *cv_eval, *vbias_eval;  // the same for pimd_bias_forces
     double *xrd_row;               // [B] f_i sum_j f_j sinc(Q R_ij)
     float *xrd_grad;               // [B][3] dS/dq_i
-    int2 *xrd_tiles;               // (bead, first row) of every 256-row tile
+    int4 *xrd_items;               // (bead, tile I, tile J >= I, first partial of the bead) of the pair sum
+    int32_t *xrd_part0;            // [beads] first partial of every bead
+    double4 *xrd_part;             // per bead [partner tile][row] (sum_j f_j sinc, gradient sum)
     int32_t *cv_atoms;             // [n_terms][2]
     double *cv_coef;               // [n_terms]
     double *wt_scale;              // [n_sys] 1 / (k_B T (gamma - 1)), 0 for gamma = infinity
@@ -253,7 +257,7 @@ void launch_check_finite(const float *a, int64_t n, uint32_t *status, hipStream_
 // Metadynamics: CV rows (XRD), then per bead the CV, bias, optional
 // deposition (deposit != 0: when the step that is completing is a multiple of
 // the stride) and the bias forces (add != 0: F += bias force, else F = bias force).
-void launch_metad(const float *q, const DevBuffers &d, const Sizes &z, const MetadParams &mp, int n_xrd_tiles,
+void launch_metad(const float *q, const DevBuffers &d, const Sizes &z, const MetadParams &mp, int n_xrd_items,
                   float *F, int add, int deposit, double *cv_out, double *v_out, hipStream_t s);
 void launch_metad_advance(const DevBuffers &d, const MetadParams &mp, hipStream_t s);
 void launch_metad_fes(const DevBuffers &d, const MetadParams &mp, int bead0, int P, double kT, double gamma_ratio,
