@@ -180,6 +180,126 @@ class RingPolymers:
         return slice(b0, b0 + self.systems[s][1])
 
 
+# ---------------------------------------------------------------- staging
+# Sec. 2.1 names the staging transformation beside normal modes as the way to
+# decouple the ring-polymer springs (Tuckerman, Berne, Martyna, Klein, J.
+# Chem. Phys. 99, 2796 (1993)).  With beads r_1..r_P (r_{P+1} = r_1):
+#   u_1 = r_1,   u_l = r_l - ((l - 1) r_{l+1} + r_1) / l   (l = 2..P),
+# the springs become sum_{l>=2} 1/2 m_l' w_P^2 u_l^2 with m_l' = l m / (l - 1).
+# Dynamics use kinetic masses m~_1 = m, m~_l = m_l' (every u_l, l >= 2, then
+# oscillates at w_P), the momenta p~_l conjugate to u_l are the state, and
+# the thermostat is a Langevin friction per staging coordinate: gamma_1 =
+# 1/tau0, gamma_l = 2 lambda w_P.  Arrays below are [P, ...] with index
+# k = l - 1.
+
+
+def staging_forward(r):
+    """u from bead values r [P, ...]."""
+    r = np.asarray(r, dtype=np.float64)
+    P = len(r)
+    u = np.empty_like(r)
+    u[0] = r[0]
+    for k in range(1, P):
+        l = k + 1
+        u[k] = r[k] - ((l - 1) * r[(k + 1) % P] + r[0]) / l
+    return u
+
+
+def staging_inverse(u):
+    """r from u, by the recursion r_l = u_l + ((l - 1)/l) r_{l+1} + u_1 / l from l = P down."""
+    u = np.asarray(u, dtype=np.float64)
+    P = len(u)
+    r = np.empty_like(u)
+    r[0] = u[0]
+    nxt = u[0]
+    for k in range(P - 1, 0, -1):
+        l = k + 1
+        r[k] = u[k] + ((l - 1) / l) * nxt + u[0] / l
+        nxt = r[k]
+    return r
+
+
+def staging_forces(F):
+    """-dU/du from F = -dU/dr [P, ...]: the chain rule through r(u), summed as
+    f~_1 = sum_l F_l,  f~_2 = F_2,  f~_l = F_l + ((l - 2)/(l - 1)) f~_{l-1}."""
+    F = np.asarray(F, dtype=np.float64)
+    P = len(F)
+    G = np.empty_like(F)
+    G[0] = F.sum(axis=0)
+    for k in range(1, P):
+        l = k + 1
+        G[k] = F[k] + ((l - 2) / (l - 1)) * G[k - 1] if l > 2 else F[k]
+    return G
+
+
+def staging_mass_factors(P):
+    """m~_l / m: 1 for l = 1, l / (l - 1) otherwise."""
+    return np.array([1.0] + [(k + 1) / k for k in range(1, P)])
+
+
+class StagingRingPolymers(RingPolymers):
+    """RingPolymers propagated in staging coordinates (same splitting
+    O(dt/2) B(dt/2) A(dt) [forces] B(dt/2) O(dt/2)).  The state momenta p are
+    the staging momenta p~ (row of bead k holds p~ of staging coordinate k)."""
+
+    def _o_step_staging(self, s, pt, xi):
+        n, P, T, m = self.systems[s]
+        _, wP = mode_frequencies(P, T)
+        mt = staging_mass_factors(P)[:, None] * m[None, :]
+        if self.tau0 > 0:
+            gamma = np.full(P, 2.0 * self.lam * wP)
+            gamma[0] = 1.0 / self.tau0
+        else:
+            gamma = np.zeros(P)
+        c1 = np.exp(-gamma * self.dt / 2)
+        c2 = np.sqrt(1.0 - c1 * c1)
+        sigma = np.sqrt(mt * KB * T * P / MVV2E)
+        ke0 = 0.5 * MVV2E * np.sum(pt * pt / mt[:, :, None])
+        pt = c1[:, None, None] * pt + sigma[:, :, None] * c2[:, None, None] * xi
+        ke1 = 0.5 * MVV2E * np.sum(pt * pt / mt[:, :, None])
+        self.heat[s] -= ke1 - ke0
+        return pt
+
+    def step(self, noise=None):
+        xi0 = self._noise(0, noise)
+        for s in range(len(self.systems)):
+            n, P, T, m = self.systems[s]
+            _, wP = mode_frequencies(P, T)
+            mt = staging_mass_factors(P)[:, None] * m[None, :]
+            p, q, F = self._view(self.p, s), self._view(self.q, s), self._view(self.F, s)
+            pt = self._o_step_staging(s, p.copy(), self._view(xi0, s))
+            pt = pt + (self.dt / 2) * staging_forces(F) / MVV2E
+            u = staging_forward(q)
+            u[0] = u[0] + self.dt * pt[0] / m[:, None]
+            if P > 1:
+                c, sn = np.cos(wP * self.dt), np.sin(wP * self.dt)
+                mw = mt[1:, :, None] * wP
+                un = sn * pt[1:] / mw + c * u[1:]
+                pn = c * pt[1:] - mw * sn * u[1:]
+                u[1:], pt[1:] = un, pn
+            q[...] = staging_inverse(u)
+            p[...] = pt
+        self.E, self.F = self.force_fn(self.q)
+        xi1 = self._noise(1, noise)
+        for s in range(len(self.systems)):
+            p, F = self._view(self.p, s), self._view(self.F, s)
+            pt = p + (self.dt / 2) * staging_forces(F) / MVV2E
+            p[...] = self._o_step_staging(s, pt, self._view(xi1, s))
+        self.step_count += 1
+
+    def estimators(self):
+        out = super().estimators()
+        for s, o in enumerate(out):
+            n, P, T, m = self.systems[s]
+            mt = staging_mass_factors(P)[:, None] * m[None, :]
+            p = self._view(self.p, s)
+            k_beads = 0.5 * MVV2E * np.sum(p * p / mt[:, :, None])
+            o["H_conserved"] += k_beads - o["K_beads"]
+            o["K_beads"] = k_beads
+            o["T_beads"] = 2 * k_beads / (3 * n * P * KB)
+        return out
+
+
 def harmonic_force_fn(systems, omega):
     """V = sum_i 1/2 m_i omega^2 |q_i|^2 per bead (isotropic oscillator about
     the origin); returns E per bead and F = -m omega^2 q."""

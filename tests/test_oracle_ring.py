@@ -243,3 +243,86 @@ def test_philox_normals_moments():
     zz = philox.thermostat_noise(99, 3, 1, 200000)
     c = np.corrcoef(zz.T)
     assert np.abs(c - np.eye(3)).max() < 4 / np.sqrt(200000)
+
+
+# ---------------------------------------------------------------- staging (Sec. 2.1)
+
+@pytest.mark.parametrize("P", [2, 4, 8, 32])
+def test_staging_transform_round_trip_and_spring_identity(P):
+    rng = np.random.default_rng(P)
+    r = rng.normal(size=(P, 7, 3))
+    u = ring.staging_forward(r)
+    assert np.max(np.abs(ring.staging_inverse(u) - r)) < 1e-13
+    assert np.array_equal(u[0], r[0])
+    # the ring's springs, sum_l |r_{l+1} - r_l|^2, are diagonal in u with weights l/(l-1)
+    springs = np.sum((np.roll(r, -1, axis=0) - r) ** 2)
+    fac = ring.staging_mass_factors(P)
+    assert np.sum(fac[1:, None, None] * u[1:] ** 2) == pytest.approx(springs, rel=1e-12)
+    assert fac[0] == 1.0 and fac[1] == 2.0 and fac[-1] == pytest.approx(P / (P - 1))
+
+
+@pytest.mark.parametrize("P", [2, 4, 8])
+def test_staging_forces_are_the_chain_rule_by_central_differences(P):
+    rng = np.random.default_rng(10 + P)
+    a = rng.normal(size=(P, 3))
+    b = rng.normal(size=(P, 3))
+
+    def U(r):                        # a smooth potential of every bead coordinate
+        return float(np.sum(a * np.sin(b * r)) + 0.3 * np.sum(r ** 2) * np.sum(np.cos(r)))
+
+    def F(r):
+        return -(a * b * np.cos(b * r) + 0.6 * r * np.sum(np.cos(r)) - 0.3 * np.sum(r ** 2) * np.sin(r))
+    r = rng.normal(size=(P, 3))
+    u = ring.staging_forward(r)
+    G = ring.staging_forces(F(r))
+    h = 1e-6
+    G_fd = np.zeros_like(u)
+    for k in range(P):
+        for c in range(3):
+            up, um = u.copy(), u.copy()
+            up[k, c] += h
+            um[k, c] -= h
+            G_fd[k, c] = -(U(ring.staging_inverse(up)) - U(ring.staging_inverse(um))) / (2 * h)
+    assert np.max(np.abs(G - G_fd)) < 1e-7
+
+
+def test_staging_free_ring_polymer_conserves_energy():
+    P, n, T = 8, 5, 300.0
+    systems = _systems(n, P, T)
+    rp = ring.StagingRingPolymers(systems, 0.5, 0.0, 1.0, 3,
+                                  lambda q: (np.zeros(P), np.zeros_like(q)))
+    rng = np.random.default_rng(3)
+    rp.set_state(rng.normal(0, 0.2, (n * P, 3)), rng.normal(0, 0.3, (n * P, 3)))
+    H0 = _hamiltonian(rp, 0.0)
+    for _ in range(200):
+        rp.step()
+    assert _hamiltonian(rp, 0.0) == pytest.approx(H0, rel=1e-11)
+
+
+@pytest.mark.parametrize("P", [4, 8])
+def test_staging_samples_exact_finite_P_harmonic_average(P):
+    g = json.load(open(os.path.join(GOLDEN, "qho_s1.json")))
+    m, w = g["mass_amu"], g["omega_per_fs"]
+    T = 100.0
+    n = 600
+    systems = _systems(n, P, T, mass=m)
+    rp = ring.StagingRingPolymers(systems, g["dt_fs"], 100.0, 1.0, 19, ring.harmonic_force_fn(systems, w))
+    rng = np.random.default_rng(9)
+    rp.set_state(rng.normal(0, 0.3, (n * P, 3)), rng.normal(0, 0.2, (n * P, 3)))
+    for _ in range(1500):
+        rp.step()
+    x2, kcv, tb = [], [], []
+    for t in range(3000):
+        rp.step()
+        if t % 5 == 0:
+            x2.append(np.mean(rp.q ** 2))
+            est = rp.estimators()[0]
+            kcv.append(est["K_cv"] / (3 * n))
+            tb.append(est["T_beads"])
+    mean, err = _block_mean(x2)
+    want = qho.x2_beads_sum(m, w, T, P)
+    assert abs(mean - want) < 3.5 * err + 2e-3 * want
+    kmean, kerr = _block_mean(kcv)
+    assert abs(kmean - 0.5 * qho.energy_beads(m, w, T, P)) < 3.5 * kerr + 2e-3 * kmean
+    tmean, terr = _block_mean(tb)                      # fictitious kinetic masses: still P T
+    assert abs(tmean - P * T) < 3.5 * terr + 5e-3 * P * T
