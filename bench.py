@@ -235,6 +235,8 @@ def main():
                     help="energy model with adjoint forces, or the direct-force head")
     ap.add_argument("--gfn-width", type=int, default=16)
     ap.add_argument("--gfn-layers", type=int, default=2)
+    ap.add_argument("--transform", default="normal-modes", choices=["normal-modes", "staging"],
+                    help="ring-polymer coordinates of the integrator")
     ap.add_argument("--metad", action="store_true",
                     help="add the well-tempered metadynamics bias of the workload's study (s_dimer or XRD CV)")
     args = ap.parse_args()
@@ -252,7 +254,8 @@ def main():
     wl = S.gfn_workload(args.config, args.gfn_width, args.gfn_layers) if gfn_mode else S.workload(args.config)
     B = wl.bead_atoms
     spec = S.metad_spec(wl, max_hills=4096) if args.metad else None
-    eng = Pimd.from_workload(wl, precision="fp32" if gfn_mode else args.precision, device=device, metad=spec)
+    eng = Pimd.from_workload(wl, precision="fp32" if gfn_mode else args.precision, device=device, metad=spec,
+                             transform=args.transform)
     q, p = S.initial_state(wl)
     eng.set_state(torch.from_numpy(q).to(device), torch.from_numpy(p).to(device))
     if args.no_tune:
@@ -325,6 +328,7 @@ def main():
         "config": {"workload": wl.name, "systems": len(wl.systems), "bead_atoms": B,
                    "beads": sum(s.n_beads for s in wl.systems), "dt_fs": wl.dt,
                    "precision": "fp32" if gfn_mode else args.precision, "potential": args.potential,
+                   "transform": args.transform,
                    "launch": "hip graph per step" + (", 25-step blocks from the initial state" if gfn_mode else ""),
                    "launch_shape": shape,
                    "shape_source": {None: "default", True: "tuning cache", False: "autotuner"}[cached]},

@@ -186,6 +186,18 @@ typedef struct {
  * force), step lo, step hi), words u = (x + 1/2) 2^-32, Box-Muller on
  * (u0,u1) -> x, y and (u2,u3) -> z.
  */
+/* Ring-polymer coordinates of the integrator (Sec. 2.1 names both):
+ *   NORMAL_MODES  as above; the state momenta are Cartesian bead momenta.
+ *   STAGING       u_1 = r_1, u_l = r_l - ((l-1) r_{l+1} + r_1)/l (l = 2..P,
+ *                 r_{P+1} = r_1); springs sum_{l>=2} 1/2 m_l' w_P^2 u_l^2 with
+ *                 m_l' = l m/(l-1); kinetic masses m for u_1 and m_l' for u_l,
+ *                 so every u_l (l >= 2) turns at w_P in the exact A step;
+ *                 friction 1/tau0 on u_1 and 2 pile_lambda w_P on the others.
+ *                 The state momenta (pimd_set_state, pimd_get_state) are the
+ *                 staging momenta, row of bead l - 1 holding the momentum of
+ *                 u_l; K_beads and T_beads use the kinetic masses. */
+enum { PIMD_TRANSFORM_NORMAL_MODES = 0, PIMD_TRANSFORM_STAGING = 1 };
+
 typedef struct {
     int32_t n_systems;                 /* >= 1 */
     const int32_t *n_atoms;            /* [n_systems], >= 1 */
@@ -204,6 +216,7 @@ typedef struct {
     int32_t max_neighbors;             /* neighbour slots per atom: 0 => 128; a multiple of 16, <= 256 */
     const pimd_gfn_model *gfn;         /* PIMD_POT_GFN: the direct-force head (precision is ignored: FP32) */
     const pimd_metad *metad;           /* well-tempered metadynamics bias, or NULL for none */
+    int32_t transform;                 /* PIMD_TRANSFORM_* (0: normal modes) */
 } pimd_config;
 
 /* Finite-P estimators of one system (Sec. 2.1; virial kinetic energy of

@@ -18,6 +18,7 @@ PIMD_OK, PIMD_E_ARG, PIMD_E_UNSUPPORTED, PIMD_E_DEVICE, PIMD_E_OOM, PIMD_E_CAPAC
 PIMD_PREC_FP32, PIMD_PREC_BF16_MLP, PIMD_PREC_BF16_PLAIN, PIMD_PREC_FP64_MLP = 0, 1, 2, 3
 PIMD_POT_BPNN, PIMD_POT_HARMONIC, PIMD_POT_GFN = 0, 1, 2
 PIMD_CV_DISTANCES, PIMD_CV_XRD = 1, 2
+PIMD_TRANSFORM_NORMAL_MODES, PIMD_TRANSFORM_STAGING = 0, 1
 
 
 class pimd_bpnn_model(ctypes.Structure):
@@ -46,7 +47,7 @@ class pimd_config(ctypes.Structure):
                 ("dt_fs", c_double), ("tau0_fs", c_double), ("pile_lambda", c_double), ("seed", c_uint64),
                 ("precision", c_int32), ("potential", c_int32), ("model", POINTER(pimd_bpnn_model)),
                 ("harmonic_omega_per_fs", c_double), ("max_neighbors", c_int32),
-                ("gfn", POINTER(pimd_gfn_model)), ("metad", POINTER(pimd_metad))]
+                ("gfn", POINTER(pimd_gfn_model)), ("metad", POINTER(pimd_metad)), ("transform", c_int32)]
 
 
 class pimd_tuning(ctypes.Structure):

@@ -59,8 +59,42 @@ __device__ double block_sum_double(double v, double *red)
     return red[0];
 }
 
+// Staging coordinates of one column (bead values v[0..P-1], index k = l - 1):
+//   u_k = v_k - (k v_{k+1} + v_0) / (k + 1)  (k >= 1, v_P = v_0),  u_0 = v_0;
+//   force on u_k:  k = 0: sum_j F_j;  k >= 1: (1/k) sum_{j=1..k} j F_j
+//   (the chain rule through the inverse, written out);
+//   inverse:  v_0 = u_0,  v_j = u_0 + j sum_{k=j..P-1} u_k / k  (j >= 1).
+__device__ __forceinline__ double staging_u(const double *v, int k, int P)
+{
+    return k == 0 ? v[0] : v[k] - ((double)k * v[(k + 1) % P] + v[0]) / (double)(k + 1);
+}
+
+__device__ __forceinline__ double staging_force(const double *f, int k, int P)
+{
+    double a = 0.0;
+    if (k == 0) {
+        for (int j = 0; j < P; ++j)
+            a += f[j];
+        return a;
+    }
+    for (int j = 1; j <= k; ++j)
+        a += (double)j * f[j];
+    return a / (double)k;
+}
+
+__device__ __forceinline__ double staging_r(const double *u, int j, int P)
+{
+    if (j == 0)
+        return u[0];
+    double a = 0.0;
+    for (int k = j; k < P; ++k)
+        a += u[k] / (double)k;
+    return u[0] + (double)j * a;
+}
+
 // LDS (doubles): CT[P][P+1] | s0[256] | s1[256] | s2[256] | red[256]
-template <bool PRE>
+// (STAGING leaves CT unused: its transforms are the closed forms above.)
+template <bool PRE, bool STAGING>
 __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
 {
     extern __shared__ double ism[];
@@ -73,9 +107,11 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
     double *s2 = s1 + 256;
     double *red = s2 + 256;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < P * P; idx += 256) {
-        const int j = idx / P, k = idx - j * P;
-        CT[k * (P + 1) + j] = a.cmat[S.cmat0 + idx];  // C[j][k]
+    if (!STAGING) {
+        for (int idx = tid; idx < P * P; idx += 256) {
+            const int j = idx / P, k = idx - j * P;
+            CT[k * (P + 1) + j] = a.cmat[S.cmat0 + idx];  // C[j][k]
+        }
     }
     const int cl = tid / P, kk = tid - cl * P;
     const bool valid = cl < u.ncol;
@@ -99,37 +135,48 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
         const double *ct = CT + kk * (P + 1);
         const double *sp = s0 + cl * P, *sf = s1 + cl * P, *sq = s2 + cl * P;
         const ModeInfo M = a.modes[S.mode0 + kk];
-        const double sig = sqrt(m) * (double)S.sig_T;
+        const double mk = m * M.mfac;                 // kinetic mass of mode kk
+        const double sig = sqrt(mk) * (double)S.sig_T;
         if (PRE) {
             double Ft = 0.0;
-            for (int j = 0; j < P; ++j) {
-                const double c = ct[j];
-                pt += c * sp[j];
-                Ft += c * sf[j];
-                qt += c * sq[j];
+            if (STAGING) {
+                pt = sp[kk];                          // the state holds staging momenta
+                Ft = staging_force(sf, kk, P);
+                qt = staging_u(sq, kk, P);
+            } else {
+                for (int j = 0; j < P; ++j) {
+                    const double c = ct[j];
+                    pt += c * sp[j];
+                    Ft += c * sf[j];
+                    qt += c * sq[j];
+                }
             }
             // O(dt/2), half 0
             const double xi = (double)noise_value(a, 0, row, cc, step);
             const double pn = M.c1 * pt + sig * M.c2 * xi;
-            dke = 0.5 * (pn * pn - pt * pt) / m * kMvv2e;
+            dke = 0.5 * (pn * pn - pt * pt) / mk * kMvv2e;
             pt = pn + kick * Ft;  // B(dt/2)
             // A(dt)
             if (kk == 0) {
-                qt += (double)a.dt * pt / m;
+                qt += (double)a.dt * pt / mk;
             } else {
-                const double mw = m * M.w;
+                const double mw = mk * M.w;
                 const double qn = M.sw * pt / mw + M.cw * qt;
                 const double pn2 = M.cw * pt - mw * M.sw * qt;
                 qt = qn;
                 pt = pn2;
             }
         } else {
-            // B(dt/2) in bead space, then to modes
-            for (int j = 0; j < P; ++j)
-                pt += ct[j] * (sp[j] + kick * sf[j]);
+            // B(dt/2), then O(dt/2) in modes
+            if (STAGING) {
+                pt = sp[kk] + kick * staging_force(sf, kk, P);
+            } else {
+                for (int j = 0; j < P; ++j)
+                    pt += ct[j] * (sp[j] + kick * sf[j]);
+            }
             const double xi = (double)noise_value(a, 1, row, cc, step);
             const double pn = M.c1 * pt + sig * M.c2 * xi;
-            dke = 0.5 * (pn * pn - pt * pt) / m * kMvv2e;
+            dke = 0.5 * (pn * pn - pt * pt) / mk * kMvv2e;
             pt = pn;
         }
     }
@@ -141,14 +188,20 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
     }
     __syncthreads();
     if (valid) {
-        // back to beads: x_j = sum_k C[j][k] x~_k, with j = kk
-        double pj = 0.0, qj = 0.0;
         const double *sp = s0 + cl * P, *sq = s2 + cl * P;
-        for (int k = 0; k < P; ++k) {
-            const double c = CT[k * (P + 1) + kk];
-            pj += c * sp[k];
+        double pj = 0.0, qj = 0.0;
+        if (STAGING) {
+            pj = pt;
             if (PRE)
-                qj += c * sq[k];
+                qj = staging_r(sq, kk, P);
+        } else {
+            // back to beads: x_j = sum_k C[j][k] x~_k, with j = kk
+            for (int k = 0; k < P; ++k) {
+                const double c = CT[k * (P + 1) + kk];
+                pj += c * sp[k];
+                if (PRE)
+                    qj += c * sq[k];
+            }
         }
         a.p[row * 3 + cc] = (float)pj;
         if (PRE)
@@ -179,9 +232,10 @@ __global__ __launch_bounds__(256) void k_finish_step(const SysInfo *__restrict__
 }
 
 // Estimator terms per column (atom, xyz) of every system:
-// [0] m sum_k (q_{k+1} - q_k)^2, [1] sum_k (q_k - qbar) F_k, [2] sum_k p_k^2 / m
+// [0] m sum_k (q_{k+1} - q_k)^2, [1] sum_k (q_k - qbar) F_k, [2] sum_k p_k^2 / (m mfac_k)
 __global__ __launch_bounds__(256) void k_estimator_terms(const float *__restrict__ q, const float *__restrict__ p,
                                                          const float *__restrict__ F, const SysInfo *__restrict__ sys,
+                                                         const ModeInfo *__restrict__ modes,
                                                          const int32_t *__restrict__ col_sys,
                                                          const float *__restrict__ mass_atom,
                                                          float *__restrict__ out, int ncol)
@@ -206,7 +260,7 @@ __global__ __launch_bounds__(256) void k_estimator_terms(const float *__restrict
         spring += dq * dq;
         cv += (qk - qbar) * F[r * 3 + cc];
         const float pk = p[r * 3 + cc];
-        ke += pk * pk;
+        ke += pk * pk / (float)modes[S.mode0 + k].mfac;   // kinetic mass of the slot's momentum
     }
     out[3 * (int64_t)col + 0] = m * spring;
     out[3 * (int64_t)col + 1] = cv;
@@ -292,24 +346,34 @@ size_t integrator_lds_bytes(int max_P) { return integ_lds(max_P); }
 hipError_t configure_integrator_lds(int max_P)
 {
     const int b = (int)integ_lds(max_P);
-    hipError_t e = hipFuncSetAttribute((const void *)k_integrate<true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_integrate<false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipError_t e = hipSuccess;
+    for (const void *f : {(const void *)k_integrate<true, false>, (const void *)k_integrate<false, false>,
+                          (const void *)k_integrate<true, true>, (const void *)k_integrate<false, true>})
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     return e;
 }
 
 void launch_integrate_pre(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi,
-                          int max_P, hipStream_t s)
+                          int max_P, bool staging, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_integrate<true>, dim3(z.n_units), dim3(256), integ_lds(max_P), s,
-                       integ_args(d, z, dt, k0, k1, xi));
+    if (staging)
+        hipLaunchKernelGGL((k_integrate<true, true>), dim3(z.n_units), dim3(256), integ_lds(max_P), s,
+                           integ_args(d, z, dt, k0, k1, xi));
+    else
+        hipLaunchKernelGGL((k_integrate<true, false>), dim3(z.n_units), dim3(256), integ_lds(max_P), s,
+                           integ_args(d, z, dt, k0, k1, xi));
 }
 
 void launch_integrate_post(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi,
-                           int max_P, hipStream_t s)
+                           int max_P, bool staging, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_integrate<false>, dim3(z.n_units), dim3(256), integ_lds(max_P), s,
-                       integ_args(d, z, dt, k0, k1, xi));
+    if (staging)
+        hipLaunchKernelGGL((k_integrate<false, true>), dim3(z.n_units), dim3(256), integ_lds(max_P), s,
+                           integ_args(d, z, dt, k0, k1, xi));
+    else
+        hipLaunchKernelGGL((k_integrate<false, false>), dim3(z.n_units), dim3(256), integ_lds(max_P), s,
+                           integ_args(d, z, dt, k0, k1, xi));
 }
 
 void launch_finish_step(const DevBuffers &d, const Sizes &z, hipStream_t s)
@@ -320,7 +384,7 @@ void launch_finish_step(const DevBuffers &d, const Sizes &z, hipStream_t s)
 void launch_estimator_terms(const DevBuffers &d, const Sizes &z, hipStream_t s)
 {
     hipLaunchKernelGGL(k_estimator_terms, dim3((z.ncol + 255) / 256), dim3(256), 0, s, d.q, d.p, d.F, d.sys,
-                       d.col_sys, d.mass_atom, d.est_cols, z.ncol);
+                       d.modes, d.col_sys, d.mass_atom, d.est_cols, z.ncol);
 }
 
 void launch_harmonic(const float *q, const DevBuffers &d, const Sizes &z, float w2_mvv2e, float *F, hipStream_t s)

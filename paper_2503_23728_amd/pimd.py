@@ -87,7 +87,7 @@ def make_metad(spec, keep):
 
 
 def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
-                omega=0.0, max_neighbors=0, masses=None, metad=None):
+                omega=0.0, max_neighbors=0, masses=None, metad=None, transform="normal-modes"):
     """Build the pimd_config (and the storage it points into).
 
     systems: sequence with n_atoms, n_beads, temperature, box, species.
@@ -148,6 +148,7 @@ def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", p
     cfg.harmonic_omega_per_fs = omega
     cfg.max_neighbors = max_neighbors
     cfg.metad = ctypes.pointer(make_metad(metad, keep)) if metad is not None else None
+    cfg.transform = {"normal-modes": abi.PIMD_TRANSFORM_NORMAL_MODES, "staging": abi.PIMD_TRANSFORM_STAGING}[transform]
     return cfg, keep
 
 
@@ -155,13 +156,14 @@ class Pimd:
     """One library context: state, workspace and stream on one device."""
 
     def __init__(self, systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
-                 omega=0.0, max_neighbors=0, masses=None, device="cuda:0", stream=None, metad=None):
+                 omega=0.0, max_neighbors=0, masses=None, device="cuda:0", stream=None, metad=None,
+                 transform="normal-modes"):
         self.device = torch.device(device)
         self.metad = metad
         self.systems = list(systems)
         self.model, self.precision, self.max_neighbors = model, precision, max_neighbors
         self.cfg, self._keep = make_config(self.systems, model, dt, tau0, pile_lambda, seed, precision,
-                                           potential, omega, max_neighbors, masses, metad)
+                                           potential, omega, max_neighbors, masses, metad, transform)
         st, nbytes = abi.pimd_workspace_size(self.cfg)
         _check(st)
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)

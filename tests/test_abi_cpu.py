@@ -52,6 +52,7 @@ def test_workspace_grows_with_max_neighbors(lib):
     (lambda cfg, k: setattr(cfg, "dt_fs", 0.0), abi.PIMD_E_ARG),
     (lambda cfg, k: setattr(cfg, "precision", 7), abi.PIMD_E_ARG),
     (lambda cfg, k: setattr(cfg, "potential", 9), abi.PIMD_E_ARG),
+    (lambda cfg, k: setattr(cfg, "transform", 5), abi.PIMD_E_ARG),
     (lambda cfg, k: setattr(cfg, "max_neighbors", 100), abi.PIMD_E_ARG),
     (lambda cfg, k: setattr(cfg, "max_neighbors", 1000), abi.PIMD_E_UNSUPPORTED),
     (lambda cfg, k: setattr(cfg, "species", None), abi.PIMD_E_ARG),
