@@ -300,6 +300,63 @@ class StagingRingPolymers(RingPolymers):
         return out
 
 
+# ---------------------------------------------------------------- primitive
+# Sec. 2.3 also runs "primitive" PIMD: the inter-bead springs are one more
+# force term and the beads move in Cartesian coordinates.  Here: the same
+# O(dt/2) B(dt/2) A(dt) [forces] B(dt/2) O(dt/2) splitting with
+#   B: p_k += dt/2 (F_k - m w_P^2 (2 q_k - q_{k+1} - q_{k-1})),
+#   A: q_k += dt p_k / m (free drift),
+#   O: Langevin friction 1/tau0 on every bead's momentum,
+# i.e. velocity Verlet on the full ring Hamiltonian H_P; the spring
+# frequencies up to 2 w_P must stay well below 2/dt.
+
+
+def spring_forces(q, m, wP):
+    """-dE_spring/dq of one system's beads q [P, n, 3] (eV/A), E_spring =
+    sum_k 1/2 m w_P^2 |q_{k+1} - q_k|^2 (cyclic)."""
+    if len(q) == 1:
+        return np.zeros_like(q)
+    lap = 2.0 * q - np.roll(q, -1, axis=0) - np.roll(q, 1, axis=0)
+    return -(m[None, :, None] * wP * wP * MVV2E) * lap
+
+
+class PrimitiveRingPolymers(RingPolymers):
+    """RingPolymers propagated in Cartesian bead coordinates with the
+    springs as forces (see above)."""
+
+    def _o_step_beads(self, s, p, xi):
+        n, P, T, m = self.systems[s]
+        gamma = 1.0 / self.tau0 if self.tau0 > 0 else 0.0
+        c1 = np.exp(-gamma * self.dt / 2)
+        c2 = np.sqrt(1.0 - c1 * c1)
+        sigma = np.sqrt(m * KB * T * P / MVV2E)
+        ke0 = 0.5 * MVV2E * np.sum(p * p / m[None, :, None])
+        p = c1 * p + sigma[None, :, None] * c2 * xi
+        ke1 = 0.5 * MVV2E * np.sum(p * p / m[None, :, None])
+        self.heat[s] -= ke1 - ke0
+        return p
+
+    def step(self, noise=None):
+        xi0 = self._noise(0, noise)
+        for s in range(len(self.systems)):
+            n, P, T, m = self.systems[s]
+            _, wP = mode_frequencies(P, T)
+            p, q, F = self._view(self.p, s), self._view(self.q, s), self._view(self.F, s)
+            pt = self._o_step_beads(s, p.copy(), self._view(xi0, s))
+            pt = pt + (self.dt / 2) * (F + spring_forces(q, m, wP)) / MVV2E
+            q[...] = q + self.dt * pt / m[None, :, None]
+            p[...] = pt
+        self.E, self.F = self.force_fn(self.q)
+        xi1 = self._noise(1, noise)
+        for s in range(len(self.systems)):
+            n, P, T, m = self.systems[s]
+            _, wP = mode_frequencies(P, T)
+            p, q, F = self._view(self.p, s), self._view(self.q, s), self._view(self.F, s)
+            pt = p + (self.dt / 2) * (F + spring_forces(q, m, wP)) / MVV2E
+            p[...] = self._o_step_beads(s, pt, self._view(xi1, s))
+        self.step_count += 1
+
+
 def harmonic_force_fn(systems, omega):
     """V = sum_i 1/2 m_i omega^2 |q_i|^2 per bead (isotropic oscillator about
     the origin); returns E per bead and F = -m omega^2 q."""

@@ -326,3 +326,81 @@ def test_staging_samples_exact_finite_P_harmonic_average(P):
     assert abs(kmean - 0.5 * qho.energy_beads(m, w, T, P)) < 3.5 * kerr + 2e-3 * kmean
     tmean, terr = _block_mean(tb)                      # fictitious kinetic masses: still P T
     assert abs(tmean - P * T) < 3.5 * terr + 5e-3 * P * T
+
+
+# ---------------------------------------------------------------- primitive (Sec. 2.3)
+
+def test_spring_forces_are_minus_the_gradient_of_the_spring_energy():
+    rng = np.random.default_rng(40)
+    P, n = 6, 3
+    m = np.array([1.0, 2.0, 16.0])
+    wP = 0.7
+    q = rng.normal(size=(P, n, 3))
+
+    def E(x):
+        return 0.5 * MVV2E * wP * wP * np.sum(m[None, :, None] * (np.roll(x, -1, axis=0) - x) ** 2)
+    F = ring.spring_forces(q, m, wP)
+    h = 1e-6
+    for (k, i, c) in [(0, 0, 0), (3, 2, 1), (5, 1, 2)]:
+        qp, qm = q.copy(), q.copy()
+        qp[k, i, c] += h
+        qm[k, i, c] -= h
+        assert F[k, i, c] == pytest.approx(-(E(qp) - E(qm)) / (2 * h), rel=1e-7)
+
+
+def test_primitive_single_bead_equals_normal_modes():
+    n, T = 20, 300.0
+    systems = _systems(n, 1, T)
+    fn = ring.harmonic_force_fn(systems, 0.02)
+    rng = np.random.default_rng(41)
+    q0, p0 = rng.normal(0, 0.2, (n, 3)), rng.normal(0, 0.3, (n, 3))
+    a = ring.RingPolymers(systems, 0.5, 50.0, 1.0, 5, fn)
+    b = ring.PrimitiveRingPolymers(systems, 0.5, 50.0, 1.0, 5, fn)
+    a.set_state(q0, p0)
+    b.set_state(q0, p0)
+    for _ in range(20):
+        a.step()
+        b.step()
+    assert np.max(np.abs(a.q - b.q)) < 1e-12 and np.max(np.abs(a.p - b.p)) < 1e-12
+
+
+def test_primitive_nve_error_scales_as_dt_squared():
+    # velocity Verlet on the full ring Hamiltonian: energy error ~ dt^2
+    P, n, T = 8, 4, 300.0
+    systems = _systems(n, P, T)
+    fn = ring.harmonic_force_fn(systems, 0.02)
+    rng = np.random.default_rng(42)
+    q0, p0 = rng.normal(0, 0.05, (n * P, 3)), rng.normal(0, 0.3, (n * P, 3))
+    errs = []
+    for dt in (0.1, 0.05):
+        rp = ring.PrimitiveRingPolymers(systems, dt, 0.0, 1.0, 3, fn)
+        rp.set_state(q0, p0)
+        H0 = _hamiltonian(rp, rp.E.sum())
+        dev = 0.0
+        for _ in range(int(round(20.0 / dt))):
+            rp.step()
+            dev = max(dev, abs(_hamiltonian(rp, rp.E.sum()) - H0))
+        errs.append(dev)
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.15)
+
+
+def test_primitive_samples_exact_finite_P_harmonic_average():
+    g = json.load(open(os.path.join(GOLDEN, "qho_s1.json")))
+    m, w = g["mass_amu"], g["omega_per_fs"]
+    T, P, n = 100.0, 4, 600
+    systems = _systems(n, P, T, mass=m)
+    # w_P = 0.052/fs at P = 4, T = 100 K: dt = 0.25 fs keeps 2 w_P dt = 0.026
+    rp = ring.PrimitiveRingPolymers(systems, 0.25, 50.0, 1.0, 21, ring.harmonic_force_fn(systems, w))
+    rng = np.random.default_rng(11)
+    rp.set_state(rng.normal(0, 0.3, (n * P, 3)), rng.normal(0, 0.2, (n * P, 3)))
+    for _ in range(3000):
+        rp.step()
+    x2 = []
+    for t in range(6000):
+        rp.step()
+        if t % 10 == 0:
+            x2.append(np.mean(rp.q ** 2))
+    mean, err = _block_mean(x2)
+    want = qho.x2_beads_sum(m, w, T, P)
+    # velocity Verlet samples the harmonic ring with an O((w dt)^2) bias, ~1e-4 here
+    assert abs(mean - want) < 3.5 * err + 2e-3 * want
