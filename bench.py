@@ -235,7 +235,7 @@ def main():
                     help="energy model with adjoint forces, or the direct-force head")
     ap.add_argument("--gfn-width", type=int, default=16)
     ap.add_argument("--gfn-layers", type=int, default=2)
-    ap.add_argument("--transform", default="normal-modes", choices=["normal-modes", "staging"],
+    ap.add_argument("--transform", default="normal-modes", choices=["normal-modes", "staging", "primitive"],
                     help="ring-polymer coordinates of the integrator")
     ap.add_argument("--metad", action="store_true",
                     help="add the well-tempered metadynamics bias of the workload's study (s_dimer or XRD CV)")

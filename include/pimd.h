@@ -190,13 +190,19 @@ typedef struct {
  *   NORMAL_MODES  as above; the state momenta are Cartesian bead momenta.
  *   STAGING       u_1 = r_1, u_l = r_l - ((l-1) r_{l+1} + r_1)/l (l = 2..P,
  *                 r_{P+1} = r_1); springs sum_{l>=2} 1/2 m_l' w_P^2 u_l^2 with
- *                 m_l' = l m/(l-1); kinetic masses m for u_1 and m_l' for u_l,
- *                 so every u_l (l >= 2) turns at w_P in the exact A step;
- *                 friction 1/tau0 on u_1 and 2 pile_lambda w_P on the others.
- *                 The state momenta (pimd_set_state, pimd_get_state) are the
- *                 staging momenta, row of bead l - 1 holding the momentum of
- *                 u_l; K_beads and T_beads use the kinetic masses. */
-enum { PIMD_TRANSFORM_NORMAL_MODES = 0, PIMD_TRANSFORM_STAGING = 1 };
+ *                 m_l' = l m/(l-1); kinetic masses P m for u_1 and P m_l' for
+ *                 u_l (the staging masses of the V/P form, times P in this
+ *                 bead-potential form), so every u_l (l >= 2) turns at
+ *                 w_P/sqrt(P) in the exact A step; friction 1/tau0 on u_1 and
+ *                 2 pile_lambda w_P/sqrt(P) on the others.  The state momenta
+ *                 (pimd_set_state, pimd_get_state) are the staging momenta, row
+ *                 of bead l - 1 holding the momentum of u_l; K_beads and
+ *                 T_beads use the kinetic masses.
+ *   PRIMITIVE     Cartesian beads (Sec. 2.3 "primitive PIMD"): the springs are
+ *                 forces -m w_P^2 (2 q_k - q_{k+1} - q_{k-1}) added in both B
+ *                 steps, A is a free drift, O a friction 1/tau0 on every bead
+ *                 (velocity Verlet on H_P: keep 2 w_P dt well below 2). */
+enum { PIMD_TRANSFORM_NORMAL_MODES = 0, PIMD_TRANSFORM_STAGING = 1, PIMD_TRANSFORM_PRIMITIVE = 2 };
 
 typedef struct {
     int32_t n_systems;                 /* >= 1 */

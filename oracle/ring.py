@@ -186,11 +186,15 @@ class RingPolymers:
 # Chem. Phys. 99, 2796 (1993)).  With beads r_1..r_P (r_{P+1} = r_1):
 #   u_1 = r_1,   u_l = r_l - ((l - 1) r_{l+1} + r_1) / l   (l = 2..P),
 # the springs become sum_{l>=2} 1/2 m_l' w_P^2 u_l^2 with m_l' = l m / (l - 1).
-# Dynamics use kinetic masses m~_1 = m, m~_l = m_l' (every u_l, l >= 2, then
-# oscillates at w_P), the momenta p~_l conjugate to u_l are the state, and
-# the thermostat is a Langevin friction per staging coordinate: gamma_1 =
-# 1/tau0, gamma_l = 2 lambda w_P.  Arrays below are [P, ...] with index
-# k = l - 1.
+# Kinetic masses: those of staging dynamics in the primitive form (V/P at
+# beta: m~_1 = m, m~_l = m_l'), carried over to the bead-potential form used
+# here (V at beta/P), which multiplies every kinetic mass by P:
+# m~_1 = P m, m~_l = P m_l'.  Then u_1 carries the sum of the bead forces
+# with P times the mass (physical time scales), and every u_l (l >= 2)
+# oscillates at w_s = w_P / sqrt(P).  The momenta p~_l conjugate to u_l are
+# the state; the thermostat is a Langevin friction per staging coordinate,
+# gamma_1 = 1/tau0, gamma_l = 2 lambda w_s.  Arrays below are [P, ...] with
+# index k = l - 1.
 
 
 def staging_forward(r):
@@ -233,8 +237,14 @@ def staging_forces(F):
 
 
 def staging_mass_factors(P):
-    """m~_l / m: 1 for l = 1, l / (l - 1) otherwise."""
+    """m_l' / m of the staging springs: l / (l - 1) for l >= 2 (1 for l = 1,
+    which carries no spring)."""
     return np.array([1.0] + [(k + 1) / k for k in range(1, P)])
+
+
+def staging_kinetic_factors(P):
+    """m~_l / m = P m_l' / m (see above)."""
+    return P * staging_mass_factors(P)
 
 
 class StagingRingPolymers(RingPolymers):
@@ -245,9 +255,9 @@ class StagingRingPolymers(RingPolymers):
     def _o_step_staging(self, s, pt, xi):
         n, P, T, m = self.systems[s]
         _, wP = mode_frequencies(P, T)
-        mt = staging_mass_factors(P)[:, None] * m[None, :]
+        mt = staging_kinetic_factors(P)[:, None] * m[None, :]
         if self.tau0 > 0:
-            gamma = np.full(P, 2.0 * self.lam * wP)
+            gamma = np.full(P, 2.0 * self.lam * wP / np.sqrt(P))
             gamma[0] = 1.0 / self.tau0
         else:
             gamma = np.zeros(P)
@@ -265,15 +275,16 @@ class StagingRingPolymers(RingPolymers):
         for s in range(len(self.systems)):
             n, P, T, m = self.systems[s]
             _, wP = mode_frequencies(P, T)
-            mt = staging_mass_factors(P)[:, None] * m[None, :]
+            ws = wP / np.sqrt(P)
+            mt = staging_kinetic_factors(P)[:, None] * m[None, :]
             p, q, F = self._view(self.p, s), self._view(self.q, s), self._view(self.F, s)
             pt = self._o_step_staging(s, p.copy(), self._view(xi0, s))
             pt = pt + (self.dt / 2) * staging_forces(F) / MVV2E
             u = staging_forward(q)
-            u[0] = u[0] + self.dt * pt[0] / m[:, None]
+            u[0] = u[0] + self.dt * pt[0] / mt[0][:, None]
             if P > 1:
-                c, sn = np.cos(wP * self.dt), np.sin(wP * self.dt)
-                mw = mt[1:, :, None] * wP
+                c, sn = np.cos(ws * self.dt), np.sin(ws * self.dt)
+                mw = mt[1:, :, None] * ws
                 un = sn * pt[1:] / mw + c * u[1:]
                 pn = c * pt[1:] - mw * sn * u[1:]
                 u[1:], pt[1:] = un, pn
@@ -291,7 +302,7 @@ class StagingRingPolymers(RingPolymers):
         out = super().estimators()
         for s, o in enumerate(out):
             n, P, T, m = self.systems[s]
-            mt = staging_mass_factors(P)[:, None] * m[None, :]
+            mt = staging_kinetic_factors(P)[:, None] * m[None, :]
             p = self._view(self.p, s)
             k_beads = 0.5 * MVV2E * np.sum(p * p / mt[:, :, None])
             o["H_conserved"] += k_beads - o["K_beads"]

@@ -18,7 +18,7 @@ PIMD_OK, PIMD_E_ARG, PIMD_E_UNSUPPORTED, PIMD_E_DEVICE, PIMD_E_OOM, PIMD_E_CAPAC
 PIMD_PREC_FP32, PIMD_PREC_BF16_MLP, PIMD_PREC_BF16_PLAIN, PIMD_PREC_FP64_MLP = 0, 1, 2, 3
 PIMD_POT_BPNN, PIMD_POT_HARMONIC, PIMD_POT_GFN = 0, 1, 2
 PIMD_CV_DISTANCES, PIMD_CV_XRD = 1, 2
-PIMD_TRANSFORM_NORMAL_MODES, PIMD_TRANSFORM_STAGING = 0, 1
+PIMD_TRANSFORM_NORMAL_MODES, PIMD_TRANSFORM_STAGING, PIMD_TRANSFORM_PRIMITIVE = 0, 1, 2
 
 
 class pimd_bpnn_model(ctypes.Structure):

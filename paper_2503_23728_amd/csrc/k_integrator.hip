@@ -92,11 +92,21 @@ __device__ __forceinline__ double staging_r(const double *u, int j, int P)
     return u[0] + (double)j * a;
 }
 
+// Coordinates of the integrator: normal modes, staging, or primitive
+// (Cartesian beads, springs as forces: -m w_P^2 (2 q_k - q_{k+1} - q_{k-1})).
+enum { kNormalModes = 0, kStaging = 1, kPrimitive = 2 };
+
+__device__ __forceinline__ double spring_force(const double *q, int k, int P, double m_w2)
+{
+    return P == 1 ? 0.0 : -m_w2 * kMvv2e * (2.0 * q[k] - q[(k + 1) % P] - q[(k + P - 1) % P]);
+}
+
 // LDS (doubles): CT[P][P+1] | s0[256] | s1[256] | s2[256] | red[256]
-// (STAGING leaves CT unused: its transforms are the closed forms above.)
-template <bool PRE, bool STAGING>
+// (staging and primitive leave CT unused: their transforms are closed forms.)
+template <bool PRE, int XF>
 __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
 {
+    constexpr bool STAGING = XF == kStaging, PRIMITIVE = XF == kPrimitive, NM = XF == kNormalModes;
     extern __shared__ double ism[];
     const IntegUnit u = a.units[blockIdx.x];
     const SysInfo S = a.sys[u.sys];
@@ -107,7 +117,7 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
     double *s2 = s1 + 256;
     double *red = s2 + 256;
     const int tid = threadIdx.x;
-    if (!STAGING) {
+    if (NM) {
         for (int idx = tid; idx < P * P; idx += 256) {
             const int j = idx / P, k = idx - j * P;
             CT[k * (P + 1) + j] = a.cmat[S.cmat0 + idx];  // C[j][k]
@@ -124,7 +134,7 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
         m = (double)a.mass_atom[S.atom0 + atom];
         s0[tid] = (double)a.p[row * 3 + cc];
         s1[tid] = (double)a.F[row * 3 + cc];
-        if (PRE)
+        if (PRE || PRIMITIVE)
             s2[tid] = (double)a.q[row * 3 + cc];
     }
     __syncthreads();
@@ -143,6 +153,10 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
                 pt = sp[kk];                          // the state holds staging momenta
                 Ft = staging_force(sf, kk, P);
                 qt = staging_u(sq, kk, P);
+            } else if (PRIMITIVE) {
+                pt = sp[kk];
+                Ft = sf[kk] + spring_force(sq, kk, P, m * M.w * M.w);
+                qt = sq[kk];
             } else {
                 for (int j = 0; j < P; ++j) {
                     const double c = ct[j];
@@ -157,7 +171,7 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
             dke = 0.5 * (pn * pn - pt * pt) / mk * kMvv2e;
             pt = pn + kick * Ft;  // B(dt/2)
             // A(dt)
-            if (kk == 0) {
+            if (kk == 0 || PRIMITIVE) {
                 qt += (double)a.dt * pt / mk;
             } else {
                 const double mw = mk * M.w;
@@ -170,6 +184,8 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
             // B(dt/2), then O(dt/2) in modes
             if (STAGING) {
                 pt = sp[kk] + kick * staging_force(sf, kk, P);
+            } else if (PRIMITIVE) {
+                pt = sp[kk] + kick * (sf[kk] + spring_force(sq, kk, P, m * M.w * M.w));
             } else {
                 for (int j = 0; j < P; ++j)
                     pt += ct[j] * (sp[j] + kick * sf[j]);
@@ -194,6 +210,9 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
             pj = pt;
             if (PRE)
                 qj = staging_r(sq, kk, P);
+        } else if (PRIMITIVE) {
+            pj = pt;
+            qj = qt;
         } else {
             // back to beads: x_j = sum_k C[j][k] x~_k, with j = kk
             for (int k = 0; k < P; ++k) {
@@ -347,33 +366,38 @@ hipError_t configure_integrator_lds(int max_P)
 {
     const int b = (int)integ_lds(max_P);
     hipError_t e = hipSuccess;
-    for (const void *f : {(const void *)k_integrate<true, false>, (const void *)k_integrate<false, false>,
-                          (const void *)k_integrate<true, true>, (const void *)k_integrate<false, true>})
+    for (const void *f : {(const void *)k_integrate<true, kNormalModes>, (const void *)k_integrate<false, kNormalModes>,
+                          (const void *)k_integrate<true, kStaging>, (const void *)k_integrate<false, kStaging>,
+                          (const void *)k_integrate<true, kPrimitive>, (const void *)k_integrate<false, kPrimitive>})
         if (e == hipSuccess)
             e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     return e;
 }
 
-void launch_integrate_pre(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi,
-                          int max_P, bool staging, hipStream_t s)
+template <bool PRE>
+static void launch_integrate(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi,
+                             int max_P, int transform, hipStream_t s)
 {
-    if (staging)
-        hipLaunchKernelGGL((k_integrate<true, true>), dim3(z.n_units), dim3(256), integ_lds(max_P), s,
-                           integ_args(d, z, dt, k0, k1, xi));
+    const IntegArgs args = integ_args(d, z, dt, k0, k1, xi);
+    const size_t lds = integ_lds(max_P);
+    if (transform == kStaging)
+        hipLaunchKernelGGL((k_integrate<PRE, kStaging>), dim3(z.n_units), dim3(256), lds, s, args);
+    else if (transform == kPrimitive)
+        hipLaunchKernelGGL((k_integrate<PRE, kPrimitive>), dim3(z.n_units), dim3(256), lds, s, args);
     else
-        hipLaunchKernelGGL((k_integrate<true, false>), dim3(z.n_units), dim3(256), integ_lds(max_P), s,
-                           integ_args(d, z, dt, k0, k1, xi));
+        hipLaunchKernelGGL((k_integrate<PRE, kNormalModes>), dim3(z.n_units), dim3(256), lds, s, args);
+}
+
+void launch_integrate_pre(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi,
+                          int max_P, int transform, hipStream_t s)
+{
+    launch_integrate<true>(d, z, dt, k0, k1, xi, max_P, transform, s);
 }
 
 void launch_integrate_post(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi,
-                           int max_P, bool staging, hipStream_t s)
+                           int max_P, int transform, hipStream_t s)
 {
-    if (staging)
-        hipLaunchKernelGGL((k_integrate<false, true>), dim3(z.n_units), dim3(256), integ_lds(max_P), s,
-                           integ_args(d, z, dt, k0, k1, xi));
-    else
-        hipLaunchKernelGGL((k_integrate<false, false>), dim3(z.n_units), dim3(256), integ_lds(max_P), s,
-                           integ_args(d, z, dt, k0, k1, xi));
+    launch_integrate<false>(d, z, dt, k0, k1, xi, max_P, transform, s);
 }
 
 void launch_finish_step(const DevBuffers &d, const Sizes &z, hipStream_t s)

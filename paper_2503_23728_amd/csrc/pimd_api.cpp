@@ -106,7 +106,8 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
         return fail(err, PIMD_E_ARG, "unknown precision");
     if (cfg->potential != PIMD_POT_BPNN && cfg->potential != PIMD_POT_HARMONIC && cfg->potential != PIMD_POT_GFN)
         return fail(err, PIMD_E_ARG, "unknown potential");
-    if (cfg->transform != PIMD_TRANSFORM_NORMAL_MODES && cfg->transform != PIMD_TRANSFORM_STAGING)
+    if (cfg->transform != PIMD_TRANSFORM_NORMAL_MODES && cfg->transform != PIMD_TRANSFORM_STAGING &&
+        cfg->transform != PIMD_TRANSFORM_PRIMITIVE)
         return fail(err, PIMD_E_ARG, "unknown ring-polymer transform");
     if (cfg->max_neighbors < 0 || cfg->max_neighbors > kMaxNeighbors)
         return fail(err, PIMD_E_UNSUPPORTED, "max_neighbors must be in [0, 256]");
@@ -446,7 +447,7 @@ struct pimd_ctx {
     int64_t host_step = 0;
     int host_hills = 0;
     bool deposit_now = false;
-    bool staging = false;          // ring polymers propagated in staging coordinates
+    int transform = PIMD_TRANSFORM_NORMAL_MODES;   // coordinates of the integrator
     int device = 0;
     std::string err;
 };
@@ -563,7 +564,7 @@ pimd_status run_step(pimd_ctx *c, hipStream_t s, const float *xi)
     c->stream = s;
     if (c->stage_ev)
         (void)hipEventRecord(c->stage_ev[0], s);
-    launch_integrate_pre(c->d, c->z, (float)c->dt, k0, k1, xi, c->pl.max_P, c->staging, s);
+    launch_integrate_pre(c->d, c->z, (float)c->dt, k0, k1, xi, c->pl.max_P, c->transform, s);
     if (c->stage_ev)
         (void)hipEventRecord(c->stage_ev[1], s);
     c->deposit_now = true;
@@ -571,7 +572,7 @@ pimd_status run_step(pimd_ctx *c, hipStream_t s, const float *xi)
     c->deposit_now = false;
     if (c->pl.metad)
         launch_metad_advance(c->d, c->mp, s);
-    launch_integrate_post(c->d, c->z, (float)c->dt, k0, k1, xi, c->pl.max_P, c->staging, s);
+    launch_integrate_post(c->d, c->z, (float)c->dt, k0, k1, xi, c->pl.max_P, c->transform, s);
     launch_finish_step(c->d, c->z, s);
     if (c->stage_ev)
         (void)hipEventRecord(c->stage_ev[7], s);
@@ -682,7 +683,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     c->precision = cfg->precision;
     c->potential = cfg->potential;
     c->omega = cfg->harmonic_omega_per_fs;
-    c->staging = cfg->transform == PIMD_TRANSFORM_STAGING;
+    c->transform = cfg->transform;
     const pimd_bpnn_model *m = cfg->model;
     const ModelView mv = model_view(cfg);
     c->masses_el.assign(mv.mass, mv.mass + mv.n_el);
@@ -811,11 +812,18 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         const double wP = P * kKB * T / kHbar;
         for (int k = 0; k < P; ++k) {
             // normal mode k: w_k = 2 w_P sin(k pi / P), physical mass; staging
-            // coordinate k + 1: w_P for k >= 1 with kinetic mass (k + 1)/k m
-            const double w = c->staging ? (k == 0 ? 0.0 : wP) : 2.0 * wP * std::sin(k * kPi / P);
+            // coordinate k + 1: kinetic mass P m for k = 0 and P (k + 1)/k m
+            // otherwise, so u_{k+1} turns at w_P / sqrt(P) under its spring
+            // (k + 1)/k m w_P^2; primitive bead k: w = w_P (the spring
+            // constant), friction 1/tau0
+            const bool staging = c->transform == PIMD_TRANSFORM_STAGING;
+            const bool primitive = c->transform == PIMD_TRANSFORM_PRIMITIVE;
+            const double w = primitive ? (P > 1 ? wP : 0.0)
+                             : staging ? (k == 0 ? 0.0 : wP / std::sqrt((double)P))
+                                       : 2.0 * wP * std::sin(k * kPi / P);
             double gamma = 0.0;
             if (c->tau0 > 0.0)
-                gamma = k == 0 ? 1.0 / c->tau0 : 2.0 * c->lam * w;
+                gamma = (k == 0 || primitive) ? 1.0 / c->tau0 : 2.0 * c->lam * w;
             const double c1 = std::exp(-0.5 * gamma * c->dt);
             ModeInfo mi{};
             mi.c1 = c1;
@@ -823,7 +831,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
             mi.cw = std::cos(w * c->dt);
             mi.sw = std::sin(w * c->dt);
             mi.w = w;
-            mi.mfac = c->staging && k > 0 ? (double)(k + 1) / (double)k : 1.0;
+            mi.mfac = staging ? (double)P * (k > 0 ? (double)(k + 1) / (double)k : 1.0) : 1.0;
             modes.push_back(mi);
         }
         for (int k = 0; k < P; ++k) {

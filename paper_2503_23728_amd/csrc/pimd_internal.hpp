@@ -107,7 +107,7 @@ struct ModeInfo {
     double c1, c2;      // O step: exp(-gamma dt/2), sqrt(1 - c1^2)
     double cw, sw;      // cos(w dt), sin(w dt)
     double w;           // mode frequency (1/fs)
-    double mfac;        // kinetic mass / physical mass: 1 for normal modes, l/(l-1) for staging coordinate l >= 2
+    double mfac;        // kinetic mass / physical mass: 1 (normal modes, beads); staging: P, P l/(l-1) for l >= 2
     double pad[2];
 };
 
@@ -245,11 +245,12 @@ void launch_bead_sums(const DevBuffers &d, const Sizes &z, float *E_bead, float 
                       hipStream_t s);
 void launch_harmonic(const float *q, const DevBuffers &d, const Sizes &z, float k_over_m,
                      float *F, hipStream_t s);
-// staging: propagate in staging coordinates (momenta state = staging momenta)
+// transform: 0 normal modes, 1 staging (momenta state = staging momenta),
+// 2 primitive (Cartesian beads, springs as forces)
 void launch_integrate_pre(const DevBuffers &d, const Sizes &z, float dt, uint32_t key0, uint32_t key1,
-                          const float *xi, int max_P, bool staging, hipStream_t s);
+                          const float *xi, int max_P, int transform, hipStream_t s);
 void launch_integrate_post(const DevBuffers &d, const Sizes &z, float dt, uint32_t key0, uint32_t key1,
-                           const float *xi, int max_P, bool staging, hipStream_t s);
+                           const float *xi, int max_P, int transform, hipStream_t s);
 void launch_finish_step(const DevBuffers &d, const Sizes &z, hipStream_t s);
 void launch_estimator_terms(const DevBuffers &d, const Sizes &z, hipStream_t s);
 void launch_philox_words(uint32_t key0, uint32_t key1, int64_t step, int half, int64_t n, uint32_t *out,

@@ -148,7 +148,8 @@ def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", p
     cfg.harmonic_omega_per_fs = omega
     cfg.max_neighbors = max_neighbors
     cfg.metad = ctypes.pointer(make_metad(metad, keep)) if metad is not None else None
-    cfg.transform = {"normal-modes": abi.PIMD_TRANSFORM_NORMAL_MODES, "staging": abi.PIMD_TRANSFORM_STAGING}[transform]
+    cfg.transform = {"normal-modes": abi.PIMD_TRANSFORM_NORMAL_MODES, "staging": abi.PIMD_TRANSFORM_STAGING,
+                     "primitive": abi.PIMD_TRANSFORM_PRIMITIVE}[transform]
     return cfg, keep
 
 

@@ -1,8 +1,9 @@
-"""GPU parity of the staging-coordinate integrator (Sec. 2.1 names the
-staging transformation beside normal modes) against the oracle's
-StagingRingPolymers: one step with injected noise, graph-replayed steps with
-Philox noise, estimators with the staging kinetic masses, and the exact
-finite-P harmonic average sampled on the GPU."""
+"""GPU parity of the two other ring-polymer integrators against the oracle:
+staging coordinates (Sec. 2.1 names the staging transformation beside normal
+modes; oracle StagingRingPolymers) and primitive Cartesian beads with the
+springs as forces (Sec. 2.3; oracle PrimitiveRingPolymers).  One step with
+injected noise, graph-replayed steps with Philox noise, estimators, and the
+exact finite-P harmonic average sampled on the GPU."""
 import sys
 
 import numpy as np
@@ -23,18 +24,21 @@ def say(*a):
     sys.stdout.flush()
 
 
-def _engine(wl, **kw):
+ORACLES = {"staging": ring.StagingRingPolymers, "primitive": ring.PrimitiveRingPolymers}
+
+
+def _engine(wl, transform, **kw):
     from paper_2503_23728_amd.pimd import Pimd
-    return Pimd.from_workload(wl, device="cuda:0", transform="staging", **kw)
+    return Pimd.from_workload(wl, device="cuda:0", transform=transform, **kw)
 
 
-def _oracle(wl, q0, p0):
+def _oracle(wl, q0, p0, transform):
     systems = [(s.n_atoms, s.n_beads, s.temperature, wl.model.masses[s.species]) for s in wl.systems]
 
     def fn(q):
         E, F, _ = bpnn.energy_forces(wl, np.asarray(q, np.float32))
         return E, F
-    rp = ring.StagingRingPolymers(systems, wl.dt, wl.tau0, wl.pile_lambda, wl.philox_seed, fn)
+    rp = ORACLES[transform](systems, wl.dt, wl.tau0, wl.pile_lambda, wl.philox_seed, fn)
     rp.set_state(q0.astype(np.float64), p0.astype(np.float64))
     return rp
 
@@ -55,11 +59,12 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("transform", list(ORACLES))
 @pytest.mark.parametrize("name", list(CASES))
-def test_one_staging_step_with_injected_noise_matches_oracle(name):
+def test_one_step_with_injected_noise_matches_oracle(name, transform):
     wl = CASES[name]()
-    say(f"staging step {name}")
-    eng = _engine(wl, precision="fp64-mlp")
+    say(f"{transform} step {name}")
+    eng = _engine(wl, transform, precision="fp64-mlp")
     q0 = S.perturbed_beads(wl, 0.03, seed=31)
     _, p0 = S.initial_state(wl)
     xi = np.random.default_rng(32).normal(size=(2, len(q0), 3)).astype(np.float32)
@@ -67,7 +72,7 @@ def test_one_staging_step_with_injected_noise_matches_oracle(name):
     eng.inject_noise(torch.from_numpy(xi).cuda())
     eng.step(1)
     q, p, _, step = eng.get_state()
-    rp = _oracle(wl, q0, p0)
+    rp = _oracle(wl, q0, p0, transform)
     rp.step(noise=xi.astype(np.float64))
     dq = np.max(np.abs(q.cpu().numpy() - rp.q)) / np.max(np.abs(rp.q))
     dp = rel_max(p.cpu().numpy(), rp.p)
@@ -78,13 +83,14 @@ def test_one_staging_step_with_injected_noise_matches_oracle(name):
             assert a[k] == pytest.approx(b[k], rel=1e-4, abs=1e-6), k
 
 
-def test_staging_graph_steps_follow_oracle_with_philox_noise():
+@pytest.mark.parametrize("transform", list(ORACLES))
+def test_graph_steps_follow_oracle_with_philox_noise(transform):
     wl = CASES["fad-P4"]()
-    say("staging graph steps")
-    eng = _engine(wl)
+    say(f"{transform} graph steps")
+    eng = _engine(wl, transform)
     q0, p0 = S.initial_state(wl)
     eng.set_state(torch.from_numpy(q0).cuda(), torch.from_numpy(p0).cuda(), step=0)
-    rp = _oracle(wl, q0, p0)
+    rp = _oracle(wl, q0, p0, transform)
     for _ in range(5):
         eng.step(1)
         rp.step()
@@ -96,13 +102,15 @@ def test_staging_graph_steps_follow_oracle_with_philox_noise():
         assert eng.estimators()[0][k] == pytest.approx(rp.estimators()[0][k], rel=1e-4, abs=1e-5), k
 
 
-def test_staging_differs_from_normal_modes_but_samples_the_same_oscillator():
+@pytest.mark.parametrize("transform", list(ORACLES))
+def test_samples_the_exact_finite_P_oscillator(transform):
     from paper_2503_23728_amd.pimd import Pimd
     m, w, T, P, n = 1.008, 0.01244, 100.0, 8, 2048
-    say("staging QHO")
+    say(f"{transform} QHO")
     sys_ = S.System(n, P, T, np.zeros(3), np.zeros(n, np.int32), np.zeros((n, 3)))
+    # primitive: 2 w_P dt = 0.105 at dt = 0.5 fs (P = 8, 100 K); the velocity-Verlet bias is ~1e-3
     eng = Pimd([sys_], None, 0.5, 100.0, 1.0, 33, potential="harmonic", omega=w, masses=np.array([m]),
-               device="cuda:0", transform="staging")
+               device="cuda:0", transform=transform)
     rng = np.random.default_rng(P)
     q0 = rng.normal(0, 0.3, (n * P, 3)).astype(np.float32)
     eng.set_state(torch.from_numpy(q0).cuda(), torch.zeros(n * P, 3).cuda())
