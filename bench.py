@@ -254,8 +254,7 @@ def main():
     wl = S.gfn_workload(args.config, args.gfn_width, args.gfn_layers) if gfn_mode else S.workload(args.config)
     B = wl.bead_atoms
     spec = S.metad_spec(wl, max_hills=4096) if args.metad else None
-    eng = Pimd.from_workload(wl, precision="fp32" if gfn_mode else args.precision, device=device, metad=spec,
-                             transform=args.transform)
+    eng = Pimd.from_workload(wl, precision=args.precision, device=device, metad=spec, transform=args.transform)
     q, p = S.initial_state(wl)
     eng.set_state(torch.from_numpy(q).to(device), torch.from_numpy(p).to(device))
     if args.no_tune:
@@ -322,12 +321,12 @@ def main():
         "value": value, "unit": "bead-atom force evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if gfn_mode else {"fp32": "f32", "bf16": "f32 (MLP GEMM operands bf16 x3 split)",
-                                         "bf16-plain": "f32 (MLP GEMM operands bf16)"}[args.precision],
+        "dtype": {"fp32": "f32", "bf16": "f32 (MLP GEMM operands bf16 x3 split)",
+                  "bf16-plain": "f32 (MLP GEMM operands bf16)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": wl.name, "systems": len(wl.systems), "bead_atoms": B,
                    "beads": sum(s.n_beads for s in wl.systems), "dt_fs": wl.dt,
-                   "precision": "fp32" if gfn_mode else args.precision, "potential": args.potential,
+                   "precision": args.precision, "potential": args.potential,
                    "transform": args.transform,
                    "launch": "hip graph per step" + (", 25-step blocks from the initial state" if gfn_mode else ""),
                    "launch_shape": shape,

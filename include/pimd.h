@@ -220,7 +220,9 @@ typedef struct {
     const pimd_bpnn_model *model;      /* PIMD_POT_BPNN: the model; HARMONIC: masses only */
     double harmonic_omega_per_fs;      /* PIMD_POT_HARMONIC: V = sum 1/2 m w^2 |q|^2 */
     int32_t max_neighbors;             /* neighbour slots per atom: 0 => 128; a multiple of 16, <= 256 */
-    const pimd_gfn_model *gfn;         /* PIMD_POT_GFN: the direct-force head (precision is ignored: FP32) */
+    const pimd_gfn_model *gfn;         /* PIMD_POT_GFN: the direct-force head; FP32 and FP64_MLP run its
+                                          per-edge products on the float32 vector ALU, BF16_MLP and
+                                          BF16_PLAIN on BF16 MFMA (split or single operands) */
     const pimd_metad *metad;           /* well-tempered metadynamics bias, or NULL for none */
     int32_t transform;                 /* PIMD_TRANSFORM_* (0: normal modes) */
 } pimd_config;

@@ -42,6 +42,7 @@ struct Plan {
     bool nl = false;                           // neighbour lists (the energy model or the direct-force head)
     int gfn_H = 0, gfn_L = 0;
     size_t gfn_floats = 0;                     // packed weights of the direct-force head
+    size_t gfn_tiles = 0;                      // bfloat16 16 x 16 weight tiles of its MFMA path
     std::vector<int> cells_per_sys;            // cells per bead of each system
     std::vector<std::array<int, 3>> nc;
     size_t mlp_f32_floats = 0, mlp_bf16_elems = 0, mlp_f64_elems = 0, cmat_elems = 0, modes = 0;
@@ -147,6 +148,10 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
         pl.gfn_H = g->width;
         pl.gfn_L = g->n_layers;
         const size_t H = g->width, ne = g->n_elements;
+        {
+            const size_t HB = H / 16, RB = (g->n_rad + 15) / 16;
+            pl.gfn_tiles = HB * RB + (size_t)g->n_layers * 4 * HB * HB + HB * HB;
+        }
         pl.gfn_floats = ne * H + ne * ne * H + H * g->n_rad +
                         (size_t)g->n_layers * ((H * H + 2 * H + H * H) + (2 * H * H + 2 * H + H * H) +
                                                (H * H + 2 * H + H * H)) +
@@ -343,6 +348,7 @@ Layout make_layout(const Plan &pl)
     if (pl.gfn) {
         L.add("gfn_params", pl.gfn_floats * 4);
         L.add("gfn_nodes", (size_t)(pl.gfn_L + 1) * B * pl.gfn_H * 4);
+        L.add("gfn_tiles", pl.gfn_tiles * kWave * 8 * 2);
     }
     if (pl.bpnn) {
         L.add("xhat", B * D * 4);
@@ -718,6 +724,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     d.nbr_fence = (int32_t *)at("nbr_fence");
     d.gfn_params = (float *)at("gfn_params");
     d.gfn_nodes = (float *)at("gfn_nodes");
+    d.gfn_tiles = (uint16_t *)at("gfn_tiles");
     d.xhat = (float *)at("xhat");
     d.dEdG = (float *)at("dEdG");
     d.vslot = (float4 *)at("vslot");
@@ -931,6 +938,42 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         gp.fw2 = take(H);
         gp.fb2 = g->params[o];
         (void)take(1);
+        // MFMA path (BF16 precisions): bfloat16 tiles of the per-edge matrices in
+        // A-operand order -- tile (ob, kb), lane (lr, lg): W[16 ob + lr][16 kb + 4 lg + q],
+        // q = 0..3, as 4 hi parts then 4 lo parts (lo = bf16(w - hi))
+        gp.mode = cfg->precision == PIMD_PREC_BF16_MLP ? 1 : cfg->precision == PIMD_PREC_BF16_PLAIN ? 2 : 0;
+        std::vector<uint16_t> tiles;
+        auto pack = [&](const float *Wdev, int rows, int cols) -> const uint16_t * {
+            const float *W = g->params + (Wdev - p0);     // the same weights on the host
+            const size_t first = tiles.size() / (kWave * 8);
+            for (int ob = 0; ob < (rows + 15) / 16; ++ob)
+                for (int kb = 0; kb < (cols + 15) / 16; ++kb)
+                    for (int lane = 0; lane < kWave; ++lane) {
+                        const int rr = 16 * ob + (lane & 15);
+                        uint16_t hi[4], lo[4];
+                        for (int q = 0; q < 4; ++q) {
+                            const int cc = 16 * kb + 4 * (lane >> 4) + q;
+                            const float w = rr < rows && cc < cols ? W[(size_t)rr * cols + cc] : 0.0f;
+                            hi[q] = bf16_bits(w);
+                            uint32_t u = (uint32_t)hi[q] << 16;
+                            float h;
+                            std::memcpy(&h, &u, 4);
+                            lo[q] = bf16_bits(w - h);
+                        }
+                        tiles.insert(tiles.end(), hi, hi + 4);
+                        tiles.insert(tiles.end(), lo, lo + 4);
+                    }
+            return d.gfn_tiles + first * kWave * 8;
+        };
+        gp.t_in = pack(gp.edge_in, H, g->n_rad);
+        for (int l = 0; l < g->n_layers; ++l) {
+            gp.t_msg1[l] = pack(gp.msg[l].W1, H, H);
+            gp.t_msg2[l] = pack(gp.msg[l].W2, H, H);
+            gp.t_edge1[l] = pack(gp.edge[l].W1, H, H);
+            gp.t_edge2[l] = pack(gp.edge[l].W2, H, H);
+        }
+        gp.t_f1 = pack(gp.fW1, H, H);
+        push(d.gfn_tiles, tiles.data(), tiles.size() * 2);
     }
     if (pl.bpnn) {
         DescParams &dp = c->dp;

@@ -125,6 +125,14 @@ struct GfnParams {
     const float *fW1, *fb1, *fw2;
     float fb2;
     int32_t H, L;
+    // MFMA path: 0 off (float32 vector ALU), 1 BF16 operands split hi + lo
+    // (three products), 2 BF16 operands rounded once; bfloat16 weight tiles in
+    // A-operand order (16 x 16 blocks, 64 lanes x (4 hi, 4 lo) each)
+    int32_t mode;
+    const uint16_t *t_in;                       // edge_in [H][n_rad]
+    const uint16_t *t_msg1[3], *t_msg2[3];      // phi_msg W1, W2 per layer
+    const uint16_t *t_edge1[3], *t_edge2[3];    // phi_edge W1, W2 per layer
+    const uint16_t *t_f1;                       // readout W1
 };
 
 // Well-tempered metadynamics on bead CVs, passed by value to its kernels.
@@ -178,6 +186,7 @@ struct DevBuffers {
     float *norm;                   // [n_el][2][D] shift, 1/scale
     float *gfn_params;             // direct-force head: packed weights
     float *gfn_nodes;              // direct-force head: node states n^(0..L) [L+1][B][H]
+    uint16_t *gfn_tiles;           // direct-force head: bfloat16 weight tiles of the MFMA path
     // metadynamics
     double2 *hills;                // [beads][max_hills] (center, height)
     int32_t *n_hills;              // hills deposited per bead (one counter: all beads deposit together)
