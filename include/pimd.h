@@ -365,17 +365,22 @@ pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled);
  *                 (default 4)
  *   centre_grid   0 (default): one wave per centre atom; > 0: at most this
  *                 many workgroups, whose waves stride over the centres
- *   mlp_rows      rows per MLP workgroup tile: 16 (default), 32 or 64;
- *                 PIMD_PREC_FP64_MLP takes 16 only
+ *   mlp_rows      rows per MLP workgroup tile: 16, 32 or 64 (default 32
+ *                 with a BF16 MLP, else 16); PIMD_PREC_FP64_MLP takes 16 only
  *   neighbor_cells  periodic neighbour search: 0 = one wave per centre
  *                 gathering its stencil from global memory, 1 = one workgroup
  *                 per cell with the stencil staged in LDS once for all of the
- *                 cell's centres (default 1 from 4096 cells on, else 0) */
+ *                 cell's centres (default 1 from 4096 cells on, else 0)
+ *   mlp_waves     waves per workgroup of the BF16 MLP: 4 (two 16-column
+ *                 tiles of every layer each) or 8 (default; one each, so each
+ *                 row tile's chain of MFMAs is half as long); the FP32 and
+ *                 FP64 MLPs ignore it */
 typedef struct {
     int32_t centre_waves;
     int32_t centre_grid;
     int32_t mlp_rows;
     int32_t neighbor_cells;
+    int32_t mlp_waves;
 } pimd_tuning;
 
 pimd_status pimd_get_tuning(const pimd_ctx *ctx, pimd_tuning *out);
@@ -391,7 +396,8 @@ pimd_status pimd_set_tuning(pimd_ctx *ctx, const pimd_tuning *t);
  * stream) for every centre_waves x centre_grid candidate (centre_grid from 0
  * and 2, 4, 8, 16 workgroups per compute unit), then for every mlp_rows
  * candidate with the best centre shape, then for the other neighbor_cells
- * value (systems with a box); applies the fastest (a candidate
+ * value (systems with a box), then for the other mlp_waves (BF16 MLP); applies
+ * the fastest (a candidate
  * replaces the current best only when at least 1% faster) and writes it to
  * best (may be NULL).  The state does not advance; the forces left behind are
  * those of the current positions.  Needs pimd_set_state first

@@ -259,20 +259,22 @@ __device__ __forceinline__ void store_bf16(uint16_t *hi, uint16_t *lo, int idx, 
         lo[idx] = to_bf16(v - bf16_value(h));
 }
 
-// acc[r][t] = A[16 r .. 16 r + 15][K] * B[K][16 ct ...] (ct = w + 4t < nct),
-// B[k][n] = Bt[n][k] with Bt row-major [N][ldb] in bfloat16 parts.
-template <int MODE, int RT>
+// acc[r][t] = A[16 r .. 16 r + 15][K] * B[K][16 ct ...] (ct = w + NW t < nct),
+// B[k][n] = Bt[n][k] with Bt row-major [N][ldb] in bfloat16 parts; NW waves
+// share the (at most 8) column tiles of a layer, CT = 8 / NW each.
+template <int MODE, int RT, int NW>
 __device__ __forceinline__ void gemm_bf16(const uint16_t *ahi, const uint16_t *alo, int K, const uint16_t *Bh,
-                                          const uint16_t *Bl, int ldb, int nct, int w, f32x4 (&acc)[RT][2])
+                                          const uint16_t *Bl, int ldb, int nct, int w, f32x4 (&acc)[RT][8 / NW])
 {
     constexpr int SB = kBfStride;
+    constexpr int CT = 8 / NW;
     const int lane = lane_id();
     const int lr = lane & 15, lg = lane >> 4;
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
-        acc[r][0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        acc[r][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    }
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int t = 0; t < CT; ++t)
+            acc[r][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     int k0 = 0;
     for (; k0 + 32 <= K; k0 += 32) {
         i16x8 ah[RT], al[RT];
@@ -284,8 +286,8 @@ __device__ __forceinline__ void gemm_bf16(const uint16_t *ahi, const uint16_t *a
                 al[r] = *reinterpret_cast<const i16x8 *>(alo + o);
         }
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int ct = w + 4 * t;
+        for (int t = 0; t < CT; ++t) {
+            const int ct = w + NW * t;
             if (ct < nct) {
                 const int64_t o = (int64_t)(ct * 16 + lr) * ldb + k0 + 8 * lg;
                 const i16x8 bh = *reinterpret_cast<const i16x8 *>(Bh + o);
@@ -313,8 +315,8 @@ __device__ __forceinline__ void gemm_bf16(const uint16_t *ahi, const uint16_t *a
                 al[r] = *reinterpret_cast<const i16x4 *>(alo + o);
         }
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int ct = w + 4 * t;
+        for (int t = 0; t < CT; ++t) {
+            const int ct = w + NW * t;
             if (ct < nct) {
                 const int64_t o = (int64_t)(ct * 16 + lr) * ldb + k0 + 4 * lg;
                 const i16x4 bh = *reinterpret_cast<const i16x4 *>(Bh + o);
@@ -336,8 +338,8 @@ __device__ __forceinline__ void gemm_bf16(const uint16_t *ahi, const uint16_t *a
 
 // One workgroup per tile of 16 RT rows of one element, as k_mlp; the energy
 // readout is taken from the last layer's FP32 tanh values in registers.
-template <int MODE, int RT>
-__global__ __launch_bounds__(256) void k_mlp_bf16(const int32_t *__restrict__ rows,
+template <int MODE, int RT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_mlp_bf16(const int32_t *__restrict__ rows,
                                                   const MlpTile *__restrict__ tiles,
                                                   const float *__restrict__ xhat, int D, int Dp, MlpNets nets,
                                                   float *__restrict__ E_atom, float *__restrict__ dEdG)
@@ -346,7 +348,11 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const int32_t *__restrict__ ro
     constexpr int MT = 16 * RT;
     __shared__ __attribute__((aligned(16))) uint16_t ahi[MT * SB];
     __shared__ __attribute__((aligned(16))) uint16_t alo[MODE == 1 ? MT * SB : 8];
+    constexpr int CT = 8 / NW;
     __shared__ float epart[4][MT];
+    // NW = 8: the second half of the waves hands its per-lane readout partials
+    // to the first half, so the sums keep the order of the four-wave layout
+    __shared__ float ehand[NW == 8 ? 4 * 64 * 4 * RT : 1];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int lr = lane & 15, lg = lane >> 4;
     const MlpTile tile = tiles[blockIdx.x];
@@ -354,14 +360,14 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const int32_t *__restrict__ ro
     const int32_t *trows = rows + tile.row0;
     const int nrows = tile.nrows;
 
-    for (int idx = threadIdx.x; idx < MT * Dp; idx += 256) {
+    for (int idx = threadIdx.x; idx < MT * Dp; idx += 64 * NW) {
         const int r = idx / Dp, c = idx - r * Dp;
         store_bf16<MODE>(ahi, alo, r * SB + c, (r < nrows && c < D) ? xhat[(int64_t)trows[r] * D + c] : 0.0f);
     }
     __syncthreads();
 
-    f32x4 dsave[3][RT][2];
-    f32x4 acc[RT][2];
+    f32x4 dsave[3][RT][CT];
+    f32x4 acc[RT][CT];
     float e_part[RT][4];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
@@ -374,11 +380,11 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const int32_t *__restrict__ ro
     for (int l = 0; l < 3; ++l) {
         if (l < nh) {
             const MlpLayer L = net.layer[l];
-            gemm_bf16<MODE, RT>(ahi, alo, K, L.Wb, L.Wb_lo, L.in_pad, L.out / 16, w, acc);
+            gemm_bf16<MODE, RT, NW>(ahi, alo, K, L.Wb, L.Wb_lo, L.in_pad, L.out / 16, w, acc);
             __syncthreads();
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int ct = w + 4 * t;
+            for (int t = 0; t < CT; ++t) {
+                const int ct = w + NW * t;
                 if (ct < L.out / 16) {
                     const int col = ct * 16 + lr;
                     const float bias = L.b[col];
@@ -405,13 +411,29 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const int32_t *__restrict__ ro
             K = L.out;
         }
     }
-    // energy readout: the column slices of the four waves
+    // energy readout: the column slices of the four waves (tiles w and w + 4
+    // of wave w, as one wave holds them when NW = 4)
+    if (NW == 8) {
+        if (w >= 4)
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    ehand[(((w - 4) * RT + r) * 4 + q) * 64 + lane] = e_part[r][q];
+        __syncthreads();
+        if (w < 4)
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    e_part[r][q] += ehand[((w * RT + r) * 4 + q) * 64 + lane];
+    }
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             e_part[r][q] = row16_sum(e_part[r][q]);
-    if (lr == 0)
+    if (lr == 0 && w < 4)
 #pragma unroll
         for (int r = 0; r < RT; ++r)
 #pragma unroll
@@ -423,8 +445,8 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const int32_t *__restrict__ ro
     for (int l = 2; l >= 0; --l) {
         if (l == nh - 1) {
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int ct = w + 4 * t;
+            for (int t = 0; t < CT; ++t) {
+                const int ct = w + NW * t;
                 if (ct < nlast) {
                     const int col = ct * 16 + lr;
                     const float wo = net.wo[col];
@@ -446,11 +468,11 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const int32_t *__restrict__ ro
     for (int l = 2; l >= 1; --l) {
         if (l < nh) {
             const MlpLayer L = net.layer[l];
-            gemm_bf16<MODE, RT>(ahi, alo, L.out, L.WTb, L.WTb_lo, L.out, L.in_pad / 16, w, acc);
+            gemm_bf16<MODE, RT, NW>(ahi, alo, L.out, L.WTb, L.WTb_lo, L.out, L.in_pad / 16, w, acc);
             __syncthreads();
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int ct = w + 4 * t;
+            for (int t = 0; t < CT; ++t) {
+                const int ct = w + NW * t;
                 if (ct < L.in_pad / 16) {
                     const int col = ct * 16 + lr;
 #pragma unroll
@@ -466,10 +488,10 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const int32_t *__restrict__ ro
     }
     // dE/dx = W_1^T g_1 and dE/dG = dE/dx / scale
     const MlpLayer L0 = net.layer[0];
-    gemm_bf16<MODE, RT>(ahi, alo, L0.out, L0.WTb, L0.WTb_lo, L0.out, Dp / 16, w, acc);
+    gemm_bf16<MODE, RT, NW>(ahi, alo, L0.out, L0.WTb, L0.WTb_lo, L0.out, Dp / 16, w, acc);
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int ct = w + 4 * t;
+    for (int t = 0; t < CT; ++t) {
+        const int ct = w + NW * t;
         if (ct < Dp / 16) {
             const int col = ct * 16 + lr;
             if (col < D) {
@@ -659,33 +681,37 @@ static void launch_mlp_fp32(const DevBuffers &d, const MlpNets &nets, int n_tile
                            nets, d.E_atom, d.dEdG);
 }
 
-template <int MODE>
+template <int MODE, int NW>
 static void launch_mlp_bf16(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int rows,
                             hipStream_t s)
 {
     if (rows == 64)
-        hipLaunchKernelGGL((k_mlp_bf16<MODE, 4>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat,
-                           D, Dp, nets, d.E_atom, d.dEdG);
+        hipLaunchKernelGGL((k_mlp_bf16<MODE, 4, NW>), dim3(n_tiles), dim3(64 * NW), 0, s, d.elem_rows, d.mlp_tiles,
+                           d.xhat, D, Dp, nets, d.E_atom, d.dEdG);
     else if (rows == 32)
-        hipLaunchKernelGGL((k_mlp_bf16<MODE, 2>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat,
-                           D, Dp, nets, d.E_atom, d.dEdG);
+        hipLaunchKernelGGL((k_mlp_bf16<MODE, 2, NW>), dim3(n_tiles), dim3(64 * NW), 0, s, d.elem_rows, d.mlp_tiles,
+                           d.xhat, D, Dp, nets, d.E_atom, d.dEdG);
     else
-        hipLaunchKernelGGL((k_mlp_bf16<MODE, 1>), dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat,
-                           D, Dp, nets, d.E_atom, d.dEdG);
+        hipLaunchKernelGGL((k_mlp_bf16<MODE, 1, NW>), dim3(n_tiles), dim3(64 * NW), 0, s, d.elem_rows, d.mlp_tiles,
+                           d.xhat, D, Dp, nets, d.E_atom, d.dEdG);
 }
 
 void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int mlp_mode, int rows,
-                hipStream_t s)
+                int waves, hipStream_t s)
 {
     if (n_tiles <= 0)
         return;
     if (mlp_mode == 3)
         hipLaunchKernelGGL(k_mlp_f64, dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp, nets,
                            d.E_atom, d.dEdG);
+    else if (mlp_mode == 1 && waves == 8)
+        launch_mlp_bf16<1, 8>(d, nets, n_tiles, D, Dp, rows, s);
     else if (mlp_mode == 1)
-        launch_mlp_bf16<1>(d, nets, n_tiles, D, Dp, rows, s);
+        launch_mlp_bf16<1, 4>(d, nets, n_tiles, D, Dp, rows, s);
+    else if (mlp_mode == 2 && waves == 8)
+        launch_mlp_bf16<2, 8>(d, nets, n_tiles, D, Dp, rows, s);
     else if (mlp_mode == 2)
-        launch_mlp_bf16<2>(d, nets, n_tiles, D, Dp, rows, s);
+        launch_mlp_bf16<2, 4>(d, nets, n_tiles, D, Dp, rows, s);
     else
         launch_mlp_fp32(d, nets, n_tiles, D, Dp, rows, s);
 }

@@ -430,7 +430,7 @@ struct pimd_ctx {
     MlpNets nets{};
     int n_mlp_tiles = 0;
     std::vector<int32_t> elem_row0;   // [n_el + 1] first MLP row of each element in elem_rows
-    Tuning tn{4, 0, 16, 0};         // nl_cells is set from the cell count at init
+    Tuning tn{4, 0, 16, 0, 4};      // nl_cells is set from the cell count at init
     pimd_tuning last_tuning_out{};     // sink for pimd_autotune(best = NULL)
     std::vector<SysInfo> sys_host;
     std::vector<double> temperature, masses_el;
@@ -505,7 +505,8 @@ void launch_force_stage(pimd_ctx *c, int stage, const float *q, float *E_out, fl
         break;
     case 2:
         if (c->pl.bpnn)
-            launch_mlp(d, c->nets, c->n_mlp_tiles, c->pl.D, c->pl.Dp, c->precision, c->tn.mlp_rows, s);
+            launch_mlp(d, c->nets, c->n_mlp_tiles, c->pl.D, c->pl.Dp, c->precision, c->tn.mlp_rows, c->tn.mlp_waves,
+                       s);
         break;
     case 3:
         if (c->pl.gfn) {
@@ -761,6 +762,10 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     z.Kmax = pl.Kmax;
     z.any_periodic = pl.any_periodic ? 1 : 0;
     c->tn.nl_cells = pl.total_cells >= 4096 ? 1 : 0;
+    if (c->precision == PIMD_PREC_BF16_MLP || c->precision == PIMD_PREC_BF16_PLAIN) {
+        c->tn.mlp_rows = 32;    // 32-row tiles, one 16-column tile per wave: fastest at 64 to 16384 bead-atoms
+        c->tn.mlp_waves = 8;
+    }
     z.any_open = pl.any_open ? 1 : 0;
     z.any_box = pl.any_box ? 1 : 0;
 
@@ -1690,7 +1695,8 @@ pimd_status pimd_get_tuning(const pimd_ctx *ctx, pimd_tuning *out)
 {
     if (!ctx || !out)
         return PIMD_E_ARG;
-    *out = pimd_tuning{ctx->tn.centre_waves, ctx->tn.centre_grid, ctx->tn.mlp_rows, ctx->tn.nl_cells};
+    *out = pimd_tuning{ctx->tn.centre_waves, ctx->tn.centre_grid, ctx->tn.mlp_rows, ctx->tn.nl_cells,
+                       ctx->tn.mlp_waves};
     return PIMD_OK;
 }
 
@@ -1722,16 +1728,17 @@ pimd_status pimd_set_tuning(pimd_ctx *ctx, const pimd_tuning *t)
         return PIMD_E_ARG;
     const bool waves_ok = t->centre_waves == 1 || t->centre_waves == 2 || t->centre_waves == 4;
     const bool rows_ok = t->mlp_rows == 16 || t->mlp_rows == 32 || t->mlp_rows == 64;
-    if (!waves_ok || !rows_ok || t->centre_grid < 0 || (t->neighbor_cells != 0 && t->neighbor_cells != 1)) {
+    if (!waves_ok || !rows_ok || t->centre_grid < 0 || (t->neighbor_cells != 0 && t->neighbor_cells != 1) ||
+        (t->mlp_waves != 4 && t->mlp_waves != 8)) {
         ctx->err = "tuning: centre_waves in {1, 2, 4}, centre_grid >= 0, mlp_rows in {16, 32, 64}, "
-                   "neighbor_cells in {0, 1}";
+                   "neighbor_cells in {0, 1}, mlp_waves in {4, 8}";
         return PIMD_E_ARG;
     }
     if (ctx->precision == PIMD_PREC_FP64_MLP && t->mlp_rows != 16) {
         ctx->err = "the FP64 MLP runs 16-row tiles only";
         return PIMD_E_UNSUPPORTED;
     }
-    return apply_tuning(ctx, Tuning{t->centre_waves, t->centre_grid, t->mlp_rows, t->neighbor_cells});
+    return apply_tuning(ctx, Tuning{t->centre_waves, t->centre_grid, t->mlp_rows, t->neighbor_cells, t->mlp_waves});
 }
 
 // Mean milliseconds of one force evaluation of the current positions.
@@ -1801,7 +1808,7 @@ pimd_status pimd_autotune(pimd_ctx *ctx, int32_t n_reps, pimd_tuning *best)
                 Tuning cand = top;
                 cand.centre_waves = waves;
                 cand.centre_grid = per_cu * n_cu;
-                if (cand.centre_grid >= centre_grid(ctx->z.B, Tuning{waves, 0, 16, 0}))
+                if (cand.centre_grid >= centre_grid(ctx->z.B, Tuning{waves, 0, 16, 0, 4}))
                     continue;   // no fewer workgroups than one wave per centre gives
                 if (cand.centre_waves == cur.centre_waves && cand.centre_grid == cur.centre_grid)
                     continue;
@@ -1817,6 +1824,12 @@ pimd_status pimd_autotune(pimd_ctx *ctx, int32_t n_reps, pimd_tuning *best)
                 if ((st = consider(cand)) != PIMD_OK)
                     return st;
             }
+        if (ctx->pl.bpnn && (ctx->precision == PIMD_PREC_BF16_MLP || ctx->precision == PIMD_PREC_BF16_PLAIN)) {
+            Tuning cand = top;
+            cand.mlp_waves = 12 - top.mlp_waves;
+            if ((st = consider(cand)) != PIMD_OK)
+                return st;
+        }
         if (ctx->z.any_periodic) {
             Tuning cand = top;
             cand.nl_cells = 1 - top.nl_cells;

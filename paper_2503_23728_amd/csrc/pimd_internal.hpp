@@ -209,6 +209,7 @@ struct Tuning {
     int32_t centre_grid;   // 0: one wave per centre; > 0: at most this many workgroups, waves stride over centres
     int32_t mlp_rows;      // rows per MLP workgroup tile: 16, 32 or 64
     int32_t nl_cells;      // periodic neighbour search per cell with the stencil in LDS (1) or per centre (0)
+    int32_t mlp_waves;     // waves per BF16 MLP workgroup: 4 (two column tiles each) or 8 (one each)
 };
 
 // Workgroups of a per-centre launch over B centres.
@@ -241,9 +242,9 @@ void launch_cell_fill(const DevBuffers &d, const Sizes &z, hipStream_t s);
 void launch_neighbors(const DevBuffers &d, const Sizes &z, float rc2, int n_el, const Tuning &tn, hipStream_t s);
 void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s);
 // mlp_mode: 0 FP32 operands; 1 BF16 operands, three-term split; 2 BF16 operands, one term; 3 FP64
-// rows: rows per tile of d.mlp_tiles (16, 32 or 64; mode 3 takes 16 only)
+// rows: rows per tile of d.mlp_tiles (16, 32 or 64; mode 3 takes 16 only); waves: 4 or 8 (BF16 modes)
 void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int mlp_mode, int rows,
-                hipStream_t s);
+                int waves, hipStream_t s);
 void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s);
 void launch_gfn_layers(const DevBuffers &d, const Sizes &z, const DescParams &dp, const GfnParams &gp,
                        const Tuning &tn, hipStream_t s);

@@ -12,7 +12,7 @@ import hashlib
 import json
 import os
 
-FIELDS = ("centre_waves", "centre_grid", "mlp_rows", "neighbor_cells")
+FIELDS = ("centre_waves", "centre_grid", "mlp_rows", "neighbor_cells", "mlp_waves")
 
 
 def cache_path():

@@ -378,9 +378,10 @@ def test_every_launch_shape_gives_bitwise_identical_results(name, prec):
         for grid in (0, 7, 300):
             for rows in (16, 32, 64):
                 cells = (waves + rows // 16) % 2
-                eng.set_tuning(centre_waves=waves, centre_grid=grid, mlp_rows=rows, neighbor_cells=cells)
+                mw = 8 if (grid + rows) % 3 else 4
+                eng.set_tuning(centre_waves=waves, centre_grid=grid, mlp_rows=rows, neighbor_cells=cells, mlp_waves=mw)
                 E, F, W = eng.energy_forces(q, virial=True)
-                shape = (waves, grid, rows, cells)
+                shape = (waves, grid, rows, cells, mw)
                 assert torch.equal(E, E0) and torch.equal(F, F0) and torch.equal(W, W0), shape
                 assert torch.equal(eng.debug_descriptors(), x0), shape
 
@@ -397,7 +398,7 @@ def test_autotune_picks_a_valid_shape_and_the_cache_reapplies_it(tmp_path, monke
     shape, cached = a.autotune(n_reps=2)
     assert not cached
     assert shape["centre_waves"] in (1, 2, 4) and shape["mlp_rows"] in (16, 32, 64) and shape["centre_grid"] >= 0
-    assert shape["neighbor_cells"] in (0, 1)
+    assert shape["neighbor_cells"] in (0, 1) and shape["mlp_waves"] in (4, 8)
     # the state does not move and the forces are those of the same positions
     _, _, F_after, step1 = a.get_state()
     assert step1 == step0 and torch.equal(F_before, F_after)
@@ -417,7 +418,8 @@ def test_bad_launch_shapes_are_rejected():
     from paper_2503_23728_amd.abi import PimdError, PIMD_E_ARG, PIMD_E_UNSUPPORTED
     wl = WORKLOADS["fad-P4"]()
     eng = _engine(wl)
-    for bad in ({"centre_waves": 3}, {"centre_waves": 8}, {"mlp_rows": 48}, {"centre_grid": -1}, {"neighbor_cells": 2}):
+    for bad in ({"centre_waves": 3}, {"centre_waves": 8}, {"mlp_rows": 48}, {"centre_grid": -1}, {"neighbor_cells": 2},
+                {"mlp_waves": 6}):
         with pytest.raises(PimdError) as ei:
             eng.set_tuning(**bad)
         assert ei.value.status == PIMD_E_ARG
