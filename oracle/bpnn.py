@@ -34,9 +34,9 @@ def _core():
                   ctypes.c_int, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double),
                   ctypes.c_int, P(ctypes.c_double), ctypes.c_double,
                   ctypes.c_int, P(ctypes.c_int32), P(ctypes.c_int64), P(ctypes.c_int32)]
-        _lib.oracle_descriptors.argtypes = common + [P(ctypes.c_double), P(ctypes.c_int64)]
+        _lib.oracle_descriptors.argtypes = common + [P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int]
         _lib.oracle_descriptors.restype = None
-        _lib.oracle_descriptor_vjp.argtypes = common + [P(ctypes.c_double), P(ctypes.c_double)]
+        _lib.oracle_descriptor_vjp.argtypes = common + [P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int]
         _lib.oracle_descriptor_vjp.restype = None
     return _lib
 
@@ -71,13 +71,22 @@ class _Call:
                 _ptr(self.idx, ctypes.c_int32)]
 
 
+def _angular(model):
+    """0: G4 angular functions (with the r_jk factors), 1: G5 (without)."""
+    kind = getattr(model, "angular", "g4")
+    if kind not in ("g4", "g5"):
+        raise ValueError(f"unknown angular form {kind!r}")
+    return int(kind == "g5")
+
+
 def descriptors(model, q, species, box, centers, start, idx, with_counts=False):
     """Raw symmetry functions G[len(centers), D] (before normalisation).
     start/idx: CSR neighbour lists of the centres (one row per centre)."""
     call = _Call(model, q, species, box, centers, start, idx)
     G = np.zeros((len(call.centers), model.n_features))
     counts = np.zeros((len(call.centers), 2), dtype=np.int64)
-    _core().oracle_descriptors(*call.args(), _ptr(G, ctypes.c_double), _ptr(counts, ctypes.c_int64))
+    _core().oracle_descriptors(*call.args(), _ptr(G, ctypes.c_double), _ptr(counts, ctypes.c_int64),
+                               _angular(model))
     return (G, counts) if with_counts else G
 
 
@@ -86,7 +95,8 @@ def descriptor_vjp(model, q, species, box, centers, start, idx, dEdG):
     call = _Call(model, q, species, box, centers, start, idx)
     g = np.ascontiguousarray(dEdG, dtype=np.float64)
     v = np.zeros((len(call.idx), 3))
-    _core().oracle_descriptor_vjp(*call.args(), _ptr(g, ctypes.c_double), _ptr(v, ctypes.c_double))
+    _core().oracle_descriptor_vjp(*call.args(), _ptr(g, ctypes.c_double), _ptr(v, ctypes.c_double),
+                                  _angular(model))
     return v
 
 

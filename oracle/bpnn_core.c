@@ -18,6 +18,12 @@
  *   r_jk = |d_ik - d_ij|, each unordered triplet counted once (j < k in the
  *   neighbour list order).
  *
+ * angular = 1 selects the G5 form of the angular functions instead: the same
+ * sum without the factors that involve r_jk,
+ *   G5[{e1,e2},(eta,zeta,lambda)] = 2^(1-zeta) sum_{j<k in N(i), {Z_j,Z_k} = {e1,e2}}
+ *        (1 + lambda cos theta_jik)^zeta exp(-eta (r_ij^2 + r_ik^2)) f_c(r_ij) f_c(r_ik)
+ * so every pair of neighbours counts, however far apart j and k are.
+ *
  * Feature layout: radial index e*n_rad + s; angular index
  * n_el*n_rad + pair*n_ang + (i_eta*4 + i_zeta)*2 + i_lambda, with zeta in
  * {1,2,4,8}, lambda in {+1,-1}, pair = lexicographic index of (e1 <= e2).
@@ -82,7 +88,7 @@ void oracle_descriptors(int n_atoms, const double *q, const int32_t *species,
                         int n_ang_eta, const double *ang_eta, double rc,
                         int n_centers, const int32_t *centers,
                         const int64_t *nbr_start, const int32_t *nbr_idx,
-                        double *G, int64_t *counts)
+                        double *G, int64_t *counts, int angular)
 {
     (void)n_atoms;
     const int D = oracle_n_features(n_el, n_rad, n_ang_eta);
@@ -119,14 +125,16 @@ void oracle_descriptors(int n_atoms, const double *q, const int32_t *species,
                     djk[t] = dik[t] - dij[t];
                 const double rik = norm3(dik), rjk = norm3(djk);
                 ++n_trip;
-                if (rjk >= rc)
+                if (!angular && rjk >= rc)
                     continue;
                 ++n_trip_in;
                 const double cos_t = (dij[0] * dik[0] + dij[1] * dik[1] + dij[2] * dik[2]) / (rij * rik);
-                const double fcs = cutoff_fn(rij, rc) * cutoff_fn(rik, rc) * cutoff_fn(rjk, rc);
+                const double fcs = angular ? cutoff_fn(rij, rc) * cutoff_fn(rik, rc)
+                                           : cutoff_fn(rij, rc) * cutoff_fn(rik, rc) * cutoff_fn(rjk, rc);
+                const double r2sum = angular ? rij * rij + rik * rik : rij * rij + rik * rik + rjk * rjk;
                 const int base = n_el * n_rad + pair_index(species[j], species[k], n_el) * n_ang;
                 for (int ie = 0; ie < n_ang_eta; ++ie) {
-                    const double radial = exp(-ang_eta[ie] * (rij * rij + rik * rik + rjk * rjk)) * fcs;
+                    const double radial = exp(-ang_eta[ie] * r2sum) * fcs;
                     for (int iz = 0; iz < 4; ++iz)
                         for (int il = 0; il < 2; ++il) {
                             const double ang = pow(2.0, 1 - ZETA[iz]) * ipow(1.0 + LAMBDA[il] * cos_t, ZETA[iz]);
@@ -152,7 +160,7 @@ void oracle_descriptor_vjp(int n_atoms, const double *q, const int32_t *species,
                            int n_ang_eta, const double *ang_eta, double rc,
                            int n_centers, const int32_t *centers,
                            const int64_t *nbr_start, const int32_t *nbr_idx,
-                           const double *dEdG, double *v)
+                           const double *dEdG, double *v, int angular)
 {
     (void)n_atoms;
     const int D = oracle_n_features(n_el, n_rad, n_ang_eta);
@@ -194,21 +202,25 @@ void oracle_descriptor_vjp(int n_atoms, const double *q, const int32_t *species,
                 for (int t = 0; t < 3; ++t)
                     C[t] = B[t] - A[t];
                 const double rik = norm3(B), rjk = norm3(C);
-                if (rjk >= rc)
+                if (!angular && rjk >= rc)
                     continue;
                 const double cos_t = (A[0] * B[0] + A[1] * B[1] + A[2] * B[2]) / (rij * rik);
-                const double fij = cutoff_fn(rij, rc), fik = cutoff_fn(rik, rc), fjk = cutoff_fn(rjk, rc);
-                const double dfij = cutoff_deriv(rij, rc), dfik = cutoff_deriv(rik, rc), dfjk = cutoff_deriv(rjk, rc);
+                /* G5: the r_jk factor is 1 and its derivative 0 */
+                const double fij = cutoff_fn(rij, rc), fik = cutoff_fn(rik, rc);
+                const double fjk = angular ? 1.0 : cutoff_fn(rjk, rc);
+                const double dfij = cutoff_deriv(rij, rc), dfik = cutoff_deriv(rik, rc);
+                const double dfjk = angular ? 0.0 : cutoff_deriv(rjk, rc);
+                const double eta_jk = angular ? 0.0 : 1.0;
                 const int base = n_el * n_rad + pair_index(species[j], species[k], n_el) * n_ang;
                 double S_c = 0.0, S_ij = 0.0, S_ik = 0.0, S_jk = 0.0;
                 for (int ie = 0; ie < n_ang_eta; ++ie) {
                     const double eta = ang_eta[ie];
-                    const double ex = exp(-eta * (rij * rij + rik * rik + rjk * rjk));
+                    const double ex = exp(-eta * (rij * rij + rik * rik + eta_jk * rjk * rjk));
                     /* radial factor R = ex * fij * fik * fjk and its partials */
                     const double R = ex * fij * fik * fjk;
                     const double dR_dij = ex * fik * fjk * (-2.0 * eta * rij * fij + dfij);
                     const double dR_dik = ex * fij * fjk * (-2.0 * eta * rik * fik + dfik);
-                    const double dR_djk = ex * fij * fik * (-2.0 * eta * rjk * fjk + dfjk);
+                    const double dR_djk = ex * fij * fik * (-2.0 * eta * eta_jk * rjk * fjk + dfjk);
                     for (int iz = 0; iz < 4; ++iz)
                         for (int il = 0; il < 2; ++il) {
                             const double w = g[base + (ie * 4 + iz) * 2 + il] * pow(2.0, 1 - ZETA[iz]);

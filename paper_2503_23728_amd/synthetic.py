@@ -17,6 +17,7 @@ Units: Angstrom, fs, amu, eV.
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass, field
 import math
 
@@ -47,6 +48,8 @@ class Model:
       (i_eta * len(ZETAS) + i_zeta) * len(LAMBDAS) + i_lambda.
     Layers: W[l] has shape [out, in] (float32), b[l] shape [out]; the last
     layer has out = 1.
+    angular: "g4" (angular functions with the r_jk factors) or "g5" (without
+    them; same feature layout).
     """
     elements: list
     masses: np.ndarray
@@ -58,6 +61,7 @@ class Model:
     weights: list           # weights[e] = [(W0, b0), (W1, b1), ..., (Wout, bout)]
     feat_shift: np.ndarray  # [n_el, D] float32
     feat_scale: np.ndarray  # [n_el, D] float32
+    angular: str = "g4"
 
     @property
     def n_elements(self):
@@ -236,6 +240,19 @@ def gfn_workload(c, width=16, n_layers=2, seed_offset=0):
     head = make_gfn_model(wl.model.elements, wl.model.n_rad, width, n_layers, 2500 + c + seed_offset)
     return Workload(wl.name + "-gfn", wl.systems, head, wl.dt, wl.tau0, wl.pile_lambda, wl.n_steps,
                     wl.philox_seed, wl.momentum_seed)
+
+
+def with_g5(wl):
+    """The same workload with the G5 angular functions in the descriptor
+    network (no r_jk factors: every neighbour pair counts, so the angular sums
+    are larger and their block scale grows, 1.5x for the formic-acid model,
+    3x for water, to keep the normalised features O(1))."""
+    m = wl.model
+    factor = 1.5 if "C" in m.elements else 3.0
+    scale = m.feat_scale.copy()
+    scale[:, m.n_elements * m.n_rad:] *= np.float32(factor)
+    model = dataclasses.replace(m, angular="g5", feat_scale=scale)
+    return dataclasses.replace(wl, name=wl.name + "-g5", model=model)
 
 
 # ----------------------------------------------------------------------------
