@@ -79,6 +79,30 @@ def flops_model(n_rad, n_eta, pairs, triplets, triplets_in):
     return fwd, adj
 
 
+def g5_flops_model(n_rad, n_eta, n_el, slots, centres):
+    """Algorithmic FLOPs of the G5 forward and adjoint passes (spherical-harmonic
+    moments up to l = 8: 81 harmonics, 45 (l, m >= 0) recursion steps), counted
+    like flops_model (a fused multiply-add is two):
+      forward  per slot:   the G4 pair terms (13 + 3 n_eta + 6 n_rad); (x + iy)^m 48;
+                           recursion 45 x 4; harmonics 81; per eta and harmonic:
+                           M += w Y 2, R += (w Y)^2 3
+               per centre: per element pair and eta: power spectrum 81 x 3,
+                           8 features x 18
+      adjoint  per slot:   the G4 adjoint pair terms (fwd pair + 2 n_eta + 10 n_rad + 22);
+                           (x + iy)^m 48; recursion with z derivative 45 x 8; per eta:
+                           six (four for m = 0) accumulations per (l, m) 9 x 8 + 36 x 12,
+                           fold per m 9 x 20; tangent projection and vector 30; virial 18
+               per centre: H 9 x 16 and dE/dM 81 x 2 n_el per element pair / element and eta
+    """
+    n_pairs = n_el * (n_el + 1) // 2
+    fwd_slot = 13 + 3 * n_eta + 6 * n_rad + 48 + 180 + 81 + 81 * 5 * n_eta
+    fwd_centre = n_pairs * n_eta * (81 * 3 + 8 * 18)
+    adj_slot = (13 + 3 * n_eta + 6 * n_rad) + 2 * n_eta + 10 * n_rad + 22 + 48 + 360 + \
+        n_eta * (9 * 8 + 36 * 12 + 9 * 20) + 30 + 18
+    adj_centre = n_pairs * n_eta * 9 * 16 + n_el * n_eta * 81 * 2 * n_el
+    return slots * fwd_slot + centres * fwd_centre, slots * adj_slot + centres * adj_centre
+
+
 def gfn_flops_per_edge(n_rad, H, L):
     """Algorithmic FLOPs of the direct-force head per directed edge, counted
     from its definition (one FLOP per add, multiply, exp or divide; tanh 5):
@@ -237,6 +261,9 @@ def main():
     ap.add_argument("--gfn-layers", type=int, default=2)
     ap.add_argument("--transform", default="normal-modes", choices=["normal-modes", "staging", "primitive"],
                     help="ring-polymer coordinates of the integrator")
+    ap.add_argument("--angular", default="g4", choices=["g4", "g5"],
+                    help="angular symmetry functions: G4 (triplets within the cutoff) or G5 (no r_jk "
+                         "factors, summed through spherical-harmonic moments)")
     ap.add_argument("--metad", action="store_true",
                     help="add the well-tempered metadynamics bias of the workload's study (s_dimer or XRD CV)")
     args = ap.parse_args()
@@ -252,6 +279,10 @@ def main():
     device = "cuda:0"
     gfn_mode = args.potential == "gfn"
     wl = S.gfn_workload(args.config, args.gfn_width, args.gfn_layers) if gfn_mode else S.workload(args.config)
+    if args.angular == "g5":
+        if gfn_mode:
+            sys.exit("--angular g5 applies to the energy model only")
+        wl = S.with_g5(wl)
     B = wl.bead_atoms
     spec = S.metad_spec(wl, max_hills=4096) if args.metad else None
     eng = Pimd.from_workload(wl, precision=args.precision, device=device, metad=spec, transform=args.transform)
@@ -294,6 +325,26 @@ def main():
                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
                     "flops_per_launch": flops, "launch_ms": round(head_ms, 4),
                     "work": {"pairs": pairs, "width": m.width, "layers": m.n_layers}}
+    elif args.angular == "g5":
+        # the forward (FP64 moment sums) is the dominant kernel; FP64 and unpacked
+        # FP32 vector instructions issue at the same rate, 78.6 TFLOP/s
+        fwd_flops, adj_flops = g5_flops_model(m.n_rad, len(m.ang_eta), m.n_elements, pairs, B)
+        fwd_ms, adj_ms = kern["descriptors"], kern["adjoint"]
+        achieved = fwd_flops / (fwd_ms * 1e-3) / 1e12
+        mlp_flops = B * mlp_flops_per_row(eng.D, m.hidden)
+        roofline = {"kernel": "k_descriptors_g5 (spherical-harmonic moments, FP64 sums)", "bound": "alu",
+                    "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                    "flops_per_launch": fwd_flops, "launch_ms": round(fwd_ms, 4),
+                    "adjoint": {"kernel": "k_adjoint_g5", "flops_per_launch": adj_flops,
+                                "launch_ms": round(adj_ms, 4),
+                                "achieved": round(adj_flops / (adj_ms * 1e-3) / 1e12, 3)},
+                    "mlp": {"kernel": "k_mlp", "bound": "mfma", "flops_per_launch": mlp_flops,
+                            "launch_ms": round(kern["mlp"], 4),
+                            "achieved": round(mlp_flops / (kern["mlp"] * 1e-3) / 1e12, 3),
+                            "peak": BF16_MFMA_PEAK_TFLOPS,
+                            "frac": round(mlp_flops / (kern["mlp"] * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4)},
+                    "work": {"slots": pairs, "centres": B}}
     else:
         fwd_flops, adj_flops = flops_model(m.n_rad, len(m.ang_eta), pairs, trip, trip_in)
         adj_ms = kern["adjoint"]
@@ -326,7 +377,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "systems": len(wl.systems), "bead_atoms": B,
                    "beads": sum(s.n_beads for s in wl.systems), "dt_fs": wl.dt,
-                   "precision": args.precision, "potential": args.potential,
+                   "precision": args.precision, "potential": args.potential, "angular": args.angular,
                    "transform": args.transform,
                    "launch": "hip graph per step" + (", 25-step blocks from the initial state" if gfn_mode else ""),
                    "launch_shape": shape,

@@ -66,6 +66,7 @@ typedef enum {
  * Descriptors, adjoint and integrator are FP32 in every mode. */
 enum { PIMD_PREC_FP32 = 0, PIMD_PREC_BF16_MLP = 1, PIMD_PREC_BF16_PLAIN = 2, PIMD_PREC_FP64_MLP = 3 };
 enum { PIMD_POT_BPNN = 0, PIMD_POT_HARMONIC = 1, PIMD_POT_GFN = 2 };
+enum { PIMD_ANGULAR_G4 = 0, PIMD_ANGULAR_G5 = 1 };
 
 /*
  * Behler-Parrinello model.  Symmetry functions of centre atom i with
@@ -78,6 +79,11 @@ enum { PIMD_POT_BPNN = 0, PIMD_POT_HARMONIC = 1, PIMD_POT_GFN = 2 };
  *   with zeta = {1,2,4,8}[iz], lambda = {+1,-1}[il], r_jk = |d_ik - d_ij|,
  *   pair = lexicographic index of (min(Z_j,Z_k), max(Z_j,Z_k)), n_ang = 8*n_ang_eta,
  *   D = n_el*n_rad + n_el*(n_el+1)/2 * n_ang features.
+ * angular = PIMD_ANGULAR_G5 drops the two factors of r_jk from the angular
+ *   sum (the G5 form): exp(-ang_eta[ie] (r_ij^2 + r_ik^2)) f_c(r_ij) f_c(r_ik),
+ *   every pair of neighbours counting; same layout.  The library then sums it
+ *   through 81 spherical-harmonic moments per (element, eta) of each centre,
+ *   O(K) per atom instead of O(K^2).
  * Network per element e: x = (G - feat_shift[e]) / feat_scale[e];
  *   h_l = tanh(W_l h_{l-1} + b_l) for the n_hidden hidden layers, E_i = w_o . h + b_o.
  * params: for each element in order, for each layer (hidden layers, then the
@@ -98,6 +104,7 @@ typedef struct {
     const float *params;         /* packed weights, see above */
     const float *feat_shift;     /* [n_elements][D] */
     const float *feat_scale;     /* [n_elements][D], non-zero */
+    int32_t angular;             /* PIMD_ANGULAR_G4 (0) or PIMD_ANGULAR_G5 (1); PIMD_E_ARG otherwise */
 } pimd_bpnn_model;
 
 /*

@@ -26,7 +26,8 @@ class pimd_bpnn_model(ctypes.Structure):
                 ("n_rad", c_int32), ("rad_center_A", POINTER(c_double)), ("rad_eta", POINTER(c_double)),
                 ("n_ang_eta", c_int32), ("ang_eta", POINTER(c_double)),
                 ("n_hidden", c_int32), ("hidden", c_int32 * 3),
-                ("params", POINTER(c_float)), ("feat_shift", POINTER(c_float)), ("feat_scale", POINTER(c_float))]
+                ("params", POINTER(c_float)), ("feat_shift", POINTER(c_float)), ("feat_scale", POINTER(c_float)),
+                ("angular", c_int32)]
 
 
 class pimd_gfn_model(ctypes.Structure):

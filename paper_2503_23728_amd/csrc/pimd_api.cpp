@@ -38,6 +38,7 @@ struct Layout {
 struct Plan {
     int n_sys = 0, n_el = 0, B = 0, n_beads = 0, n_atoms = 0, ncol = 0, total_cells = 0, n_units = 0;
     int D = 0, Dp = 0, Kmax = 0, max_P = 1, n_rad = 0, n_ang_eta = 0;
+    int angular = 0;                           // 0: G4, 1: G5 angular functions
     bool any_periodic = false, any_open = false, bpnn = false, gfn = false;
     bool nl = false;                           // neighbour lists (the energy model or the direct-force head)
     int gfn_H = 0, gfn_L = 0;
@@ -171,6 +172,8 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
         for (int s = 0; s < m->n_ang_eta; ++s)
             if (!(m->ang_eta[s] >= 0.0) || !std::isfinite(m->ang_eta[s]))
                 return fail(err, PIMD_E_ARG, "bad angular eta");
+        if (m->angular != PIMD_ANGULAR_G4 && m->angular != PIMD_ANGULAR_G5)
+            return fail(err, PIMD_E_ARG, "angular must be PIMD_ANGULAR_G4 or PIMD_ANGULAR_G5");
         if (m->n_hidden < 1 || m->n_hidden > 3)
             return fail(err, PIMD_E_UNSUPPORTED, "n_hidden must be in [1, 3]");
         for (int l = 0; l < m->n_hidden; ++l)
@@ -178,6 +181,7 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
                 return fail(err, PIMD_E_UNSUPPORTED, "hidden widths must be multiples of 16 in [16, 128]");
         pl.n_rad = m->n_rad;
         pl.n_ang_eta = m->n_ang_eta;
+        pl.angular = m->angular;
         pl.D = n_features(m->n_elements, m->n_rad, m->n_ang_eta);
         pl.Dp = (pl.D + 15) & ~15;
         if (pl.Dp > 128)
@@ -354,6 +358,8 @@ Layout make_layout(const Plan &pl)
         L.add("xhat", B * D * 4);
         L.add("dEdG", B * D * 4);
         L.add("vslot", B * K * 16);
+        if (pl.angular)
+            L.add("g5_mom", B * (size_t)pl.n_el * pl.n_ang_eta * kG5Mom * 4);
         L.add("mlp_f32", pl.mlp_f32_floats * 4);
         L.add("mlp_bf16", pl.mlp_bf16_elems * 2);
         L.add("mlp_f64", pl.mlp_f64_elems * 8);
@@ -500,6 +506,8 @@ void launch_force_stage(pimd_ctx *c, int stage, const float *q, float *E_out, fl
     case 1:
         if (c->pl.gfn)
             launch_gfn_layers(d, z, c->dp, c->gp, c->tn, s);
+        else if (c->dp.angular)
+            launch_descriptors_g5(d, z, c->dp, c->tn, s);
         else
             launch_descriptors(d, z, c->dp, c->tn, s);
         break;
@@ -518,7 +526,10 @@ void launch_force_stage(pimd_ctx *c, int stage, const float *q, float *E_out, fl
                 launch_zero_i32(reinterpret_cast<int32_t *>(d.vir_atom), (int64_t)z.B * 9, s);
             }
         } else if (F_out || W_out) {
-            launch_adjoint(d, z, c->dp, c->tn, s);
+            if (c->dp.angular)
+                launch_adjoint_g5(d, z, c->dp, c->tn, s);
+            else
+                launch_adjoint(d, z, c->dp, c->tn, s);
         }
         break;
     default:
@@ -729,6 +740,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     d.xhat = (float *)at("xhat");
     d.dEdG = (float *)at("dEdG");
     d.vslot = (float4 *)at("vslot");
+    d.g5_mom = pl.angular ? (float *)at("g5_mom") : nullptr;
     d.mlp_f32 = (float *)at("mlp_f32");
     d.mlp_bf16 = (uint16_t *)at("mlp_bf16");
     d.mlp_f64 = (double *)at("mlp_f64");
@@ -987,6 +999,27 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         dp.D = pl.D;
         for (int s = 0; s < m->n_ang_eta; ++s)
             dp.ang_eta[s] = (float)m->ang_eta[s];
+        dp.angular = pl.angular;
+        {
+            // Legendre coefficients of (1 + c)^zeta: multiply by (1 + c) zeta times,
+            // with c P_l = ((l + 1) P_{l+1} + l P_{l-1}) / (2l + 1)
+            static const int kZeta[4] = {1, 2, 4, 8};
+            for (int iz = 0; iz < 4; ++iz) {
+                double a[10] = {1.0};
+                for (int t = 0; t < kZeta[iz]; ++t) {
+                    double b[10] = {0.0};
+                    for (int l = 0; l <= 8; ++l) {
+                        b[l] += a[l];
+                        b[l + 1] += a[l] * (l + 1) / (2.0 * l + 1.0);
+                        if (l > 0)
+                            b[l - 1] += a[l] * l / (2.0 * l + 1.0);
+                    }
+                    std::copy(b, b + 10, a);
+                }
+                for (int l = 0; l <= 8; ++l)
+                    dp.g5_leg[iz][l] = (float)(a[l] * std::ldexp(1.0, 1 - kZeta[iz]));
+            }
+        }
         // rows grouped by element for the MLP gather, cut into tiles of tn.mlp_rows
         std::vector<int32_t> rows;
         c->elem_row0.assign(1, 0);
@@ -1172,7 +1205,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     if (e != hipSuccess)
         return bail(PIMD_E_DEVICE, std::string("upload sync: ") + hipGetErrorString(e));
     if (pl.bpnn) {
-        e = configure_descriptor_lds(c->dp);
+        e = pl.angular ? configure_g5_lds(c->dp) : configure_descriptor_lds(c->dp);
         if (e != hipSuccess)
             return bail(PIMD_E_DEVICE, std::string("descriptor LDS: ") + hipGetErrorString(e));
     }

@@ -10,6 +10,7 @@ namespace pimd {
 constexpr int kWave = 64;
 constexpr int kMaxElements = 4;
 constexpr int kMaxRad = 32;
+constexpr int kG5Mom = 84;       // floats per (centre, element, eta) of the G5 moments: 81 and 3 of padding
 constexpr int kMaxBeads = 128;
 constexpr int kMaxNeighbors = 256;
 constexpr int kKeyShift = 27;                 // neighbour key = (element << 27) | row
@@ -49,6 +50,8 @@ struct DescParams {
     float rad_center_lo[kMaxRad];  // ... and the remainder R_s - float(R_s)
     float rad_eta[kMaxRad];
     float ang_eta[2];
+    int32_t angular;               // 0: G4 angular functions, 1: G5
+    float g5_leg[4][9];            // G5: 2^(1-zeta) a_l of (1 + c)^zeta = sum_l a_l P_l(c), zeta = 1, 2, 4, 8
 };
 
 // One layer of one element network on the device.
@@ -162,6 +165,7 @@ struct DevBuffers {
     int32_t *nbr, *nbr_cnt, *nbr_grp;
     int32_t *nbr_fence;            // [B][kFence]: list count, then every 16th key (reverse-slot search)
     float *xhat, *dEdG, *E_atom;
+    float *g5_mom;           // G5: per centre [element][eta][kG5Mom] moments, kept for the adjoint
     float4 *vslot;
     float *vir_atom, *W_bead;
     double *heat, *dke_part;       // heat bath per system; O-step energy changes per unit (2 halves)
@@ -281,6 +285,11 @@ void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &d
 
 // Raise the dynamic-LDS limit of kernels whose LDS grows with Kmax or P.
 hipError_t configure_descriptor_lds(const DescParams &dp);
+// G5 angular functions (dp.angular = 1): forward (xhat, g5_mom) and adjoint (vslot, vir_atom)
+hipError_t configure_g5_lds(const DescParams &dp);
+void launch_descriptors_g5(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn,
+                           hipStream_t s);
+void launch_adjoint_g5(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s);
 hipError_t configure_integrator_lds(int max_P);
 hipError_t configure_neighbor_lds(int Kmax);
 size_t descriptor_lds_bytes(const DescParams &dp, bool adjoint);

@@ -86,6 +86,9 @@ def make_metad(spec, keep):
     return md
 
 
+ANGULAR = {"g4": 0, "g5": 1}     # PIMD_ANGULAR_G4, PIMD_ANGULAR_G5
+
+
 def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
                 omega=0.0, max_neighbors=0, masses=None, metad=None, transform="normal-modes"):
     """Build the pimd_config (and the storage it points into).
@@ -123,6 +126,10 @@ def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", p
         m.params = keep.arr(pack_params(model), np.float32, ctypes.c_float)
         m.feat_shift = keep.arr(model.feat_shift, np.float32, ctypes.c_float)
         m.feat_scale = keep.arr(model.feat_scale, np.float32, ctypes.c_float)
+        angular = getattr(model, "angular", "g4")
+        if angular not in ANGULAR:
+            raise ValueError(f"angular must be one of {sorted(ANGULAR)}")
+        m.angular = ANGULAR[angular]
     else:
         m.n_elements = len(masses)
         m.mass_amu = keep.arr(masses, np.float64, ctypes.c_double)

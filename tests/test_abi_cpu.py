@@ -47,6 +47,16 @@ def test_workspace_grows_with_max_neighbors(lib):
     assert b > a
 
 
+def test_g5_workspace_holds_the_moments(lib):
+    # G5: per centre 84 floats of moments per (element, eta) on top of the G4 buffers
+    wl = S.workload(2)
+    a = abi.pimd_workspace_size(_cfg(wl)[0])[1]
+    b = abi.pimd_workspace_size(_cfg(S.with_g5(wl))[0])[1]
+    m = wl.model
+    need = wl.bead_atoms * m.n_elements * len(m.ang_eta) * 84 * 4
+    assert need <= b - a <= need + 4096
+
+
 @pytest.mark.parametrize("mutate,status", [
     (lambda cfg, k: setattr(cfg, "n_systems", 0), abi.PIMD_E_ARG),
     (lambda cfg, k: setattr(cfg, "dt_fs", 0.0), abi.PIMD_E_ARG),
@@ -66,6 +76,7 @@ def test_workspace_grows_with_max_neighbors(lib):
     (lambda cfg, k: cfg.species.__setitem__(0, 5), abi.PIMD_E_ARG),
     (lambda cfg, k: setattr(cfg.model.contents, "n_elements", 0), abi.PIMD_E_UNSUPPORTED),
     (lambda cfg, k: setattr(cfg.model.contents, "n_ang_eta", 3), abi.PIMD_E_UNSUPPORTED),
+    (lambda cfg, k: setattr(cfg.model.contents, "angular", 2), abi.PIMD_E_ARG),
     (lambda cfg, k: cfg.model.contents.hidden.__setitem__(0, 40), abi.PIMD_E_UNSUPPORTED),
     (lambda cfg, k: cfg.model.contents.feat_scale.__setitem__(0, 0.0), abi.PIMD_E_ARG),
 ])
