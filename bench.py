@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -172,10 +174,10 @@ def time_steps(eng, steps, warmup, restart=None):
     return wall, gpu
 
 
-def plain_fp32(wl, steps, warmup, device, shape=None):
+def plain_fp32(wl, steps, warmup, device, shape=None, skin=0.0):
     """The comparison path: FP32 MLP, no graph, one context per system (with the
-    launch shape of the timed path, so the two differ only in MLP precision,
-    batching and graph replay)."""
+    launch shape and neighbour lists of the timed path, so the two differ only
+    in MLP precision, batching and graph replay)."""
     import torch
     from paper_2503_23728_amd import synthetic as S
     from paper_2503_23728_amd.pimd import Pimd
@@ -185,7 +187,8 @@ def plain_fp32(wl, steps, warmup, device, shape=None):
     for s in wl.systems:
         n = s.n_atoms * s.n_beads
         e = Pimd([s], wl.model, wl.dt, wl.tau0, wl.pile_lambda, wl.philox_seed, precision="fp32", device=device,
-                 potential="gfn" if hasattr(wl.model, "width") else "bpnn")
+                 potential="gfn" if hasattr(wl.model, "width") else "bpnn",
+                 neighbor_skin=skin if np.any(np.asarray(s.box) > 0) else 0.0)
         e.set_graph(False)
         if shape is not None:
             e.set_tuning(**shape)
@@ -207,7 +210,6 @@ def cpu_baseline(wl, budget_s=20.0):
     """FP64 oracle steps on the host cores over a bounded sample of the
     workload: whole integrator steps of the first ring polymer(s), repeated
     until about budget_s seconds have passed."""
-    import numpy as np
     from paper_2503_23728_amd import synthetic as S
     from oracle import bpnn, gfn, ring
     q, p = S.initial_state(wl)
@@ -264,6 +266,10 @@ def main():
     ap.add_argument("--angular", default="g4", choices=["g4", "g5"],
                     help="angular symmetry functions: G4 (triplets within the cutoff) or G5 (no r_jk "
                          "factors, summed through spherical-harmonic moments)")
+    ap.add_argument("--skin", type=float, default=2.0,
+                    help="neighbour lists shared by the beads of a ring polymer: centroid lists with this skin "
+                         "(A), filtered per bead (the same lists); 0 searches every bead's cells each step; "
+                         "ignored for systems without a box")
     ap.add_argument("--metad", action="store_true",
                     help="add the well-tempered metadynamics bias of the workload's study (s_dimer or XRD CV)")
     args = ap.parse_args()
@@ -285,7 +291,9 @@ def main():
         wl = S.with_g5(wl)
     B = wl.bead_atoms
     spec = S.metad_spec(wl, max_hills=4096) if args.metad else None
-    eng = Pimd.from_workload(wl, precision=args.precision, device=device, metad=spec, transform=args.transform)
+    skin = args.skin if all(np.any(np.asarray(s.box) > 0) for s in wl.systems) else 0.0
+    eng = Pimd.from_workload(wl, precision=args.precision, device=device, metad=spec, transform=args.transform,
+                             neighbor_skin=skin)
     q, p = S.initial_state(wl)
     eng.set_state(torch.from_numpy(q).to(device), torch.from_numpy(p).to(device))
     if args.no_tune:
@@ -381,6 +389,9 @@ def main():
                    "transform": args.transform,
                    "launch": "hip graph per step" + (", 25-step blocks from the initial state" if gfn_mode else ""),
                    "launch_shape": shape,
+                   "neighbor_lists": (f"shared by the beads: centroid lists, skin {skin} A, "
+                                      f"{eng.neighbor_rebuilds()[0]} builds in {args.warmup + args.steps} steps + "
+                                      f"profiling" if skin > 0 else "per bead, cell search every evaluation"),
                    "shape_source": {None: "default", True: "tuning cache", False: "autotuner"}[cached]},
         "ns_per_day": ns_day, "gpu_event_s": gpu_s,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
@@ -389,7 +400,7 @@ def main():
     }
     if not args.no_plain:
         psteps = max(1, min(args.steps, 50 if len(wl.systems) > 1 else args.steps))
-        pwall = plain_fp32(wl, psteps, min(args.warmup, 5), device, shape)
+        pwall = plain_fp32(wl, psteps, min(args.warmup, 5), device, shape, skin)
         pval = B * psteps / pwall
         out["plain_fp32"] = {"value": pval, "steps": psteps, "ms_per_step": 1e3 * pwall / psteps,
                              "launch": "eager, one context per system"}

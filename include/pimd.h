@@ -232,6 +232,14 @@ typedef struct {
                                           BF16_PLAIN on BF16 MFMA (split or single operands) */
     const pimd_metad *metad;           /* well-tempered metadynamics bias, or NULL for none */
     int32_t transform;                 /* PIMD_TRANSFORM_* (0: normal modes) */
+    double neighbor_skin_A;            /* 0: every bead's neighbour list searched through cell lists each
+                                          force evaluation; > 0: one list per atom of the ring-polymer
+                                          centroids with the cutoff widened by this skin, 3 * max_neighbors
+                                          slots, rebuilt when a bead-atom is more than half the skin from its
+                                          atom's centroid of the last build, filtered per bead each
+                                          evaluation (the same lists, key for key).  Needs a box for every
+                                          system (PIMD_E_UNSUPPORTED otherwise); a full centroid list is
+                                          PIMD_E_CAPACITY like a full bead list */
 } pimd_config;
 
 /* Finite-P estimators of one system (Sec. 2.1; virial kinetic energy of
@@ -438,6 +446,13 @@ pimd_status pimd_time_stages(pimd_ctx *ctx, int32_t n_reps, double *ms_host);
  * neighbour pairs of every centre (triplets) and the triplets with
  * r_jk < cutoff.  Synchronises. */
 pimd_status pimd_work_counts(pimd_ctx *ctx, int64_t *pairs, int64_t *triplets, int64_t *triplets_in_range);
+
+/* Shared neighbour lists (neighbor_skin_A > 0): how many times the centroid
+ * lists have been built since pimd_init (the first force evaluation builds
+ * them), and how many force evaluations found a bead farther than half the
+ * skin from its fresh centroid (a ring wider than the skin) and tested every
+ * atom of the bead instead.  PIMD_E_STATE without a skin.  Synchronises. */
+pimd_status pimd_neighbor_rebuilds(pimd_ctx *ctx, int64_t *builds, int64_t *full_scans);
 
 /* Sizes of a configured context: total bead-atoms B, total beads, features D. */
 pimd_status pimd_sizes(const pimd_ctx *ctx, int64_t *bead_atoms, int64_t *beads, int32_t *features);

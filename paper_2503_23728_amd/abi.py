@@ -48,7 +48,8 @@ class pimd_config(ctypes.Structure):
                 ("dt_fs", c_double), ("tau0_fs", c_double), ("pile_lambda", c_double), ("seed", c_uint64),
                 ("precision", c_int32), ("potential", c_int32), ("model", POINTER(pimd_bpnn_model)),
                 ("harmonic_omega_per_fs", c_double), ("max_neighbors", c_int32),
-                ("gfn", POINTER(pimd_gfn_model)), ("metad", POINTER(pimd_metad)), ("transform", c_int32)]
+                ("gfn", POINTER(pimd_gfn_model)), ("metad", POINTER(pimd_metad)), ("transform", c_int32),
+                ("neighbor_skin_A", c_double)]
 
 
 class pimd_tuning(ctypes.Structure):
@@ -88,6 +89,7 @@ _SIGNATURES = {
     "pimd_profile_stages": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "pimd_time_stages": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     "pimd_work_counts": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
+    "pimd_neighbor_rebuilds": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
     "pimd_sizes": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32)]),
     "pimd_last_error": (ctypes.c_char_p, [c_void_p]),
     "pimd_status_str": (ctypes.c_char_p, [c_int32]),
@@ -273,6 +275,12 @@ def pimd_work_counts(ctx):
     a, b, c = c_int64(0), c_int64(0), c_int64(0)
     st = lib().pimd_work_counts(c_void_p(ctx), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
     return st, a.value, b.value, c.value
+
+
+def pimd_neighbor_rebuilds(ctx):
+    n, f = c_int64(0), c_int64(0)
+    st = lib().pimd_neighbor_rebuilds(c_void_p(ctx), ctypes.byref(n), ctypes.byref(f))
+    return st, n.value, f.value
 
 
 def pimd_sizes(ctx):

@@ -413,6 +413,241 @@ void launch_cell_fill(const DevBuffers &d, const Sizes &z, hipStream_t s)
                        d.atom_slot, d.cell_start, d.cell_atoms, z.B);
 }
 
+// ---------------------------------------------------------------------------
+// Shared neighbour lists with a skin: one list per atom of the ring-polymer
+// centroids, with the cutoff widened by the skin, rebuilt only when some bead
+// has left the sphere of half the skin around its atom's centroid of the
+// last build; every bead's list is that list filtered with the float32
+// decision above.  If every bead-atom q^k_i is within s/2 of c_i (the build
+// centroid), a pair of bead k within R_c under the image shift n has
+// |c_i - c_j - n L| < R_c + s, so the minimum-image centroid distance is below
+// R_c + s too and the centroid list holds j; the filtered lists equal the
+// per-bead search key for key (same decision, same (element, row) order).
+// The guarantee needs the positions of the step itself within s/2 of the
+// centroids of the list: when the rebuild finds a bead already farther
+// than that from its fresh centroid (a ring spread wider than the skin), the
+// step's filter tests every atom of the bead instead.
+// flag[0]: rebuild request; flag[1]: this step's lists cannot be trusted.
+// ---------------------------------------------------------------------------
+
+// Wrap as k_wrap_bin (no cells) and flag a rebuild when a bead-atom's
+// unwrapped position is more than half the skin from its build centroid.
+__global__ __launch_bounds__(256) void k_wrap_skin(const float *__restrict__ q, const BeadInfo *__restrict__ beads,
+                                                   const int32_t *__restrict__ bead_of_ba,
+                                                   const int32_t *__restrict__ species_atom,
+                                                   const SysInfo *__restrict__ sys, const double4 *__restrict__ c0,
+                                                   double half_skin2, float4 *__restrict__ pos4,
+                                                   float4 *__restrict__ posu4, int32_t *__restrict__ flag, int B)
+{
+    const int ba = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ba == 0)
+        flag[1] = 0;
+    if (ba >= B)
+        return;
+    const BeadInfo bi = beads[bead_of_ba[ba]];
+    const int atom = sys[bi.sys].atom0 + (ba - bi.ba0);
+    const int z = species_atom[atom];
+    float x = q[3 * ba + 0], y = q[3 * ba + 1], w = q[3 * ba + 2];
+    posu4[ba] = make_float4(x, y, w, __int_as_float(z));
+    const double4 c = c0[atom];
+    const double dx = (double)x - c.x, dy = (double)y - c.y, dz = (double)w - c.z;
+    if (!(dx * dx + dy * dy + dz * dz <= half_skin2))   // also catches a non-finite position
+        atomicOr(&flag[0], 1);
+    x = wrap_coord(x, bi.L[0], bi.invL[0]);
+    y = wrap_coord(y, bi.L[1], bi.invL[1]);
+    w = wrap_coord(w, bi.L[2], bi.invL[2]);
+    pos4[ba] = make_float4(x, y, w, __int_as_float(z));
+}
+
+// Rebuild, step 1 (only when flagged): centroid of every atom over its beads,
+// and whether every bead is within s/2 of it.
+__global__ __launch_bounds__(256) void k_skin_centroids(const float4 *__restrict__ posu4,
+                                                        const SysInfo *__restrict__ sys,
+                                                        const int32_t *__restrict__ sys_of_atom,
+                                                        double half_skin2, int32_t *__restrict__ flag,
+                                                        double4 *__restrict__ c0, int A)
+{
+    if (flag[0] == 0)
+        return;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= A)
+        return;
+    const SysInfo S = sys[sys_of_atom[a]];
+    const int local = a - S.atom0;
+    double x = 0.0, y = 0.0, z = 0.0;
+    for (int k = 0; k < S.P; ++k) {
+        const float4 p = posu4[S.ba0 + k * S.N + local];
+        x += p.x;
+        y += p.y;
+        z += p.z;
+    }
+    const double inv = 1.0 / S.P;
+    x *= inv;
+    y *= inv;
+    z *= inv;
+    c0[a] = make_double4(x, y, z, 0.0);
+    for (int k = 0; k < S.P; ++k) {
+        const float4 p = posu4[S.ba0 + k * S.N + local];
+        const double dx = p.x - x, dy = p.y - y, dz = p.z - z;
+        if (!(dx * dx + dy * dy + dz * dz <= half_skin2)) {
+            atomicOr(&flag[1], 1);
+            break;
+        }
+    }
+}
+
+// Rebuild, step 2 (only when flagged): one wave per atom, every atom of its
+// system tested in FP64 (minimum image) against (R_c + s + 1e-3 A)^2, one pass
+// per element so the keys (element << 27) | local atom come out sorted.
+__global__ __launch_bounds__(256) void k_skin_lists(const double4 *__restrict__ c0, const SysInfo *__restrict__ sys,
+                                                    const int32_t *__restrict__ sys_of_atom,
+                                                    const int32_t *__restrict__ species_atom,
+                                                    const BeadInfo *__restrict__ beads,
+                                                    const int32_t *__restrict__ bead_of_ba, double reach2, int n_el,
+                                                    int Kc, const int32_t *__restrict__ flag,
+                                                    int32_t *__restrict__ keys, int32_t *__restrict__ cnt,
+                                                    unsigned long long *__restrict__ builds,
+                                                    uint32_t *__restrict__ status, int A)
+{
+    if (flag[0] == 0)
+        return;
+    const int lane = lane_id();
+    const int a = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        atomicAdd(builds, 1ull);
+    if (a >= A)
+        return;
+    const SysInfo S = sys[sys_of_atom[a]];
+    const BeadInfo bi = beads[bead_of_ba[S.ba0]];
+    const int il = a - S.atom0;
+    const double4 ci = c0[a];
+    int32_t *out = keys + (int64_t)a * Kc;
+    int count = 0;
+    for (int e = 0; e < n_el; ++e)
+        for (int j0 = 0; j0 < S.N; j0 += kWave) {
+            const int jl = j0 + lane;
+            bool acc = false;
+            if (jl < S.N && jl != il && species_atom[S.atom0 + jl] == e) {
+                const double4 cj = c0[S.atom0 + jl];
+                double dx = cj.x - ci.x, dy = cj.y - ci.y, dz = cj.z - ci.z;
+                dx -= bi.L64[0] * rint(dx * bi.invL64[0]);
+                dy -= bi.L64[1] * rint(dy * bi.invL64[1]);
+                dz -= bi.L64[2] * rint(dz * bi.invL64[2]);
+                acc = dx * dx + dy * dy + dz * dz < reach2;
+            }
+            const uint64_t m = __ballot(acc);
+            const int pos = count + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (acc && pos < Kc)
+                out[pos] = (e << kKeyShift) | jl;
+            count += __popcll(m);
+        }
+    if (lane == 0) {
+        cnt[a] = count < Kc ? count : Kc;
+        if (count > Kc)
+            atomicOr(status, kStatusOverflow);
+    }
+}
+
+// Every step: one wave per bead-atom row, its atom's centroid list filtered
+// with within_cutoff on the wrapped bead positions, written in order (the
+// candidates are sorted, and row = first row of the bead + local atom keeps
+// the order), with the element groups and the fence row of finish_list.
+// When flag[1] is set, every atom of the bead is a candidate, element by
+// element in row order (the same order).
+__global__ __launch_bounds__(256) void k_skin_filter(const float4 *__restrict__ pos4,
+                                                     const BeadInfo *__restrict__ beads,
+                                                     const int32_t *__restrict__ bead_of_ba,
+                                                     const SysInfo *__restrict__ sys,
+                                                     const int32_t *__restrict__ keys,
+                                                     const int32_t *__restrict__ cnt, int Kc, float rc2, int Kmax,
+                                                     int n_el, int32_t *__restrict__ flag,
+                                                     unsigned long long *__restrict__ full_scans,
+                                                     int32_t *__restrict__ nbr, int32_t *__restrict__ nbr_cnt,
+                                                     int32_t *__restrict__ nbr_grp, int32_t *__restrict__ fence,
+                                                     uint32_t *__restrict__ status, int B)
+{
+    const int lane = lane_id();
+    const bool scan_all = __builtin_amdgcn_readfirstlane(flag[1]) != 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        flag[0] = 0;   // this step's lists are built (the build kernels ran before)
+        if (scan_all)
+            atomicAdd(full_scans, 1ull);
+    }
+    const CentreRange cr = centre_range(B);
+    for (int i = cr.begin; i < cr.end; ++i) {
+        const BeadInfo bi = beads[bead_of_ba[i]];
+        const int atom = sys[bi.sys].atom0 + (i - bi.ba0);
+        const int n_cand = scan_all ? n_el * bi.n : cnt[atom];
+        const int32_t *cand = keys + (int64_t)atom * Kc;
+        const float4 pi = pos4[i];
+        int32_t *out = nbr + (int64_t)i * Kmax;
+        int count = 0;
+        int grp[kMaxElements] = {0, 0, 0, 0};
+        for (int t0 = 0; t0 < n_cand; t0 += kWave) {
+            const int t = t0 + lane;
+            int key = 0;
+            bool acc = false;
+            if (scan_all) {
+                // candidate t: element t / n, row ba0 + t % n (passes per element keep the order)
+                const int e = t / bi.n, j = bi.ba0 + (t - e * bi.n);
+                if (t < n_cand && j != i) {
+                    const float4 pj = pos4[j];
+                    acc = __float_as_int(pj.w) == e && within_cutoff(pi, pj, bi, rc2);
+                    key = (e << kKeyShift) | j;
+                }
+            } else if (t < n_cand) {
+                const int c = cand[t];
+                const int j = bi.ba0 + (c & (int)kRowMask);
+                acc = within_cutoff(pi, pos4[j], bi, rc2);
+                key = (c & ~(int)kRowMask) | j;
+            }
+            const uint64_t m = __ballot(acc);
+            const int pos = count + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            const bool keep = acc && pos < Kmax;
+            if (keep) {
+                out[pos] = key;
+                if ((pos & 15) == 0 && pos > 0 && (pos >> 4) < kFence)
+                    fence[(int64_t)i * kFence + (pos >> 4)] = key;
+            }
+#pragma unroll
+            for (int e = 0; e < kMaxElements; ++e)
+                grp[e] += __popcll(__ballot(keep && (key >> kKeyShift) == e));
+            count += __popcll(m);
+        }
+        if (count > Kmax && lane == 0)
+            atomicOr(status, kStatusOverflow);
+        const int K = count < Kmax ? count : Kmax;
+        if (lane < n_el) {
+            int c = grp[0];
+#pragma unroll
+            for (int e = 1; e < kMaxElements; ++e)
+                c = lane == e ? grp[e] : c;
+            nbr_grp[(int64_t)i * kMaxElements + lane] = c;
+        }
+        if (lane == 0)
+            nbr_cnt[i] = K;
+        if (lane < kFence && (lane == 0 || 16 * lane >= K))
+            fence[(int64_t)i * kFence + lane] = lane == 0 ? K : 0x7FFFFFFF;
+    }
+}
+
+void launch_skin_neighbors(const float *q, const DevBuffers &d, const Sizes &z, const SkinParams &sp, float rc2,
+                           int n_el, const Tuning &tn, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_wrap_skin, dim3((z.B + 255) / 256), dim3(256), 0, s, q, d.beads, d.bead_of_ba,
+                       d.species_atom, d.sys, d.skin_c0, sp.half_skin2, d.pos4, d.posu4, d.skin_flag, z.B);
+    hipLaunchKernelGGL(k_skin_centroids, dim3((z.n_atoms_total + 255) / 256), dim3(256), 0, s, d.posu4, d.sys,
+                       d.sys_of_atom, sp.half_skin2, d.skin_flag, d.skin_c0, z.n_atoms_total);
+    hipLaunchKernelGGL(k_skin_lists, dim3((z.n_atoms_total + 3) / 4), dim3(256), 0, s, d.skin_c0, d.sys,
+                       d.sys_of_atom, d.species_atom, d.beads, d.bead_of_ba, sp.reach2, n_el, sp.Kc, d.skin_flag,
+                       d.skin_keys, d.skin_cnt, d.skin_builds, d.status, z.n_atoms_total);
+    hipLaunchKernelGGL(k_skin_filter, dim3(centre_grid(z.B, tn)), dim3(kWave * tn.centre_waves), 0, s, d.pos4,
+                       d.beads, d.bead_of_ba, d.sys, d.skin_keys, d.skin_cnt, sp.Kc, rc2, z.Kmax, n_el, d.skin_flag,
+                       d.skin_builds + 1, d.nbr, d.nbr_cnt, d.nbr_grp, d.nbr_fence, d.status, z.B);
+}
+
 // Candidates staged per cell: up to kMaxCand stencil atoms (27 cells of ~30).
 constexpr int kMaxCand = 1536;
 

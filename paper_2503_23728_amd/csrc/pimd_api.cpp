@@ -39,6 +39,8 @@ struct Plan {
     int n_sys = 0, n_el = 0, B = 0, n_beads = 0, n_atoms = 0, ncol = 0, total_cells = 0, n_units = 0;
     int D = 0, Dp = 0, Kmax = 0, max_P = 1, n_rad = 0, n_ang_eta = 0;
     int angular = 0;                           // 0: G4, 1: G5 angular functions
+    double skin = 0.0;                         // shared centroid lists: skin (0: per-bead cell lists)
+    int Kc = 0;                                // slots per centroid list
     bool any_periodic = false, any_open = false, bpnn = false, gfn = false;
     bool nl = false;                           // neighbour lists (the energy model or the direct-force head)
     int gfn_H = 0, gfn_L = 0;
@@ -196,6 +198,14 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
     }
     pl.n_sys = cfg->n_systems;
     pl.Kmax = cfg->max_neighbors == 0 ? 128 : cfg->max_neighbors;
+    if (!(cfg->neighbor_skin_A >= 0.0) || !std::isfinite(cfg->neighbor_skin_A))
+        return fail(err, PIMD_E_ARG, "neighbor_skin_A must be >= 0");
+    if (cfg->neighbor_skin_A > 0.0) {
+        if (!pl.nl)
+            return fail(err, PIMD_E_UNSUPPORTED, "neighbor_skin_A needs a neural potential");
+        pl.skin = cfg->neighbor_skin_A;
+        pl.Kc = 3 * pl.Kmax;
+    }
     int64_t B = 0, nb = 0, na = 0, cells = 0;
     for (int s = 0; s < cfg->n_systems; ++s) {
         const int N = cfg->n_atoms[s], P = cfg->n_beads[s];
@@ -225,6 +235,8 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
             pl.any_box = true;
         } else {
             pl.any_open = true;
+            if (pl.skin > 0.0)
+                return fail(err, PIMD_E_UNSUPPORTED, "neighbor_skin_A needs a box for every system");
         }
         pl.nc.push_back(nc);
         const int per_bead = zero || !pl.nl ? 0 : nc[0] * nc[1] * nc[2];
@@ -349,6 +361,14 @@ Layout make_layout(const Plan &pl)
         L.add("nbr_grp", B * kMaxElements * 4);
         L.add("nbr_fence", B * kFence * 4);
     }
+    if (pl.skin > 0.0) {
+        L.add("skin_keys", (size_t)pl.n_atoms * pl.Kc * 4);
+        L.add("skin_cnt", (size_t)pl.n_atoms * 4);
+        L.add("skin_c0", (size_t)pl.n_atoms * 32);
+        L.add("skin_flag", 8);
+        L.add("skin_builds", 16);
+        L.add("sys_of_atom", (size_t)pl.n_atoms * 4);
+    }
     if (pl.gfn) {
         L.add("gfn_params", pl.gfn_floats * 4);
         L.add("gfn_nodes", (size_t)(pl.gfn_L + 1) * B * pl.gfn_H * 4);
@@ -454,6 +474,7 @@ struct pimd_ctx {
     // metadynamics: parameters, host mirrors of the step and hill counters
     // (the capacity check of pimd_step), deposition switch of the force pass
     MetadParams mp{};
+    SkinParams skin{};                 // shared centroid lists (z.skin)
     double bias_factor = 0.0;
     double *fes_grid = nullptr, *fes_out = nullptr;
     int64_t host_step = 0;
@@ -494,6 +515,10 @@ void launch_force_stage(pimd_ctx *c, int stage, const float *q, float *E_out, fl
     hipStream_t s = c->stream;
     switch (stage) {
     case 0:
+        if (z.skin) {
+            launch_skin_neighbors(q, d, z, c->skin, c->dp.rc2, c->pl.n_el, c->tn, s);
+            break;
+        }
         if (z.any_periodic)
             launch_zero_i32(d.cell_count, z.total_cells, s);
         launch_wrap_bin(q, d, z, s);
@@ -741,6 +766,14 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     d.dEdG = (float *)at("dEdG");
     d.vslot = (float4 *)at("vslot");
     d.g5_mom = pl.angular ? (float *)at("g5_mom") : nullptr;
+    if (pl.skin > 0.0) {
+        d.skin_keys = (int32_t *)at("skin_keys");
+        d.skin_cnt = (int32_t *)at("skin_cnt");
+        d.skin_c0 = (double4 *)at("skin_c0");
+        d.skin_flag = (int32_t *)at("skin_flag");
+        d.skin_builds = (unsigned long long *)at("skin_builds");
+        d.sys_of_atom = (int32_t *)at("sys_of_atom");
+    }
     d.mlp_f32 = (float *)at("mlp_f32");
     d.mlp_bf16 = (uint16_t *)at("mlp_bf16");
     d.mlp_f64 = (double *)at("mlp_f64");
@@ -780,6 +813,11 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     }
     z.any_open = pl.any_open ? 1 : 0;
     z.any_box = pl.any_box ? 1 : 0;
+    z.skin = pl.skin > 0.0 ? 1 : 0;
+    if (z.skin) {
+        const double reach = mv.cutoff + pl.skin + 1e-3;
+        c->skin = SkinParams{0.25 * pl.skin * pl.skin, reach * reach, pl.Kc};
+    }
 
     // ---- host tables
     std::vector<BeadInfo> beads;
@@ -901,6 +939,19 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     push(d.beads, beads.data(), beads.size() * sizeof(BeadInfo));
     push(d.bead_of_ba, bead_of_ba.data(), bead_of_ba.size() * 4);
     push(d.species_atom, cfg->species, (size_t)pl.n_atoms * 4);
+    std::vector<int32_t> sys_of_atom;
+    std::vector<double> skin_c0;
+    const int32_t skin_init[2] = {1, 0};           // the first force evaluation builds the lists
+    const unsigned long long builds0[2] = {0, 0};
+    if (pl.skin > 0.0) {
+        for (int s = 0; s < pl.n_sys; ++s)
+            sys_of_atom.insert(sys_of_atom.end(), cfg->n_atoms[s], s);
+        skin_c0.assign((size_t)pl.n_atoms * 4, 0.0);
+        push(d.sys_of_atom, sys_of_atom.data(), sys_of_atom.size() * 4);
+        push(d.skin_c0, skin_c0.data(), skin_c0.size() * 8);
+        push(d.skin_flag, skin_init, sizeof(skin_init));
+        push(d.skin_builds, builds0, sizeof(builds0));
+    }
     push(d.mass_atom, mass_atom.data(), mass_atom.size() * 4);
     push(d.sys, c->sys_host.data(), c->sys_host.size() * sizeof(SysInfo));
     push(d.modes, modes.data(), modes.size() * sizeof(ModeInfo));
@@ -2000,6 +2051,22 @@ pimd_status pimd_work_counts(pimd_ctx *ctx, int64_t *pairs, int64_t *triplets, i
     *pairs = (int64_t)h[0];
     *triplets = (int64_t)h[1];
     *triplets_in_range = (int64_t)h[2];
+    return PIMD_OK;
+}
+
+pimd_status pimd_neighbor_rebuilds(pimd_ctx *ctx, int64_t *builds, int64_t *full_scans)
+{
+    if (!ctx || !builds || !full_scans)
+        return PIMD_E_ARG;
+    if (!ctx->z.skin) {
+        ctx->err = "no shared neighbour lists (neighbor_skin_A is 0)";
+        return PIMD_E_STATE;
+    }
+    unsigned long long h[2] = {0, 0};
+    HIPCHK(ctx, hipMemcpyAsync(h, ctx->d.skin_builds, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    *builds = (int64_t)h[0];
+    *full_scans = (int64_t)h[1];
     return PIMD_OK;
 }
 

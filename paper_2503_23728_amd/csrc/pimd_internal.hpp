@@ -166,6 +166,13 @@ struct DevBuffers {
     int32_t *nbr_fence;            // [B][kFence]: list count, then every 16th key (reverse-slot search)
     float *xhat, *dEdG, *E_atom;
     float *g5_mom;           // G5: per centre [element][eta][kG5Mom] moments, kept for the adjoint
+    // shared neighbour lists with a skin (neighbor_skin_A > 0)
+    int32_t *skin_keys;      // [atoms][Kc] (element << 27) | atom within its system, sorted
+    int32_t *skin_cnt;       // [atoms]
+    double4 *skin_c0;        // [atoms] centroid at the last build
+    int32_t *skin_flag;      // [0] rebuild before this step's filter, [1] the step's lists cannot be trusted
+    unsigned long long *skin_builds;   // [0] builds, [1] evaluations that scanned every atom of the bead
+    int32_t *sys_of_atom;    // [atoms]
     float4 *vslot;
     float *vir_atom, *W_bead;
     double *heat, *dke_part;       // heat bath per system; O-step energy changes per unit (2 halves)
@@ -229,6 +236,13 @@ struct Sizes {
     int32_t any_periodic;   // some system has a box (cell lists)
     int32_t any_open;       // some system has none (all-pairs lists)
     int32_t any_box;        // some system has a box (minimum image of the metadynamics CVs)
+    int32_t skin;           // shared centroid lists with a skin instead of per-bead cell lists
+};
+
+struct SkinParams {
+    double half_skin2;      // (skin / 2)^2: a bead-atom farther from its build centroid forces a rebuild
+    double reach2;          // (cutoff + skin + 1e-3 A)^2 of the centroid lists
+    int32_t Kc;             // slots per centroid list
 };
 
 // Order in which the per-centre kernels visit the rows: cell order within
@@ -236,7 +250,7 @@ struct Sizes {
 // row order itself (null).
 inline const int32_t *centre_order(const DevBuffers &d, const Sizes &z)
 {
-    return z.any_periodic ? d.cell_atoms : nullptr;
+    return z.any_periodic && !z.skin ? d.cell_atoms : nullptr;
 }
 
 void launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
@@ -285,6 +299,10 @@ void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &d
 
 // Raise the dynamic-LDS limit of kernels whose LDS grows with Kmax or P.
 hipError_t configure_descriptor_lds(const DescParams &dp);
+// neighbour stage with shared centroid lists: wrap and drift check, rebuild when
+// flagged (centroids, lists), per-bead filter into nbr / nbr_cnt / nbr_grp / fence
+void launch_skin_neighbors(const float *q, const DevBuffers &d, const Sizes &z, const SkinParams &sp, float rc2,
+                           int n_el, const Tuning &tn, hipStream_t s);
 // G5 angular functions (dp.angular = 1): forward (xhat, g5_mom) and adjoint (vslot, vir_atom)
 hipError_t configure_g5_lds(const DescParams &dp);
 void launch_descriptors_g5(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn,

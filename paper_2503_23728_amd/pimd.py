@@ -90,7 +90,7 @@ ANGULAR = {"g4": 0, "g5": 1}     # PIMD_ANGULAR_G4, PIMD_ANGULAR_G5
 
 
 def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
-                omega=0.0, max_neighbors=0, masses=None, metad=None, transform="normal-modes"):
+                omega=0.0, max_neighbors=0, masses=None, metad=None, transform="normal-modes", neighbor_skin=0.0):
     """Build the pimd_config (and the storage it points into).
 
     systems: sequence with n_atoms, n_beads, temperature, box, species.
@@ -157,6 +157,7 @@ def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", p
     cfg.metad = ctypes.pointer(make_metad(metad, keep)) if metad is not None else None
     cfg.transform = {"normal-modes": abi.PIMD_TRANSFORM_NORMAL_MODES, "staging": abi.PIMD_TRANSFORM_STAGING,
                      "primitive": abi.PIMD_TRANSFORM_PRIMITIVE}[transform]
+    cfg.neighbor_skin_A = float(neighbor_skin)
     return cfg, keep
 
 
@@ -165,13 +166,14 @@ class Pimd:
 
     def __init__(self, systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
                  omega=0.0, max_neighbors=0, masses=None, device="cuda:0", stream=None, metad=None,
-                 transform="normal-modes"):
+                 transform="normal-modes", neighbor_skin=0.0):
         self.device = torch.device(device)
         self.metad = metad
         self.systems = list(systems)
         self.model, self.precision, self.max_neighbors = model, precision, max_neighbors
         self.cfg, self._keep = make_config(self.systems, model, dt, tau0, pile_lambda, seed, precision,
-                                           potential, omega, max_neighbors, masses, metad, transform)
+                                           potential, omega, max_neighbors, masses, metad, transform,
+                                           neighbor_skin)
         st, nbytes = abi.pimd_workspace_size(self.cfg)
         _check(st)
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
@@ -304,6 +306,13 @@ class Pimd:
         st, ms = abi.pimd_time_stages(self.ctx, int(n_reps))
         _check(st, self.ctx)
         return dict(zip(abi.FORCE_STAGE_NAMES, ms))
+
+    def neighbor_rebuilds(self):
+        """(builds of the shared centroid lists, force evaluations that scanned whole
+        beads because a ring was wider than the skin), contexts with a skin."""
+        st, n, f = abi.pimd_neighbor_rebuilds(self.ctx)
+        _check(st, self.ctx)
+        return n, f
 
     def work_counts(self):
         """(pairs, triplets, triplets with r_jk < cutoff) of the last force evaluation."""

@@ -47,6 +47,22 @@ def test_workspace_grows_with_max_neighbors(lib):
     assert b > a
 
 
+def test_skin_configs(lib):
+    # shared centroid lists: a box for every system, skin >= 0; their buffers sized per atom
+    wl = S.workload(2)
+    a = abi.pimd_workspace_size(_cfg(wl)[0])[1]
+    st, b = abi.pimd_workspace_size(_cfg(wl, neighbor_skin=2.0)[0])
+    n = wl.systems[0].n_atoms
+    assert st == abi.PIMD_OK and n * (3 * 128 * 4 + 40) <= b - a <= n * (3 * 128 * 4 + 40) + 4096
+    assert abi.pimd_workspace_size(_cfg(wl, neighbor_skin=-1.0)[0])[0] == abi.PIMD_E_ARG
+    assert abi.pimd_workspace_size(_cfg(wl, neighbor_skin=float("nan"))[0])[0] == abi.PIMD_E_ARG
+    fad = S.workload(1)
+    assert abi.pimd_workspace_size(_cfg(fad, neighbor_skin=1.0)[0])[0] == abi.PIMD_E_UNSUPPORTED
+    harm = make_config(wl.systems, None, 0.5, 100.0, 1.0, 1, potential="harmonic", omega=0.01,
+                       masses=np.array([1.0, 16.0]), neighbor_skin=1.0)[0]
+    assert abi.pimd_workspace_size(harm)[0] == abi.PIMD_E_UNSUPPORTED
+
+
 def test_g5_workspace_holds_the_moments(lib):
     # G5: per centre 84 floats of moments per (element, eta) on top of the G4 buffers
     wl = S.workload(2)
