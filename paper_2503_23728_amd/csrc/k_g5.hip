@@ -498,10 +498,15 @@ hipError_t configure_g5_lds(const DescParams &dp)
     return e;
 }
 
+// The forward always runs one wave per workgroup: its 21.8 kB of LDS per wave
+// (water) make bigger workgroups leave CUs idle (water 4096: 3.81 ms at one
+// wave, 4.51 at two, 6.29 at four), whatever shape suits the other kernels.
 void launch_descriptors_g5(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn,
                            hipStream_t s)
 {
-    const int wpg = tn.centre_waves, grid = centre_grid(z.B, tn);
+    Tuning one = tn;
+    one.centre_waves = 1;
+    const int wpg = 1, grid = centre_grid(z.B, one);
     const size_t lds = wpg * g5_forward_wave_bytes(dp);
     if (dp.n_ang_eta == 2)
         hipLaunchKernelGGL(k_descriptors_g5<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads,
