@@ -266,10 +266,11 @@ def main():
     ap.add_argument("--angular", default="g4", choices=["g4", "g5"],
                     help="angular symmetry functions: G4 (triplets within the cutoff) or G5 (no r_jk "
                          "factors, summed through spherical-harmonic moments)")
-    ap.add_argument("--skin", type=float, default=2.0,
+    ap.add_argument("--skin", type=float, default=None,
                     help="neighbour lists shared by the beads of a ring polymer: centroid lists with this skin "
                          "(A), filtered per bead (the same lists); 0 searches every bead's cells each step; "
-                         "ignored for systems without a box")
+                         "ignored for systems without a box.  Default 2 for the energy model, 0 for the "
+                         "direct-force head (its random weights heat the rings past any skin)")
     ap.add_argument("--metad", action="store_true",
                     help="add the well-tempered metadynamics bias of the workload's study (s_dimer or XRD CV)")
     args = ap.parse_args()
@@ -291,7 +292,8 @@ def main():
         wl = S.with_g5(wl)
     B = wl.bead_atoms
     spec = S.metad_spec(wl, max_hills=4096) if args.metad else None
-    skin = args.skin if all(np.any(np.asarray(s.box) > 0) for s in wl.systems) else 0.0
+    skin = args.skin if args.skin is not None else (0.0 if gfn_mode else 2.0)
+    skin = skin if all(np.any(np.asarray(s.box) > 0) for s in wl.systems) else 0.0
     eng = Pimd.from_workload(wl, precision=args.precision, device=device, metad=spec, transform=args.transform,
                              neighbor_skin=skin)
     q, p = S.initial_state(wl)
