@@ -50,6 +50,24 @@ def test_skin_lists_match_oracle_and_forces_match_cell_lists(name, skin):
     assert eng.neighbor_rebuilds()[0] >= 1
 
 
+@pytest.mark.parametrize("model", ["g5", "gfn"])
+def test_skin_gives_the_same_forces_for_every_model(model):
+    # the G5 descriptors and the direct-force head read the same lists
+    wl = S.with_g5(S.workload(2)) if model == "g5" else S.gfn_workload(2)
+    say(f"skin with the {model} model")
+    q = torch.from_numpy(S.perturbed_beads(wl, 0.05, seed=6)).cuda()
+    ref = _engine(wl, precision="bf16")
+    eng = _engine(wl, precision="bf16", neighbor_skin=2.0)
+    _, F0, _ = ref.energy_forces(q)
+    _, F1, _ = eng.energy_forces(q)
+    assert torch.equal(F0, F1)
+    q0, p0 = S.initial_state(wl)
+    for e in (ref, eng):
+        e.set_state(torch.from_numpy(q0).cuda(), torch.from_numpy(p0).cuda(), step=0)
+        e.step(10)
+    assert torch.equal(ref.get_state()[0], eng.get_state()[0])
+
+
 def test_skin_ring_wider_than_skin_scans_whole_beads():
     # every 7th bead-atom moved 25 A in unwrapped coordinates (not a box vector):
     # those rings are far wider than the skin, so the step tests every atom
