@@ -112,6 +112,28 @@ def test_skin_trajectory_is_bitwise_the_cell_list_trajectory(skin):
         assert builds < 10 and scans == 0
 
 
+def test_skin_long_trajectory_is_bitwise_the_cell_list_trajectory():
+    # 400 steps (100 fs) from the classical geometry: the rings spread to their
+    # thermal size and the centroids diffuse, so the lists are rebuilt many times
+    wl = S.workload(2)
+    say("skin: 400-step trajectory")
+    q0, p0 = S.initial_state(wl)
+    states = []
+    for kw in ({}, {"neighbor_skin": 2.0}):
+        eng = _engine(wl, precision="bf16", **kw)
+        eng.set_state(torch.from_numpy(q0).cuda(), torch.from_numpy(p0).cuda(), step=0)
+        eng.step(400)
+        q, p, F, step = eng.get_state()
+        states.append((q.clone(), p.clone(), F.clone(), step, eng.estimators()[0]))
+    builds, scans = eng.neighbor_rebuilds()
+    say(f"  {builds} builds, {scans} whole-bead scans in 400 steps")
+    (qa, pa, Fa, sa, ea), (qb, pb, Fb, sb, eb) = states
+    assert sa == sb == 400
+    assert torch.equal(qa, qb) and torch.equal(pa, pb) and torch.equal(Fa, Fb)
+    assert ea == eb
+    assert 5 <= builds <= 200 and scans == 0
+
+
 def test_skin_rebuilds_after_positions_jump():
     wl = S.workload(2)
     say("skin: a jump of the positions forces a rebuild")
