@@ -171,6 +171,7 @@ class Pimd:
         self.metad = metad
         self.systems = list(systems)
         self.model, self.precision, self.max_neighbors = model, precision, max_neighbors
+        self.neighbor_skin = float(neighbor_skin)
         self.cfg, self._keep = make_config(self.systems, model, dt, tau0, pile_lambda, seed, precision,
                                            potential, omega, max_neighbors, masses, metad, transform,
                                            neighbor_skin)
@@ -272,7 +273,7 @@ class Pimd:
         props = torch.cuda.get_device_properties(self.device)
         arch = getattr(props, "gcnArchName", props.name)
         return tuning.config_key(arch, props.multi_processor_count, self.systems, self.model, self.precision,
-                                 self.max_neighbors)
+                                 self.max_neighbors, self.neighbor_skin)
 
     def autotune(self, n_reps=5, cache=True):
         """Pick the fastest launch shape for this batch (needs the state set).

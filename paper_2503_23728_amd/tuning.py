@@ -22,7 +22,7 @@ def cache_path():
     return os.path.join(os.path.expanduser("~"), ".cache", "paper_2503_23728_amd", "tuning.json")
 
 
-def config_key(arch, n_cu, systems, model, precision, max_neighbors):
+def config_key(arch, n_cu, systems, model, precision, max_neighbors, neighbor_skin=0.0):
     """Hash of everything the fastest launch shape can depend on."""
     desc = {
         "arch": arch, "cu": int(n_cu), "precision": precision, "kmax": int(max_neighbors),
@@ -35,6 +35,10 @@ def config_key(arch, n_cu, systems, model, precision, max_neighbors):
         desc["model"] = {"elements": int(model.n_elements), "n_rad": int(model.n_rad),
                          "n_ang_eta": len(model.ang_eta), "hidden": [int(h) for h in model.hidden],
                          "cutoff": float(model.cutoff)}
+        if getattr(model, "angular", "g4") != "g4":
+            desc["model"]["angular"] = model.angular
+    if neighbor_skin:
+        desc["skin"] = round(float(neighbor_skin), 4)
     blob = json.dumps(desc, sort_keys=True).encode()
     return hashlib.sha256(blob).hexdigest()[:32]
 

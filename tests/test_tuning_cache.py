@@ -22,6 +22,15 @@ def test_key_is_stable_and_sensitive_to_what_the_shape_depends_on():
     assert k != _key(wl, max_neighbors=64)
 
 
+def test_key_separates_the_angular_form_and_the_shared_lists():
+    wl = S.workload(2)
+    base = _key(wl)
+    assert _key(S.with_g5(wl)) != base
+    assert _key(wl, neighbor_skin=2.0) != base
+    assert _key(wl, neighbor_skin=2.0) != _key(wl, neighbor_skin=3.0)
+    assert _key(wl, neighbor_skin=0.0) == base
+
+
 def test_key_ignores_system_order():
     wl = S.workload(4)
     a = tuning.config_key("gfx950", 256, wl.systems, wl.model, "bf16", 0)
