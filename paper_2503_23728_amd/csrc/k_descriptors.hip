@@ -15,7 +15,10 @@
 // (e1 < e2) or a triangle n1 (n1 - 1)/2 (e1 = e2) of slot pairs; the pairs of
 // a block are flattened and dealt to the 64 lanes.  Per-neighbour terms
 // (displacement, r, f_c, exp(-eta r^2) f_c and their r-derivatives) are staged
-// once in LDS and shared by all triplets of the centre.
+// once in LDS and shared by all triplets of the centre.  The forward keeps
+// the slot pairs it finds within range (one 16-bit (j, k) slot pair per
+// triplet, in processing order, with a count per element-pair block), and the
+// adjoint walks that list instead of testing every slot pair again.
 #include "device_common.hpp"
 #include "pair_terms.hpp"
 
@@ -194,13 +197,12 @@ __device__ __forceinline__ float exp_small(float neg_eta_log2e, float x)
 }
 
 // LDS per wave of the adjoint kernel: records D and E (16 B each per slot),
-// the FP64 slot accumulators (24 B per slot), the dE/dG row and the pair
-// queue, rounded up to 16 bytes.  The pair terms of the radial part never
-// leave registers.
+// the FP64 slot accumulators (24 B per slot) and the dE/dG row, rounded up to
+// 16 bytes.  The pair terms of the radial part never leave registers.
 __host__ __device__ inline size_t adjoint_wave_bytes(const DescParams &dp)
 {
     const int Dcap = (dp.D + 3) & ~3;
-    const size_t b = (size_t)56 * dp.Kmax + 4 * (size_t)Dcap + 4 * (size_t)kQueue;
+    const size_t b = (size_t)56 * dp.Kmax + 4 * (size_t)Dcap;
     return (b + 15) & ~(size_t)15;
 }
 
@@ -216,7 +218,8 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
                                                      const int32_t *__restrict__ nbr_cnt,
                                                      const int32_t *__restrict__ nbr_grp,
                                                      const float *__restrict__ norm, DescParams dp,
-                                                     float *__restrict__ xhat, int B)
+                                                     float *__restrict__ xhat, uint16_t *__restrict__ tri_pairs,
+                                                     int32_t *__restrict__ tri_cnt, int B)
 {
     extern __shared__ float4 lds4[];
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -267,16 +270,23 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
             if (lane < 32 && f < Frad)
                 Gs[f] = acc;
         }
-        // angular blocks
+        // angular blocks; the in-range slot pairs are kept for the adjoint
+        uint16_t *kept = tri_pairs + (int64_t)i * tri_capacity(dp.Kmax);
+        int n_kept = 0;
         int pair = 0;
         for (int e1 = 0; e1 < dp.n_el; ++e1)
             for (int e2 = e1; e2 < dp.n_el; ++e2, ++pair) {
                 const BlockWalk bw(e1, e2, gcnt, goff);
+                const int kept0 = n_kept;
                 float acc[8 * NETA];
 #pragma unroll
                 for (int q = 0; q < 8 * NETA; ++q)
                     acc[q] = 0.0f;
                 for_each_triplet_in_range(bw, rec.D, dp.rc2, queue, [&](uint32_t ia, uint32_t ic, bool ok) {
+                    // the pairs of a batch occupy its first lanes
+                    if (ok)
+                        kept[n_kept + lane] = (uint16_t)((ia << 8) | ic);
+                    n_kept += __popcll(__ballot(ok));
                     if (!ok)
                         return;
                     const float4 Ad = rec.D[ia], Cd = rec.D[ic], Ae = rec.E[ia], Ce = rec.E[ic];
@@ -305,6 +315,8 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
                         acc[ie * 8 + 7] += m8 * R;
                     }
                 });
+                if (lane == 0)
+                    tri_cnt[(int64_t)i * kMaxPairs + pair] = n_kept - kept0;
                 // lane l ends with the total of feature l / (64 / (8 NETA))
                 const float tot = transpose_reduce<8 * NETA>(acc);
                 constexpr int group = 64 / (8 * NETA);
@@ -330,13 +342,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                                                  const int32_t *__restrict__ bead_of_ba, const int32_t *__restrict__ order,
                                                  const int32_t *__restrict__ nbr,
                                                  const int32_t *__restrict__ nbr_cnt,
-                                                 const int32_t *__restrict__ nbr_grp,
-                                                 const float *__restrict__ dEdG, DescParams dp,
+                                                 const float *__restrict__ dEdG,
+                                                 const uint16_t *__restrict__ tri_pairs,
+                                                 const int32_t *__restrict__ tri_cnt, DescParams dp,
                                                  float4 *__restrict__ vslot, float *__restrict__ vir_atom, int B)
 {
     extern __shared__ float4 lds4[];
     const int lane = lane_id(), w = threadIdx.x >> 6;
-    const int Dcap = (dp.D + 3) & ~3;
     char *base = reinterpret_cast<char *>(lds4) + w * adjoint_wave_bytes(dp);
     const Recs rec{reinterpret_cast<float4 *>(base), reinterpret_cast<float4 *>(base) + dp.Kmax, nullptr};
     // slot accumulators: three FP64 arrays (one per component, so gathers by
@@ -345,7 +357,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     double *vy = vx + dp.Kmax;
     double *vz = vy + dp.Kmax;
     float *gl = reinterpret_cast<float *>(base + 56 * dp.Kmax);
-    uint32_t *queue = reinterpret_cast<uint32_t *>(gl + Dcap);
     const int Frad = dp.n_el * dp.n_rad;
     const float nel0 = -dp.ang_eta[0] * 1.4426950408889634f, nel1 = -dp.ang_eta[1] * 1.4426950408889634f;
     const float inv_rc = 1.0f / dp.rc;
@@ -375,13 +386,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 vy[n] = (double)(c * d.y);
                 vz[n] = (double)(c * d.z);
             });
-        int gcnt[kMaxElements], goff[kMaxElements];
-        group_offsets(nbr_grp, i, dp.n_el, gcnt, goff);
         wave_sync();
+        const uint16_t *kept = tri_pairs + (int64_t)i * tri_capacity(dp.Kmax);
         int pair = 0;
         for (int e1 = 0; e1 < dp.n_el; ++e1)
             for (int e2 = e1; e2 < dp.n_el; ++e2, ++pair) {
-                const BlockWalk bw(e1, e2, gcnt, goff);
+                const int n_pairs_block = tri_cnt[(int64_t)i * kMaxPairs + pair];
                 // block coefficients with the 2^(1-zeta) factors folded in, and
                 // those of dS/dcos (d/dc (1 +- c)^zeta = +-zeta (1 +- c)^(zeta-1))
                 float gq[8 * NETA], gd[8 * NETA];
@@ -401,7 +411,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     h[6] = 8.0f * g[7];
                     h[7] = 0.0f;
                 }
-                for_each_triplet_in_range(bw, rec.D, dp.rc2, queue, [&](uint32_t ia, uint32_t ic, bool ok) {
+                auto body = [&](uint32_t ia, uint32_t ic, bool ok) {
                     if (!ok)
                         return;
                     const float4 Ad = rec.D[ia], Cd = rec.D[ic], Ae = rec.E[ia], Ce = rec.E[ic];
@@ -457,7 +467,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     atomicAdd(&vx[ic], (double)(kc * Cd.x + kb * Ad.x));
                     atomicAdd(&vy[ic], (double)(kc * Cd.y + kb * Ad.y));
                     atomicAdd(&vz[ic], (double)(kc * Cd.z + kb * Ad.z));
-                });
+                };
+                // the block's in-range slot pairs as the forward found them, one per lane
+                for (int t0 = 0; t0 < n_pairs_block; t0 += kWave) {
+                    const int t = t0 + lane;
+                    const uint32_t v = t < n_pairs_block ? kept[t] : 0u;
+                    body(v >> 8, v & 0xFFu, t < n_pairs_block);
+                }
+                kept += n_pairs_block;
             }
         wave_sync();
         float W[16];
@@ -677,10 +694,12 @@ void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &d
     const size_t lds = wpg * forward_wave_bytes(dp);
     if (dp.n_ang_eta == 2)
         hipLaunchKernelGGL(k_descriptors<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, z.B);
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, d.tri_pairs,
+                           d.tri_cnt, z.B);
     else
         hipLaunchKernelGGL(k_descriptors<1>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, z.B);
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, d.tri_pairs,
+                           d.tri_cnt, z.B);
 }
 
 void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s)
@@ -689,10 +708,12 @@ void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, c
     const size_t lds = wpg * adjoint_wave_bytes(dp);
     if (dp.n_ang_eta == 2)
         hipLaunchKernelGGL(k_adjoint<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_grp, d.dEdG, dp, d.vslot, d.vir_atom, z.B);
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.tri_pairs, d.tri_cnt, dp,
+                           d.vslot, d.vir_atom, z.B);
     else
         hipLaunchKernelGGL(k_adjoint<1>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_grp, d.dEdG, dp, d.vslot, d.vir_atom, z.B);
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.tri_pairs, d.tri_cnt, dp,
+                           d.vslot, d.vir_atom, z.B);
 }
 
 void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &dp, unsigned long long *counts,

@@ -380,6 +380,10 @@ Layout make_layout(const Plan &pl)
         L.add("vslot", B * K * 16);
         if (pl.angular)
             L.add("g5_mom", B * (size_t)pl.n_el * pl.n_ang_eta * kG5Mom * 4);
+        else {
+            L.add("tri_pairs", B * (size_t)tri_capacity((int)K) * 2);
+            L.add("tri_cnt", B * (size_t)kMaxPairs * 4);
+        }
         L.add("mlp_f32", pl.mlp_f32_floats * 4);
         L.add("mlp_bf16", pl.mlp_bf16_elems * 2);
         L.add("mlp_f64", pl.mlp_f64_elems * 8);
@@ -766,6 +770,8 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     d.dEdG = (float *)at("dEdG");
     d.vslot = (float4 *)at("vslot");
     d.g5_mom = pl.angular ? (float *)at("g5_mom") : nullptr;
+    d.tri_pairs = pl.bpnn && !pl.angular ? (uint16_t *)at("tri_pairs") : nullptr;
+    d.tri_cnt = pl.bpnn && !pl.angular ? (int32_t *)at("tri_cnt") : nullptr;
     if (pl.skin > 0.0) {
         d.skin_keys = (int32_t *)at("skin_keys");
         d.skin_cnt = (int32_t *)at("skin_cnt");

@@ -10,6 +10,10 @@ namespace pimd {
 constexpr int kWave = 64;
 constexpr int kMaxElements = 4;
 constexpr int kMaxRad = 32;
+constexpr int kMaxPairs = kMaxElements * (kMaxElements + 1) / 2;   // element-pair blocks
+// slot pairs kept per centre by the descriptor forward for the adjoint: every
+// unordered pair of Kmax slots (16 bits each: the two slot indices)
+__host__ __device__ inline int64_t tri_capacity(int Kmax) { return (int64_t)Kmax * (Kmax - 1) / 2; }
 constexpr int kG5Mom = 84;       // floats per (centre, element, eta) of the G5 moments: 81 and 3 of padding
 constexpr int kMaxBeads = 128;
 constexpr int kMaxNeighbors = 256;
@@ -166,6 +170,8 @@ struct DevBuffers {
     int32_t *nbr_fence;            // [B][kFence]: list count, then every 16th key (reverse-slot search)
     float *xhat, *dEdG, *E_atom;
     float *g5_mom;           // G5: per centre [element][eta][kG5Mom] moments, kept for the adjoint
+    uint16_t *tri_pairs;     // G4: per centre the in-range slot pairs (j << 8 | k) found by the forward
+    int32_t *tri_cnt;        // G4: per centre [kMaxPairs] pairs per element-pair block
     // shared neighbour lists with a skin (neighbor_skin_A > 0)
     int32_t *skin_keys;      // [atoms][Kc] (element << 27) | atom within its system, sorted
     int32_t *skin_cnt;       // [atoms]
