@@ -152,5 +152,54 @@ __device__ __forceinline__ CentreRange centre_range(int B)
     return CentreRange{b0 < B ? b0 : B, b0 + per < B ? b0 + per : B};
 }
 
-}  // namespace pimd
+// Slot of key_i in atom j's sorted list, or -1 when it is not there.  The
+// lists are symmetric, so this is where atom j keeps the pair (j, i): j's
+// fence row (its count and every 16th key) picks the 16-key segment, the
+// segment the slot; two dependent 64-byte reads instead of a binary search.
+__device__ __forceinline__ int reverse_slot(const int32_t *__restrict__ nbr, const int32_t *__restrict__ fence,
+                                            int Kmax, int j, int key_i)
+{
+    const int4 *fj = reinterpret_cast<const int4 *>(fence + (int64_t)j * kFence);
+    int seg = 0, Kj = 0;
+#pragma unroll
+    for (int c = 0; c < kFence / 4; ++c) {
+        const int4 f = fj[c];
+        Kj = c == 0 ? f.x : Kj;
+        seg += (c > 0 && f.x <= key_i) + (f.y <= key_i) + (f.z <= key_i) + (f.w <= key_i);
+    }
+    const int4 *sj = reinterpret_cast<const int4 *>(nbr + (int64_t)j * Kmax + 16 * seg);
+    int m = 16 * seg, hit = -1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int4 kv = 16 * seg + 4 * c < Kj ? sj[c] : make_int4(0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF);
+        const int kk[4] = {kv.x, kv.y, kv.z, kv.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int pos = 16 * seg + 4 * c + e;
+            const bool in = pos < Kj;
+            m += (in && kk[e] < key_i) ? 1 : 0;
+            hit = (in && kk[e] == key_i) ? pos : hit;
+        }
+    }
+    return hit >= 0 && hit == m ? hit : -1;
+}
 
+// After the adjoint of centre i: v[i][n] goes to its own slot and to the
+// slot that atom j = nbr[i][n] keeps for i, so that the force assembly reads
+// both terms of every pair from atom i's own rows.  An asymmetric list (never
+// built by the neighbour kernels) is reported as an overflow.
+__device__ __forceinline__ void store_slot_values(const int32_t *__restrict__ nbr, const int32_t *__restrict__ fence,
+                                                  int Kmax, int i, int key_i, int n, const float4 &v,
+                                                  float4 *__restrict__ vslot, float4 *__restrict__ vrev,
+                                                  bool &missing)
+{
+    vslot[(int64_t)i * Kmax + n] = v;
+    const int j = nbr[(int64_t)i * Kmax + n] & (int)kRowMask;
+    const int hit = reverse_slot(nbr, fence, Kmax, j, key_i);
+    if (hit >= 0)
+        vrev[(int64_t)j * Kmax + hit] = v;
+    else
+        missing = true;
+}
+
+}  // namespace pimd

@@ -197,12 +197,12 @@ __device__ __forceinline__ float exp_small(float neg_eta_log2e, float x)
 }
 
 // LDS per wave of the adjoint kernel: records D and E (16 B each per slot),
-// the FP64 slot accumulators (24 B per slot) and the dE/dG row, rounded up to
-// 16 bytes.  The pair terms of the radial part never leave registers.
+// the FP64 slot accumulators (24 B per slot), the dE/dG row and the reverse
+// slots (2 B per slot), rounded up to 16 bytes.  The pair terms of the radial part never leave registers.
 __host__ __device__ inline size_t adjoint_wave_bytes(const DescParams &dp)
 {
     const int Dcap = (dp.D + 3) & ~3;
-    const size_t b = (size_t)56 * dp.Kmax + 4 * (size_t)Dcap;
+    const size_t b = (size_t)58 * dp.Kmax + 4 * (size_t)Dcap;
     return (b + 15) & ~(size_t)15;
 }
 
@@ -344,8 +344,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                                                  const int32_t *__restrict__ nbr_cnt,
                                                  const float *__restrict__ dEdG,
                                                  const uint16_t *__restrict__ tri_pairs,
-                                                 const int32_t *__restrict__ tri_cnt, DescParams dp,
-                                                 float4 *__restrict__ vslot, float *__restrict__ vir_atom, int B)
+                                                 const int32_t *__restrict__ tri_cnt,
+                                                 const int32_t *__restrict__ fence, DescParams dp,
+                                                 float4 *__restrict__ vslot, float4 *__restrict__ vrev,
+                                                 float *__restrict__ vir_atom, uint32_t *__restrict__ status, int B)
 {
     extern __shared__ float4 lds4[];
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -357,6 +359,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     double *vy = vx + dp.Kmax;
     double *vz = vy + dp.Kmax;
     float *gl = reinterpret_cast<float *>(base + 56 * dp.Kmax);
+    // reverse slots: where atom j = nbr[i][n] keeps the pair (j, i)
+    int16_t *rev = reinterpret_cast<int16_t *>(gl + ((dp.D + 3) & ~3));
     const int Frad = dp.n_el * dp.n_rad;
     const float nel0 = -dp.ang_eta[0] * 1.4426950408889634f, nel1 = -dp.ang_eta[1] * 1.4426950408889634f;
     const float inv_rc = 1.0f / dp.rc;
@@ -369,12 +373,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const float4 pi = posu[i];
         for (int f = lane; f < dp.D; f += kWave)
             gl[f] = dEdG[(int64_t)i * dp.D + f];
+        const int key_i = (__float_as_int(pi.w) << kKeyShift) | i;
         wave_sync();
-        // staging, and the radial part of every slot in the lane that staged
-        // it: v = sum_s g[e,s] dG2/dr * d/r
+        // staging, the reverse slots (their loads overlap the triplet work of
+        // this centre), and the radial part of every slot in the lane that
+        // staged it: v = sum_s g[e,s] dG2/dr * d/r
         const int K = stage_neighbors<NETA, true>(
             i, pi, bi, nbr, nbr_cnt, posu, dp, rec,
             [&](int n, int e, const float3 &d, float r, float r_lo, float inv_r, float fc, float dfc) {
+                const int j = nbr[(int64_t)i * dp.Kmax + n] & (int)kRowMask;
+                rev[n] = (int16_t)reverse_slot(nbr, fence, dp.Kmax, j, key_i);
                 float acc = 0.0f;
                 for (int t = 0; t < dp.n_rad; ++t) {
                     const float x = (r - dp.rad_center[t]) + (r_lo - dp.rad_center_lo[t]);
@@ -481,10 +489,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
         for (int q = 0; q < 16; ++q)
             W[q] = 0.0f;
-        float4 *out = vslot + (int64_t)i * dp.Kmax;
+        bool missing = false;
         for (int n = lane; n < K; n += kWave) {
             const float4 v = make_float4((float)vx[n], (float)vy[n], (float)vz[n], 0.0f);
-            out[n] = v;
+            vslot[(int64_t)i * dp.Kmax + n] = v;
+            const int j = nbr[(int64_t)i * dp.Kmax + n] & (int)kRowMask;
+            const int hit = rev[n];
+            if (hit >= 0)
+                vrev[(int64_t)j * dp.Kmax + hit] = v;
+            else
+                missing = true;
             const float4 dn = rec.D[n];
             const float dd[3] = {dn.x, dn.y, dn.z}, vv[3] = {v.x, v.y, v.z};
 #pragma unroll
@@ -497,22 +511,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const float tot = transpose_reduce<16>(W);
         if ((lane & 3) == 0 && (lane >> 2) < 9)
             vir_atom[(int64_t)i * 9 + (lane >> 2)] = tot;
+        const bool any_missing = __ballot(missing) != 0;
+        if (lane == 0 && any_missing)
+            atomicOr(status, kStatusOverflow);
         wave_sync();
     }
 }
 
 // ---------------------------------------------------------------------------
-// forces: F_i = sum_slots v[i][n] - sum_slots v[j][slot of i in j's list]
-// (the list is symmetric, so the reverse slot is the rank of i's key in j's
-// sorted list: two dependent 64-byte reads, j's fence row and one 16-key
-// segment, instead of a binary search); no atomics, fixed summation order.
+// forces: F_i = sum_slots v[i][n] - sum_slots v[j][slot of i in j's list];
+// the adjoint stored the second term at i's slot n (vrev), so both are
+// contiguous rows of i.  No atomics, fixed summation order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_assemble_forces(const float4 *__restrict__ pos4,
-                                                         const int32_t *__restrict__ order,
-                                                         const int32_t *__restrict__ nbr,
+__global__ __launch_bounds__(256) void k_assemble_forces(const int32_t *__restrict__ order,
                                                          const int32_t *__restrict__ nbr_cnt,
-                                                         const int32_t *__restrict__ fence,
-                                                         const float4 *__restrict__ vslot, int Kmax,
+                                                         const float4 *__restrict__ vslot,
+                                                         const float4 *__restrict__ vrev, int Kmax,
                                                          float *__restrict__ F, uint32_t *__restrict__ status, int B)
 {
     const int lane = lane_id();
@@ -521,60 +535,24 @@ __global__ __launch_bounds__(256) void k_assemble_forces(const float4 *__restric
         // wave-uniform: the per-centre values below live in scalar registers
         const int i = __builtin_amdgcn_readfirstlane(order ? order[ci] : ci);
         const int K = nbr_cnt[i];
-        const int key_i = (__float_as_int(pos4[i].w) << kKeyShift) | i;
-        const int32_t *row = nbr + (int64_t)i * Kmax;
         double fx = 0.0, fy = 0.0, fz = 0.0;
-        bool missing = false;
         for (int n = lane; n < K; n += kWave) {
             const float4 v = vslot[(int64_t)i * Kmax + n];
-            const int j = row[n] & (int)kRowMask;
-            // reverse slot of i in j's sorted list: j's fence row (its count
-            // and every 16th key) picks the 16-key segment, the segment the slot
-            const int4 *fj = reinterpret_cast<const int4 *>(fence + (int64_t)j * kFence);
-            int seg = 0, Kj = 0;
-#pragma unroll
-            for (int c = 0; c < kFence / 4; ++c) {
-                const int4 f = fj[c];
-                Kj = c == 0 ? f.x : Kj;
-                seg += (c > 0 && f.x <= key_i) + (f.y <= key_i) + (f.z <= key_i) + (f.w <= key_i);
-            }
-            const int4 *sj = reinterpret_cast<const int4 *>(nbr + (int64_t)j * Kmax + 16 * seg);
-            int m = 16 * seg, hit = -1;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int4 kv = 16 * seg + 4 * c < Kj ? sj[c] : make_int4(0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF,
-                                                                            0x7FFFFFFF);
-                const int kk[4] = {kv.x, kv.y, kv.z, kv.w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int pos = 16 * seg + 4 * c + e;
-                    const bool in = pos < Kj;
-                    m += (in && kk[e] < key_i) ? 1 : 0;
-                    hit = (in && kk[e] == key_i) ? pos : hit;
-                }
-            }
+            const float4 u = vrev[(int64_t)i * Kmax + n];
             fx += (double)v.x;
             fy += (double)v.y;
             fz += (double)v.z;
-            if (hit >= 0 && hit == m) {
-                const float4 u = vslot[(int64_t)j * Kmax + hit];
-                fx -= (double)u.x;
-                fy -= (double)u.y;
-                fz -= (double)u.z;
-            } else {
-                missing = true;
-            }
+            fx -= (double)u.x;
+            fy -= (double)u.y;
+            fz -= (double)u.z;
         }
         fx = wave_sum_f64(fx);
         fy = wave_sum_f64(fy);
         fz = wave_sum_f64(fz);
-        const bool any_missing = __ballot(missing) != 0;
         if (lane == 0) {
             F[3 * (int64_t)i + 0] = (float)fx;
             F[3 * (int64_t)i + 1] = (float)fy;
             F[3 * (int64_t)i + 2] = (float)fz;
-            if (any_missing)
-                atomicOr(status, kStatusOverflow);
             if (!(isfinite(fx) && isfinite(fy) && isfinite(fz)))
                 atomicOr(status, kStatusNonFinite);
         }
@@ -708,12 +686,12 @@ void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, c
     const size_t lds = wpg * adjoint_wave_bytes(dp);
     if (dp.n_ang_eta == 2)
         hipLaunchKernelGGL(k_adjoint<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.tri_pairs, d.tri_cnt, dp,
-                           d.vslot, d.vir_atom, z.B);
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.tri_pairs, d.tri_cnt, d.nbr_fence,
+                           dp, d.vslot, d.vrev, d.vir_atom, d.status, z.B);
     else
         hipLaunchKernelGGL(k_adjoint<1>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.tri_pairs, d.tri_cnt, dp,
-                           d.vslot, d.vir_atom, z.B);
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.tri_pairs, d.tri_cnt, d.nbr_fence,
+                           dp, d.vslot, d.vrev, d.vir_atom, d.status, z.B);
 }
 
 void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &dp, unsigned long long *counts,
@@ -726,8 +704,8 @@ void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &d
 
 void launch_assemble_forces(const DevBuffers &d, const Sizes &z, float *F, const Tuning &tn, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_assemble_forces, dim3(centre_grid(z.B, tn)), dim3(kWave * tn.centre_waves), 0, s, d.pos4,
-                       centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_fence, d.vslot, z.Kmax, F, d.status, z.B);
+    hipLaunchKernelGGL(k_assemble_forces, dim3(centre_grid(z.B, tn)), dim3(kWave * tn.centre_waves), 0, s,
+                       centre_order(d, z), d.nbr_cnt, d.vslot, d.vrev, z.Kmax, F, d.status, z.B);
 }
 
 void launch_bead_sums(const DevBuffers &d, const Sizes &z, float *E_bead, float *W_bead, bool virial, hipStream_t s)

@@ -325,8 +325,10 @@ __global__ __launch_bounds__(256) void k_adjoint_g5(const float4 *__restrict__ p
                                                     const int32_t *__restrict__ order, const int32_t *__restrict__ nbr,
                                                     const int32_t *__restrict__ nbr_cnt,
                                                     const float *__restrict__ dEdG, const float *__restrict__ mom,
-                                                    DescParams dp, float4 *__restrict__ vslot,
-                                                    float *__restrict__ vir_atom, int B)
+                                                    const int32_t *__restrict__ fence, DescParams dp,
+                                                    float4 *__restrict__ vslot, float4 *__restrict__ vrev,
+                                                    float *__restrict__ vir_atom, uint32_t *__restrict__ status,
+                                                    int B)
 {
     extern __shared__ float lds[];
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -387,7 +389,8 @@ __global__ __launch_bounds__(256) void k_adjoint_g5(const float4 *__restrict__ p
             W[q] = 0.0f;
         const int K = nbr_cnt[i];
         const int32_t *row = nbr + (int64_t)i * dp.Kmax;
-        float4 *out = vslot + (int64_t)i * dp.Kmax;
+        const int key_i = (__float_as_int(pi.w) << kKeyShift) | i;
+        bool missing = false;
         for (int n = lane; n < K; n += kWave) {
             const int key = row[n];
             const int e = key >> kKeyShift;
@@ -466,7 +469,7 @@ __global__ __launch_bounds__(256) void k_adjoint_g5(const float4 *__restrict__ p
             const float ut = ux * tx + uy * ty + uz * tz;
             const float4 v = make_float4(sr * ux + (tx - ut * ux) * inv_r, sr * uy + (ty - ut * uy) * inv_r,
                                          sr * uz + (tz - ut * uz) * inv_r, 0.0f);
-            out[n] = v;
+            store_slot_values(nbr, fence, dp.Kmax, i, key_i, n, v, vslot, vrev, missing);
             const float dd[3] = {d.x, d.y, d.z}, vv[3] = {v.x, v.y, v.z};
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -477,6 +480,9 @@ __global__ __launch_bounds__(256) void k_adjoint_g5(const float4 *__restrict__ p
         const float tot = transpose_reduce<16>(W);
         if ((lane & 3) == 0 && (lane >> 2) < 9)
             vir_atom[(int64_t)i * 9 + (lane >> 2)] = tot;
+        const bool any_missing = __ballot(missing) != 0;
+        if (lane == 0 && any_missing)
+            atomicOr(status, kStatusOverflow);
         wave_sync();
     }
 }
@@ -524,10 +530,12 @@ void launch_adjoint_g5(const DevBuffers &d, const Sizes &z, const DescParams &dp
     const size_t lds = wpg * sizeof(float) * g5_adjoint_wave_floats(dp);
     if (dp.n_ang_eta == 2)
         hipLaunchKernelGGL(k_adjoint_g5<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.g5_mom, dp, d.vslot, d.vir_atom, z.B);
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.g5_mom, d.nbr_fence, dp, d.vslot, d.vrev,
+                           d.vir_atom, d.status, z.B);
     else
         hipLaunchKernelGGL(k_adjoint_g5<1>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.g5_mom, dp, d.vslot, d.vir_atom, z.B);
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.g5_mom, d.nbr_fence, dp, d.vslot, d.vrev,
+                           d.vir_atom, d.status, z.B);
 }
 
 }  // namespace pimd

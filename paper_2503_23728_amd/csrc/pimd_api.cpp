@@ -378,6 +378,7 @@ Layout make_layout(const Plan &pl)
         L.add("xhat", B * D * 4);
         L.add("dEdG", B * D * 4);
         L.add("vslot", B * K * 16);
+        L.add("vrev", B * K * 16);
         if (pl.angular)
             L.add("g5_mom", B * (size_t)pl.n_el * pl.n_ang_eta * kG5Mom * 4);
         else {
@@ -769,6 +770,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     d.xhat = (float *)at("xhat");
     d.dEdG = (float *)at("dEdG");
     d.vslot = (float4 *)at("vslot");
+    d.vrev = (float4 *)at("vrev");
     d.g5_mom = pl.angular ? (float *)at("g5_mom") : nullptr;
     d.tri_pairs = pl.bpnn && !pl.angular ? (uint16_t *)at("tri_pairs") : nullptr;
     d.tri_cnt = pl.bpnn && !pl.angular ? (int32_t *)at("tri_cnt") : nullptr;

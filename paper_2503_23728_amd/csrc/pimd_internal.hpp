@@ -179,7 +179,8 @@ struct DevBuffers {
     int32_t *skin_flag;      // [0] rebuild before this step's filter, [1] the step's lists cannot be trusted
     unsigned long long *skin_builds;   // [0] builds, [1] evaluations that scanned every atom of the bead
     int32_t *sys_of_atom;    // [atoms]
-    float4 *vslot;
+    float4 *vslot;                 // [B][Kmax] v[i][n] = dE/d d_(i, slot n)
+    float4 *vrev;                  // [B][Kmax] v[j][slot of i in j's list], at i's slot n of j
     float *vir_atom, *W_bead;
     double *heat, *dke_part;       // heat bath per system; O-step energy changes per unit (2 halves)
     int64_t *step;
