@@ -36,12 +36,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
 
 def measured_traffic(workload):
     """HBM bytes per k_adjoint launch from the committed rocprofv3 counters, when
-    they were taken on this workload and the kernel source has not changed since."""
+    they were taken on this workload and the kernel's sources have not changed
+    since (SHA-256 over the listed files, in order)."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    except (OSError, ValueError, KeyError):
+        src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])
+    except (OSError, ValueError, KeyError, TypeError):
         return None
     if rec.get("workload") != workload or hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
         return None

@@ -389,13 +389,20 @@ pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled);
  *   mlp_waves     waves per workgroup of the BF16 MLP: 4 (two 16-column
  *                 tiles of every layer each) or 8 (default; one each, so each
  *                 row tile's chain of MFMAs is half as long); the FP32 and
- *                 FP64 MLPs ignore it */
+ *                 FP64 MLPs ignore it
+ *   force_rows    energy network only: 1 = the adjoint also stores each
+ *                 slot value v[i][n] at the slot where atom j = nbr[i][n]
+ *                 keeps the pair, and the force assembly reads two contiguous
+ *                 rows per atom (default with a box); 0 = the assembly looks
+ *                 the reverse slot up itself (default without).  The forces
+ *                 are bitwise the same */
 typedef struct {
     int32_t centre_waves;
     int32_t centre_grid;
     int32_t mlp_rows;
     int32_t neighbor_cells;
     int32_t mlp_waves;
+    int32_t force_rows;
 } pimd_tuning;
 
 pimd_status pimd_get_tuning(const pimd_ctx *ctx, pimd_tuning *out);
@@ -411,7 +418,8 @@ pimd_status pimd_set_tuning(pimd_ctx *ctx, const pimd_tuning *t);
  * stream) for every centre_waves x centre_grid candidate (centre_grid from 0
  * and 2, 4, 8, 16 workgroups per compute unit), then for every mlp_rows
  * candidate with the best centre shape, then for the other neighbor_cells
- * value (systems with a box), then for the other mlp_waves (BF16 MLP); applies
+ * value (systems with a box), then for the other mlp_waves (BF16 MLP), then
+ * for the other force_rows (energy network); applies
  * the fastest (a candidate
  * replaces the current best only when at least 1% faster) and writes it to
  * best (may be NULL).  The state does not advance; the forces left behind are

@@ -184,16 +184,19 @@ __device__ __forceinline__ int reverse_slot(const int32_t *__restrict__ nbr, con
     return hit >= 0 && hit == m ? hit : -1;
 }
 
-// After the adjoint of centre i: v[i][n] goes to its own slot and to the
-// slot that atom j = nbr[i][n] keeps for i, so that the force assembly reads
-// both terms of every pair from atom i's own rows.  An asymmetric list (never
-// built by the neighbour kernels) is reported as an overflow.
+// After the adjoint of centre i: v[i][n] goes to its own slot and, with
+// vrev, to the slot that atom j = nbr[i][n] keeps for i, so that the force
+// assembly reads both terms of every pair from atom i's own rows.  An
+// asymmetric list (never built by the neighbour kernels) is reported as an
+// overflow.
 __device__ __forceinline__ void store_slot_values(const int32_t *__restrict__ nbr, const int32_t *__restrict__ fence,
                                                   int Kmax, int i, int key_i, int n, const float4 &v,
                                                   float4 *__restrict__ vslot, float4 *__restrict__ vrev,
                                                   bool &missing)
 {
     vslot[(int64_t)i * Kmax + n] = v;
+    if (!vrev)
+        return;
     const int j = nbr[(int64_t)i * Kmax + n] & (int)kRowMask;
     const int hit = reverse_slot(nbr, fence, Kmax, j, key_i);
     if (hit >= 0)

@@ -375,14 +375,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             gl[f] = dEdG[(int64_t)i * dp.D + f];
         const int key_i = (__float_as_int(pi.w) << kKeyShift) | i;
         wave_sync();
-        // staging, the reverse slots (their loads overlap the triplet work of
-        // this centre), and the radial part of every slot in the lane that
+        // staging, the reverse slots when the slot values are also stored
+        // there (their loads overlap the triplet work of this centre), and
+        // the radial part of every slot in the lane that
         // staged it: v = sum_s g[e,s] dG2/dr * d/r
         const int K = stage_neighbors<NETA, true>(
             i, pi, bi, nbr, nbr_cnt, posu, dp, rec,
             [&](int n, int e, const float3 &d, float r, float r_lo, float inv_r, float fc, float dfc) {
-                const int j = nbr[(int64_t)i * dp.Kmax + n] & (int)kRowMask;
-                rev[n] = (int16_t)reverse_slot(nbr, fence, dp.Kmax, j, key_i);
+                if (vrev) {
+                    const int j = nbr[(int64_t)i * dp.Kmax + n] & (int)kRowMask;
+                    rev[n] = (int16_t)reverse_slot(nbr, fence, dp.Kmax, j, key_i);
+                }
                 float acc = 0.0f;
                 for (int t = 0; t < dp.n_rad; ++t) {
                     const float x = (r - dp.rad_center[t]) + (r_lo - dp.rad_center_lo[t]);
@@ -493,12 +496,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         for (int n = lane; n < K; n += kWave) {
             const float4 v = make_float4((float)vx[n], (float)vy[n], (float)vz[n], 0.0f);
             vslot[(int64_t)i * dp.Kmax + n] = v;
-            const int j = nbr[(int64_t)i * dp.Kmax + n] & (int)kRowMask;
-            const int hit = rev[n];
-            if (hit >= 0)
-                vrev[(int64_t)j * dp.Kmax + hit] = v;
-            else
-                missing = true;
+            if (vrev) {
+                const int j = nbr[(int64_t)i * dp.Kmax + n] & (int)kRowMask;
+                const int hit = rev[n];
+                if (hit >= 0)
+                    vrev[(int64_t)j * dp.Kmax + hit] = v;
+                else
+                    missing = true;
+            }
             const float4 dn = rec.D[n];
             const float dd[3] = {dn.x, dn.y, dn.z}, vv[3] = {v.x, v.y, v.z};
 #pragma unroll
@@ -519,12 +524,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 }
 
 // ---------------------------------------------------------------------------
-// forces: F_i = sum_slots v[i][n] - sum_slots v[j][slot of i in j's list];
-// the adjoint stored the second term at i's slot n (vrev), so both are
-// contiguous rows of i.  No atomics, fixed summation order.
+// forces: F_i = sum_slots v[i][n] - sum_slots v[j][slot of i in j's list].
+// With vrev the adjoint stored the second term at i's slot n, so both are
+// contiguous rows of i; without, it is gathered from j's row through the
+// reverse-slot search.  The same sums in the same order either way, no
+// atomics.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_assemble_forces(const int32_t *__restrict__ order,
+__global__ __launch_bounds__(256) void k_assemble_forces(const float4 *__restrict__ pos4,
+                                                         const int32_t *__restrict__ order,
+                                                         const int32_t *__restrict__ nbr,
                                                          const int32_t *__restrict__ nbr_cnt,
+                                                         const int32_t *__restrict__ fence,
                                                          const float4 *__restrict__ vslot,
                                                          const float4 *__restrict__ vrev, int Kmax,
                                                          float *__restrict__ F, uint32_t *__restrict__ status, int B)
@@ -536,9 +546,20 @@ __global__ __launch_bounds__(256) void k_assemble_forces(const int32_t *__restri
         const int i = __builtin_amdgcn_readfirstlane(order ? order[ci] : ci);
         const int K = nbr_cnt[i];
         double fx = 0.0, fy = 0.0, fz = 0.0;
+        bool missing = false;
         for (int n = lane; n < K; n += kWave) {
             const float4 v = vslot[(int64_t)i * Kmax + n];
-            const float4 u = vrev[(int64_t)i * Kmax + n];
+            float4 u = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (vrev) {
+                u = vrev[(int64_t)i * Kmax + n];
+            } else {
+                const int j = nbr[(int64_t)i * Kmax + n] & (int)kRowMask;
+                const int hit = reverse_slot(nbr, fence, Kmax, j, (__float_as_int(pos4[i].w) << kKeyShift) | i);
+                if (hit >= 0)
+                    u = vslot[(int64_t)j * Kmax + hit];
+                else
+                    missing = true;
+            }
             fx += (double)v.x;
             fy += (double)v.y;
             fz += (double)v.z;
@@ -549,10 +570,13 @@ __global__ __launch_bounds__(256) void k_assemble_forces(const int32_t *__restri
         fx = wave_sum_f64(fx);
         fy = wave_sum_f64(fy);
         fz = wave_sum_f64(fz);
+        const bool any_missing = __ballot(missing) != 0;
         if (lane == 0) {
             F[3 * (int64_t)i + 0] = (float)fx;
             F[3 * (int64_t)i + 1] = (float)fy;
             F[3 * (int64_t)i + 2] = (float)fz;
+            if (any_missing)
+                atomicOr(status, kStatusOverflow);
             if (!(isfinite(fx) && isfinite(fy) && isfinite(fz)))
                 atomicOr(status, kStatusNonFinite);
         }
@@ -687,11 +711,11 @@ void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, c
     if (dp.n_ang_eta == 2)
         hipLaunchKernelGGL(k_adjoint<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
                            centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.tri_pairs, d.tri_cnt, d.nbr_fence,
-                           dp, d.vslot, d.vrev, d.vir_atom, d.status, z.B);
+                           dp, d.vslot, tn.force_rows ? d.vrev : nullptr, d.vir_atom, d.status, z.B);
     else
         hipLaunchKernelGGL(k_adjoint<1>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
                            centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.tri_pairs, d.tri_cnt, d.nbr_fence,
-                           dp, d.vslot, d.vrev, d.vir_atom, d.status, z.B);
+                           dp, d.vslot, tn.force_rows ? d.vrev : nullptr, d.vir_atom, d.status, z.B);
 }
 
 void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &dp, unsigned long long *counts,
@@ -704,8 +728,9 @@ void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &d
 
 void launch_assemble_forces(const DevBuffers &d, const Sizes &z, float *F, const Tuning &tn, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_assemble_forces, dim3(centre_grid(z.B, tn)), dim3(kWave * tn.centre_waves), 0, s,
-                       centre_order(d, z), d.nbr_cnt, d.vslot, d.vrev, z.Kmax, F, d.status, z.B);
+    hipLaunchKernelGGL(k_assemble_forces, dim3(centre_grid(z.B, tn)), dim3(kWave * tn.centre_waves), 0, s, d.pos4,
+                       centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_fence, d.vslot, tn.force_rows ? d.vrev : nullptr,
+                       z.Kmax, F, d.status, z.B);
 }
 
 void launch_bead_sums(const DevBuffers &d, const Sizes &z, float *E_bead, float *W_bead, bool virial, hipStream_t s)

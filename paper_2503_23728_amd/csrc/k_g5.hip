@@ -530,11 +530,13 @@ void launch_adjoint_g5(const DevBuffers &d, const Sizes &z, const DescParams &dp
     const size_t lds = wpg * sizeof(float) * g5_adjoint_wave_floats(dp);
     if (dp.n_ang_eta == 2)
         hipLaunchKernelGGL(k_adjoint_g5<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.g5_mom, d.nbr_fence, dp, d.vslot, d.vrev,
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.g5_mom, d.nbr_fence, dp, d.vslot,
+                           tn.force_rows ? d.vrev : nullptr,
                            d.vir_atom, d.status, z.B);
     else
         hipLaunchKernelGGL(k_adjoint_g5<1>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.g5_mom, d.nbr_fence, dp, d.vslot, d.vrev,
+                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.g5_mom, d.nbr_fence, dp, d.vslot,
+                           tn.force_rows ? d.vrev : nullptr,
                            d.vir_atom, d.status, z.B);
 }
 

@@ -815,6 +815,9 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     z.Kmax = pl.Kmax;
     z.any_periodic = pl.any_periodic ? 1 : 0;
     c->tn.nl_cells = pl.total_cells >= 4096 ? 1 : 0;
+    // dense periodic liquids hide the reverse-slot loads behind the adjoint's
+    // triplet work; a few neighbours per atom leave nothing to hide them behind
+    c->tn.force_rows = pl.any_periodic ? 1 : 0;
     if (c->precision == PIMD_PREC_BF16_MLP || c->precision == PIMD_PREC_BF16_PLAIN) {
         c->tn.mlp_rows = 32;    // 32-row tiles, one 16-column tile per wave: fastest at 64 to 16384 bead-atoms
         c->tn.mlp_waves = 8;
@@ -1788,7 +1791,7 @@ pimd_status pimd_get_tuning(const pimd_ctx *ctx, pimd_tuning *out)
     if (!ctx || !out)
         return PIMD_E_ARG;
     *out = pimd_tuning{ctx->tn.centre_waves, ctx->tn.centre_grid, ctx->tn.mlp_rows, ctx->tn.nl_cells,
-                       ctx->tn.mlp_waves};
+                       ctx->tn.mlp_waves, ctx->tn.force_rows};
     return PIMD_OK;
 }
 
@@ -1821,16 +1824,17 @@ pimd_status pimd_set_tuning(pimd_ctx *ctx, const pimd_tuning *t)
     const bool waves_ok = t->centre_waves == 1 || t->centre_waves == 2 || t->centre_waves == 4;
     const bool rows_ok = t->mlp_rows == 16 || t->mlp_rows == 32 || t->mlp_rows == 64;
     if (!waves_ok || !rows_ok || t->centre_grid < 0 || (t->neighbor_cells != 0 && t->neighbor_cells != 1) ||
-        (t->mlp_waves != 4 && t->mlp_waves != 8)) {
+        (t->mlp_waves != 4 && t->mlp_waves != 8) || (t->force_rows != 0 && t->force_rows != 1)) {
         ctx->err = "tuning: centre_waves in {1, 2, 4}, centre_grid >= 0, mlp_rows in {16, 32, 64}, "
-                   "neighbor_cells in {0, 1}, mlp_waves in {4, 8}";
+                   "neighbor_cells in {0, 1}, mlp_waves in {4, 8}, force_rows in {0, 1}";
         return PIMD_E_ARG;
     }
     if (ctx->precision == PIMD_PREC_FP64_MLP && t->mlp_rows != 16) {
         ctx->err = "the FP64 MLP runs 16-row tiles only";
         return PIMD_E_UNSUPPORTED;
     }
-    return apply_tuning(ctx, Tuning{t->centre_waves, t->centre_grid, t->mlp_rows, t->neighbor_cells, t->mlp_waves});
+    return apply_tuning(ctx, Tuning{t->centre_waves, t->centre_grid, t->mlp_rows, t->neighbor_cells, t->mlp_waves,
+                                    t->force_rows});
 }
 
 // Mean milliseconds of one force evaluation of the current positions.
@@ -1900,7 +1904,7 @@ pimd_status pimd_autotune(pimd_ctx *ctx, int32_t n_reps, pimd_tuning *best)
                 Tuning cand = top;
                 cand.centre_waves = waves;
                 cand.centre_grid = per_cu * n_cu;
-                if (cand.centre_grid >= centre_grid(ctx->z.B, Tuning{waves, 0, 16, 0, 4}))
+                if (cand.centre_grid >= centre_grid(ctx->z.B, Tuning{waves, 0, 16, 0, 4, 0}))
                     continue;   // no fewer workgroups than one wave per centre gives
                 if (cand.centre_waves == cur.centre_waves && cand.centre_grid == cur.centre_grid)
                     continue;
@@ -1925,6 +1929,12 @@ pimd_status pimd_autotune(pimd_ctx *ctx, int32_t n_reps, pimd_tuning *best)
         if (ctx->z.any_periodic) {
             Tuning cand = top;
             cand.nl_cells = 1 - top.nl_cells;
+            if ((st = consider(cand)) != PIMD_OK)
+                return st;
+        }
+        if (ctx->pl.bpnn) {
+            Tuning cand = top;
+            cand.force_rows = 1 - top.force_rows;
             if ((st = consider(cand)) != PIMD_OK)
                 return st;
         }

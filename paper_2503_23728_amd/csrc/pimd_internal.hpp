@@ -228,6 +228,8 @@ struct Tuning {
     int32_t mlp_rows;      // rows per MLP workgroup tile: 16, 32 or 64
     int32_t nl_cells;      // periodic neighbour search per cell with the stencil in LDS (1) or per centre (0)
     int32_t mlp_waves;     // waves per BF16 MLP workgroup: 4 (two column tiles each) or 8 (one each)
+    int32_t force_rows;    // 1: the adjoint also stores each slot value at the neighbour's reverse slot and the
+                           // force assembly reads rows; 0: the assembly gathers through the reverse-slot search
 };
 
 // Workgroups of a per-centre launch over B centres.

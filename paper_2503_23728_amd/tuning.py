@@ -12,7 +12,7 @@ import hashlib
 import json
 import os
 
-FIELDS = ("centre_waves", "centre_grid", "mlp_rows", "neighbor_cells", "mlp_waves")
+FIELDS = ("centre_waves", "centre_grid", "mlp_rows", "neighbor_cells", "mlp_waves", "force_rows")
 
 
 def cache_path():

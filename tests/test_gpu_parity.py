@@ -379,9 +379,11 @@ def test_every_launch_shape_gives_bitwise_identical_results(name, prec):
             for rows in (16, 32, 64):
                 cells = (waves + rows // 16) % 2
                 mw = 8 if (grid + rows) % 3 else 4
-                eng.set_tuning(centre_waves=waves, centre_grid=grid, mlp_rows=rows, neighbor_cells=cells, mlp_waves=mw)
+                fr = (waves + grid + rows // 16) % 2
+                eng.set_tuning(centre_waves=waves, centre_grid=grid, mlp_rows=rows, neighbor_cells=cells, mlp_waves=mw,
+                               force_rows=fr)
                 E, F, W = eng.energy_forces(q, virial=True)
-                shape = (waves, grid, rows, cells, mw)
+                shape = (waves, grid, rows, cells, mw, fr)
                 assert torch.equal(E, E0) and torch.equal(F, F0) and torch.equal(W, W0), shape
                 assert torch.equal(eng.debug_descriptors(), x0), shape
 
@@ -398,7 +400,7 @@ def test_autotune_picks_a_valid_shape_and_the_cache_reapplies_it(tmp_path, monke
     shape, cached = a.autotune(n_reps=2)
     assert not cached
     assert shape["centre_waves"] in (1, 2, 4) and shape["mlp_rows"] in (16, 32, 64) and shape["centre_grid"] >= 0
-    assert shape["neighbor_cells"] in (0, 1) and shape["mlp_waves"] in (4, 8)
+    assert shape["neighbor_cells"] in (0, 1) and shape["mlp_waves"] in (4, 8) and shape["force_rows"] in (0, 1)
     # the state does not move and the forces are those of the same positions
     _, _, F_after, step1 = a.get_state()
     assert step1 == step0 and torch.equal(F_before, F_after)
@@ -419,7 +421,7 @@ def test_bad_launch_shapes_are_rejected():
     wl = WORKLOADS["fad-P4"]()
     eng = _engine(wl)
     for bad in ({"centre_waves": 3}, {"centre_waves": 8}, {"mlp_rows": 48}, {"centre_grid": -1}, {"neighbor_cells": 2},
-                {"mlp_waves": 6}):
+                {"mlp_waves": 6}, {"force_rows": 2}):
         with pytest.raises(PimdError) as ei:
             eng.set_tuning(**bad)
         assert ei.value.status == PIMD_E_ARG
