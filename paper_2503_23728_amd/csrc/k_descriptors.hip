@@ -121,12 +121,14 @@ struct BlockWalk {
     }
 };
 
-constexpr int kQueue = 128;   // in-range slot pairs waiting per wave (< 64 + one shift's 64)
+constexpr int kQueue = 128;   // ring of in-range slot pairs per wave (< 64 waiting + one shift's 64)
 
 // Phase 1 of a block: every lane tests its (own, partner) pairs with the
 // cheap r_jk^2 < rc^2 test and appends the pairs in range to the wave's LDS
-// queue; whenever 64 are waiting, `body` runs on them with one pair per lane
-// (phase 2), so the costly triplet terms never run on idle lanes.
+// ring; whenever 64 are waiting, `body` runs on the oldest 64 with one pair
+// per lane (phase 2), so the costly triplet terms never run on idle lanes.
+// Fewer than 64 wait before a shift appends at most 64, so the ring of 128
+// never overwrites a pair that has not been taken.
 template <typename Body>
 __device__ __forceinline__ void for_each_triplet_in_range(const BlockWalk &bw, const float4 *recD, float rc2,
                                                           uint32_t *queue, Body &&body)
@@ -136,7 +138,7 @@ __device__ __forceinline__ void for_each_triplet_in_range(const BlockWalk &bw, c
     const int lane = lane_id();
     // the half shift of an even triangle pairs only the own slots b < s
     const int s_half = (bw.tri && 2 * bw.s1 == bw.n_own) ? bw.s1 : -1;
-    int qn = 0;
+    int qh = 0, qn = 0;   // ring head and pairs waiting (wave-uniform)
     for (int b0 = 0; b0 < bw.n_own; b0 += kWave) {
         const int b = b0 + lane;
         const bool own_ok = b < bw.n_own;
@@ -156,28 +158,24 @@ __device__ __forceinline__ void for_each_triplet_in_range(const BlockWalk &bw, c
             if (inr) {
                 const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                queue[qn + (int)below] = ((uint32_t)ia << 16) | (uint32_t)ic;
+                queue[(qh + qn + (int)below) & (kQueue - 1)] = ((uint32_t)ia << 16) | (uint32_t)ic;
             }
             qn = __builtin_amdgcn_readfirstlane(qn + (int)__popcll(m));   // uniform: a scalar branch below
             ++p;
             p -= p >= bw.n_par ? bw.n_par : 0;
             if (qn >= kWave) {
                 wave_sync();
-                const uint32_t q = queue[lane];
+                const uint32_t q = queue[(qh + lane) & (kQueue - 1)];
                 body(q >> 16, q & 0xFFFFu, true);
-                const int rest = qn - kWave;
-                const uint32_t carry = lane < rest ? queue[kWave + lane] : 0u;
                 wave_sync();
-                if (lane < rest)
-                    queue[lane] = carry;
-                wave_sync();
-                qn = rest;
+                qh = (qh + kWave) & (kQueue - 1);
+                qn -= kWave;
             }
         }
     }
     if (qn > 0) {
         wave_sync();
-        const uint32_t q = lane < qn ? queue[lane] : 0u;
+        const uint32_t q = lane < qn ? queue[(qh + lane) & (kQueue - 1)] : 0u;
         body(q >> 16, q & 0xFFFFu, lane < qn);
         wave_sync();
     }
