@@ -523,11 +523,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 
 // ---------------------------------------------------------------------------
 // forces: F_i = sum_slots v[i][n] - sum_slots v[j][slot of i in j's list].
-// With vrev the adjoint stored the second term at i's slot n, so both are
+// With ROWS the adjoint stored the second term at i's slot n, so both are
 // contiguous rows of i; without, it is gathered from j's row through the
 // reverse-slot search.  The same sums in the same order either way, no
 // atomics.
 // ---------------------------------------------------------------------------
+template <bool ROWS>
 __global__ __launch_bounds__(256) void k_assemble_forces(const float4 *__restrict__ pos4,
                                                          const int32_t *__restrict__ order,
                                                          const int32_t *__restrict__ nbr,
@@ -548,7 +549,7 @@ __global__ __launch_bounds__(256) void k_assemble_forces(const float4 *__restric
         for (int n = lane; n < K; n += kWave) {
             const float4 v = vslot[(int64_t)i * Kmax + n];
             float4 u = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (vrev) {
+            if constexpr (ROWS) {
                 u = vrev[(int64_t)i * Kmax + n];
             } else {
                 const int j = nbr[(int64_t)i * Kmax + n] & (int)kRowMask;
@@ -726,9 +727,14 @@ void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &d
 
 void launch_assemble_forces(const DevBuffers &d, const Sizes &z, float *F, const Tuning &tn, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_assemble_forces, dim3(centre_grid(z.B, tn)), dim3(kWave * tn.centre_waves), 0, s, d.pos4,
-                       centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_fence, d.vslot, tn.force_rows ? d.vrev : nullptr,
-                       z.Kmax, F, d.status, z.B);
+    if (tn.force_rows)
+        hipLaunchKernelGGL(k_assemble_forces<true>, dim3(centre_grid(z.B, tn)), dim3(kWave * tn.centre_waves), 0, s,
+                           d.pos4, centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_fence, d.vslot, d.vrev, z.Kmax, F,
+                           d.status, z.B);
+    else
+        hipLaunchKernelGGL(k_assemble_forces<false>, dim3(centre_grid(z.B, tn)), dim3(kWave * tn.centre_waves), 0, s,
+                           d.pos4, centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_fence, d.vslot, nullptr, z.Kmax, F,
+                           d.status, z.B);
 }
 
 void launch_bead_sums(const DevBuffers &d, const Sizes &z, float *E_bead, float *W_bead, bool virial, hipStream_t s)
