@@ -12,9 +12,12 @@ kernel (algorithmic FLOPs per launch / mean launch time from HIP events on
 the launch stream, against the FP32 vector peak) and the FP64 CPU oracle
 timed on a bounded sample on the host cores.
 
-Workloads (--config): 1 formic-acid-dimer 10 atoms P=8; 2 water 64 H2O P=32
-(default); 3 ice 96 H2O P=32; 4 512 dimer-like ring polymers with P in
-{8,16,32,64}; 5 water 4096 H2O P=32.
+Workloads (--config): 1 formic-acid-dimer 10 atoms P=8; 2 water 64 H2O P=32;
+3 ice 96 H2O P=32; 4 512 dimer-like ring polymers with P in {8,16,32,64};
+5 water 4096 H2O P=32 (default: the largest workload, 393,216 bead-atoms).
+The default run also reports, as extra keys, the same workload with every
+bead's neighbour list searched through cell lists each step, and the batched
+workload 4 against its plain-FP32 path.
 """
 import argparse
 import json
@@ -31,7 +34,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X published dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X published FP64 vector peak
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_traffic.json")
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"adjoint_traffic_{workload}.json")
 
 
 def measured_traffic(workload):
@@ -40,7 +44,7 @@ def measured_traffic(workload):
     since (SHA-256 over the listed files, in order)."""
     import hashlib
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(traffic_file(workload)))
         src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])
     except (OSError, ValueError, KeyError, TypeError):
         return None
@@ -208,12 +212,38 @@ def plain_fp32(wl, steps, warmup, device, shape=None, skin=0.0):
 
 
 def cpu_baseline(wl, budget_s=20.0):
-    """FP64 oracle steps on the host cores over a bounded sample of the
-    workload: whole integrator steps of the first ring polymer(s), repeated
-    until about budget_s seconds have passed."""
+    """FP64 oracle on the host cores over a bounded sample of the workload:
+    whole integrator steps of the first ring polymer(s), repeated until about
+    budget_s seconds have passed; when one step of the first ring polymer is
+    itself too large for that (more than 20,000 bead-atoms), force evaluations
+    of its beads one at a time (every atom of a bead with all its neighbours;
+    the integrator is a few percent of a step on either side)."""
     from paper_2503_23728_amd import synthetic as S
     from oracle import bpnn, gfn, ring
     q, p = S.initial_state(wl)
+    first = wl.systems[0]
+    cores = len(os.sched_getaffinity(0))
+    threads = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    if first.n_atoms * first.n_beads > 20000:
+        n_at = first.n_atoms
+        t0 = time.perf_counter()
+        k = 0
+        while True:
+            qb = q[k * n_at:(k + 1) * n_at]
+            if hasattr(wl.model, "width"):
+                sub = S.Workload(wl.name, [S.System(n_at, 1, first.temperature, first.box, first.species,
+                                                    first.q0)], wl.model, wl.dt, wl.tau0, wl.pile_lambda,
+                                 wl.n_steps, wl.philox_seed, wl.momentum_seed)
+                gfn.forces(sub, qb)
+            else:
+                bpnn.bead_energy_forces(wl.model, qb, first.species, first.box)
+            k += 1
+            if time.perf_counter() - t0 > budget_s or k >= first.n_beads:
+                break
+        dt = time.perf_counter() - t0
+        return dict(value=n_at * k / dt, unit="bead-atom force evals/s", cores=threads, kind="oracle",
+                    sample=f"{k} FP64 oracle force evaluations of whole beads of {n_at} atoms "
+                           f"({n_at * k} bead-atoms, {dt:.1f} s)")
     systems, rows, n_sys = [], 0, 0
     for s in wl.systems:
         systems.append(s)
@@ -240,11 +270,54 @@ def cpu_baseline(wl, budget_s=20.0):
         if time.perf_counter() - t0 > budget_s or n >= 200:
             break
     dt = time.perf_counter() - t0
-    cores = len(os.sched_getaffinity(0))
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    return dict(value=rows * n / dt, unit="bead-atom force evals/s", cores=min(cores, threads), kind="oracle",
+    return dict(value=rows * n / dt, unit="bead-atom force evals/s", cores=threads, kind="oracle",
                 sample=f"{n} FP64 oracle integrator steps of {len(systems)} ring polymer(s), {rows} bead-atoms "
                        f"({dt:.1f} s)")
+
+
+def extra_keys(args, wl, eng, skin, shape, device):
+    """The same workload with per-bead cell searches every step (no shared
+    lists), and the batched workload 4 (512 ring polymers in one graph per step)
+    against its plain-FP32 path (one eager context per ring polymer)."""
+    import torch
+    from paper_2503_23728_amd import synthetic as S
+    from paper_2503_23728_amd.pimd import Pimd
+    out = {}
+    q, p = S.initial_state(wl)
+    if skin > 0:
+        cell = Pimd.from_workload(wl, precision=args.precision, device=device, transform=args.transform)
+        cell.set_state(torch.from_numpy(q).to(device), torch.from_numpy(p).to(device))
+        if not args.no_tune:
+            cell.autotune(n_reps=3)
+        wall, _ = time_steps(cell, args.steps, args.warmup)
+        out["cell_search_every_step"] = {"value": wl.bead_atoms * args.steps / wall,
+                                         "ms_per_step": 1e3 * wall / args.steps,
+                                         "neighbor_lists": "per bead, cell search every evaluation"}
+        print(f"[bench] cell search every step: {1e3 * wall / args.steps:.3f} ms/step", file=sys.stderr,
+              flush=True)
+        cell.close()
+        del cell
+    if args.config != 4:
+        bwl = S.workload(4)
+        bat = Pimd.from_workload(bwl, precision=args.precision, device=device)
+        bq, bp = S.initial_state(bwl)
+        bat.set_state(torch.from_numpy(bq).to(device), torch.from_numpy(bp).to(device))
+        bshape = bat.get_tuning() if args.no_tune else bat.autotune(n_reps=3)[0]
+        wall, _ = time_steps(bat, args.steps, args.warmup)
+        bat.close()
+        del bat
+        psteps = max(1, min(args.steps, 50))
+        pwall = plain_fp32(bwl, psteps, min(args.warmup, 5), device, bshape, 0.0)
+        val, pval = bwl.bead_atoms * args.steps / wall, bwl.bead_atoms * psteps / pwall
+        out["batched_workload"] = {"workload": bwl.name, "bead_atoms": bwl.bead_atoms, "value": val,
+                                   "ms_per_step": 1e3 * wall / args.steps,
+                                   "plain_fp32": {"value": pval, "steps": psteps,
+                                                  "ms_per_step": 1e3 * pwall / psteps,
+                                                  "launch": "eager, one context per system"},
+                                   "vs_plain_fp32": val / pval}
+        print(f"[bench] batched {bwl.name}: {1e3 * wall / args.steps:.3f} ms/step, plain fp32 "
+              f"{1e3 * pwall / psteps:.3f} ms/step", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -252,10 +325,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=5)
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "bf16-plain"])
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-FP32 comparison path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the extra keys (per-step cell search; batched workload 4 against plain FP32)")
     ap.add_argument("--profile-reps", type=int, default=10)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape (no autotuner)")
     ap.add_argument("--potential", default="bpnn", choices=["bpnn", "gfn"],
@@ -425,6 +500,8 @@ def main():
         out["metad"] = metad_report(eng, wl, spec, max(args.profile_reps, 5))
         out["config"]["workload"] += f"+wt-metad({spec.cv})"
         print(f"[bench] metad {json.dumps(out['metad'])}", file=sys.stderr, flush=True)
+    if not args.no_extras and not gfn_mode and not args.metad and args.angular == "g4":
+        out.update(extra_keys(args, wl, eng, skin, shape, device))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

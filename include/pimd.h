@@ -261,7 +261,11 @@ typedef struct {
 /* Bytes of device workspace a context needs for cfg.  No GPU needed. */
 pimd_status pimd_workspace_size(const pimd_config *cfg, size_t *bytes);
 
-/* Validate cfg, carve the workspace and upload tables and weights.
+/* Validate cfg, carve the workspace and upload tables and weights: the
+ * system (coordinates come with pimd_set_state), its potential and the
+ * integrator settings, the parts the paper wraps together before running
+ * (Sec. 2.3, Charts 1 and 2; ring polymer and normal modes of Sec. 2.1;
+ * PILE-L of Table S3).
  * workspace_dev: device memory of ws_bytes (>= pimd_workspace_size), 256-byte
  * aligned, owned by the caller.  hip_stream: a hipStream_t (NULL = default).
  * On success *out holds a new context; the state must be set with
@@ -281,7 +285,30 @@ pimd_status pimd_set_state(pimd_ctx *ctx, const float *q_dev, const float *p_dev
  * context.  Synchronises; returns a latched device fault, if any. */
 pimd_status pimd_get_state(pimd_ctx *ctx, float *q_dev, float *p_dev, float *forces_dev, int64_t *step);
 
-/* Potential energy of every bead at positions q_dev (state layout):
+/* Heat bath of every system (heat_host[n_systems], eV: minus the kinetic
+ * energy the thermostat's O steps have added since pimd_set_state, the term
+ * that makes H_conserved conserved).  pimd_set_state zeroes it; a checkpoint
+ * carries it with pimd_get_heat_bath and puts it back with
+ * pimd_set_heat_bath after pimd_set_state.  Both synchronise; set takes
+ * finite values only (PIMD_E_ARG). */
+pimd_status pimd_get_heat_bath(pimd_ctx *ctx, double *heat_host);
+pimd_status pimd_set_heat_bath(pimd_ctx *ctx, const double *heat_host);
+
+/* Synchronise the context stream and return a latched device fault, if any,
+ * clearing it.  A fault latched during a step freezes the integrator: that
+ * step and every later one enqueued before this call leave positions,
+ * momenta, step counter, heat bath and hills as they were after the last step
+ * that completed without a fault, so a caller can read that state back
+ * (pimd_get_state), rebuild the context (e.g. with more max_neighbors) and
+ * replay the lost steps.  The forces are evaluated again at the next step.
+ * Every synchronising call that reports faults does the same. */
+pimd_status pimd_check(pimd_ctx *ctx);
+
+/* Potential energy of every bead at positions q_dev (state layout), with
+ * forces as minus the gradient of the energy (the energy-model route of
+ * Sec. 2.2, here a descriptor network of the family the Introduction
+ * cites, differentiated by a hand-written adjoint) -- the bead potentials
+ * V(r^(k)) of the effective Hamiltonian of Sec. 2.1:
  * energy_dev[sum P_s] (eV); forces_dev [B][3] = -dE/dq (eV/A) or NULL for
  * energy only; virial_dev [sum P_s][9] (row-major W_ab = -sum_i sum_j
  * d_ij,a dE_i/dd_ij,b, eV) or NULL.  The integrator state is not touched.
@@ -290,12 +317,16 @@ pimd_status pimd_energy_forces(pimd_ctx *ctx, const float *q_dev, float *energy_
                                float *forces_dev, float *virial_dev);
 
 /* Advance every system by n_steps full integrator steps (one force
- * evaluation each).  After the first step the step is replayed as a captured
+ * evaluation each): normal-mode (or staging, or primitive) ring-polymer
+ * dynamics of Sec. 2.1 and Sec. 2.3 under the PILE-L thermostat of Table S3,
+ * all beads of all systems in one batch.  After the first step the step is replayed as a captured
  * HIP graph.  With metadynamics, PIMD_E_CAPACITY (nothing run) when the
  * steps would deposit more than max_hills hills per bead.  Asynchronous. */
 pimd_status pimd_step(pimd_ctx *ctx, int32_t n_steps);
 
-/* Estimators of the current state for every system (out_host[n_systems]).
+/* Estimators of the current state for every system (out_host[n_systems]):
+ * the finite-P bead averages of Sec. 2.1 and the virial kinetic energy used
+ * for the bead-convergence check of Sec. S3 (definitions at pimd_estimates).
  * Synchronises; returns a latched device fault, if any. */
 pimd_status pimd_estimators(pimd_ctx *ctx, pimd_estimates *out_host);
 

@@ -69,6 +69,9 @@ _SIGNATURES = {
     "pimd_set_stream": (c_int32, [c_void_p, c_void_p]),
     "pimd_set_state": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64]),
     "pimd_get_state": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_int64)]),
+    "pimd_get_heat_bath": (c_int32, [c_void_p, POINTER(c_double)]),
+    "pimd_set_heat_bath": (c_int32, [c_void_p, POINTER(c_double)]),
+    "pimd_check": (c_int32, [c_void_p]),
     "pimd_energy_forces": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pimd_step": (c_int32, [c_void_p, c_int32]),
     "pimd_estimators": (c_int32, [c_void_p, POINTER(pimd_estimates)]),
@@ -155,6 +158,21 @@ def pimd_get_state(ctx, q_ptr, p_ptr, f_ptr):
     step = c_int64(0)
     st = lib().pimd_get_state(c_void_p(ctx), c_void_p(q_ptr), c_void_p(p_ptr), c_void_p(f_ptr), ctypes.byref(step))
     return st, step.value
+
+
+def pimd_get_heat_bath(ctx, n_systems):
+    arr = (c_double * n_systems)()
+    st = lib().pimd_get_heat_bath(c_void_p(ctx), arr)
+    return st, list(arr)
+
+
+def pimd_set_heat_bath(ctx, heat):
+    arr = (c_double * len(heat))(*[float(h) for h in heat])
+    return lib().pimd_set_heat_bath(c_void_p(ctx), arr)
+
+
+def pimd_check(ctx):
+    return lib().pimd_check(c_void_p(ctx))
 
 
 def pimd_energy_forces(ctx, q_ptr, e_ptr, f_ptr, w_ptr):

@@ -26,6 +26,8 @@ namespace pimd {
 
 struct IntegArgs {
     float *q, *p;
+    float *q_prev, *p_prev;   // the state at the start of the step in progress
+    const uint32_t *status;   // device status word: nonzero freezes the integrator
     const float *F;
     const SysInfo *sys;
     const ModeInfo *modes;
@@ -117,25 +119,44 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
     double *s2 = s1 + 256;
     double *red = s2 + 256;
     const int tid = threadIdx.x;
+    const int cl = tid / P, kk = tid - cl * P;
+    const bool valid = cl < u.ncol;
+    const int col = u.col0 + cl;
+    const int atom = col / 3, cc = col - 3 * (col / 3);
+    const int64_t row = (int64_t)S.ba0 + (int64_t)kk * N + atom;   // bead kk (loads) = mode kk (noise)
+    // A latched fault (neighbour overflow, non-finite value) freezes the state
+    // at the last step that completed without one: the pre-force half does
+    // nothing, the post-force half puts back the state the step started from.
+    // The status word is only written by kernels of earlier stages, so every
+    // thread of the launch reads the same value.
+    if (*a.status != 0u) {
+        if (!PRE && valid) {
+            a.q[row * 3 + cc] = a.q_prev[row * 3 + cc];
+            a.p[row * 3 + cc] = a.p_prev[row * 3 + cc];
+        }
+        return;
+    }
     if (NM) {
         for (int idx = tid; idx < P * P; idx += 256) {
             const int j = idx / P, k = idx - j * P;
             CT[k * (P + 1) + j] = a.cmat[S.cmat0 + idx];  // C[j][k]
         }
     }
-    const int cl = tid / P, kk = tid - cl * P;
-    const bool valid = cl < u.ncol;
-    const int col = u.col0 + cl;
-    const int atom = col / 3, cc = col - 3 * (col / 3);
-    const int64_t row = (int64_t)S.ba0 + (int64_t)kk * N + atom;   // bead kk (loads) = mode kk (noise)
     const int64_t step = *a.step;
     double m = 1.0;
     if (valid) {
         m = (double)a.mass_atom[S.atom0 + atom];
-        s0[tid] = (double)a.p[row * 3 + cc];
+        const float pv = a.p[row * 3 + cc];
+        s0[tid] = (double)pv;
         s1[tid] = (double)a.F[row * 3 + cc];
-        if (PRE || PRIMITIVE)
-            s2[tid] = (double)a.q[row * 3 + cc];
+        if (PRE || PRIMITIVE) {
+            const float qv = a.q[row * 3 + cc];
+            s2[tid] = (double)qv;
+            if (PRE) {
+                a.q_prev[row * 3 + cc] = qv;
+                a.p_prev[row * 3 + cc] = pv;
+            }
+        }
     }
     __syncthreads();
     const double kick = 0.5 * (double)a.dt / kMvv2e;
@@ -233,11 +254,14 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
 
 // heat_bath[s] -= (sum of O-step kinetic-energy changes of the step); step += 1.
 // One workgroup per system; fixed-order tree sum in FP64.
+// Nothing while a fault is latched (the step did not complete).
 __global__ __launch_bounds__(256) void k_finish_step(const SysInfo *__restrict__ sys,
                                                      const double *__restrict__ dke_part, double *__restrict__ heat,
-                                                     int64_t *__restrict__ step)
+                                                     int64_t *__restrict__ step, const uint32_t *__restrict__ status)
 {
     __shared__ double red[256];
+    if (*status != 0u)
+        return;
     const SysInfo S = sys[blockIdx.x];
     double d = 0.0;
     for (int u = S.unit0 + threadIdx.x; u < S.unit0 + S.nunit; u += 256)
@@ -339,6 +363,9 @@ static IntegArgs integ_args(const DevBuffers &d, const Sizes &z, float dt, uint3
     IntegArgs a;
     a.q = d.q;
     a.p = d.p;
+    a.q_prev = d.q_prev;
+    a.p_prev = d.p_prev;
+    a.status = d.status;
     a.F = d.F;
     a.sys = d.sys;
     a.modes = d.modes;
@@ -402,7 +429,7 @@ void launch_integrate_post(const DevBuffers &d, const Sizes &z, float dt, uint32
 
 void launch_finish_step(const DevBuffers &d, const Sizes &z, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finish_step, dim3(z.n_sys), dim3(256), 0, s, d.sys, d.dke_part, d.heat, d.step);
+    hipLaunchKernelGGL(k_finish_step, dim3(z.n_sys), dim3(256), 0, s, d.sys, d.dke_part, d.heat, d.step, d.status);
 }
 
 void launch_estimator_terms(const DevBuffers &d, const Sizes &z, hipStream_t s)

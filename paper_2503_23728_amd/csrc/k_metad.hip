@@ -355,9 +355,10 @@ __global__ __launch_bounds__(NT) void k_metad_bias(const float *__restrict__ q, 
 }
 
 __global__ void k_metad_advance(const int64_t *__restrict__ step, int stride, int max_hills,
-                                int32_t *__restrict__ n_hills)
+                                int32_t *__restrict__ n_hills, const uint32_t *__restrict__ status)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && (*step + 1) % stride == 0 && *n_hills < max_hills)
+    // a latched fault means the step does not complete: its hill is not kept
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *status == 0u && (*step + 1) % stride == 0 && *n_hills < max_hills)
         *n_hills += 1;
 }
 
@@ -437,7 +438,7 @@ void launch_metad(const float *q, const DevBuffers &d, const Sizes &z, const Met
 
 void launch_metad_advance(const DevBuffers &d, const MetadParams &mp, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_metad_advance, dim3(1), dim3(64), 0, s, d.step, mp.stride, mp.max_hills, d.n_hills);
+    hipLaunchKernelGGL(k_metad_advance, dim3(1), dim3(64), 0, s, d.step, mp.stride, mp.max_hills, d.n_hills, d.status);
 }
 
 void launch_metad_fes(const DevBuffers &d, const MetadParams &mp, int bead0, int P, double kT, double gamma_ratio,

@@ -341,6 +341,8 @@ Layout make_layout(const Plan &pl)
     const size_t B = pl.B, nb = pl.n_beads, K = pl.Kmax, D = pl.D;
     L.add("q", B * 12);
     L.add("p", B * 12);
+    L.add("q_prev", B * 12);
+    L.add("p_prev", B * 12);
     L.add("F", B * 12);
     L.add("E_bead", nb * 4);
     L.add("W_bead", nb * 36);
@@ -638,9 +640,22 @@ pimd_status read_status(pimd_ctx *c)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (st == 0)
         return PIMD_OK;
+    // The integrator froze at the last step completed before the fault (the
+    // kernels of later steps did nothing): take the step and hill counters
+    // from the device again, and evaluate the forces of the frozen positions
+    // before the next step.
+    int64_t dstep = 0;
+    int32_t dhills = 0;
+    HIPCHK(c, hipMemcpyAsync(&dstep, c->d.step, 8, hipMemcpyDeviceToHost, c->stream));
+    if (c->pl.metad)
+        HIPCHK(c, hipMemcpyAsync(&dhills, c->d.n_hills, 4, hipMemcpyDeviceToHost, c->stream));
     const uint32_t zero = 0;
     HIPCHK(c, hipMemcpyAsync(c->d.status, &zero, 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->host_step = dstep;
+    if (c->pl.metad)
+        c->host_hills = dhills;
+    c->forces_valid = false;
     if (st & kStatusHills) {
         c->err = "a deposition found the hill store full (max_hills)";
         return PIMD_E_CAPACITY;
@@ -746,6 +761,8 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     DevBuffers &d = c->d;
     d.q = (float *)at("q");
     d.p = (float *)at("p");
+    d.q_prev = (float *)at("q_prev");
+    d.p_prev = (float *)at("p_prev");
     d.F = (float *)at("F");
     d.E_bead = (float *)at("E_bead");
     d.W_bead = (float *)at("W_bead");
@@ -1309,6 +1326,9 @@ pimd_status pimd_set_state(pimd_ctx *ctx, const float *q_dev, const float *p_dev
     const size_t bytes = (size_t)ctx->z.B * 12;
     HIPCHK(ctx, hipMemcpyAsync(ctx->d.q, q_dev, bytes, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(ctx->d.p, p_dev, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    // the state a fault before the first step freezes at
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d.q_prev, q_dev, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d.p_prev, p_dev, bytes, hipMemcpyDeviceToDevice, ctx->stream));
     std::vector<double> zeros(ctx->z.n_sys, 0.0);
     HIPCHK(ctx, hipMemcpyAsync(ctx->d.heat, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(ctx->d.step, &step, 8, hipMemcpyHostToDevice, ctx->stream));
@@ -1348,6 +1368,36 @@ pimd_status pimd_get_state(pimd_ctx *ctx, float *q_dev, float *p_dev, float *for
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     if (step)
         *step = s;
+    return read_status(ctx);
+}
+
+pimd_status pimd_get_heat_bath(pimd_ctx *ctx, double *heat_host)
+{
+    if (!ctx || !heat_host)
+        return PIMD_E_ARG;
+    HIPCHK(ctx, hipMemcpyAsync(heat_host, ctx->d.heat, (size_t)ctx->z.n_sys * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return PIMD_OK;
+}
+
+pimd_status pimd_set_heat_bath(pimd_ctx *ctx, const double *heat_host)
+{
+    if (!ctx || !heat_host)
+        return PIMD_E_ARG;
+    for (int s = 0; s < ctx->z.n_sys; ++s)
+        if (!std::isfinite(heat_host[s])) {
+            ctx->err = "heat bath values must be finite";
+            return PIMD_E_ARG;
+        }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d.heat, heat_host, (size_t)ctx->z.n_sys * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return PIMD_OK;
+}
+
+pimd_status pimd_check(pimd_ctx *ctx)
+{
+    if (!ctx)
+        return PIMD_E_ARG;
     return read_status(ctx);
 }
 

@@ -160,6 +160,7 @@ struct MetadParams {
 // Everything a step needs on the device, carved from the workspace.
 struct DevBuffers {
     float *q, *p, *F, *E_bead;     // integrator state, forces of q, bead energies
+    float *q_prev, *p_prev;        // the state at the start of the step in progress (restored on a fault)
     float *xi;                     // injected noise [2][B][3]
     float4 *pos4;                  // wrapped positions + species bits (neighbour search)
     float4 *posu4;                 // unwrapped positions + species bits (displacements)

@@ -161,32 +161,111 @@ def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", p
     return cfg, keep
 
 
+MAX_NEIGHBORS = 256          # the library's largest slot count per atom
+
+
+def grown_slots(k):
+    """Slot count after a neighbour overflow at k slots: 1.5 k rounded up to a
+    multiple of 16, at most MAX_NEIGHBORS; None when k is already the most."""
+    k = k or 128
+    if k >= MAX_NEIGHBORS:
+        return None
+    return min(MAX_NEIGHBORS, (3 * k // 2 + 15) // 16 * 16)
+
+
 class Pimd:
-    """One library context: state, workspace and stream on one device."""
+    """One library context: state, workspace and stream on one device.
+
+    regrow=True: when a synchronising call reports that an atom had more
+    neighbours than the slots per atom (PIMD_E_CAPACITY), the context is built
+    again with more slots (grown_slots), the state the library froze at (the
+    last step completed before the overflow, with its heat bath, hills and
+    launch shape) is put back, the steps asked for since are replayed, and the
+    call is made again."""
 
     def __init__(self, systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
                  omega=0.0, max_neighbors=0, masses=None, device="cuda:0", stream=None, metad=None,
-                 transform="normal-modes", neighbor_skin=0.0):
+                 transform="normal-modes", neighbor_skin=0.0, regrow=True):
         self.device = torch.device(device)
         self.metad = metad
         self.systems = list(systems)
         self.model, self.precision, self.max_neighbors = model, precision, max_neighbors
         self.neighbor_skin = float(neighbor_skin)
-        self.cfg, self._keep = make_config(self.systems, model, dt, tau0, pile_lambda, seed, precision,
-                                           potential, omega, max_neighbors, masses, metad, transform,
-                                           neighbor_skin)
+        self.regrow = regrow
+        self.regrowths = 0
+        self._cfg_args = (dt, tau0, pile_lambda, seed, precision, potential, omega, masses, metad, transform,
+                          neighbor_skin)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = None
+        self._target_step = 0          # steps the caller has asked for, counted from set_state
+        self._use_graph = True
+        self._open(max_neighbors)
+        bead_of_row = []
+        b0 = 0
+        for s in self.systems:
+            bead_of_row.append(b0 + np.repeat(np.arange(s.n_beads), s.n_atoms))
+            b0 += s.n_beads
+        self.bead_of_row = torch.as_tensor(np.concatenate(bead_of_row), device=self.device, dtype=torch.long)
+
+    def _open(self, max_neighbors):
+        dt, tau0, lam, seed, precision, potential, omega, masses, metad, transform, skin = self._cfg_args
+        self.max_neighbors = max_neighbors
+        self.cfg, self._keep = make_config(self.systems, self.model, dt, tau0, lam, seed, precision, potential,
+                                           omega, max_neighbors, masses, metad, transform, skin)
         st, nbytes = abi.pimd_workspace_size(self.cfg)
         _check(st)
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
         if self.workspace.data_ptr() % 256:
             raise RuntimeError("torch returned a workspace that is not 256-byte aligned")
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.ctx = None
         st, ctx = abi.pimd_init(self.cfg, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
         _check(st)
         self.ctx = ctx
         st, self.B, self.n_beads, self.D = abi.pimd_sizes(ctx)
         _check(st, ctx)
+
+    def _grow(self):
+        """Rebuild with more neighbour slots after an overflow; False when no
+        larger slot count exists."""
+        k = grown_slots(self.max_neighbors)
+        if k is None:
+            return False
+        q = torch.empty(self.B, 3, device=self.device)
+        p = torch.empty_like(q)
+        st, step = abi.pimd_get_state(self.ctx, q.data_ptr(), p.data_ptr(), 0)
+        state_set = st != abi.PIMD_E_STATE
+        if state_set:
+            _check(st, self.ctx)
+            st, heat = abi.pimd_get_heat_bath(self.ctx, len(self.systems))
+            _check(st, self.ctx)
+        hills = self.metad_hills() if self.metad is not None else None
+        shape = self.get_tuning()
+        abi.pimd_destroy(self.ctx)
+        self.ctx = None
+        self._open(k)
+        self.regrowths += 1
+        self.set_tuning(**shape)
+        self.set_graph(self._use_graph)
+        if hills is not None and hills[0].shape[1]:
+            self.metad_set_hills(*hills)
+        if state_set:
+            target = self._target_step
+            _check(abi.pimd_set_state(self.ctx, q.data_ptr(), p.data_ptr(), int(step)), self.ctx)
+            _check(abi.pimd_set_heat_bath(self.ctx, heat), self.ctx)
+            self._target_step = target
+            if target > step:
+                _check(abi.pimd_step(self.ctx, int(target - step)), self.ctx)
+        return True
+
+    def _sync(self, call):
+        """Run a synchronising library call (a function of the context); regrow
+        and run it again while it reports a neighbour overflow."""
+        while True:
+            st = call(self.ctx)
+            if (st == abi.PIMD_E_CAPACITY and self.regrow and "max_neighbors" in abi.pimd_last_error(self.ctx)
+                    and self._grow()):
+                continue
+            _check(st, self.ctx)
+            return
         bead_of_row = []
         b0 = 0
         for s in self.systems:
@@ -220,34 +299,66 @@ class Pimd:
             t = t.reshape(shape)
         return t
 
-    def set_state(self, q, p, step=0):
+    def set_state(self, q, p, step=0, heat_bath=None):
+        """Positions, momenta and step counter; heat_bath (one value per system,
+        from get_heat_bath) restores the thermostat's account of a checkpoint,
+        else it starts at zero."""
         q = self._vec(q, (self.B, 3))
         p = self._vec(p, (self.B, 3))
         _check(abi.pimd_set_state(self.ctx, q.data_ptr(), p.data_ptr(), int(step)), self.ctx)
+        if heat_bath is not None:
+            _check(abi.pimd_set_heat_bath(self.ctx, list(heat_bath)), self.ctx)
+        self._target_step = int(step)
 
     def get_state(self, forces=True):
         q = torch.empty(self.B, 3, device=self.device)
         p = torch.empty_like(q)
         F = torch.empty_like(q) if forces else None
-        st, step = abi.pimd_get_state(self.ctx, q.data_ptr(), p.data_ptr(), _ptr(F))
-        _check(st, self.ctx)
-        return q, p, F, step
+        out = {}
 
-    def energy_forces(self, q, forces=True, virial=False):
+        def call(ctx):
+            st, out["step"] = abi.pimd_get_state(ctx, q.data_ptr(), p.data_ptr(), _ptr(F))
+            return st
+        self._sync(call)
+        return q, p, F, out["step"]
+
+    def get_heat_bath(self):
+        st, heat = abi.pimd_get_heat_bath(self.ctx, len(self.systems))
+        _check(st, self.ctx)
+        return heat
+
+    def check(self):
+        """Wait for the enqueued work and raise on a latched device fault (after
+        regrowing and replaying, for a neighbour overflow with regrow=True)."""
+        self._sync(abi.pimd_check)
+
+    def energy_forces(self, q, forces=True, virial=False, check=True):
+        """Energies [beads], forces [B, 3] and virials [beads, 3, 3] at q.  With
+        check=True the call waits for the kernels and raises on a device fault
+        (a neighbour overflow regrows the context and evaluates again)."""
         q = self._vec(q, (self.B, 3))
         E = torch.empty(self.n_beads, device=self.device)
         F = torch.empty(self.B, 3, device=self.device) if forces else None
         W = torch.empty(self.n_beads, 3, 3, device=self.device) if virial else None
-        _check(abi.pimd_energy_forces(self.ctx, q.data_ptr(), E.data_ptr(), _ptr(F), _ptr(W)), self.ctx)
+
+        def call(ctx):
+            st = abi.pimd_energy_forces(ctx, q.data_ptr(), E.data_ptr(), _ptr(F), _ptr(W))
+            return abi.pimd_check(ctx) if st == abi.PIMD_OK and check else st
+        self._sync(call)
         return E, F, W
 
     def step(self, n=1):
         _check(abi.pimd_step(self.ctx, int(n)), self.ctx)
+        self._target_step += int(n)
 
     def estimators(self):
-        st, arr = abi.pimd_estimators(self.ctx, len(self.systems))
-        _check(st, self.ctx)
-        return [{f: getattr(a, f) for f, _ in abi.pimd_estimates._fields_} for a in arr]
+        out = {}
+
+        def call(ctx):
+            st, out["arr"] = abi.pimd_estimators(ctx, len(self.systems))
+            return st
+        self._sync(call)
+        return [{f: getattr(a, f) for f, _ in abi.pimd_estimates._fields_} for a in out["arr"]]
 
     def inject_noise(self, xi):
         xi = self._vec(xi, (2, self.B, 3))
@@ -256,6 +367,7 @@ class Pimd:
 
     def set_graph(self, enabled):
         _check(abi.pimd_set_graph(self.ctx, enabled), self.ctx)
+        self._use_graph = bool(enabled)
 
     def get_tuning(self):
         """The launch shape of the force kernels: {centre_waves, centre_grid, mlp_rows, neighbor_cells}."""

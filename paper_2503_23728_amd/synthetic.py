@@ -505,6 +505,40 @@ def small_workload(kind, seed=7, n_beads=4):
     raise ValueError(kind)
 
 
+def colliding_clusters(n_beads=4, speed=0.08, seed=7, box_len=24.0):
+    """Two clusters of three water molecules flying at each other along x in a
+    periodic box (a neighbour count that grows during a run, for the overflow
+    tests).  O atoms on an equilateral triangle of side 2.9 A in the yz plane
+    with random molecule orientations; cluster centres 12 A apart, so every
+    atom starts with the 8 other atoms of its cluster as its only neighbours
+    within 6 A.  Returns (workload, q, p): every bead at the geometry, momenta
+    m v along +x (first cluster) and -x (second), no thermal part; NVE,
+    dt = 0.5 fs, the water model of small_workload("water8")."""
+    rng = np.random.default_rng(seed)
+    body = _water_body()
+    tri = 2.9 / math.sqrt(3.0) * np.array([[0.0, math.cos(a), math.sin(a)]
+                                           for a in (0.0, 2 * math.pi / 3, 4 * math.pi / 3)])
+    centre = np.array([box_len / 2, box_len / 2, box_len / 2])
+    pos, vel = [], []
+    for dx, v in ((-6.0, speed), (6.0, -speed)):
+        for o in tri:
+            pos.append(centre + np.array([dx, 0.0, 0.0]) + o + body @ _random_rotation(rng).T)
+            vel.append(np.full(3, v))
+    pos = np.concatenate(pos)
+    species = np.tile(np.array([1, 0, 0], dtype=np.int32), 6)
+    box = np.full(3, box_len)
+    model = small_workload("water8").model
+    s = System(len(species), n_beads, 300.0, box, species, pos)
+    wl = Workload("colliding-clusters", [s], model, 0.5, 0.0, 1.0, 200, seed + 2, seed + 3)
+    m = model.masses[species]
+    vx = np.concatenate([np.full(9, speed), np.full(9, -speed)])
+    p1 = np.zeros((len(species), 3))
+    p1[:, 0] = m * vx
+    q = np.broadcast_to(pos, (n_beads, len(species), 3)).reshape(-1, 3)
+    p = np.broadcast_to(p1, (n_beads, len(species), 3)).reshape(-1, 3)
+    return wl, q.astype(np.float32), p.astype(np.float32)
+
+
 def initial_state(wl):
     """All beads at the classical geometry (unwrapped) and thermal bead momenta
     p ~ N(0, m kB T P), drawn with numpy default_rng(momentum_seed).

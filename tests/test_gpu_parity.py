@@ -331,7 +331,7 @@ def test_graph_steps_follow_oracle_with_philox_noise():
 def test_neighbor_overflow_is_reported():
     wl = WORKLOADS["water64-P32"]()
     say("overflow")
-    eng = _engine(wl, max_neighbors=32)
+    eng = _engine(wl, max_neighbors=32, regrow=False)
     q0, p0 = S.initial_state(wl)
     eng.set_state(torch.from_numpy(q0).cuda(), torch.from_numpy(p0).cuda())
     from paper_2503_23728_amd.abi import PimdError, PIMD_E_CAPACITY
