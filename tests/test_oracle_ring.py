@@ -14,6 +14,8 @@ import numpy as np
 import pytest
 
 from oracle import philox, qho, ring
+
+import ring_linear
 from oracle.constants import KB, HBAR, MVV2E
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -168,18 +170,23 @@ def test_pile_l_samples_exact_finite_P_harmonic_average(P):
     rp.set_state(rng.normal(0, 0.3, (n * P, 3)), rng.normal(0, 0.2, (n * P, 3)))
     for _ in range(1500):
         rp.step()
-    x2, kcv = [], []
+    x2, kcv, kprim = [], [], []
     for t in range(3000):
         rp.step()
         if t % 5 == 0:
             x2.append(np.mean(rp.q ** 2))
-            kcv.append(rp.estimators()[0]["K_cv"] / (3 * n))
+            est = rp.estimators()[0]
+            kcv.append(est["K_cv"] / (3 * n))
+            kprim.append(est["K_prim"] / (3 * n))
     mean, err = _block_mean(x2)
     want = qho.x2_beads_sum(m, w, T, P)
     assert abs(mean - want) < 3.5 * err + 2e-3 * want
     # virial (centroid) kinetic energy = half the harmonic energy per dimension
     kmean, kerr = _block_mean(kcv)
     assert abs(kmean - 0.5 * qho.energy_beads(m, w, T, P)) < 3.5 * kerr + 2e-3 * kmean
+    # primitive estimator: the same mean, K_prim = 3nP/(2 beta) - E_spring/P
+    pmean, perr = _block_mean(kprim)
+    assert abs(pmean - 0.5 * qho.energy_beads(m, w, T, P)) < 3.5 * perr + 2e-3 * pmean
 
 
 def test_bead_temperature_is_P_times_T():
@@ -213,6 +220,95 @@ def test_qho_bead_sum_equals_closed_form_and_limits():
     # the bead sum increases monotonically towards the quantum value
     vals = [qho.x2_beads_sum(m, w, T, P) for P in g["beads_sweep"]]
     assert all(a < b for a, b in zip(vals[:-1], vals[1:]))
+
+
+# ---------------------------------------------------------------- Sec. S1 protocol, exact
+# The three sweeps of Sec. S1 (beads at 10 K, temperature at P = 128, time
+# step at 10 K and P = 128) on the stationary covariance of the oracle's own
+# step (ring_linear.py): no sampling error, so the finite-P value is checked
+# to the integrator's O(dt^2) splitting error.  The text shows the sweeps as
+# figures without their abscissae; the temperatures and time steps below are
+# a reading.
+
+S1_TEMPERATURES_K = [10.0, 30.0, 100.0, 300.0, 1000.0]
+S1_TIME_STEPS_FS = [0.25, 0.5, 1.0, 2.0]
+
+
+def _oracle_qho_point(P, T, dt, m, w, tau0=100.0):
+    """(<x^2> per bead, <K_prim>, <K_cv>) per atom, exact stationary means."""
+    steppers = [(2 * P, P, T, np.full(2 * P, m))]
+
+    def one_step(q, p, xi):
+        rp = ring.RingPolymers(steppers, dt, tau0, 1.0, 1, ring.harmonic_force_fn(steppers, w))
+        rp.set_state(q, p)
+        rp.step(noise=xi)
+        return rp.q, rp.p
+    A, B = ring_linear.step_maps(one_step, P)
+    S = ring_linear.stationary_covariance(A, B)
+    single = [(1, P, T, np.array([m]))]
+    rp = ring.RingPolymers(single, dt, tau0, 1.0, 1, ring.harmonic_force_fn(single, w))
+
+    def estimate(key):
+        def f(q):
+            rp.set_state(q, np.zeros_like(q))
+            return rp.estimators()[0][key]
+        return f
+    return (ring_linear.bead_x2(S, P), ring_linear.quadratic_mean(estimate("K_prim"), S, P),
+            ring_linear.quadratic_mean(estimate("K_cv"), S, P))
+
+
+def _s1_check(P, T, dt, x2_tol, kprim_tol):
+    g = json.load(open(os.path.join(GOLDEN, "qho_s1.json")))
+    m, w = g["mass_amu"], g["omega_per_fs"]
+    x2, kprim, kcv = _oracle_qho_point(P, T, dt, m, w)
+    want = qho.x2_beads_sum(m, w, T, P)
+    want_k = 1.5 * qho.energy_beads(m, w, T, P)       # three dimensions, <K> = <V> = E/2 each
+    assert x2 == pytest.approx(want, rel=x2_tol)
+    assert kcv == pytest.approx(want_k, rel=x2_tol)
+    assert kprim == pytest.approx(want_k, rel=kprim_tol)
+    return x2, kprim, kcv
+
+
+@pytest.mark.parametrize("P", json.load(open(os.path.join(GOLDEN, "qho_s1.json")))["beads_sweep"])
+def test_s1_bead_sweep_stationary_average_is_the_exact_finite_P_value(P):
+    # T = 10 K, dt = 0.5 fs: the splitting error is (w dt)^2 / 4 ~ 1e-5 in <x^2>;
+    # K_prim differences the large spring energy and carries it P-fold
+    _s1_check(P, 10.0, 0.5, 2e-5, 5e-4)
+
+
+def test_s1_bead_sweep_converges_to_the_quantum_value():
+    g = json.load(open(os.path.join(GOLDEN, "qho_s1.json")))
+    m, w, T = g["mass_amu"], g["omega_per_fs"], g["temperature_K"]
+    vals = [_oracle_qho_point(P, T, g["dt_fs"], m, w)[0] for P in g["beads_sweep"]]
+    assert all(a < b for a, b in zip(vals[:-1], vals[1:]))
+    assert vals[0] == pytest.approx(qho.x2_classical(m, w, T), rel=2e-5)
+    # 128 beads reach the quantum value to 0.07 % at beta hbar w = 9.5
+    assert vals[-1] == pytest.approx(qho.x2_exact(m, w, T), rel=1e-3)
+
+
+@pytest.mark.parametrize("T", S1_TEMPERATURES_K)
+def test_s1_temperature_sweep_at_128_beads(T):
+    g = json.load(open(os.path.join(GOLDEN, "qho_s1.json")))
+    m, w = g["mass_amu"], g["omega_per_fs"]
+    x2, _, kcv = _s1_check(128, T, g["dt_fs"], 2e-5, 3e-3)
+    assert x2 == pytest.approx(qho.x2_exact(m, w, T), rel=1e-3)
+    assert kcv == pytest.approx(1.5 * qho.energy_exact(w, T), rel=1e-3)
+
+
+def test_s1_time_step_sweep_converges_as_dt_squared():
+    g = json.load(open(os.path.join(GOLDEN, "qho_s1.json")))
+    m, w, T = g["mass_amu"], g["omega_per_fs"], g["temperature_K"]
+    want = qho.x2_beads_sum(m, w, T, 128)
+    want_k = 1.5 * qho.energy_beads(m, w, T, 128)
+    ex, ek = [], []
+    for dt in S1_TIME_STEPS_FS:
+        x2, kprim, _ = _oracle_qho_point(128, T, dt, m, w)
+        ex.append(x2 / want - 1.0)
+        ek.append(kprim / want_k - 1.0)
+    for e in (ex, ek):
+        r = np.array(e[1:]) / np.array(e[:-1])
+        assert np.all((3.6 < r) & (r < 4.4)), r
+    assert abs(ex[0]) < 5e-6 and abs(ek[0]) < 2e-4
 
 
 # ---------------------------------------------------------------- Philox noise
