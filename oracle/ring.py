@@ -68,15 +68,25 @@ class RingPolymers:
     uses the same index as its Philox counter.
     """
 
-    def __init__(self, systems, dt, tau0, pile_lambda, seed, force_fn):
+    def __init__(self, systems, dt, tau0, pile_lambda, seed, force_fn, thermostat="pile-l", boxes=None):
         self.systems = systems
         self.dt, self.tau0, self.lam, self.seed = dt, tau0, pile_lambda, seed
         self.force_fn = force_fn
+        if thermostat not in ("pile-l", "pile-g"):
+            raise ValueError(thermostat)
+        self.thermostat = thermostat
+        self.boxes = None if boxes is None else np.asarray(boxes, dtype=np.float64).reshape(len(systems), 3)
         self.offsets = np.cumsum([0] + [n * P for n, P, _, _ in systems])
         self.total = int(self.offsets[-1])
         self.heat = np.zeros(len(systems))
         self.step_count = 0
-        self.q = self.p = self.F = self.E = None
+        self.q = self.p = self.F = self.E = self.W = None
+
+    def _forces(self):
+        """force_fn(q) -> (E, F) or (E, F, W) with W[sum P_s, 3, 3] the bead virials."""
+        out = self.force_fn(self.q)
+        self.E, self.F = out[0], out[1]
+        self.W = out[2] if len(out) > 2 else None
 
     # -- per-system views ---------------------------------------------------
     def _view(self, a, s):
@@ -87,25 +97,54 @@ class RingPolymers:
         self.q = np.array(q, dtype=np.float64).reshape(-1, 3)
         self.p = np.array(p, dtype=np.float64).reshape(-1, 3)
         self.step_count = step
-        self.E, self.F = self.force_fn(self.q)
+        self._forces()
 
     # -- the four sub-steps ---------------------------------------------------
     def _o_step(self, s, pt, xi):
         n, P, T, m = self.systems[s]
         wk, _ = mode_frequencies(P, T)
+        glob = self.thermostat == "pile-g" and self.tau0 > 0
         if self.tau0 > 0:
             gamma = 2.0 * self.lam * wk
-            gamma[0] = 1.0 / self.tau0
+            gamma[0] = 0.0 if glob else 1.0 / self.tau0
         else:
             gamma = np.zeros(P)
         c1 = np.exp(-gamma * self.dt / 2)
         c2 = np.sqrt(1.0 - c1 * c1)
         sigma = np.sqrt(m * KB * T * P / MVV2E)
         ke0 = 0.5 * MVV2E * np.sum(pt * pt / m[None, :, None])
+        alpha = self._svr_factor(s, pt[0], xi[0]) if glob else 1.0
         pt = c1[:, None, None] * pt + sigma[None, :, None] * c2[:, None, None] * xi
+        pt[0] = alpha * pt[0]
         ke1 = 0.5 * MVV2E * np.sum(pt * pt / m[None, :, None])
         self.heat[s] -= ke1 - ke0
         return pt
+
+    def _svr_factor(self, s, p0, xi0):
+        """PILE-G: one factor for all centroid momenta of system s over a half
+        step, the stochastic velocity rescaling of Bussi, Donadio and
+        Parrinello (J. Chem. Phys. 126, 014101 (2007), Appendix): with
+        N_f = 3N centroid degrees of freedom, centroid kinetic energy K, target
+        Kbar = N_f k_B T P / 2 (the centroid momenta of the bead-potential form
+        have variance m k_B T P) and c = exp(-(dt/2)/tau0),
+          alpha^2 = c + (Kbar/(N_f K)) (1 - c) (R_1^2 + S) + 2 R_1 sqrt(c (1 - c) Kbar/(N_f K)),
+          sign(alpha) = sign(R_1 + sqrt(c N_f K / ((1 - c) Kbar))),
+        R_1 a standard normal and S a chi-square variate with N_f - 1 degrees.
+        Its random numbers are the centroid's own normals of this half step:
+        R_1 that of (atom 0, x), S the sum of squares of the other 3N - 1."""
+        n, P, T, m = self.systems[s]
+        nf = 3 * n
+        K = 0.5 * MVV2E * np.sum(p0 * p0 / m[:, None])
+        if K <= 0.0:
+            return 1.0
+        kbar = 0.5 * nf * KB * T * P
+        c = np.exp(-0.5 * self.dt / self.tau0)
+        r1 = float(xi0[0, 0])
+        rest = float(np.sum(xi0 * xi0)) - r1 * r1
+        ratio = kbar / (nf * K)
+        a2 = c + ratio * (1.0 - c) * (r1 * r1 + rest) + 2.0 * r1 * np.sqrt(c * (1.0 - c) * ratio)
+        sign = 1.0 if r1 + np.sqrt(c / ((1.0 - c) * ratio)) >= 0.0 else -1.0
+        return sign * np.sqrt(a2)
 
     def _a_step(self, s, qt, pt):
         n, P, T, m = self.systems[s]
@@ -138,7 +177,7 @@ class RingPolymers:
             qt, pt = self._a_step(s, qt, pt)
             q[...] = np.einsum("jk,knc->jnc", C, qt)
             p[...] = np.einsum("jk,knc->jnc", C, pt)
-        self.E, self.F = self.force_fn(self.q)
+        self._forces()
         xi1 = self._noise(1, noise)
         for s in range(len(self.systems)):
             n, P, T, m = self.systems[s]
@@ -164,16 +203,32 @@ class RingPolymers:
             qbar = q.mean(axis=0)
             k_beads = 0.5 * MVV2E * np.sum(p * p / m[None, :, None])
             v_sum = float(np.sum(E))
+            k_cv = 3 * n / (2 * beta) - np.sum((q - qbar[None]) * F) / (2 * P)
             out.append(dict(
                 V_bar=v_sum / P,
                 K_prim=3 * n * P / (2 * beta) - e_spring / P,
-                K_cv=3 * n / (2 * beta) - np.sum((q - qbar[None]) * F) / (2 * P),
+                K_cv=k_cv,
                 E_spring=e_spring,
                 K_beads=k_beads,
                 T_beads=2 * k_beads / (3 * n * P * KB),
                 H_conserved=k_beads + e_spring + v_sum + self.heat[s],
-                heat_bath=self.heat[s]))
+                heat_bath=self.heat[s],
+                P_cv=self._pressure_cv(s, k_cv)))
         return out
+
+    def _pressure_cv(self, s, k_cv):
+        """Centroid-virial pressure (eV/A^3) of a periodic system: scaling the
+        box and the centroids by (1 + e) while the beads keep their offsets
+        from their centroids leaves the springs unchanged, and
+          P_cv = (2 K_cv + (1/P) sum_k tr W^(k)) / (3 V),
+        with W^(k) the virial of bead k (W_ab = -dE/deps_ab); the offsets'
+        share of tr W is the -(q - qbar).F term inside K_cv.  0 without a box
+        or without bead virials."""
+        if self.boxes is None or self.W is None or not np.all(self.boxes[s] > 0):
+            return 0.0
+        P = self.systems[s][1]
+        trW = float(np.sum(np.trace(self.W[self._bead_slice(s)], axis1=1, axis2=2)))
+        return (2.0 * k_cv + trW / P) / (3.0 * float(np.prod(self.boxes[s])))
 
     def _bead_slice(self, s):
         b0 = sum(P for _, P, _, _ in self.systems[:s])
@@ -290,7 +345,7 @@ class StagingRingPolymers(RingPolymers):
                 u[1:], pt[1:] = un, pn
             q[...] = staging_inverse(u)
             p[...] = pt
-        self.E, self.F = self.force_fn(self.q)
+        self._forces()
         xi1 = self._noise(1, noise)
         for s in range(len(self.systems)):
             p, F = self._view(self.p, s), self._view(self.F, s)
@@ -357,7 +412,7 @@ class PrimitiveRingPolymers(RingPolymers):
             pt = pt + (self.dt / 2) * (F + spring_forces(q, m, wP)) / MVV2E
             q[...] = q + self.dt * pt / m[None, :, None]
             p[...] = pt
-        self.E, self.F = self.force_fn(self.q)
+        self._forces()
         xi1 = self._noise(1, noise)
         for s in range(len(self.systems)):
             n, P, T, m = self.systems[s]

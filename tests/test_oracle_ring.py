@@ -203,6 +203,138 @@ def test_bead_temperature_is_P_times_T():
     assert abs(mean - P * T) < 3.5 * err + 5e-3 * P * T
 
 
+# ---------------------------------------------------------------- PILE-G and the centroid-virial pressure
+
+def test_pile_g_centroid_kinetic_energy_relaxes_at_the_half_step_rate():
+    # Bussi, Donadio, Parrinello (2007): over a half step, E[K'] = c K + (1 - c) Kbar,
+    # c = exp(-(dt/2)/tau0), Kbar = N_f k_B T P / 2 -- averaged over the noise
+    n, P, T, dt, tau0 = 5, 4, 300.0, 0.5, 2.0
+    m = np.linspace(1.0, 16.0, n)
+    rp = ring.RingPolymers([(n, P, T, m)], dt, tau0, 1.0, 1, lambda q: (np.zeros(P), np.zeros_like(q)),
+                           thermostat="pile-g")
+    rng = np.random.default_rng(30)
+    p0 = rng.normal(size=(n, 3)) * np.sqrt(m)[:, None]
+    kbar = 0.5 * 3 * n * KB * T * P
+    K = 0.5 * MVV2E * np.sum(p0 * p0 / m[:, None])
+    p0 *= np.sqrt(3.0 * kbar / K)                       # K = 3 Kbar
+    K = 3.0 * kbar
+    a2 = np.array([rp._svr_factor(0, p0, rng.normal(size=(n, 3))) ** 2 for _ in range(40000)])
+    c = np.exp(-0.5 * dt / tau0)
+    want = c + (1.0 - c) * kbar / K
+    assert abs(a2.mean() - want) < 4 * a2.std() / np.sqrt(len(a2))
+    # a full-step rate exp(-dt/tau0) is ruled out
+    c2 = np.exp(-dt / tau0)
+    assert abs(a2.mean() - (c2 + (1.0 - c2) * kbar / K)) > 10 * a2.std() / np.sqrt(len(a2))
+
+
+@pytest.mark.parametrize("P", [1, 4])
+def test_pile_g_samples_the_canonical_centroid_kinetic_energy(P):
+    # free ring polymers: the centroid kinetic energy is touched only by the
+    # global thermostat, whose stationary law is Gamma(N_f / 2, k_B T P) at any dt
+    n, T = 4, 200.0
+    m = np.array([1.0, 2.0, 12.0, 16.0])
+    rp = ring.RingPolymers([(n, P, T, m)], 0.5, 3.0, 1.0, 31 + P, lambda q: (np.zeros(P), np.zeros_like(q)),
+                           thermostat="pile-g")
+    rng = np.random.default_rng(32)
+    rp.set_state(np.zeros((n * P, 3)), rng.normal(size=(n * P, 3)))
+    C = ring.nm_matrix(P)
+    ks = []
+    for t in range(12000):
+        rp.step()
+        if t >= 200:
+            pt0 = np.einsum("j,jnc->nc", C[:, 0], rp.p.reshape(P, n, 3))
+            ks.append(0.5 * MVV2E * np.sum(pt0 * pt0 / m[:, None]))
+    ks = np.array(ks) / (KB * T * P)                    # in units of k_B T P: Gamma(6, 1)
+    nf = 3 * n
+    mean, err = _block_mean(ks, 40)
+    assert abs(mean - nf / 2) < 4 * err
+    var, verr = _block_mean((ks - nf / 2) ** 2, 40)
+    assert abs(var - nf / 2) < 4 * verr                 # Gamma(k, 1): variance k
+    skew, serr = _block_mean((ks - nf / 2) ** 3, 40)
+    assert abs(skew - 2 * nf / 2) < 4 * serr            # third central moment 2k
+
+
+def test_pile_g_samples_exact_finite_P_harmonic_average():
+    g = json.load(open(os.path.join(GOLDEN, "qho_s1.json")))
+    m, w = g["mass_amu"], g["omega_per_fs"]
+    T, P, n = 100.0, 8, 600
+    systems = _systems(n, P, T, mass=m)
+    rp = ring.RingPolymers(systems, g["dt_fs"], 100.0, 1.0, 33, ring.harmonic_force_fn(systems, w),
+                           thermostat="pile-g")
+    rng = np.random.default_rng(34)
+    rp.set_state(rng.normal(0, 0.3, (n * P, 3)), rng.normal(0, 0.2, (n * P, 3)))
+    for _ in range(1500):
+        rp.step()
+    x2, kcv = [], []
+    for t in range(3000):
+        rp.step()
+        if t % 5 == 0:
+            x2.append(np.mean(rp.q ** 2))
+            kcv.append(rp.estimators()[0]["K_cv"] / (3 * n))
+    mean, err = _block_mean(x2)
+    want = qho.x2_beads_sum(m, w, T, P)
+    assert abs(mean - want) < 3.5 * err + 2e-3 * want
+    kmean, kerr = _block_mean(kcv)
+    assert abs(kmean - 0.5 * qho.energy_beads(m, w, T, P)) < 3.5 * kerr + 2e-3 * kmean
+
+
+def test_pile_g_heat_balances_energy():
+    omega = 0.02
+    systems = _systems(6, 8, 300.0)
+    rp = ring.RingPolymers(systems, 0.25, 50.0, 1.0, 35, ring.harmonic_force_fn(systems, omega),
+                           thermostat="pile-g")
+    rng = np.random.default_rng(36)
+    rp.set_state(rng.normal(0, 0.1, (48, 3)), rng.normal(0, 1.0, (48, 3)))
+    h0 = rp.estimators()[0]["H_conserved"]
+    for _ in range(400):
+        rp.step()
+    est = rp.estimators()[0]
+    assert abs(est["heat_bath"]) > 1e-3
+    assert abs(est["H_conserved"] - h0) < 1e-3 * abs(est["heat_bath"])
+
+
+def test_pressure_of_free_ring_polymers_is_the_ideal_gas_law():
+    n, P, T = 7, 8, 250.0
+    box = np.array([10.0, 12.0, 9.0])
+    rp = ring.RingPolymers([(n, P, T, np.full(n, 2.0))], 0.5, 100.0, 1.0, 3,
+                           lambda q: (np.zeros(P), np.zeros_like(q), np.zeros((P, 3, 3))), boxes=[box])
+    rng = np.random.default_rng(37)
+    rp.set_state(rng.normal(0, 2.0, (n * P, 3)), rng.normal(size=(n * P, 3)))
+    assert rp.estimators()[0]["P_cv"] == pytest.approx(n * KB * T / np.prod(box), rel=1e-13)
+
+
+def test_centroid_virial_pressure_is_minus_the_free_energy_strain_derivative():
+    # P_cv V - N k_B T = -(1/3) d/de (1/P) sum_k E(q^k(e)) at e = 0, where the
+    # box and the centroids scale by (1 + e) and every bead keeps its offset
+    # from its centroid; central differences of the FP64 oracle energy
+    from paper_2503_23728_amd import synthetic as S
+    from oracle import bpnn, neighbors
+    wl = S.small_workload("water8", n_beads=4)
+    s = wl.systems[0]
+    P, n = s.n_beads, s.n_atoms
+    q = S.perturbed_beads(wl, 0.08, seed=38).astype(np.float64)
+    rp = ring.RingPolymers([(n, P, s.temperature, wl.model.masses[s.species])], wl.dt, wl.tau0, 1.0, 1,
+                           lambda qq: bpnn.energy_forces(wl, qq.astype(np.float32)), boxes=[s.box])
+    rp.set_state(q, np.zeros_like(q))
+    est = rp.estimators()[0]
+    V = float(np.prod(s.box))
+    lhs = est["P_cv"] * V - n * KB * s.temperature
+    beads = q.reshape(P, n, 3)
+    qbar = beads.mean(axis=0)
+    lists = [neighbors.brute_force_fp32(beads[k].astype(np.float32), s.box, wl.model.cutoff) for k in range(P)]
+
+    def f(e):
+        tot = 0.0
+        for k in range(P):
+            qk = (1.0 + e) * qbar + (beads[k] - qbar)
+            G = bpnn.descriptors(wl.model, qk, s.species, s.box * (1.0 + e), np.arange(n), *lists[k])
+            tot += bpnn.mlp_energy_grad(wl.model, s.species, bpnn.normalise(wl.model, G, s.species))[0].sum()
+        return tot / P
+    h = 1e-6
+    rhs = -(f(h) - f(-h)) / (2 * h) / 3.0
+    assert lhs == pytest.approx(rhs, rel=1e-6, abs=1e-9)
+
+
 # ---------------------------------------------------------------- QHO closed forms
 
 def test_qho_bead_sum_equals_closed_form_and_limits():
