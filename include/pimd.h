@@ -273,6 +273,24 @@ pimd_status pimd_workspace_size(const pimd_config *cfg, size_t *bytes);
 pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_bytes,
                       void *hip_stream, pimd_ctx **out);
 
+/* Allocation-free pimd_init, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same as pimd_init, with the workspace taken from a static
+ * device array of PIMD_STATIC_WORKSPACE_BYTES inside the library instead of
+ * the caller's memory: each device the library runs on holds its own array
+ * until the process ends.  The call allocates no device memory (no hipMalloc,
+ * hipFree, stream or graph creation; the context itself is host memory, as
+ * for pimd_init).
+ * Errors: PIMD_E_CAPACITY (nothing set up) when pimd_workspace_size(cfg)
+ * exceeds the array; PIMD_E_STATE while another context made by this call
+ * lives on the current device -- one such context per device at a time, since
+ * two would share the array (pimd_destroy releases it); PIMD_E_DEVICE when the
+ * array's device address cannot be obtained.  The array keeps the last
+ * context's contents: like pimd_init on uninitialised memory, this call writes
+ * every table, counter and flag the kernels read before they read it. */
+#define PIMD_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+pimd_status pimd_init_static(const pimd_config *cfg, void *hip_stream, pimd_ctx **out);
+
 /* Replace the stream later calls enqueue on. */
 pimd_status pimd_set_stream(pimd_ctx *ctx, void *hip_stream);
 

@@ -66,6 +66,7 @@ class pimd_estimates(ctypes.Structure):
 _SIGNATURES = {
     "pimd_workspace_size": (c_int32, [POINTER(pimd_config), POINTER(c_size_t)]),
     "pimd_init": (c_int32, [POINTER(pimd_config), c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
+    "pimd_init_static": (c_int32, [POINTER(pimd_config), c_void_p, POINTER(c_void_p)]),
     "pimd_set_stream": (c_int32, [c_void_p, c_void_p]),
     "pimd_set_state": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64]),
     "pimd_get_state": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_int64)]),
@@ -144,6 +145,15 @@ def pimd_init(cfg, workspace_ptr, ws_bytes, stream_ptr):
     st = lib().pimd_init(ctypes.byref(cfg), c_void_p(workspace_ptr), ws_bytes, c_void_p(stream_ptr),
                          ctypes.byref(out))
     return st, out.value
+
+
+def pimd_init_static(cfg, stream_ptr):
+    out = c_void_p(0)
+    st = lib().pimd_init_static(ctypes.byref(cfg), c_void_p(stream_ptr), ctypes.byref(out))
+    return st, out.value
+
+
+PIMD_STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 def pimd_set_stream(ctx, stream_ptr):

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -489,6 +490,7 @@ struct pimd_ctx {
     bool deposit_now = false;
     int transform = PIMD_TRANSFORM_NORMAL_MODES;   // coordinates of the integrator
     int device = 0;
+    int static_device = -1;            // device whose static workspace this context holds (pimd_init_static)
     std::string err;
 };
 
@@ -1296,10 +1298,58 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     e = configure_integrator_lds(pl.max_P);
     if (e != hipSuccess)
         return bail(PIMD_E_DEVICE, std::string("integrator LDS: ") + hipGetErrorString(e));
-    e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
-    if (e != hipSuccess)
-        return bail(PIMD_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     *out = c;
+    return PIMD_OK;
+}
+
+// ---- pimd_init without device allocation
+// The workspace of pimd_init_static contexts: one array per device, held until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// the device array: its device address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[PIMD_STATIC_WORKSPACE_BYTES];
+
+namespace {
+std::mutex g_static_mu;
+std::map<int, void *> g_static_ptr;   // device -> device address of its scratch array
+std::map<int, bool> g_static_busy;    // device -> a live context holds the array
+}  // namespace
+
+pimd_status pimd_init_static(const pimd_config *cfg, void *hip_stream, pimd_ctx **out)
+{
+    if (!out)
+        return fail(&g_init_error, PIMD_E_ARG, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    pimd_status st = pimd_workspace_size(cfg, &need);
+    if (st != PIMD_OK)
+        return st;
+    if (need > PIMD_STATIC_WORKSPACE_BYTES)
+        return fail(&g_init_error, PIMD_E_CAPACITY,
+                    "pimd_init_static: the workspace needs " + std::to_string(need) +
+                        " bytes; the static workspace holds " + std::to_string(PIMD_STATIC_WORKSPACE_BYTES));
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(&g_init_error, PIMD_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_busy[dev])
+        return fail(&g_init_error, PIMD_E_STATE,
+                    "pimd_init_static: another context holds this device's static workspace (destroy it first)");
+    auto it = g_static_ptr.find(dev);
+    if (it == g_static_ptr.end()) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(&g_init_error, PIMD_E_DEVICE,
+                        std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        it = g_static_ptr.emplace(dev, ptr).first;
+    }
+    st = pimd_init(cfg, it->second, PIMD_STATIC_WORKSPACE_BYTES, hip_stream, out);
+    if (st != PIMD_OK)
+        return st;
+    (*out)->static_device = dev;
+    g_static_busy[dev] = true;
     return PIMD_OK;
 }
 
@@ -1455,6 +1505,8 @@ pimd_status pimd_step(pimd_ctx *ctx, int32_t n_steps)
         return PIMD_OK;
     }
     if (done < n_steps && !ctx->gexec) {
+        if (!ctx->capture)
+            HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
         HIPCHK(ctx, hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
         pimd_status st = run_step(ctx, ctx->capture, nullptr);
         hipGraph_t g = nullptr;
@@ -2162,6 +2214,10 @@ void pimd_destroy(pimd_ctx *ctx)
         (void)hipGraphDestroy(ctx->graph);
     if (ctx->capture)
         (void)hipStreamDestroy(ctx->capture);
+    if (ctx->static_device >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_busy[ctx->static_device] = false;
+    }
     delete ctx;
 }
 

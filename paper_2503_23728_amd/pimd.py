@@ -176,6 +176,10 @@ def grown_slots(k):
 class Pimd:
     """One library context: state, workspace and stream on one device.
 
+    static_workspace=True builds the context with pimd_init_static on the
+    library's own per-device array (no device allocation at all; small
+    systems only, one such context per device at a time).
+
     regrow=True: when a synchronising call reports that an atom had more
     neighbours than the slots per atom (PIMD_E_CAPACITY), the context is built
     again with more slots (grown_slots), the state the library froze at (the
@@ -185,7 +189,7 @@ class Pimd:
 
     def __init__(self, systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
                  omega=0.0, max_neighbors=0, masses=None, device="cuda:0", stream=None, metad=None,
-                 transform="normal-modes", neighbor_skin=0.0, regrow=True):
+                 transform="normal-modes", neighbor_skin=0.0, regrow=True, static_workspace=False):
         self.device = torch.device(device)
         self.metad = metad
         self.systems = list(systems)
@@ -193,6 +197,7 @@ class Pimd:
         self.neighbor_skin = float(neighbor_skin)
         self.regrow = regrow
         self.regrowths = 0
+        self.static_workspace = bool(static_workspace)
         self._cfg_args = (dt, tau0, pile_lambda, seed, precision, potential, omega, masses, metad, transform,
                           neighbor_skin)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -212,13 +217,20 @@ class Pimd:
         self.max_neighbors = max_neighbors
         self.cfg, self._keep = make_config(self.systems, self.model, dt, tau0, lam, seed, precision, potential,
                                            omega, max_neighbors, masses, metad, transform, skin)
-        st, nbytes = abi.pimd_workspace_size(self.cfg)
-        _check(st)
-        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
-        if self.workspace.data_ptr() % 256:
-            raise RuntimeError("torch returned a workspace that is not 256-byte aligned")
-        st, ctx = abi.pimd_init(self.cfg, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
-        _check(st)
+        if self.static_workspace:
+            # the library's own per-device array: no device allocation at all
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                st, ctx = abi.pimd_init_static(self.cfg, self.stream.cuda_stream)
+            _check(st)
+        else:
+            st, nbytes = abi.pimd_workspace_size(self.cfg)
+            _check(st)
+            self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+            if self.workspace.data_ptr() % 256:
+                raise RuntimeError("torch returned a workspace that is not 256-byte aligned")
+            st, ctx = abi.pimd_init(self.cfg, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+            _check(st)
         self.ctx = ctx
         st, self.B, self.n_beads, self.D = abi.pimd_sizes(ctx)
         _check(st, ctx)

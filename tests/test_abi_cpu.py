@@ -175,3 +175,14 @@ def test_metad_calls_need_a_context(lib):
     assert lib.pimd_metad_cv(None, None, None) == abi.PIMD_E_ARG
     assert lib.pimd_metad_set_hills(None, 0, None, None) == abi.PIMD_E_ARG
     assert lib.pimd_metad_fes(None, 0, 0, None, None) == abi.PIMD_E_ARG
+
+
+def test_static_init_refuses_a_workspace_larger_than_its_array(lib):
+    # water 64, P = 32 needs about 130 MiB; the check precedes every HIP call
+    cfg, keep = _cfg(S.workload(2))
+    assert abi.pimd_workspace_size(cfg)[1] > abi.PIMD_STATIC_WORKSPACE_BYTES
+    st, ctx = abi.pimd_init_static(cfg, 0)
+    assert st == abi.PIMD_E_CAPACITY and not ctx
+    assert "static workspace" in abi.pimd_last_error(None)
+    bad, keep2 = _cfg(S.workload(1), neighbor_skin=1.0)
+    assert abi.pimd_init_static(bad, 0)[0] == abi.PIMD_E_UNSUPPORTED
