@@ -7,7 +7,8 @@
 //   g_L = w_o * (1 - h_L^2),  g_{l-1} = (W_l^T g_l) * (1 - h_{l-1}^2),  dE/dx = W_1^T g_1
 //
 // Each GEMM is rows x K times K x N with the 16x16 MFMA tiles of gfx950,
-// accumulating in FP32; the operand precision modes are listed below.
+// accumulating in FP32 (in the FP32 mode with the block-wise compensated sum
+// of gemm16_cols); the operand precision modes are listed below.
 // Activations pass between layers through the workgroup's LDS tile;
 // (1 - h^2) of every hidden layer stays in registers in the MFMA output
 // layout, which is also the layout of the backward GEMM outputs.
@@ -37,6 +38,13 @@ __device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float
 // r < RT of the tile and the column tiles ct = w + 4t < nct, with
 // B[k][n] = Bt[n][k] (row-major Bt[N][ldb]); A is the LDS tile.  Each B
 // fragment read from memory feeds RT MFMAs.
+// The k range is summed in blocks of 32 (eight MFMAs into a zeroed FP32
+// accumulator); the block sums are added into a float-float pair (hi, lo)
+// by Knuth's two-sum, so the rounding of a long FP32 running sum (which
+// grows with K) is left out: a dot product's error is that of a 32-term FP32
+// sum.  On the random-weight water and ice networks this cuts the MLP's
+// share of the worst-atom force error about threefold (float32 emulation
+// against the FP64 oracle), for three VALU operations per MFMA.
 template <int RT>
 __device__ __forceinline__ void gemm16_cols(const float *act, int K, const float *Bt, int ldb, int nct, int w,
                                             f32x4 (&acc)[RT][2])
@@ -44,27 +52,59 @@ __device__ __forceinline__ void gemm16_cols(const float *act, int K, const float
     constexpr int S = MlpCfg::S;
     const int lane = lane_id();
     const int lr = lane & 15, lg = lane >> 4;
+    f32x4 lo[RT][2];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
-        acc[r][0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        acc[r][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    }
-    for (int k0 = 0; k0 < K; k0 += 4) {
-        float a[RT];
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-            a[r] = act[(16 * r + lr) * S + k0 + lg];
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            const int ct = w + 4 * t;
-            if (ct < nct) {
-                const float b = Bt[(ct * 16 + lr) * ldb + k0 + lg];
+            acc[r][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            lo[r][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    for (int kb = 0; kb < K; kb += 32) {
+        const int ke = kb + 32 < K ? kb + 32 : K;
+        f32x4 blk[RT][2];
 #pragma unroll
-                for (int r = 0; r < RT; ++r)
-                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b, acc[r][t], 0, 0, 0);
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                blk[r][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int k0 = kb; k0 < ke; k0 += 4) {
+            float a[RT];
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+                a[r] = act[(16 * r + lr) * S + k0 + lg];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int ct = w + 4 * t;
+                if (ct < nct) {
+                    const float b = Bt[(ct * 16 + lr) * ldb + k0 + lg];
+#pragma unroll
+                    for (int r = 0; r < RT; ++r)
+                        blk[r][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b, blk[r][t], 0, 0, 0);
+                }
             }
         }
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float s0 = acc[r][t][q], b0 = blk[r][t][q];
+                    const float sum = s0 + b0;
+                    const float bv = sum - s0;
+                    const float av = sum - bv;
+                    lo[r][t][q] += (s0 - av) + (b0 - bv);
+                    acc[r][t][q] = sum;
+                }
     }
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc[r][t][q] += lo[r][t][q];
 }
 
 // One workgroup per tile of 16 RT rows (tiles of all elements in one

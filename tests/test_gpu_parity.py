@@ -18,7 +18,6 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 FP32_FORCE_TOL = 1e-5
-FP32_MLP_FORCE_TOL = 3e-5    # MLP in FP32 as well: FP32 activations, see the design notes
 FP32_ENERGY_TOL = 1e-6
 BF16_FORCE_TOL = 2e-2
 
@@ -149,8 +148,8 @@ def test_descriptors_match_oracle(name):
 @pytest.mark.parametrize("prec", ["fp64-mlp", "fp32"])
 @pytest.mark.parametrize("name", list(WORKLOADS))
 def test_fp32_energy_forces_virial(name, prec):
-    # FP32 descriptors, adjoint and integrator; MLP in FP64 (the accuracy path)
-    # or FP32 (the plain path, whose FP32 activations set a floor near 1e-5)
+    # FP32 descriptors, adjoint and integrator; MLP in FP64 or in FP32 (the
+    # plain path: FP32 operands and activations, block-compensated sums)
     wl = WORKLOADS[name]()
     say(f"{prec} forces {name}")
     eng = _engine(wl, precision=prec)
@@ -161,7 +160,7 @@ def test_fp32_energy_forces_virial(name, prec):
     fe, ee = force_error(F, F_ref), energy_error(E, E_ref, A)
     we = rel_max(W, W_ref)
     say(f"  force err {fe:.2e} energy err {ee:.2e} virial err {we:.2e}")
-    assert fe < (FP32_FORCE_TOL if prec == "fp64-mlp" else FP32_MLP_FORCE_TOL)
+    assert fe < FP32_FORCE_TOL
     assert ee < FP32_ENERGY_TOL
     assert we < 1e-4
 
