@@ -211,6 +211,23 @@ typedef struct {
  *                 (velocity Verlet on H_P: keep 2 w_P dt well below 2). */
 enum { PIMD_TRANSFORM_NORMAL_MODES = 0, PIMD_TRANSFORM_STAGING = 1, PIMD_TRANSFORM_PRIMITIVE = 2 };
 
+/* Thermostat of the normal-mode integrator (the PILE family of Table S3):
+ *   PILE_L  Langevin friction on every mode: gamma_0 = 1/tau0 on the centroid,
+ *           gamma_k = 2 pile_lambda w_k on the others.
+ *   PILE_G  the same on the non-centroid modes; the centroid of every system
+ *           is rescaled as a whole, once per half step, by the stochastic
+ *           velocity rescaling of Bussi, Donadio and Parrinello (J. Chem. Phys.
+ *           126, 014101 (2007)) with time constant tau0 towards the canonical
+ *           centroid kinetic energy 3N k_B T P / 2: with K the centroid kinetic
+ *           energy and c = exp(-(dt/2)/tau0),
+ *             alpha^2 = c + (Kbar/(3N K))(1 - c)(R_1^2 + S) + 2 R_1 sqrt(c (1 - c) Kbar/(3N K)),
+ *             sign(alpha) = sign(R_1 + sqrt(3N K c / ((1 - c) Kbar))),
+ *           R_1 the thermostat normal of (centroid mode, atom 0, x) and S the
+ *           sum of squares of the system's other 3N - 1 centroid normals (the
+ *           same Philox counters as PILE-L, or the injected noise).  Normal
+ *           modes only (PIMD_E_UNSUPPORTED with staging or primitive). */
+enum { PIMD_THERMOSTAT_PILE_L = 0, PIMD_THERMOSTAT_PILE_G = 1 };
+
 typedef struct {
     int32_t n_systems;                 /* >= 1 */
     const int32_t *n_atoms;            /* [n_systems], >= 1 */
@@ -240,6 +257,7 @@ typedef struct {
                                           evaluation (the same lists, key for key).  Needs a box for every
                                           system (PIMD_E_UNSUPPORTED otherwise); a full centroid list is
                                           PIMD_E_CAPACITY like a full bead list */
+    int32_t thermostat;                /* PIMD_THERMOSTAT_* (0: PILE-L) */
 } pimd_config;
 
 /* Finite-P estimators of one system (Sec. 2.1; virial kinetic energy of
@@ -251,11 +269,21 @@ typedef struct {
  *   K_beads = sum |p|^2 / (2m),  T_beads = 2 K_beads / (3 N P k_B)  (-> P T)
  *   heat_bath = -(sum of kinetic-energy changes made by every O step)
  *   H_conserved = K_beads + E_spring + sum_k V(q^k) + heat_bath
+ *   P_cv   = (2 K_cv + (1/P) sum_k tr W^(k)) / (3 V)  (eV/A^3), the centroid-virial
+ *            pressure of a system with a box of volume V: scaling the box and the
+ *            centroids while every bead keeps its offset from its centroid
+ *            leaves the springs unchanged, so P_cv V - N k_B T is minus the
+ *            strain derivative of (1/P) sum_k V(q^k) (the NPT estimator of
+ *            Sec. 2.1's bead averages); W^(k) the virial of bead k as in
+ *            pimd_energy_forces.  0 without a box and with the direct-force head
+ *            (no energy, no virial)
  * With a metadynamics bias the forces, and so K_cv, are those of the biased
- * ring; H_conserved leaves the (time-dependent) bias out. */
+ * ring (P_cv uses the unbiased virial); H_conserved leaves the (time-dependent)
+ * bias out. */
 typedef struct {
     double V_bar, K_prim, K_cv, E_spring, K_beads, T_beads, H_conserved, heat_bath;
     double V_bias;   /* sum_k V^(k)(s^(k)) / P, the metadynamics bias (0 without one) */
+    double P_cv;     /* centroid-virial pressure, eV/A^3 */
 } pimd_estimates;
 
 /* Bytes of device workspace a context needs for cfg.  No GPU needed. */

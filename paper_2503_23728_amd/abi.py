@@ -19,6 +19,7 @@ PIMD_PREC_FP32, PIMD_PREC_BF16_MLP, PIMD_PREC_BF16_PLAIN, PIMD_PREC_FP64_MLP = 0
 PIMD_POT_BPNN, PIMD_POT_HARMONIC, PIMD_POT_GFN = 0, 1, 2
 PIMD_CV_DISTANCES, PIMD_CV_XRD = 1, 2
 PIMD_TRANSFORM_NORMAL_MODES, PIMD_TRANSFORM_STAGING, PIMD_TRANSFORM_PRIMITIVE = 0, 1, 2
+PIMD_THERMOSTAT_PILE_L, PIMD_THERMOSTAT_PILE_G = 0, 1
 
 
 class pimd_bpnn_model(ctypes.Structure):
@@ -49,7 +50,7 @@ class pimd_config(ctypes.Structure):
                 ("precision", c_int32), ("potential", c_int32), ("model", POINTER(pimd_bpnn_model)),
                 ("harmonic_omega_per_fs", c_double), ("max_neighbors", c_int32),
                 ("gfn", POINTER(pimd_gfn_model)), ("metad", POINTER(pimd_metad)), ("transform", c_int32),
-                ("neighbor_skin_A", c_double)]
+                ("neighbor_skin_A", c_double), ("thermostat", c_int32)]
 
 
 class pimd_tuning(ctypes.Structure):
@@ -60,7 +61,7 @@ class pimd_tuning(ctypes.Structure):
 
 class pimd_estimates(ctypes.Structure):
     _fields_ = [(n, c_double) for n in ("V_bar", "K_prim", "K_cv", "E_spring", "K_beads", "T_beads",
-                                        "H_conserved", "heat_bath", "V_bias")]
+                                        "H_conserved", "heat_bath", "V_bias", "P_cv")]
 
 
 _SIGNATURES = {

@@ -1,6 +1,7 @@
 // Ring-polymer propagation in normal modes with the PILE-L thermostat
 // (Sec. 2.1: normal-mode transformation of the ring polymer; Table S3:
-// PILE-L), split as O(dt/2) B(dt/2) A(dt) [forces] B(dt/2) O(dt/2).
+// PILE-L), or PILE-G (a global thermostat on the centroid, below), split as
+// O(dt/2) B(dt/2) A(dt) [forces] B(dt/2) O(dt/2).
 //
 // A workgroup owns `ncol` columns (atom, xyz) of one system and P threads per
 // column.  The P bead values of each column are staged in LDS; thread k of a
@@ -37,6 +38,7 @@ struct IntegArgs {
     const int64_t *step;
     double *dke_part;
     const float *xi;     // injected noise [2][B][3] or null
+    const double *svr;   // PILE-G: per-system factor of the centroid momenta for this half step, else null
     int B;
     float dt;
     uint32_t key0, key1;
@@ -186,9 +188,9 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
                     qt += c * sq[j];
                 }
             }
-            // O(dt/2), half 0
+            // O(dt/2), half 0 (PILE-G: the centroid takes the global factor instead)
             const double xi = (double)noise_value(a, 0, row, cc, step);
-            const double pn = M.c1 * pt + sig * M.c2 * xi;
+            const double pn = (NM && a.svr && kk == 0) ? a.svr[u.sys] * pt : M.c1 * pt + sig * M.c2 * xi;
             dke = 0.5 * (pn * pn - pt * pt) / mk * kMvv2e;
             pt = pn + kick * Ft;  // B(dt/2)
             // A(dt)
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
                     pt += ct[j] * (sp[j] + kick * sf[j]);
             }
             const double xi = (double)noise_value(a, 1, row, cc, step);
-            const double pn = M.c1 * pt + sig * M.c2 * xi;
+            const double pn = (NM && a.svr && kk == 0) ? a.svr[u.sys] * pt : M.c1 * pt + sig * M.c2 * xi;
             dke = 0.5 * (pn * pn - pt * pt) / mk * kMvv2e;
             pt = pn;
         }
@@ -250,6 +252,85 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
     const double tot = block_sum_double(dke, red);
     if (tid == 0)
         a.dke_part[2 * blockIdx.x + (PRE ? 0 : 1)] = tot;
+}
+
+// PILE-G: the centroid mode of every system is thermostatted by one factor
+// per half step, the stochastic velocity rescaling of Bussi, Donadio and
+// Parrinello (J. Chem. Phys. 126, 014101 (2007), Appendix), while the other
+// modes keep their Langevin friction.  With N_f = 3N, the centroid kinetic
+// energy K (of p~_0 = sum_j p_j / sqrt(P), after the force kick in the second
+// half), Kbar = N_f k_B T P / 2 and c = exp(-(dt/2)/tau0):
+//   alpha^2 = c + (Kbar/(N_f K))(1 - c)(R_1^2 + S) + 2 R_1 sqrt(c (1 - c) Kbar/(N_f K)),
+//   sign(alpha) = sign(R_1 + sqrt(c N_f K / ((1 - c) Kbar))),
+// R_1 the centroid normal of (atom 0, x) and S the sum of squares of its other
+// 3N - 1 normals, so the random numbers are those of the thermostat's own
+// counters (or the injected buffer).
+// k_centroid_terms: per integrator unit, one thread per column: K and sum xi^2
+// of its columns, tree-summed in FP64 -> part[2 unit], part[2 unit + 1].
+template <bool PRE>
+__global__ __launch_bounds__(256) void k_centroid_terms(IntegArgs a, double *__restrict__ part)
+{
+    __shared__ double red[256];
+    const IntegUnit u = a.units[blockIdx.x];
+    const SysInfo S = a.sys[u.sys];
+    const int tid = threadIdx.x;
+    const int64_t step = *a.step;
+    const double kick = 0.5 * (double)a.dt / kMvv2e;
+    double ke = 0.0, x2 = 0.0;
+    for (int cl = tid; cl < u.ncol; cl += 256) {
+        const int col = u.col0 + cl;
+        const int atom = col / 3, cc = col - 3 * atom;
+        double sum = 0.0;
+        for (int j = 0; j < S.P; ++j) {
+            const int64_t r = (int64_t)S.ba0 + (int64_t)j * S.N + atom;
+            sum += (double)a.p[r * 3 + cc];
+            if (!PRE)
+                sum += kick * (double)a.F[r * 3 + cc];
+        }
+        const double m = (double)a.mass_atom[S.atom0 + atom];
+        ke += 0.5 * kMvv2e * sum * sum / ((double)S.P * m);
+        const double xi = (double)noise_value(a, PRE ? 0 : 1, (int64_t)S.ba0 + atom, cc, step);
+        x2 += xi * xi;
+    }
+    const double kt = block_sum_double(ke, red);
+    __syncthreads();
+    const double xt = block_sum_double(x2, red);
+    if (tid == 0) {
+        part[2 * blockIdx.x] = kt;
+        part[2 * blockIdx.x + 1] = xt;
+    }
+}
+
+// k_svr_alpha: one workgroup per system: its units' terms summed in a fixed
+// order, then alpha (alpha = 1 when K = 0: no direction to rescale).
+template <bool PRE>
+__global__ __launch_bounds__(256) void k_svr_alpha(IntegArgs a, const double *__restrict__ part,
+                                                   const double *__restrict__ kbar, double c, double *__restrict__ alpha)
+{
+    __shared__ double red[256];
+    const SysInfo S = a.sys[blockIdx.x];
+    double ke = 0.0, x2 = 0.0;
+    for (int u = S.unit0 + threadIdx.x; u < S.unit0 + S.nunit; u += 256) {
+        ke += part[2 * u];
+        x2 += part[2 * u + 1];
+    }
+    const double K = block_sum_double(ke, red);
+    __syncthreads();
+    const double X = block_sum_double(x2, red);
+    if (threadIdx.x == 0) {
+        double f = 1.0;
+        if (K > 0.0) {
+            const double nf = 3.0 * (double)S.N;
+            const double r1 = (double)noise_value(a, PRE ? 0 : 1, (int64_t)S.ba0, 0, *a.step);
+            const double rest = X - r1 * r1;
+            const double ratio = kbar[blockIdx.x] / (nf * K);
+            const double a2 = c + ratio * (1.0 - c) * (r1 * r1 + rest) + 2.0 * r1 * sqrt(c * (1.0 - c) * ratio);
+            f = sqrt(a2);
+            if (r1 + sqrt(c / ((1.0 - c) * ratio)) < 0.0)
+                f = -f;
+        }
+        alpha[blockIdx.x] = f;
+    }
 }
 
 // heat_bath[s] -= (sum of O-step kinetic-energy changes of the step); step += 1.
@@ -361,6 +442,7 @@ __global__ void k_check_finite(const float *a, int64_t n, uint32_t *status)
 static IntegArgs integ_args(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi)
 {
     IntegArgs a;
+    a.svr = d.svr_alpha;
     a.q = d.q;
     a.p = d.p;
     a.q_prev = d.q_prev;
@@ -403,10 +485,15 @@ hipError_t configure_integrator_lds(int max_P)
 
 template <bool PRE>
 static void launch_integrate(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi,
-                             int max_P, int transform, hipStream_t s)
+                             int max_P, int transform, double svr_c, hipStream_t s)
 {
     const IntegArgs args = integ_args(d, z, dt, k0, k1, xi);
     const size_t lds = integ_lds(max_P);
+    if (d.svr_alpha && transform == kNormalModes) {
+        hipLaunchKernelGGL(k_centroid_terms<PRE>, dim3(z.n_units), dim3(256), 0, s, args, d.svr_part);
+        hipLaunchKernelGGL(k_svr_alpha<PRE>, dim3(z.n_sys), dim3(256), 0, s, args, d.svr_part, d.svr_kbar, svr_c,
+                           d.svr_alpha);
+    }
     if (transform == kStaging)
         hipLaunchKernelGGL((k_integrate<PRE, kStaging>), dim3(z.n_units), dim3(256), lds, s, args);
     else if (transform == kPrimitive)
@@ -416,15 +503,15 @@ static void launch_integrate(const DevBuffers &d, const Sizes &z, float dt, uint
 }
 
 void launch_integrate_pre(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi,
-                          int max_P, int transform, hipStream_t s)
+                          int max_P, int transform, double svr_c, hipStream_t s)
 {
-    launch_integrate<true>(d, z, dt, k0, k1, xi, max_P, transform, s);
+    launch_integrate<true>(d, z, dt, k0, k1, xi, max_P, transform, svr_c, s);
 }
 
 void launch_integrate_post(const DevBuffers &d, const Sizes &z, float dt, uint32_t k0, uint32_t k1, const float *xi,
-                           int max_P, int transform, hipStream_t s)
+                           int max_P, int transform, double svr_c, hipStream_t s)
 {
-    launch_integrate<false>(d, z, dt, k0, k1, xi, max_P, transform, s);
+    launch_integrate<false>(d, z, dt, k0, k1, xi, max_P, transform, svr_c, s);
 }
 
 void launch_finish_step(const DevBuffers &d, const Sizes &z, hipStream_t s)

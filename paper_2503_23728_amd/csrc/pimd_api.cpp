@@ -53,6 +53,7 @@ struct Plan {
     std::vector<int> distinct_P;
     bool any_box = false;                      // some system has a box (metadynamics minimum image)
     bool metad = false;                        // well-tempered metadynamics bias
+    bool pile_g = false;                       // PILE-G: global thermostat on the centroids
     int cv = 0, n_terms = 0, max_hills = 0;
     int xrd_tile = 64, n_xrd_items = 0;          // XRD pair sum: rows per tile, work items
     int64_t n_xrd_part = 0;                    // per-tile partials of the XRD pair sum
@@ -114,6 +115,11 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
     if (cfg->transform != PIMD_TRANSFORM_NORMAL_MODES && cfg->transform != PIMD_TRANSFORM_STAGING &&
         cfg->transform != PIMD_TRANSFORM_PRIMITIVE)
         return fail(err, PIMD_E_ARG, "unknown ring-polymer transform");
+    if (cfg->thermostat != PIMD_THERMOSTAT_PILE_L && cfg->thermostat != PIMD_THERMOSTAT_PILE_G)
+        return fail(err, PIMD_E_ARG, "unknown thermostat");
+    if (cfg->thermostat == PIMD_THERMOSTAT_PILE_G && cfg->transform != PIMD_TRANSFORM_NORMAL_MODES)
+        return fail(err, PIMD_E_UNSUPPORTED, "PILE-G needs the normal-mode integrator");
+    pl.pile_g = cfg->thermostat == PIMD_THERMOSTAT_PILE_G;
     if (cfg->max_neighbors < 0 || cfg->max_neighbors > kMaxNeighbors)
         return fail(err, PIMD_E_UNSUPPORTED, "max_neighbors must be in [0, 256]");
     if (cfg->max_neighbors % 16)
@@ -397,6 +403,11 @@ Layout make_layout(const Plan &pl)
     }
     L.add("heat", (size_t)pl.n_sys * 8);
     L.add("dke_part", (size_t)pl.n_units * 16);
+    if (pl.pile_g) {
+        L.add("svr_part", (size_t)pl.n_units * 16);
+        L.add("svr_alpha", (size_t)pl.n_sys * 8);
+        L.add("svr_kbar", (size_t)pl.n_sys * 8);
+    }
     L.add("step", 8);
     L.add("status", 8);
     L.add("est_cols", (size_t)pl.ncol * 12);
@@ -468,6 +479,7 @@ struct pimd_ctx {
     pimd_tuning last_tuning_out{};     // sink for pimd_autotune(best = NULL)
     std::vector<SysInfo> sys_host;
     std::vector<double> temperature, masses_el;
+    std::vector<double> sys_host_box;   // [n_sys][3] box lengths (0: no box)
     std::vector<int> species;
     double dt = 0, tau0 = 0, lam = 0, omega = 0;
     uint64_t seed = 0;
@@ -491,6 +503,7 @@ struct pimd_ctx {
     int transform = PIMD_TRANSFORM_NORMAL_MODES;   // coordinates of the integrator
     int device = 0;
     int static_device = -1;            // device whose static workspace this context holds (pimd_init_static)
+    double svr_c = 1.0;                // PILE-G: exp(-(dt/2)/tau0)
     std::string err;
 };
 
@@ -616,15 +629,15 @@ pimd_status run_step(pimd_ctx *c, hipStream_t s, const float *xi)
     c->stream = s;
     if (c->stage_ev)
         (void)hipEventRecord(c->stage_ev[0], s);
-    launch_integrate_pre(c->d, c->z, (float)c->dt, k0, k1, xi, c->pl.max_P, c->transform, s);
+    launch_integrate_pre(c->d, c->z, (float)c->dt, k0, k1, xi, c->pl.max_P, c->transform, c->svr_c, s);
     if (c->stage_ev)
         (void)hipEventRecord(c->stage_ev[1], s);
     c->deposit_now = true;
-    pimd_status st = run_forces(c, c->d.q, c->d.E_bead, c->d.F, nullptr);
+    pimd_status st = run_forces(c, c->d.q, c->d.E_bead, c->d.F, c->d.W_bead);
     c->deposit_now = false;
     if (c->pl.metad)
         launch_metad_advance(c->d, c->mp, s);
-    launch_integrate_post(c->d, c->z, (float)c->dt, k0, k1, xi, c->pl.max_P, c->transform, s);
+    launch_integrate_post(c->d, c->z, (float)c->dt, k0, k1, xi, c->pl.max_P, c->transform, c->svr_c, s);
     launch_finish_step(c->d, c->z, s);
     if (c->stage_ev)
         (void)hipEventRecord(c->stage_ev[7], s);
@@ -754,6 +767,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     c->masses_el.assign(mv.mass, mv.mass + mv.n_el);
     c->species.assign(cfg->species, cfg->species + pl.n_atoms);
     c->temperature.assign(cfg->temperature_K, cfg->temperature_K + pl.n_sys);
+    c->sys_host_box.assign(cfg->box_A, cfg->box_A + 3 * pl.n_sys);
 
     char *ws = (char *)workspace_dev;
     auto at = [&](const char *name) -> void * {
@@ -809,6 +823,11 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     d.mlp_tiles = (MlpTile *)at("mlp_tiles");
     d.heat = (double *)at("heat");
     d.dke_part = (double *)at("dke_part");
+    // PILE-G with a thermostat (tau0 > 0); NVE needs no centroid factor
+    d.svr_part = (double *)at("svr_part");
+    d.svr_alpha = cfg->tau0_fs > 0.0 ? (double *)at("svr_alpha") : nullptr;
+    d.svr_kbar = (double *)at("svr_kbar");
+    c->svr_c = cfg->tau0_fs > 0.0 ? std::exp(-0.5 * cfg->dt_fs / cfg->tau0_fs) : 1.0;
     d.step = (int64_t *)at("step");
     d.status = (uint32_t *)at("status");
     d.est_cols = (float *)at("est_cols");
@@ -1264,6 +1283,13 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     }
     std::vector<double> zeros_d(pl.n_sys, 0.0);
     push(d.heat, zeros_d.data(), zeros_d.size() * 8);
+    if (pl.pile_g) {
+        // target centroid kinetic energy N_f k_B T P / 2 with N_f = 3N
+        std::vector<double> kbar(pl.n_sys);
+        for (int s = 0; s < pl.n_sys; ++s)
+            kbar[s] = 1.5 * cfg->n_atoms[s] * kKB * cfg->temperature_K[s] * cfg->n_beads[s];
+        push(d.svr_kbar, kbar.data(), kbar.size() * 8);
+    }
     const int64_t zero64 = 0;
     push(d.step, &zero64, 8);
     push(d.status, &zero64, 8);
@@ -1537,14 +1563,15 @@ pimd_status pimd_estimators(pimd_ctx *ctx, pimd_estimates *out_host)
         return PIMD_E_STATE;
     }
     if (!ctx->forces_valid) {
-        pimd_status st = run_forces(ctx, ctx->d.q, ctx->d.E_bead, ctx->d.F, nullptr);
+        pimd_status st = run_forces(ctx, ctx->d.q, ctx->d.E_bead, ctx->d.F, ctx->d.W_bead);
         if (st != PIMD_OK)
             return st;
         ctx->forces_valid = true;
     }
     launch_estimator_terms(ctx->d, ctx->z, ctx->stream);
     CHECK_LAUNCH(ctx);
-    std::vector<float> cols((size_t)ctx->z.ncol * 3), E(ctx->z.n_beads_total);
+    std::vector<float> cols((size_t)ctx->z.ncol * 3), E(ctx->z.n_beads_total), Wb((size_t)ctx->z.n_beads_total * 9);
+    HIPCHK(ctx, hipMemcpyAsync(Wb.data(), ctx->d.W_bead, Wb.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
     std::vector<double> heat(ctx->z.n_sys), vb(ctx->pl.metad ? ctx->z.n_beads_total : 0);
     if (ctx->pl.metad)
         HIPCHK(ctx, hipMemcpyAsync(vb.data(), ctx->d.vbias_bead, vb.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
@@ -1564,11 +1591,13 @@ pimd_status pimd_estimators(pimd_ctx *ctx, pimd_estimates *out_host)
             cv += cols[3 * (size_t)col + 1];
             ke += cols[3 * (size_t)col + 2];
         }
-        double vbias = 0;
+        double vbias = 0, trW = 0;
         for (int k = 0; k < si.P; ++k) {
             V += E[bead0 + k];
             if (ctx->pl.metad)
                 vbias += vb[bead0 + k];
+            for (int a = 0; a < 3; ++a)
+                trW += Wb[9 * (size_t)(bead0 + k) + 4 * a];
         }
         bead0 += si.P;
         pimd_estimates &o = out_host[s];
@@ -1581,6 +1610,10 @@ pimd_status pimd_estimators(pimd_ctx *ctx, pimd_estimates *out_host)
         o.T_beads = 2.0 * o.K_beads / (3.0 * si.N * si.P * kKB);
         o.heat_bath = heat[s];
         o.H_conserved = o.K_beads + o.E_spring + V + heat[s];
+        // centroid-virial pressure of a periodic system (the direct-force head has no virial)
+        const double *Lb = ctx->sys_host_box.data() + 3 * s;
+        const double vol = Lb[0] * Lb[1] * Lb[2];
+        o.P_cv = (vol > 0.0 && !ctx->pl.gfn) ? (2.0 * o.K_cv + trW / si.P) / (3.0 * vol) : 0.0;
     }
     return read_status(ctx);
 }

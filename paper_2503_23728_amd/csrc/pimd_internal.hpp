@@ -184,6 +184,9 @@ struct DevBuffers {
     float4 *vrev;                  // [B][Kmax] v[j][slot of i in j's list], at i's slot n of j
     float *vir_atom, *W_bead;
     double *heat, *dke_part;       // heat bath per system; O-step energy changes per unit (2 halves)
+    double *svr_part;              // PILE-G: per unit (centroid kinetic energy, sum of centroid normals^2)
+    double *svr_alpha;             // PILE-G: per system factor of the centroid momenta (null: PILE-L)
+    double *svr_kbar;              // PILE-G: per system N_f k_B T P / 2
     int64_t *step;
     uint32_t *status;
     float *est_cols;               // estimator terms per column [ncol][3]
@@ -284,11 +287,13 @@ void launch_bead_sums(const DevBuffers &d, const Sizes &z, float *E_bead, float 
 void launch_harmonic(const float *q, const DevBuffers &d, const Sizes &z, float k_over_m,
                      float *F, hipStream_t s);
 // transform: 0 normal modes, 1 staging (momenta state = staging momenta),
-// 2 primitive (Cartesian beads, springs as forces)
+// 2 primitive (Cartesian beads, springs as forces); with d.svr_alpha set
+// (PILE-G, normal modes) the centroid's global factor is formed first, with
+// svr_c = exp(-(dt/2)/tau0)
 void launch_integrate_pre(const DevBuffers &d, const Sizes &z, float dt, uint32_t key0, uint32_t key1,
-                          const float *xi, int max_P, int transform, hipStream_t s);
+                          const float *xi, int max_P, int transform, double svr_c, hipStream_t s);
 void launch_integrate_post(const DevBuffers &d, const Sizes &z, float dt, uint32_t key0, uint32_t key1,
-                           const float *xi, int max_P, int transform, hipStream_t s);
+                           const float *xi, int max_P, int transform, double svr_c, hipStream_t s);
 void launch_finish_step(const DevBuffers &d, const Sizes &z, hipStream_t s);
 void launch_estimator_terms(const DevBuffers &d, const Sizes &z, hipStream_t s);
 void launch_philox_words(uint32_t key0, uint32_t key1, int64_t step, int half, int64_t n, uint32_t *out,

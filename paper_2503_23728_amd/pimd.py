@@ -90,7 +90,8 @@ ANGULAR = {"g4": 0, "g5": 1}     # PIMD_ANGULAR_G4, PIMD_ANGULAR_G5
 
 
 def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
-                omega=0.0, max_neighbors=0, masses=None, metad=None, transform="normal-modes", neighbor_skin=0.0):
+                omega=0.0, max_neighbors=0, masses=None, metad=None, transform="normal-modes", neighbor_skin=0.0,
+                thermostat="pile-l"):
     """Build the pimd_config (and the storage it points into).
 
     systems: sequence with n_atoms, n_beads, temperature, box, species.
@@ -158,6 +159,7 @@ def make_config(systems, model, dt, tau0, pile_lambda, seed, precision="fp32", p
     cfg.transform = {"normal-modes": abi.PIMD_TRANSFORM_NORMAL_MODES, "staging": abi.PIMD_TRANSFORM_STAGING,
                      "primitive": abi.PIMD_TRANSFORM_PRIMITIVE}[transform]
     cfg.neighbor_skin_A = float(neighbor_skin)
+    cfg.thermostat = {"pile-l": abi.PIMD_THERMOSTAT_PILE_L, "pile-g": abi.PIMD_THERMOSTAT_PILE_G}[thermostat]
     return cfg, keep
 
 
@@ -189,7 +191,8 @@ class Pimd:
 
     def __init__(self, systems, model, dt, tau0, pile_lambda, seed, precision="fp32", potential="bpnn",
                  omega=0.0, max_neighbors=0, masses=None, device="cuda:0", stream=None, metad=None,
-                 transform="normal-modes", neighbor_skin=0.0, regrow=True, static_workspace=False):
+                 transform="normal-modes", neighbor_skin=0.0, regrow=True, static_workspace=False,
+                 thermostat="pile-l"):
         self.device = torch.device(device)
         self.metad = metad
         self.systems = list(systems)
@@ -199,7 +202,7 @@ class Pimd:
         self.regrowths = 0
         self.static_workspace = bool(static_workspace)
         self._cfg_args = (dt, tau0, pile_lambda, seed, precision, potential, omega, masses, metad, transform,
-                          neighbor_skin)
+                          neighbor_skin, thermostat)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = None
         self._target_step = 0          # steps the caller has asked for, counted from set_state
@@ -213,10 +216,10 @@ class Pimd:
         self.bead_of_row = torch.as_tensor(np.concatenate(bead_of_row), device=self.device, dtype=torch.long)
 
     def _open(self, max_neighbors):
-        dt, tau0, lam, seed, precision, potential, omega, masses, metad, transform, skin = self._cfg_args
+        dt, tau0, lam, seed, precision, potential, omega, masses, metad, transform, skin, thermostat = self._cfg_args
         self.max_neighbors = max_neighbors
         self.cfg, self._keep = make_config(self.systems, self.model, dt, tau0, lam, seed, precision, potential,
-                                           omega, max_neighbors, masses, metad, transform, skin)
+                                           omega, max_neighbors, masses, metad, transform, skin, thermostat)
         if self.static_workspace:
             # the library's own per-device array: no device allocation at all
             self.workspace = None

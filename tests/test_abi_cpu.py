@@ -186,3 +186,18 @@ def test_static_init_refuses_a_workspace_larger_than_its_array(lib):
     assert "static workspace" in abi.pimd_last_error(None)
     bad, keep2 = _cfg(S.workload(1), neighbor_skin=1.0)
     assert abi.pimd_init_static(bad, 0)[0] == abi.PIMD_E_UNSUPPORTED
+
+
+def test_thermostat_is_validated(lib):
+    wl = S.workload(1)
+    assert abi.pimd_workspace_size(_cfg(wl, thermostat="pile-g")[0])[0] == abi.PIMD_OK
+    cfg, keep = _cfg(wl)
+    cfg.thermostat = 7
+    assert abi.pimd_workspace_size(cfg)[0] == abi.PIMD_E_ARG
+    # PILE-G thermostats normal modes only
+    st = abi.pimd_workspace_size(_cfg(wl, thermostat="pile-g", transform="staging")[0])[0]
+    assert st == abi.PIMD_E_UNSUPPORTED
+    # its buffers: per integrator unit and per system
+    a = abi.pimd_workspace_size(_cfg(wl)[0])[1]
+    b = abi.pimd_workspace_size(_cfg(wl, thermostat="pile-g")[0])[1]
+    assert b > a
