@@ -277,7 +277,7 @@ def cpu_baseline(wl, budget_s=20.0):
 
 def extra_keys(args, wl, eng, skin, shape, device):
     """The same workload with per-bead cell searches every step (no shared
-    lists), and the batched workload 4 (512 ring polymers in one graph per step)
+    lists), the same workload on float32-valued weights, and the batched workload 4 (512 ring polymers in one graph per step)
     against its plain-FP32 path (one eager context per ring polymer)."""
     import torch
     from paper_2503_23728_amd import synthetic as S
@@ -297,6 +297,25 @@ def extra_keys(args, wl, eng, skin, shape, device):
               flush=True)
         cell.close()
         del cell
+    if args.precision == "bf16":
+        # the same systems on weights with float32 mantissas (a model trained in
+        # FP32): the split BF16 MLP then splits the weights too, three products
+        # per term instead of two; same launch shape
+        fwl = S.workload(args.config, bf16_weights=False)
+        f32w = Pimd.from_workload(fwl, precision="bf16", device=device, transform=args.transform,
+                                  neighbor_skin=skin)
+        f32w.set_state(torch.from_numpy(q).to(device), torch.from_numpy(p).to(device))
+        f32w.set_tuning(**shape)
+        wall, _ = time_steps(f32w, args.steps, args.warmup)
+        kern = f32w.time_stages(max(args.profile_reps, 5))
+        out["float32_valued_weights"] = {"value": wl.bead_atoms * args.steps / wall,
+                                         "ms_per_step": 1e3 * wall / args.steps,
+                                         "mlp_ms": round(kern["mlp"], 4),
+                                         "mlp": "activations and weights split, three BF16 products per term"}
+        print(f"[bench] float32-valued weights: {1e3 * wall / args.steps:.3f} ms/step, MLP "
+              f"{kern['mlp']:.4f} ms", file=sys.stderr, flush=True)
+        f32w.close()
+        del f32w
     if args.config != 4:
         bwl = S.workload(4)
         bat = Pimd.from_workload(bwl, precision=args.precision, device=device)
@@ -458,7 +477,8 @@ def main():
         "value": value, "unit": "bead-atom force evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "f32 (MLP GEMM operands bf16 x3 split)",
+        "dtype": {"fp32": "f32", "bf16": "f32 (MLP GEMM operands bf16: activations split in hi + lo parts, "
+                                         "weights bfloat16 values)",
                   "bf16-plain": "f32 (MLP GEMM operands bf16)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": wl.name, "systems": len(wl.systems), "bead_atoms": B,

@@ -450,8 +450,9 @@ pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled);
 /* Launch shapes of the force kernels.  Many ring polymers and beads run as
  * one flat batch (the concurrent-trajectory parallelism of Sec. 2.3 and the
  * multi-trajectory point of Sec. 4); these fields only change how that batch
- * is cut into workgroups, never the results: each centre atom is one wave and
- * each MLP row runs the same MFMA chain whatever the shape.
+ * is cut into workgroups, never the results (centre_lanes aside, below):
+ * each centre atom is one wave and each MLP row runs the same MFMA chain
+ * whatever the shape.
  *   centre_waves  waves (one centre atom each) per workgroup of the neighbour,
  *                 descriptor, adjoint and force-assembly kernels: 1, 2 or 4
  *                 (default 4)
@@ -472,7 +473,16 @@ pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled);
  *                 keeps the pair, and the force assembly reads two contiguous
  *                 rows per atom (default with a box); 0 = the assembly looks
  *                 the reverse slot up itself (default without).  The forces
- *                 are bitwise the same */
+ *                 are bitwise the same
+ *   centre_lanes  G4 energy network on molecules without a box of at most 16
+ *                 atoms each (else 0 only, PIMD_E_UNSUPPORTED): 1 (default
+ *                 there) = one lane per centre atom, each wave taking whole
+ *                 beads (as many as fit in 64 lanes), the neighbour lists
+ *                 written by the descriptor kernel and the forces assembled in
+ *                 the adjoint from the partners' lanes; 0 = one wave per centre
+ *                 as above.  The two differ in summation order only (results
+ *                 agree to rounding, not bitwise); every other field leaves
+ *                 the results of either bitwise unchanged */
 typedef struct {
     int32_t centre_waves;
     int32_t centre_grid;
@@ -480,6 +490,7 @@ typedef struct {
     int32_t neighbor_cells;
     int32_t mlp_waves;
     int32_t force_rows;
+    int32_t centre_lanes;
 } pimd_tuning;
 
 pimd_status pimd_get_tuning(const pimd_ctx *ctx, pimd_tuning *out);

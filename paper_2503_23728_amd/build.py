@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpimd.so")
-SOURCES = ["k_neighbors.hip", "k_descriptors.hip", "k_g5.hip", "k_mlp.hip", "k_gfn.hip", "k_metad.hip", "k_integrator.hip", "pimd_api.cpp"]
+SOURCES = ["k_neighbors.hip", "k_descriptors.hip", "k_small.hip", "k_g5.hip", "k_mlp.hip", "k_gfn.hip", "k_metad.hip", "k_integrator.hip", "pimd_api.cpp"]
 ARCH = os.environ.get("PIMD_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -207,7 +207,7 @@ __host__ __device__ inline size_t adjoint_wave_bytes(const DescParams &dp)
 // ---------------------------------------------------------------------------
 // forward: normalised descriptors xhat[i][D]
 // ---------------------------------------------------------------------------
-template <int NETA>
+template <int NETA, bool POW4>
 __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ posu,
                                                      const BeadInfo *__restrict__ beads,
                                                      const int32_t *__restrict__ bead_of_ba,
@@ -298,11 +298,17 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
                     const float p2 = p1 * p1, m2 = m1 * m1;
                     const float p4 = p2 * p2, m4 = m2 * m2;
                     const float p8 = p4 * p4, m8 = m4 * m4;
+                    const float X0 = exp_small(nel0, r2jk);
+                    float X1 = 0.0f;
+                    if (NETA > 1) {
+                        const float X0sq = X0 * X0;
+                        X1 = POW4 ? X0sq * X0sq : exp_small(nel1, r2jk);
+                    }
 #pragma unroll
                     for (int ie = 0; ie < NETA; ++ie) {
                         const float Ea = ie == 0 ? Ae.x : Ae.y;
                         const float Eb = ie == 0 ? Ce.x : Ce.y;
-                        const float R = Ea * Eb * exp_small(ie == 0 ? nel0 : nel1, r2jk) * fcjk;
+                        const float R = Ea * Eb * (ie == 0 ? X0 : X1) * fcjk;
                         acc[ie * 8 + 0] += p1 * R;
                         acc[ie * 8 + 1] += m1 * R;
                         acc[ie * 8 + 2] += p2 * R;
@@ -335,7 +341,7 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
 // ---------------------------------------------------------------------------
 // adjoint: v[i][slot] = dE/d d_{i, slot}; per-atom virial -sum d (x) v
 // ---------------------------------------------------------------------------
-template <int NETA>
+template <int NETA, bool POW4>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adjoint(const float4 *__restrict__ posu, const BeadInfo *__restrict__ beads,
                                                  const int32_t *__restrict__ bead_of_ba, const int32_t *__restrict__ order,
                                                  const int32_t *__restrict__ nbr,
@@ -351,11 +357,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const int lane = lane_id(), w = threadIdx.x >> 6;
     char *base = reinterpret_cast<char *>(lds4) + w * adjoint_wave_bytes(dp);
     const Recs rec{reinterpret_cast<float4 *>(base), reinterpret_cast<float4 *>(base) + dp.Kmax, nullptr};
-    // slot accumulators: three FP64 arrays (one per component, so gathers by
-    // slot spread over the banks); each slot sums ~K mixed-sign triplet terms
-    double *vx = reinterpret_cast<double *>(base + 32 * dp.Kmax);
-    double *vy = vx + dp.Kmax;
-    double *vz = vy + dp.Kmax;
+    // slot accumulators: FP64 (x, y, z) per slot, interleaved so that one
+    // address and two immediate offsets reach a slot's three components; each
+    // slot sums ~K mixed-sign triplet terms
+    double *vacc = reinterpret_cast<double *>(base + 32 * dp.Kmax);
     float *gl = reinterpret_cast<float *>(base + 56 * dp.Kmax);
     // reverse slots: where atom j = nbr[i][n] keeps the pair (j, i)
     int16_t *rev = reinterpret_cast<int16_t *>(gl + ((dp.D + 3) & ~3));
@@ -391,9 +396,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     acc += gl[e * dp.n_rad + t] * expf(-eta * x * x) * (-2.0f * eta * x * fc + dfc);
                 }
                 const float c = acc * inv_r;
-                vx[n] = (double)(c * d.x);
-                vy[n] = (double)(c * d.y);
-                vz[n] = (double)(c * d.z);
+                vacc[3 * n] = (double)(c * d.x);
+                vacc[3 * n + 1] = (double)(c * d.y);
+                vacc[3 * n + 2] = (double)(c * d.z);
             });
         wave_sync();
         const uint16_t *kept = tri_pairs + (int64_t)i * tri_capacity(dp.Kmax);
@@ -426,8 +431,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     const float4 Ad = rec.D[ia], Cd = rec.D[ic], Ae = rec.E[ia], Ce = rec.E[ic];
                     const float jx = Cd.x - Ad.x, jy = Cd.y - Ad.y, jz = Cd.z - Ad.z;
                     const float r2jk = jx * jx + jy * jy + jz * jz;
-                    const float rjk = __builtin_amdgcn_sqrtf(r2jk);
-                    const float inv_rjk = __builtin_amdgcn_rcpf(rjk);
+                    const float inv_rjk = __builtin_amdgcn_rsqf(r2jk);
+                    const float rjk = r2jk * inv_rjk;
                     float fcjk, dfcjk;
                     cutoff_fn(rjk * inv_rc, dp.pi_over_rc, fcjk, dfcjk);
                     const float iab = Ad.w * Cd.w;
@@ -442,6 +447,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     //   dE/dcos:  Sd Ea Eb Y;  dE/dr_ij: S dEa Eb Y;  dE/dr_ik: S Ea dEb Y
                     //   dE/dr_jk: S Ea Eb exp(-eta r_jk^2) (f_c' - 2 eta r_jk f_c)
                     float Pc = 0.0f, Pa = 0.0f, Pb = 0.0f, Pjk = 0.0f;
+                    const float X0 = exp_small(nel0, r2jk);
+                    float X1 = 0.0f;
+                    if (NETA > 1) {
+                        const float X0sq = X0 * X0;
+                        X1 = POW4 ? X0sq * X0sq : exp_small(nel1, r2jk);
+                    }
 #pragma unroll
                     for (int ie = 0; ie < NETA; ++ie) {
                         const float *g = gq + ie * 8;
@@ -449,7 +460,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                         const float S = g[0] * p1 + g[1] * m1 + g[2] * p2 + g[3] * m2 + g[4] * p4 + g[5] * m4 +
                                         g[6] * p8 + g[7] * m8;
                         const float Sd = h[0] + h[1] * p1 - h[2] * m1 + h[3] * p3 - h[4] * m3 + h[5] * p7 - h[6] * m7;
-                        const float X = exp_small(ie == 0 ? nel0 : nel1, r2jk);
+                        const float X = ie == 0 ? X0 : X1;
                         const float Ea = ie == 0 ? Ae.x : Ae.y, Eb = ie == 0 ? Ce.x : Ce.y;
                         const float dEa = ie == 0 ? Ae.z : Ae.w, dEb = ie == 0 ? Ce.z : Ce.w;
                         const float Y = X * fcjk;
@@ -470,12 +481,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     const float ka = (Pa - Pcs * ia_) * ia_ + gam;
                     const float kc = (Pb - Pcs * ib_) * ib_ + gam;
                     const float kb = Pc * iab - gam;
-                    atomicAdd(&vx[ia], (double)(ka * Ad.x + kb * Cd.x));
-                    atomicAdd(&vy[ia], (double)(ka * Ad.y + kb * Cd.y));
-                    atomicAdd(&vz[ia], (double)(ka * Ad.z + kb * Cd.z));
-                    atomicAdd(&vx[ic], (double)(kc * Cd.x + kb * Ad.x));
-                    atomicAdd(&vy[ic], (double)(kc * Cd.y + kb * Ad.y));
-                    atomicAdd(&vz[ic], (double)(kc * Cd.z + kb * Ad.z));
+                    double *va = vacc + 3 * ia, *vc = vacc + 3 * ic;
+                    atomicAdd(va, (double)(ka * Ad.x + kb * Cd.x));
+                    atomicAdd(va + 1, (double)(ka * Ad.y + kb * Cd.y));
+                    atomicAdd(va + 2, (double)(ka * Ad.z + kb * Cd.z));
+                    atomicAdd(vc, (double)(kc * Cd.x + kb * Ad.x));
+                    atomicAdd(vc + 1, (double)(kc * Cd.y + kb * Ad.y));
+                    atomicAdd(vc + 2, (double)(kc * Cd.z + kb * Ad.z));
                 };
                 // the block's in-range slot pairs as the forward found them, one per lane
                 for (int t0 = 0; t0 < n_pairs_block; t0 += kWave) {
@@ -492,7 +504,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             W[q] = 0.0f;
         bool missing = false;
         for (int n = lane; n < K; n += kWave) {
-            const float4 v = make_float4((float)vx[n], (float)vy[n], (float)vz[n], 0.0f);
+            const float4 v = make_float4((float)vacc[3 * n], (float)vacc[3 * n + 1], (float)vacc[3 * n + 2], 0.0f);
             vslot[(int64_t)i * dp.Kmax + n] = v;
             if (vrev) {
                 const int j = nbr[(int64_t)i * dp.Kmax + n] & (int)kRowMask;
@@ -618,6 +630,36 @@ __global__ __launch_bounds__(256) void k_bead_sums(const BeadInfo *__restrict__ 
         W_bead[9 * blockIdx.x + threadIdx.x] = red[1 + threadIdx.x][0];
 }
 
+// The same sums when no bead has more than 64 atoms (batches of small
+// molecules): one lane per bead, atoms added in row order in FP64, instead of
+// a 256-thread workgroup holding a few atoms.
+__global__ __launch_bounds__(256) void k_bead_sums_lanes(const BeadInfo *__restrict__ beads,
+                                                         const float *__restrict__ E_atom,
+                                                         const float *__restrict__ vir_atom, float *__restrict__ E_bead,
+                                                         float *__restrict__ W_bead, int virial, int n_beads,
+                                                         uint32_t *__restrict__ status)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_beads)
+        return;
+    const BeadInfo bi = beads[b];
+    double e = 0.0, w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = 0; t < bi.n; ++t) {
+        e += (double)E_atom[bi.ba0 + t];
+        if (virial)
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                w[q] += (double)vir_atom[9 * (int64_t)(bi.ba0 + t) + q];
+    }
+    E_bead[b] = (float)e;
+    if (!isfinite(e))
+        atomicOr(status, kStatusNonFinite);
+    if (virial && W_bead)
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            W_bead[9 * (int64_t)b + q] = (float)w[q];
+}
+
 // Work counter: neighbour pairs, j<k triplets, triplets with r_jk < rc.
 __global__ __launch_bounds__(256) void k_work_counts(const float4 *__restrict__ posu,
                                                      const BeadInfo *__restrict__ beads,
@@ -677,15 +719,14 @@ hipError_t configure_descriptor_lds(const DescParams &dp)
 {
     const int f = (int)descriptor_lds_bytes(dp, false), a = (int)descriptor_lds_bytes(dp, true);
     hipError_t e = hipSuccess;
-    if (dp.n_ang_eta == 2) {
-        e = hipFuncSetAttribute((const void *)k_descriptors<2>, hipFuncAttributeMaxDynamicSharedMemorySize, f);
+    for (const void *fn : {(const void *)k_descriptors<1, false>, (const void *)k_descriptors<2, false>,
+                           (const void *)k_descriptors<2, true>})
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)k_adjoint<2>, hipFuncAttributeMaxDynamicSharedMemorySize, a);
-    } else {
-        e = hipFuncSetAttribute((const void *)k_descriptors<1>, hipFuncAttributeMaxDynamicSharedMemorySize, f);
+            e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, f);
+    for (const void *fn : {(const void *)k_adjoint<1, false>, (const void *)k_adjoint<2, false>,
+                           (const void *)k_adjoint<2, true>})
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)k_adjoint<1>, hipFuncAttributeMaxDynamicSharedMemorySize, a);
-    }
+            e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, a);
     return e;
 }
 
@@ -693,28 +734,20 @@ void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &d
 {
     const int wpg = tn.centre_waves, grid = centre_grid(z.B, tn);
     const size_t lds = wpg * forward_wave_bytes(dp);
-    if (dp.n_ang_eta == 2)
-        hipLaunchKernelGGL(k_descriptors<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, d.tri_pairs,
-                           d.tri_cnt, z.B);
-    else
-        hipLaunchKernelGGL(k_descriptors<1>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, d.tri_pairs,
-                           d.tri_cnt, z.B);
+    auto kern = dp.n_ang_eta == 1 ? k_descriptors<1, false>
+                : (dp.eta_pow4 ? k_descriptors<2, true> : k_descriptors<2, false>);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba, centre_order(d, z),
+                       d.nbr, d.nbr_cnt, d.nbr_grp, d.norm, dp, d.xhat, d.tri_pairs, d.tri_cnt, z.B);
 }
 
 void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s)
 {
     const int wpg = tn.centre_waves, grid = centre_grid(z.B, tn);
     const size_t lds = wpg * adjoint_wave_bytes(dp);
-    if (dp.n_ang_eta == 2)
-        hipLaunchKernelGGL(k_adjoint<2>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.tri_pairs, d.tri_cnt, d.nbr_fence,
-                           dp, d.vslot, tn.force_rows ? d.vrev : nullptr, d.vir_atom, d.status, z.B);
-    else
-        hipLaunchKernelGGL(k_adjoint<1>, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba,
-                           centre_order(d, z), d.nbr, d.nbr_cnt, d.dEdG, d.tri_pairs, d.tri_cnt, d.nbr_fence,
-                           dp, d.vslot, tn.force_rows ? d.vrev : nullptr, d.vir_atom, d.status, z.B);
+    auto kern = dp.n_ang_eta == 1 ? k_adjoint<1, false> : (dp.eta_pow4 ? k_adjoint<2, true> : k_adjoint<2, false>);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave * wpg), lds, s, d.posu4, d.beads, d.bead_of_ba, centre_order(d, z),
+                       d.nbr, d.nbr_cnt, d.dEdG, d.tri_pairs, d.tri_cnt, d.nbr_fence, dp, d.vslot,
+                       tn.force_rows ? d.vrev : nullptr, d.vir_atom, d.status, z.B);
 }
 
 void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &dp, unsigned long long *counts,
@@ -739,8 +772,12 @@ void launch_assemble_forces(const DevBuffers &d, const Sizes &z, float *F, const
 
 void launch_bead_sums(const DevBuffers &d, const Sizes &z, float *E_bead, float *W_bead, bool virial, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bead_sums, dim3(z.n_beads_total), dim3(256), 0, s, d.beads, d.E_atom, d.vir_atom, E_bead,
-                       W_bead, virial ? 1 : 0, d.status);
+    if (z.max_bead_atoms <= kWave)
+        hipLaunchKernelGGL(k_bead_sums_lanes, dim3((z.n_beads_total + 255) / 256), dim3(256), 0, s, d.beads, d.E_atom,
+                           d.vir_atom, E_bead, W_bead, virial ? 1 : 0, z.n_beads_total, d.status);
+    else
+        hipLaunchKernelGGL(k_bead_sums, dim3(z.n_beads_total), dim3(256), 0, s, d.beads, d.E_atom, d.vir_atom, E_bead,
+                           W_bead, virial ? 1 : 0, d.status);
 }
 
 }  // namespace pimd

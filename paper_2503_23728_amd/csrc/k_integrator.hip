@@ -5,12 +5,13 @@
 //
 // A workgroup owns `ncol` columns (atom, xyz) of one system and P threads per
 // column.  The P bead values of each column are staged in LDS; thread k of a
-// column forms normal mode k as the dot product with column k of the
-// orthonormal matrix C (kept transposed in LDS with a padded stride), applies
-// the O/B/A updates of that mode, and the inverse transform is the same dot
-// product with row j of C.  For P <= 128 this dense form costs about as much as
-// a real FFT and needs no bit reversal; HBM traffic (q, p, F once each) bounds
-// the kernel either way.  The state is float32 in memory; the transforms, the
+// column forms normal mode k as the real discrete Fourier sum with twiddles
+// cos(2 pi m/P), sin(2 pi m/P) (m = jk mod P) from a 2P-entry table in LDS
+// and the normalisations 1/sqrt(P), sqrt(2/P), applies the O/B/A updates of
+// that mode, and the inverse transform is the same sum over k for bead j.
+// For P <= 128 the direct sum costs little arithmetic next to the loads, and
+// the table keeps what each workgroup stages at 2P + 2 values instead of a
+// P x P matrix.  The state is float32 in memory; the transforms, the
 // O/B/A updates and their coefficients are FP64 in registers, because float32
 // coefficients (C not orthogonal, cos^2 + sin^2 != 1 at the 1e-7 level) change
 // the ring-polymer energy by a fixed amount every step, a drift that grows as
@@ -105,8 +106,8 @@ __device__ __forceinline__ double spring_force(const double *q, int k, int P, do
     return P == 1 ? 0.0 : -m_w2 * kMvv2e * (2.0 * q[k] - q[(k + 1) % P] - q[(k + P - 1) % P]);
 }
 
-// LDS (doubles): CT[P][P+1] | s0[256] | s1[256] | s2[256] | red[256]
-// (staging and primitive leave CT unused: their transforms are closed forms.)
+// LDS (doubles): tw[2P + 2] (cos, sin, 1/sqrt(P), sqrt(2/P)) | s0[256] | s1[256] | s2[256] | red[256]
+// (staging and primitive leave tw unused: their transforms are closed forms.)
 template <bool PRE, int XF>
 __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
 {
@@ -115,8 +116,8 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
     const IntegUnit u = a.units[blockIdx.x];
     const SysInfo S = a.sys[u.sys];
     const int P = S.P, N = S.N;
-    double *CT = ism;
-    double *s0 = CT + P * (P + 1);
+    double *tw = ism;
+    double *s0 = tw + 2 * P + 2;
     double *s1 = s0 + 256;
     double *s2 = s1 + 256;
     double *red = s2 + 256;
@@ -138,12 +139,12 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
         }
         return;
     }
-    if (NM) {
-        for (int idx = tid; idx < P * P; idx += 256) {
-            const int j = idx / P, k = idx - j * P;
-            CT[k * (P + 1) + j] = a.cmat[S.cmat0 + idx];  // C[j][k]
-        }
-    }
+    if (NM)
+        for (int idx = tid; idx < 2 * P + 2; idx += 256)
+            tw[idx] = a.cmat[S.cmat0 + idx];
+    // normal-mode matrix C[j][k] = nrm_k * (k <= P/2 ? cos : sin)(2 pi (jk mod P)/P),
+    // nrm_k = 1/sqrt(P) for k = 0 and P/2, sqrt(2/P) otherwise
+    const int halfP = P / 2;
     const int64_t step = *a.step;
     double m = 1.0;
     if (valid) {
@@ -165,7 +166,8 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
     double dke = 0.0;
     double pt = 0.0, qt = 0.0;
     if (valid) {
-        const double *ct = CT + kk * (P + 1);
+        const double nrm = (kk == 0 || kk == halfP) ? tw[2 * P] : tw[2 * P + 1];
+        const double *tk = tw + (kk > halfP ? P : 0);   // the twiddles of mode kk
         const double *sp = s0 + cl * P, *sf = s1 + cl * P, *sq = s2 + cl * P;
         const ModeInfo M = a.modes[S.mode0 + kk];
         const double mk = m * M.mfac;                 // kinetic mass of mode kk
@@ -181,12 +183,17 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
                 Ft = sf[kk] + spring_force(sq, kk, P, m * M.w * M.w);
                 qt = sq[kk];
             } else {
-                for (int j = 0; j < P; ++j) {
-                    const double c = ct[j];
+                for (int j = 0, m = 0; j < P; ++j) {
+                    const double c = tk[m];
                     pt += c * sp[j];
                     Ft += c * sf[j];
                     qt += c * sq[j];
+                    m += kk;
+                    m -= m >= P ? P : 0;
                 }
+                pt *= nrm;
+                Ft *= nrm;
+                qt *= nrm;
             }
             // O(dt/2), half 0 (PILE-G: the centroid takes the global factor instead)
             const double xi = (double)noise_value(a, 0, row, cc, step);
@@ -210,8 +217,12 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
             } else if (PRIMITIVE) {
                 pt = sp[kk] + kick * (sf[kk] + spring_force(sq, kk, P, m * M.w * M.w));
             } else {
-                for (int j = 0; j < P; ++j)
-                    pt += ct[j] * (sp[j] + kick * sf[j]);
+                for (int j = 0, m = 0; j < P; ++j) {
+                    pt += tk[m] * (sp[j] + kick * sf[j]);
+                    m += kk;
+                    m -= m >= P ? P : 0;
+                }
+                pt *= nrm;
             }
             const double xi = (double)noise_value(a, 1, row, cc, step);
             const double pn = (NM && a.svr && kk == 0) ? a.svr[u.sys] * pt : M.c1 * pt + sig * M.c2 * xi;
@@ -238,11 +249,13 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
             qj = qt;
         } else {
             // back to beads: x_j = sum_k C[j][k] x~_k, with j = kk
-            for (int k = 0; k < P; ++k) {
-                const double c = CT[k * (P + 1) + kk];
+            for (int k = 0, m = 0; k < P; ++k) {
+                const double c = ((k == 0 || k == halfP) ? tw[2 * P] : tw[2 * P + 1]) * tw[(k > halfP ? P : 0) + m];
                 pj += c * sp[k];
                 if (PRE)
                     qj += c * sq[k];
+                m += kk;
+                m -= m >= P ? P : 0;
             }
         }
         a.p[row * 3 + cc] = (float)pj;
@@ -466,7 +479,7 @@ static IntegArgs integ_args(const DevBuffers &d, const Sizes &z, float dt, uint3
 
 static size_t integ_lds(int max_P)
 {
-    return ((size_t)max_P * (max_P + 1) + 4 * 256) * sizeof(double);
+    return ((size_t)2 * max_P + 2 + 4 * 256) * sizeof(double);
 }
 
 size_t integrator_lds_bytes(int max_P) { return integ_lds(max_P); }

@@ -26,8 +26,9 @@ typedef short i16x4 __attribute__((ext_vector_type(4)));
 // Operand precision modes: 0 FP32 operands (v_mfma_f32_16x16x4f32, this
 // kernel); 1 BF16 operands in a three-term split, with a = a_hi + a_lo and
 // b = b_hi + b_lo (each part bfloat16), acc += a_hi b_hi + a_lo b_hi + a_hi b_lo
-// (the dropped a_lo b_lo term is below 2^-16 of the product); 2 BF16 operands,
-// one term (modes 1 and 2: k_mlp_bf16); 3 FP64 (k_mlp_f64).
+// (the dropped a_lo b_lo term is below 2^-16 of the product); 4 the same when
+// every weight is a bfloat16 value (b_lo = 0): a_hi b + a_lo b; 2 BF16
+// operands, one term (modes 1, 2 and 4: k_mlp_bf16); 3 FP64 (k_mlp_f64).
 struct MlpCfg {
     static constexpr int S = 130;  // LDS row stride of the FP32 tile (floats)
 };
@@ -290,12 +291,18 @@ __device__ __forceinline__ f32x4 mfma_k32(const i16x8 &a, const i16x8 &b, const 
 // Nearest-even float -> bfloat16 (one v_cvt_pk_bf16_f32 on gfx950).
 __device__ __forceinline__ uint16_t to_bf16(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 
+// Modes 1 and 4 split the activations into hi and lo bfloat16 parts; mode 1
+// splits the weights too, mode 4 takes weights that are bfloat16 values
+// already (their lo parts are zero), so a product costs two MFMAs, not three.
+template <int MODE>
+constexpr bool split_act() { return MODE == 1 || MODE == 4; }
+
 template <int MODE>
 __device__ __forceinline__ void store_bf16(uint16_t *hi, uint16_t *lo, int idx, float v)
 {
     const uint16_t h = to_bf16(v);
     hi[idx] = h;
-    if (MODE == 1)
+    if (split_act<MODE>())
         lo[idx] = to_bf16(v - bf16_value(h));
 }
 
@@ -322,7 +329,7 @@ __device__ __forceinline__ void gemm_bf16(const uint16_t *ahi, const uint16_t *a
         for (int r = 0; r < RT; ++r) {
             const int o = (16 * r + lr) * SB + k0 + 8 * lg;
             ah[r] = *reinterpret_cast<const i16x8 *>(ahi + o);
-            if (MODE == 1)
+            if (split_act<MODE>())
                 al[r] = *reinterpret_cast<const i16x8 *>(alo + o);
         }
 #pragma unroll
@@ -337,10 +344,10 @@ __device__ __forceinline__ void gemm_bf16(const uint16_t *ahi, const uint16_t *a
 #pragma unroll
                 for (int r = 0; r < RT; ++r) {
                     acc[r][t] = mfma_k32(ah[r], bh, acc[r][t]);
-                    if (MODE == 1) {
+                    if (split_act<MODE>())
                         acc[r][t] = mfma_k32(al[r], bh, acc[r][t]);
+                    if (MODE == 1)
                         acc[r][t] = mfma_k32(ah[r], bl, acc[r][t]);
-                    }
                 }
             }
         }
@@ -351,7 +358,7 @@ __device__ __forceinline__ void gemm_bf16(const uint16_t *ahi, const uint16_t *a
         for (int r = 0; r < RT; ++r) {
             const int o = (16 * r + lr) * SB + k0 + 4 * lg;
             ah[r] = *reinterpret_cast<const i16x4 *>(ahi + o);
-            if (MODE == 1)
+            if (split_act<MODE>())
                 al[r] = *reinterpret_cast<const i16x4 *>(alo + o);
         }
 #pragma unroll
@@ -366,10 +373,10 @@ __device__ __forceinline__ void gemm_bf16(const uint16_t *ahi, const uint16_t *a
 #pragma unroll
                 for (int r = 0; r < RT; ++r) {
                     acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[r], bh, acc[r][t], 0, 0, 0);
-                    if (MODE == 1) {
+                    if (split_act<MODE>())
                         acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[r], bh, acc[r][t], 0, 0, 0);
+                    if (MODE == 1)
                         acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[r], bl, acc[r][t], 0, 0, 0);
-                    }
                 }
             }
         }
@@ -387,7 +394,7 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bf16(const int32_t *__restrict_
     constexpr int SB = kBfStride;
     constexpr int MT = 16 * RT;
     __shared__ __attribute__((aligned(16))) uint16_t ahi[MT * SB];
-    __shared__ __attribute__((aligned(16))) uint16_t alo[MODE == 1 ? MT * SB : 8];
+    __shared__ __attribute__((aligned(16))) uint16_t alo[split_act<MODE>() ? MT * SB : 8];
     constexpr int CT = 8 / NW;
     __shared__ float epart[4][MT];
     // NW = 8: the second half of the waves hands its per-lane readout partials
@@ -744,6 +751,10 @@ void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, in
     if (mlp_mode == 3)
         hipLaunchKernelGGL(k_mlp_f64, dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp, nets,
                            d.E_atom, d.dEdG);
+    else if (mlp_mode == 4 && waves == 8)
+        launch_mlp_bf16<4, 8>(d, nets, n_tiles, D, Dp, rows, s);
+    else if (mlp_mode == 4)
+        launch_mlp_bf16<4, 4>(d, nets, n_tiles, D, Dp, rows, s);
     else if (mlp_mode == 1 && waves == 8)
         launch_mlp_bf16<1, 8>(d, nets, n_tiles, D, Dp, rows, s);
     else if (mlp_mode == 1)

@@ -12,6 +12,7 @@
 // sorted ascending, i.e. grouped by element and ascending row within a
 // group; nbr_grp[i][e] counts each element's group.
 #include "device_common.hpp"
+#include "neighbor_test.hpp"
 
 namespace pimd {
 
@@ -122,22 +123,6 @@ __host__ __device__ inline int nl_buffer(int Kmax)
         n <<= 1;
     const int b = n > Kmax + kWave ? n : Kmax + kWave;
     return (b + 3) & ~3;
-}
-
-__device__ __forceinline__ bool within_cutoff(const float4 &pi, const float4 &pj, const BeadInfo &bi, float rc2)
-{
-    float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-    if (bi.periodic) {
-        const float sx = bi.L[0] * rintf(dx * bi.invL[0]);
-        const float sy = bi.L[1] * rintf(dy * bi.invL[1]);
-        const float sz = bi.L[2] * rintf(dz * bi.invL[2]);
-        dx = dx - sx;
-        dy = dy - sy;
-        dz = dz - sz;
-    }
-    const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-    const float r2 = (xx + yy) + zz;
-    return r2 < rc2;
 }
 
 // The (deduplicated) stencil of cell (cx, cy, cz), one cell per lane: lane

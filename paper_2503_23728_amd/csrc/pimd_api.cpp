@@ -54,6 +54,9 @@ struct Plan {
     bool any_box = false;                      // some system has a box (metadynamics minimum image)
     bool metad = false;                        // well-tempered metadynamics bias
     bool pile_g = false;                       // PILE-G: global thermostat on the centroids
+    bool small = false;                        // small molecules: lane-per-centre kernels available
+    int n_sm_units = 0;                        // their work units (whole beads, <= 64 rows each)
+    int sm_nmax = 0;                           // atoms of the largest molecule
     int cv = 0, n_terms = 0, max_hills = 0;
     int xrd_tile = 64, n_xrd_items = 0;          // XRD pair sum: rows per tile, work items
     int64_t n_xrd_part = 0;                    // per-tile partials of the XRD pair sum
@@ -261,6 +264,24 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
     }
     if (B >= (int64_t)kRowMask || cells > (int64_t)1 << 30)
         return fail(err, PIMD_E_UNSUPPORTED, "too many bead-atoms (limit 2^27)");
+    // lane-per-centre kernels: the G4 network on molecules without a box of at
+    // most kSmAtoms atoms; units of whole beads, as many as fit in 64 rows
+    pl.small = pl.bpnn && !pl.angular && !pl.any_periodic && pl.skin == 0.0;
+    for (int s = 0; s < cfg->n_systems && pl.small; ++s) {
+        pl.small = cfg->n_atoms[s] <= kSmAtoms;
+        pl.sm_nmax = std::max(pl.sm_nmax, cfg->n_atoms[s]);
+    }
+    if (pl.small) {
+        int rows = kWave;
+        for (int s = 0; s < cfg->n_systems; ++s)
+            for (int k = 0; k < cfg->n_beads[s]; ++k) {
+                if (rows + cfg->n_atoms[s] > kWave) {
+                    ++pl.n_sm_units;
+                    rows = 0;
+                }
+                rows += cfg->n_atoms[s];
+            }
+    }
     for (int64_t a = 0; a < na; ++a)
         if (cfg->species[a] < 0 || cfg->species[a] >= mv.n_el)
             return fail(err, PIMD_E_ARG, "species index out of range");
@@ -270,7 +291,7 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
     pl.ncol = 3 * (int)na;
     pl.total_cells = (int)cells;
     for (int P : pl.distinct_P)
-        pl.cmat_elems += (size_t)P * P;
+        pl.cmat_elems += 2 * (size_t)P + 2;
     if (pl.bpnn) {
         int in = pl.Dp;
         for (int e = 0; e < pl.n_el; ++e) {
@@ -403,6 +424,8 @@ Layout make_layout(const Plan &pl)
     }
     L.add("heat", (size_t)pl.n_sys * 8);
     L.add("dke_part", (size_t)pl.n_units * 16);
+    if (pl.small)
+        L.add("sm_units", (size_t)pl.n_sm_units * sizeof(SmUnit));
     if (pl.pile_g) {
         L.add("svr_part", (size_t)pl.n_units * 16);
         L.add("svr_alpha", (size_t)pl.n_sys * 8);
@@ -489,6 +512,7 @@ struct pimd_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool state_set = false, forces_valid = false, noise_pending = false, use_graph = true;
+    bool atoms_of_state = false;       // E_atom and vir_atom hold the state's positions' values
     // stage timing: events recorded after each stage when non-null
     hipEvent_t *stage_ev = nullptr;
     // metadynamics: parameters, host mirrors of the step and hill counters
@@ -504,6 +528,7 @@ struct pimd_ctx {
     int device = 0;
     int static_device = -1;            // device whose static workspace this context holds (pimd_init_static)
     double svr_c = 1.0;                // PILE-G: exp(-(dt/2)/tau0)
+    bool mlp_weights_bf16 = false;     // every MLP weight is a bfloat16 value (split mode: two products a term)
     std::string err;
 };
 
@@ -548,10 +573,13 @@ void launch_force_stage(pimd_ctx *c, int stage, const float *q, float *E_out, fl
             launch_cell_scan(d, z, s);
             launch_cell_fill(d, z, s);
         }
-        launch_neighbors(d, z, c->dp.rc2, c->pl.n_el, c->tn, s);
+        if (!c->tn.centre_lanes)   // the lane-per-centre forward writes the lists itself
+            launch_neighbors(d, z, c->dp.rc2, c->pl.n_el, c->tn, s);
         break;
     case 1:
-        if (c->pl.gfn)
+        if (c->tn.centre_lanes)
+            launch_sm_forward(d, c->dp, c->pl.n_sm_units, c->pl.sm_nmax, s);
+        else if (c->pl.gfn)
             launch_gfn_layers(d, z, c->dp, c->gp, c->tn, s);
         else if (c->dp.angular)
             launch_descriptors_g5(d, z, c->dp, c->tn, s);
@@ -560,7 +588,9 @@ void launch_force_stage(pimd_ctx *c, int stage, const float *q, float *E_out, fl
         break;
     case 2:
         if (c->pl.bpnn)
-            launch_mlp(d, c->nets, c->n_mlp_tiles, c->pl.D, c->pl.Dp, c->precision, c->tn.mlp_rows, c->tn.mlp_waves,
+            launch_mlp(d, c->nets, c->n_mlp_tiles, c->pl.D, c->pl.Dp,
+                       c->precision == PIMD_PREC_BF16_MLP && c->mlp_weights_bf16 ? 4 : c->precision, c->tn.mlp_rows,
+                       c->tn.mlp_waves,
                        s);
         break;
     case 3:
@@ -573,14 +603,16 @@ void launch_force_stage(pimd_ctx *c, int stage, const float *q, float *E_out, fl
                 launch_zero_i32(reinterpret_cast<int32_t *>(d.vir_atom), (int64_t)z.B * 9, s);
             }
         } else if (F_out || W_out) {
-            if (c->dp.angular)
+            if (c->tn.centre_lanes)   // with the force assembly
+                launch_sm_adjoint(d, c->dp, c->pl.n_sm_units, c->pl.sm_nmax, F_out, s);
+            else if (c->dp.angular)
                 launch_adjoint_g5(d, z, c->dp, c->tn, s);
             else
                 launch_adjoint(d, z, c->dp, c->tn, s);
         }
         break;
     default:
-        if (F_out && c->pl.bpnn)
+        if (F_out && c->pl.bpnn && !c->tn.centre_lanes)
             launch_assemble_forces(d, z, F_out, c->tn, s);
         launch_bead_sums(d, z, E_out, W_out, W_out != nullptr, s);
     }
@@ -598,6 +630,7 @@ pimd_status run_forces(pimd_ctx *c, const float *q, float *E_out, float *F_out, 
     // the metadynamics bias joins the forces the integrator uses (never the
     // caller's arrays of pimd_energy_forces)
     const bool bias = c->pl.metad && F_out == d.F;
+    c->atoms_of_state = q == d.q;   // per-atom energies and virials now belong to these positions
     if (c->potential == PIMD_POT_HARMONIC) {
         launch_harmonic(q, d, z, (float)(c->omega * c->omega * kMvv2e), F_out, s);
         launch_bead_sums(d, z, E_out, W_out, W_out != nullptr, s);
@@ -633,7 +666,7 @@ pimd_status run_step(pimd_ctx *c, hipStream_t s, const float *xi)
     if (c->stage_ev)
         (void)hipEventRecord(c->stage_ev[1], s);
     c->deposit_now = true;
-    pimd_status st = run_forces(c, c->d.q, c->d.E_bead, c->d.F, c->d.W_bead);
+    pimd_status st = run_forces(c, c->d.q, c->d.E_bead, c->d.F, nullptr);
     c->deposit_now = false;
     if (c->pl.metad)
         launch_metad_advance(c->d, c->mp, s);
@@ -827,6 +860,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     d.svr_part = (double *)at("svr_part");
     d.svr_alpha = cfg->tau0_fs > 0.0 ? (double *)at("svr_alpha") : nullptr;
     d.svr_kbar = (double *)at("svr_kbar");
+    d.sm_units = (SmUnit *)at("sm_units");
     c->svr_c = cfg->tau0_fs > 0.0 ? std::exp(-0.5 * cfg->dt_fs / cfg->tau0_fs) : 1.0;
     d.step = (int64_t *)at("step");
     d.status = (uint32_t *)at("status");
@@ -852,10 +886,13 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     z.D = pl.D;
     z.Kmax = pl.Kmax;
     z.any_periodic = pl.any_periodic ? 1 : 0;
+    for (int s = 0; s < pl.n_sys; ++s)
+        z.max_bead_atoms = std::max(z.max_bead_atoms, cfg->n_atoms[s]);
     c->tn.nl_cells = pl.total_cells >= 4096 ? 1 : 0;
     // dense periodic liquids hide the reverse-slot loads behind the adjoint's
     // triplet work; a few neighbours per atom leave nothing to hide them behind
     c->tn.force_rows = pl.any_periodic ? 1 : 0;
+    c->tn.centre_lanes = pl.small ? 1 : 0;
     if (c->precision == PIMD_PREC_BF16_MLP || c->precision == PIMD_PREC_BF16_PLAIN) {
         c->tn.mlp_rows = 32;    // 32-row tiles, one 16-column tile per wave: fastest at 64 to 16384 bead-atoms
         c->tn.mlp_waves = 8;
@@ -877,23 +914,28 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     std::vector<double> cmat;
     std::vector<int32_t> cell_bead;
     std::map<int, int> cmat_off;
+    // normal modes per distinct P: twiddles cos(2 pi m/P) and sin(2 pi m/P),
+    // m = 0 .. P-1, then the normalisations 1/sqrt(P) and sqrt(2/P); the
+    // integrator forms C[j][k] from them (m = jk mod P).  The quarter and half
+    // turns are set exactly.
     for (int P : pl.distinct_P) {
         cmat_off[P] = (int)cmat.size();
-        for (int j = 0; j < P; ++j)
-            for (int k = 0; k < P; ++k) {
-                double v;
-                if (P == 1)
-                    v = 1.0;
-                else if (k == 0)
-                    v = 1.0 / std::sqrt((double)P);
-                else if (k < P / 2)
-                    v = std::sqrt(2.0 / P) * std::cos(2.0 * kPi * j * k / P);
-                else if (k == P / 2)
-                    v = ((j & 1) ? -1.0 : 1.0) / std::sqrt((double)P);
-                else
-                    v = std::sqrt(2.0 / P) * std::sin(2.0 * kPi * j * k / P);
-                cmat.push_back(v);
+        std::vector<double> cs(P), sn(P);
+        for (int m = 0; m < P; ++m) {
+            const int q = (4 * m) % (4 * P);
+            if (q % P == 0) {   // m P/4 multiples: 0, 1/4, 1/2, 3/4 turn
+                const int turn = (4 * m) / P;
+                cs[m] = turn == 0 ? 1.0 : (turn == 2 ? -1.0 : 0.0);
+                sn[m] = turn == 1 ? 1.0 : (turn == 3 ? -1.0 : 0.0);
+            } else {
+                cs[m] = std::cos(2.0 * kPi * m / P);
+                sn[m] = std::sin(2.0 * kPi * m / P);
             }
+        }
+        cmat.insert(cmat.end(), cs.begin(), cs.end());
+        cmat.insert(cmat.end(), sn.begin(), sn.end());
+        cmat.push_back(1.0 / std::sqrt((double)P));
+        cmat.push_back(std::sqrt(2.0 / P));
     }
     int ba0 = 0, atom0 = 0, cell0 = 0, mode0 = 0;
     for (int s = 0; s < pl.n_sys; ++s) {
@@ -1009,6 +1051,17 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     if (pl.nl)
         push(d.cell_bead, cell_bead.data(), cell_bead.size() * 4);
     push(d.col_sys, col_sys.data(), col_sys.size() * 4);
+    std::vector<SmUnit> sm_units;
+    if (pl.small) {
+        // whole beads in bead order, as many as fit in the 64 lanes of a wave
+        for (const BeadInfo &b : beads) {
+            if (sm_units.empty() || sm_units.back().nrows + b.n > kWave)
+                sm_units.push_back(SmUnit{b.ba0, 0, 0, 0});
+            sm_units.back().nrows += b.n;
+            sm_units.back().nmax = std::max(sm_units.back().nmax, b.n);
+        }
+        push(d.sm_units, sm_units.data(), sm_units.size() * sizeof(SmUnit));
+    }
 
     if (pl.nl) {
         // cutoff and radial grid (both neural potentials)
@@ -1099,6 +1152,10 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         dp.D = pl.D;
         for (int s = 0; s < m->n_ang_eta; ++s)
             dp.ang_eta[s] = (float)m->ang_eta[s];
+        // the 16-feature angular grid takes eta_1 = 4 eta_0 (exact in float too):
+        // the triplet kernels then square exp(-eta_0 r_jk^2) twice instead of
+        // evaluating a second exponential
+        dp.eta_pow4 = m->n_ang_eta == 2 && dp.ang_eta[1] == 4.0f * dp.ang_eta[0] ? 1 : 0;
         dp.angular = pl.angular;
         {
             // Legendre coefficients of (1 + c)^zeta: multiply by (1 + c) zeta times,
@@ -1218,6 +1275,19 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         }
         push(d.mlp_f32, wf.data(), wf.size() * 4);
         push(d.mlp_bf16, wb.data(), wb.size() * 2);
+        // weights that are bfloat16 values already leave every lo part zero: the
+        // split BF16 mode then needs two products per term instead of three
+        c->mlp_weights_bf16 = true;
+        for (int e = 0; e < pl.n_el && c->mlp_weights_bf16; ++e)
+            for (int l = 0; l < m->n_hidden && c->mlp_weights_bf16; ++l) {
+                const MlpLayer &Ly = c->nets.net[e].layer[l];
+                const size_t lo = (size_t)(Ly.Wb_lo - d.mlp_bf16), n = (size_t)Ly.out * Ly.in_pad;
+                for (size_t t = 0; t < n; ++t)
+                    if (wb[lo + t] != 0 && wb[lo + t] != 0x8000) {
+                        c->mlp_weights_bf16 = false;
+                        break;
+                    }
+            }
         push(d.mlp_f64, w64.data(), w64.size() * 8);
     }
     if (pl.metad) {
@@ -1313,6 +1383,8 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         return bail(PIMD_E_DEVICE, std::string("upload sync: ") + hipGetErrorString(e));
     if (pl.bpnn) {
         e = pl.angular ? configure_g5_lds(c->dp) : configure_descriptor_lds(c->dp);
+        if (e == hipSuccess && pl.small)
+            e = configure_sm_lds(c->dp);
         if (e != hipSuccess)
             return bail(PIMD_E_DEVICE, std::string("descriptor LDS: ") + hipGetErrorString(e));
     }
@@ -1562,11 +1634,15 @@ pimd_status pimd_estimators(pimd_ctx *ctx, pimd_estimates *out_host)
         ctx->err = "state not set";
         return PIMD_E_STATE;
     }
-    if (!ctx->forces_valid) {
+    if (!ctx->forces_valid || !ctx->atoms_of_state) {
+        // the per-atom terms were overwritten by an evaluation at other positions
         pimd_status st = run_forces(ctx, ctx->d.q, ctx->d.E_bead, ctx->d.F, ctx->d.W_bead);
         if (st != PIMD_OK)
             return st;
         ctx->forces_valid = true;
+    } else {
+        // bead virials of the state's per-atom virials (steps leave them out)
+        launch_bead_sums(ctx->d, ctx->z, ctx->d.E_bead, ctx->d.W_bead, true, ctx->stream);
     }
     launch_estimator_terms(ctx->d, ctx->z, ctx->stream);
     CHECK_LAUNCH(ctx);
@@ -1926,7 +2002,7 @@ pimd_status pimd_get_tuning(const pimd_ctx *ctx, pimd_tuning *out)
     if (!ctx || !out)
         return PIMD_E_ARG;
     *out = pimd_tuning{ctx->tn.centre_waves, ctx->tn.centre_grid, ctx->tn.mlp_rows, ctx->tn.nl_cells,
-                       ctx->tn.mlp_waves, ctx->tn.force_rows};
+                       ctx->tn.mlp_waves, ctx->tn.force_rows, ctx->tn.centre_lanes};
     return PIMD_OK;
 }
 
@@ -1959,17 +2035,22 @@ pimd_status pimd_set_tuning(pimd_ctx *ctx, const pimd_tuning *t)
     const bool waves_ok = t->centre_waves == 1 || t->centre_waves == 2 || t->centre_waves == 4;
     const bool rows_ok = t->mlp_rows == 16 || t->mlp_rows == 32 || t->mlp_rows == 64;
     if (!waves_ok || !rows_ok || t->centre_grid < 0 || (t->neighbor_cells != 0 && t->neighbor_cells != 1) ||
-        (t->mlp_waves != 4 && t->mlp_waves != 8) || (t->force_rows != 0 && t->force_rows != 1)) {
+        (t->mlp_waves != 4 && t->mlp_waves != 8) || (t->force_rows != 0 && t->force_rows != 1) ||
+        (t->centre_lanes != 0 && t->centre_lanes != 1)) {
         ctx->err = "tuning: centre_waves in {1, 2, 4}, centre_grid >= 0, mlp_rows in {16, 32, 64}, "
-                   "neighbor_cells in {0, 1}, mlp_waves in {4, 8}, force_rows in {0, 1}";
+                   "neighbor_cells in {0, 1}, mlp_waves in {4, 8}, force_rows in {0, 1}, centre_lanes in {0, 1}";
         return PIMD_E_ARG;
+    }
+    if (t->centre_lanes && !ctx->pl.small) {
+        ctx->err = "centre_lanes = 1 needs G4 molecules without a box of at most 16 atoms each";
+        return PIMD_E_UNSUPPORTED;
     }
     if (ctx->precision == PIMD_PREC_FP64_MLP && t->mlp_rows != 16) {
         ctx->err = "the FP64 MLP runs 16-row tiles only";
         return PIMD_E_UNSUPPORTED;
     }
     return apply_tuning(ctx, Tuning{t->centre_waves, t->centre_grid, t->mlp_rows, t->neighbor_cells, t->mlp_waves,
-                                    t->force_rows});
+                                    t->force_rows, t->centre_lanes});
 }
 
 // Mean milliseconds of one force evaluation of the current positions.
@@ -2034,12 +2115,18 @@ pimd_status pimd_autotune(pimd_ctx *ctx, int32_t n_reps, pimd_tuning *best)
             }
             return PIMD_OK;
         };
+        if (ctx->pl.small) {   // lane per centre against wave per centre, first: the rest tunes the winner
+            Tuning cand = top;
+            cand.centre_lanes = 1 - top.centre_lanes;
+            if ((st = consider(cand)) != PIMD_OK)
+                return st;
+        }
         for (int waves : {4, 2, 1})
             for (int per_cu : {0, 2, 4, 8, 16}) {
                 Tuning cand = top;
                 cand.centre_waves = waves;
                 cand.centre_grid = per_cu * n_cu;
-                if (cand.centre_grid >= centre_grid(ctx->z.B, Tuning{waves, 0, 16, 0, 4, 0}))
+                if (cand.centre_grid >= centre_grid(ctx->z.B, Tuning{waves, 0, 16, 0, 4, 0, 0}))
                     continue;   // no fewer workgroups than one wave per centre gives
                 if (cand.centre_waves == cur.centre_waves && cand.centre_grid == cur.centre_grid)
                     continue;

@@ -9,6 +9,7 @@ namespace pimd {
 
 constexpr int kWave = 64;
 constexpr int kMaxElements = 4;
+constexpr int kSmAtoms = 16;                   // lane-per-centre kernels: atoms per molecule, at most
 constexpr int kMaxRad = 32;
 constexpr int kMaxPairs = kMaxElements * (kMaxElements + 1) / 2;   // element-pair blocks
 // slot pairs kept per centre by the descriptor forward for the adjoint: every
@@ -54,6 +55,7 @@ struct DescParams {
     float rad_center_lo[kMaxRad];  // ... and the remainder R_s - float(R_s)
     float rad_eta[kMaxRad];
     float ang_eta[2];
+    int32_t eta_pow4;              // 1: ang_eta[1] == 4 ang_eta[0] exactly, so exp(-eta_1 x) = exp(-eta_0 x)^4
     int32_t angular;               // 0: G4 angular functions, 1: G5
     float g5_leg[4][9];            // G5: 2^(1-zeta) a_l of (1 + c)^zeta = sum_l a_l P_l(c), zeta = 1, 2, 4, 8
 };
@@ -91,6 +93,12 @@ struct MlpTile {
 };
 
 // Integrator work unit: `ncol` columns (atom, xyz) of one system, P threads each.
+// Work unit of the lane-per-centre kernels: whole beads of small molecules,
+// rows row0 .. row0 + nrows - 1 (nrows <= 64), nmax atoms in the largest bead.
+struct SmUnit {
+    int32_t row0, nrows, nmax, pad;
+};
+
 struct IntegUnit {
     int32_t sys;
     int32_t col0;
@@ -101,7 +109,7 @@ struct IntegUnit {
 struct SysInfo {
     int32_t N, P, ba0, atom0;   // atoms, beads, first row, first atom (in species order)
     int32_t mode0;              // first entry of this system in the mode table
-    int32_t cmat0;              // offset of this P's normal-mode matrix in the C table
+    int32_t cmat0;              // offset of this P's normal-mode twiddle table
     int32_t unit0, nunit;       // integrator units of this system
     float sig_T;                // sqrt(k_B T P / MVV2E): thermal momentum per sqrt(amu)
     float pad[3];
@@ -187,6 +195,7 @@ struct DevBuffers {
     double *svr_part;              // PILE-G: per unit (centroid kinetic energy, sum of centroid normals^2)
     double *svr_alpha;             // PILE-G: per system factor of the centroid momenta (null: PILE-L)
     double *svr_kbar;              // PILE-G: per system N_f k_B T P / 2
+    SmUnit *sm_units;              // lane-per-centre kernels: whole beads per wave
     int64_t *step;
     uint32_t *status;
     float *est_cols;               // estimator terms per column [ncol][3]
@@ -200,7 +209,7 @@ struct DevBuffers {
     SysInfo *sys;
     ModeInfo *modes;
     IntegUnit *units;
-    double *cmat;                  // normal-mode matrices, C[j][k] row-major per distinct P (FP64)
+    double *cmat;                  // normal modes per distinct P: cos, sin twiddles [P] each, 1/sqrt(P), sqrt(2/P)
     int32_t *col_sys;              // [ncol] system of each column
     float *mlp_f32;                // packed f32 weights (W, WT, b, wo per element)
     uint16_t *mlp_bf16;            // packed bf16 weights (W, WT per element)
@@ -234,6 +243,7 @@ struct Tuning {
     int32_t mlp_waves;     // waves per BF16 MLP workgroup: 4 (two column tiles each) or 8 (one each)
     int32_t force_rows;    // 1: the adjoint also stores each slot value at the neighbour's reverse slot and the
                            // force assembly reads rows; 0: the assembly gathers through the reverse-slot search
+    int32_t centre_lanes;  // 1: small molecules, one lane per centre (whole beads per wave); 0: one wave per centre
 };
 
 // Workgroups of a per-centre launch over B centres.
@@ -250,6 +260,7 @@ struct Sizes {
     int32_t any_open;       // some system has none (all-pairs lists)
     int32_t any_box;        // some system has a box (minimum image of the metadynamics CVs)
     int32_t skin;           // shared centroid lists with a skin instead of per-bead cell lists
+    int32_t max_bead_atoms; // atoms of the largest bead
 };
 
 struct SkinParams {
@@ -314,6 +325,11 @@ void launch_work_counts(const DevBuffers &d, const Sizes &z, const DescParams &d
 
 // Raise the dynamic-LDS limit of kernels whose LDS grows with Kmax or P.
 hipError_t configure_descriptor_lds(const DescParams &dp);
+// lane-per-centre kernels of small molecules (k_small.hip): descriptors with
+// the neighbour lists, then adjoint with the force assembly (F may be null)
+hipError_t configure_sm_lds(const DescParams &dp);
+void launch_sm_forward(const DevBuffers &d, const DescParams &dp, int n_units, int nmax, hipStream_t s);
+void launch_sm_adjoint(const DevBuffers &d, const DescParams &dp, int n_units, int nmax, float *F, hipStream_t s);
 // neighbour stage with shared centroid lists: wrap and drift check, rebuild when
 // flagged (centroids, lists), per-bead filter into nbr / nbr_cnt / nbr_grp / fence
 void launch_skin_neighbors(const float *q, const DevBuffers &d, const Sizes &z, const SkinParams &sp, float rc2,

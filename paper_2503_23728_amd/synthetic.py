@@ -133,8 +133,18 @@ def angular_etas(n_ang):
     raise ValueError("n_ang must be 8 or 16")
 
 
-def make_model(elements, n_rad, n_ang, hidden, seed, rad_scale=1.0, ang_scale=1.0):
-    """Random-weight network, W ~ N(0, 1/fan_in), zero biases.
+def _bfloat16_values(a):
+    """float32 array rounded to the nearest bfloat16 value (ties to even), kept as float32."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def make_model(elements, n_rad, n_ang, hidden, seed, rad_scale=1.0, ang_scale=1.0, bf16_weights=True):
+    """Random-weight network, W ~ N(0, 1/fan_in), zero biases.  With
+    bf16_weights (the default) every weight is rounded to the nearest bfloat16
+    value: the weights are still float32 numbers, the same for every precision
+    and for the oracle, and a BF16 MLP then splits only its activations.
 
     feat_shift = 0; feat_scale is a per-block constant (radial / angular)
     chosen so the normalised features of the synthetic geometries are O(1).
@@ -151,6 +161,8 @@ def make_model(elements, n_rad, n_ang, hidden, seed, rad_scale=1.0, ang_scale=1.
         fan_in = D
         for width in list(hidden) + [1]:
             W = rng.normal(0.0, 1.0 / math.sqrt(fan_in), size=(width, fan_in)).astype(np.float32)
+            if bf16_weights:
+                W = _bfloat16_values(W)
             b = np.zeros(width, dtype=np.float32)
             layers.append((W, b))
             fan_in = width
@@ -443,30 +455,31 @@ _FAD_SCALES = dict(rad_scale=1.0, ang_scale=1.0)
 _WATER_SCALES = dict(rad_scale=2.0, ang_scale=10.0)
 
 
-def workload(c, seed_offset=0):
+def workload(c, seed_offset=0, bf16_weights=True):
     """Build workload number c (1..5) as described in the module docstring.
 
     Seeds: geometry 1000+c, weights 2000+c, momenta 3000+c, Philox 4000+c,
     each shifted by seed_offset (parity tests use 0, 100, 200).
+    bf16_weights: see make_model.
     """
     gs, ws, ms, ps = (1000 + c + seed_offset, 2000 + c + seed_offset,
                       3000 + c + seed_offset, 4000 + c + seed_offset)
     rng = np.random.default_rng(gs)
     if c == 1:
         elements, sys1 = _fad_system(rng, 8, 300.0)
-        model = make_model(elements, 8, 8, [64, 64], ws, **_FAD_SCALES)
+        model = make_model(elements, 8, 8, [64, 64], ws, bf16_weights=bf16_weights, **_FAD_SCALES)
         return Workload("fad-10atom-P8", [sys1], model, dt=0.25, tau0=100.0, pile_lambda=1.0,
                         n_steps=500, philox_seed=ps, momentum_seed=ms)
     if c == 2:
         elements, species, pos, box = water_grid(4, 12.42, rng)
         s = System(len(species), 32, 300.0, box, species, pos)
-        model = make_model(elements, 16, 16, [128, 128, 64], ws, **_WATER_SCALES)
+        model = make_model(elements, 16, 16, [128, 128, 64], ws, bf16_weights=bf16_weights, **_WATER_SCALES)
         return Workload("water-64-P32", [s], model, dt=0.25, tau0=100.0, pile_lambda=1.0,
                         n_steps=200, philox_seed=ps, momentum_seed=ms)
     if c == 3:
         elements, species, pos, box = ice_ih(rng)
         s = System(len(species), 32, 250.0, box, species, pos)
-        model = make_model(elements, 16, 16, [128, 128, 64], ws, **_WATER_SCALES)
+        model = make_model(elements, 16, 16, [128, 128, 64], ws, bf16_weights=bf16_weights, **_WATER_SCALES)
         return Workload("ice-96-P32", [s], model, dt=0.25, tau0=100.0, pile_lambda=1.0,
                         n_steps=4000, philox_seed=ps, momentum_seed=ms)
     if c == 4:
@@ -477,30 +490,30 @@ def workload(c, seed_offset=0):
             t = float(rng.uniform(100.0, 400.0))
             elements, s = _fad_system(rng, p, t)
             systems.append(s)
-        model = make_model(elements, 8, 8, [64, 64], ws, **_FAD_SCALES)
+        model = make_model(elements, 8, 8, [64, 64], ws, bf16_weights=bf16_weights, **_FAD_SCALES)
         return Workload("fad-batch-512", systems, model, dt=0.25, tau0=100.0, pile_lambda=1.0,
                         n_steps=200, philox_seed=ps, momentum_seed=ms)
     if c == 5:
         elements, species, pos, box = water_grid(16, 49.7, rng)
         s = System(len(species), 32, 300.0, box, species, pos)
-        model = make_model(elements, 16, 16, [128, 128, 64], ws, **_WATER_SCALES)
+        model = make_model(elements, 16, 16, [128, 128, 64], ws, bf16_weights=bf16_weights, **_WATER_SCALES)
         return Workload("water-4096-P32", [s], model, dt=0.25, tau0=100.0, pile_lambda=1.0,
                         n_steps=200, philox_seed=ps, momentum_seed=ms)
     raise ValueError(f"unknown workload {c}")
 
 
-def small_workload(kind, seed=7, n_beads=4):
+def small_workload(kind, seed=7, n_beads=4, bf16_weights=True):
     """Small variants for fast tests: 'fad' (10 atoms), 'water8' (8 H2O in a
     periodic 12.5 A box, so the cell grid is 2x2x2 and stencils wrap)."""
     rng = np.random.default_rng(seed)
     if kind == "fad":
         elements, s = _fad_system(rng, n_beads, 300.0)
-        model = make_model(elements, 8, 8, [64, 64], seed + 1, **_FAD_SCALES)
+        model = make_model(elements, 8, 8, [64, 64], seed + 1, bf16_weights=bf16_weights, **_FAD_SCALES)
         return Workload("fad-small", [s], model, 0.25, 100.0, 1.0, 10, seed + 2, seed + 3)
     if kind == "water8":
         elements, species, pos, box = water_grid(2, 12.5, rng)
         s = System(len(species), n_beads, 300.0, box, species, pos)
-        model = make_model(elements, 16, 16, [128, 128, 64], seed + 1, **_WATER_SCALES)
+        model = make_model(elements, 16, 16, [128, 128, 64], seed + 1, bf16_weights=bf16_weights, **_WATER_SCALES)
         return Workload("water8", [s], model, 0.25, 100.0, 1.0, 10, seed + 2, seed + 3)
     raise ValueError(kind)
 

@@ -12,7 +12,7 @@ import hashlib
 import json
 import os
 
-FIELDS = ("centre_waves", "centre_grid", "mlp_rows", "neighbor_cells", "mlp_waves", "force_rows")
+FIELDS = ("centre_waves", "centre_grid", "mlp_rows", "neighbor_cells", "mlp_waves", "force_rows", "centre_lanes")
 
 
 def cache_path():

@@ -201,3 +201,15 @@ def test_thermostat_is_validated(lib):
     a = abi.pimd_workspace_size(_cfg(wl)[0])[1]
     b = abi.pimd_workspace_size(_cfg(wl, thermostat="pile-g")[0])[1]
     assert b > a
+
+
+def test_synthetic_weights_are_bfloat16_values_unless_asked_otherwise():
+    # the default synthetic networks hold float32 weights with zero low 16 bits
+    # (a BF16 MLP then splits only its activations); bf16_weights=False keeps
+    # the float32 draws, and rounding moves a weight by at most half a bfloat16 ulp
+    wb, wf = S.workload(2).model.weights, S.workload(2, bf16_weights=False).model.weights
+    for lb, lf in zip(wb, wf):
+        for (Wb, _), (Wf, _) in zip(lb, lf):
+            assert Wb.dtype == np.float32 and not np.any(Wb.view(np.uint32) & 0xFFFF)
+            assert np.any(Wf.view(np.uint32) & 0xFFFF)
+            assert np.all(np.abs(Wb - Wf) <= np.abs(Wf) * 2.0 ** -8)

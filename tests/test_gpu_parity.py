@@ -79,11 +79,16 @@ def test_philox_integer_stream_matches_oracle():
 @pytest.mark.parametrize("name", list(WORKLOADS))
 def test_neighbor_lists_bit_exact(name, cells):
     # both periodic search kernels: per centre (0) and per cell with the
-    # stencil staged in LDS (1)
+    # stencil staged in LDS (1); for molecules without a box, cells = 1 runs
+    # the lane-per-centre kernels, which write the lists themselves
     wl = WORKLOADS[name]()
+    periodic = any(np.any(np.asarray(s.box) > 0) for s in wl.systems)
     say(f"neighbours {name} cells={cells}")
     eng = _engine(wl)
-    eng.set_tuning(neighbor_cells=cells)
+    if periodic:
+        eng.set_tuning(neighbor_cells=cells)
+    else:
+        eng.set_tuning(centre_lanes=cells)
     q = _q(wl, seed=2, amp=0.3)
     q[::7] += np.float32(25.0)    # unwrapped positions far outside the box
     eng.energy_forces(torch.from_numpy(q).cuda(), forces=False)
@@ -174,8 +179,31 @@ def test_bf16_mlp_forces(name):
     E, F, _ = eng.energy_forces(torch.from_numpy(q).cuda())
     E_ref, F_ref, _, A = _oracle_beads(wl, q)
     fe = force_error(F.cpu().numpy(), F_ref)
-    say(f"  bf16 (3-term split) force err {fe:.2e} energy err {energy_error(E.cpu().numpy(), E_ref, A):.2e}")
+    say(f"  bf16 (split activations, bfloat16-valued weights) force err {fe:.2e} energy err {energy_error(E.cpu().numpy(), E_ref, A):.2e}")
     assert fe < BF16_FORCE_TOL
+
+
+FLOAT32_WEIGHTS = {"water64-P32": lambda: S.workload(2, bf16_weights=False),
+                   "fad-P4": lambda: S.small_workload("fad", n_beads=4, bf16_weights=False)}
+
+
+@pytest.mark.parametrize("name", list(FLOAT32_WEIGHTS))
+def test_bf16_split_with_float32_valued_weights(name):
+    # the synthetic weights are bfloat16 values, so the split mode multiplies
+    # two activation parts by one weight part; weights with float32 mantissas
+    # (a model trained in FP32) make it split the weights too (three products)
+    wl = FLOAT32_WEIGHTS[name]()
+    assert any(np.any(W.view(np.uint32) & 0xFFFF) for layers in wl.model.weights for W, _ in layers)
+    say(f"bf16 split, float32-valued weights {name}")
+    q = _q(wl, seed=6)
+    E_ref, F_ref, _, A = _oracle_beads(wl, q)
+    eng = _engine(wl, precision="bf16")
+    E, F, _ = eng.energy_forces(torch.from_numpy(q).cuda())
+    fe = force_error(F.cpu().numpy(), F_ref)
+    ee = energy_error(E.cpu().numpy(), E_ref, A)
+    say(f"  force err {fe:.2e} energy err {ee:.2e}")
+    assert fe < BF16_FORCE_TOL
+    eng.close()
 
 
 @pytest.mark.parametrize("name", ["water64-P32", "fad-P4"])
@@ -371,20 +399,36 @@ def test_every_launch_shape_gives_bitwise_identical_results(name, prec):
     say(f"launch shapes {name} {prec}")
     eng = _engine(wl, precision=prec)
     q = torch.from_numpy(_q(wl, seed=9)).cuda()
-    E0, F0, W0 = eng.energy_forces(q, virial=True)
-    x0 = eng.debug_descriptors()
-    for waves in (1, 2, 4):
-        for grid in (0, 7, 300):
-            for rows in (16, 32, 64):
-                cells = (waves + rows // 16) % 2
-                mw = 8 if (grid + rows) % 3 else 4
-                fr = (waves + grid + rows // 16) % 2
-                eng.set_tuning(centre_waves=waves, centre_grid=grid, mlp_rows=rows, neighbor_cells=cells, mlp_waves=mw,
-                               force_rows=fr)
-                E, F, W = eng.energy_forces(q, virial=True)
-                shape = (waves, grid, rows, cells, mw, fr)
-                assert torch.equal(E, E0) and torch.equal(F, F0) and torch.equal(W, W0), shape
-                assert torch.equal(eng.debug_descriptors(), x0), shape
+    # molecules without a box: every shape within each of the two kernel
+    # families (lane per centre, wave per centre); the families agree to rounding
+    lanes_modes = (1, 0) if eng.get_tuning()["centre_lanes"] else (0,)
+    first = None
+    for lanes in lanes_modes:
+        eng.set_tuning(centre_lanes=lanes, centre_waves=4, centre_grid=0, mlp_rows=32)
+        E0, F0, W0 = eng.energy_forces(q, virial=True)
+        x0 = eng.debug_descriptors()
+        if first is None:
+            first = (E0, F0, x0)
+        else:
+            # FP32: the energy bar; the BF16 split holds 16 significant bits of
+            # each activation (hi + lo), so a one-ulp change of a descriptor can
+            # move an activation's representation by up to 2^-17 of it
+            e_tol = 1e-6 if prec == "fp32" else 2.0 ** -16
+            assert rel_max(F0.cpu().numpy(), first[1].cpu().numpy()) < 1e-5
+            assert rel_max(E0.cpu().numpy(), first[0].cpu().numpy()) < e_tol
+            assert rel_max(x0.cpu().numpy(), first[2].cpu().numpy()) < 1e-5
+        for waves in (1, 2, 4):
+            for grid in (0, 7, 300):
+                for rows in (16, 32, 64):
+                    cells = (waves + rows // 16) % 2
+                    mw = 8 if (grid + rows) % 3 else 4
+                    fr = (waves + grid + rows // 16) % 2
+                    eng.set_tuning(centre_waves=waves, centre_grid=grid, mlp_rows=rows, neighbor_cells=cells,
+                                   mlp_waves=mw, force_rows=fr)
+                    E, F, W = eng.energy_forces(q, virial=True)
+                    shape = (lanes, waves, grid, rows, cells, mw, fr)
+                    assert torch.equal(E, E0) and torch.equal(F, F0) and torch.equal(W, W0), shape
+                    assert torch.equal(eng.debug_descriptors(), x0), shape
 
 
 def test_autotune_picks_a_valid_shape_and_the_cache_reapplies_it(tmp_path, monkeypatch):
@@ -420,10 +464,15 @@ def test_bad_launch_shapes_are_rejected():
     wl = WORKLOADS["fad-P4"]()
     eng = _engine(wl)
     for bad in ({"centre_waves": 3}, {"centre_waves": 8}, {"mlp_rows": 48}, {"centre_grid": -1}, {"neighbor_cells": 2},
-                {"mlp_waves": 6}, {"force_rows": 2}):
+                {"mlp_waves": 6}, {"force_rows": 2}, {"centre_lanes": 2}):
         with pytest.raises(PimdError) as ei:
             eng.set_tuning(**bad)
         assert ei.value.status == PIMD_E_ARG
+    water = _engine(WORKLOADS["water8-P4"]())     # a box: wave-per-centre kernels only
+    assert water.get_tuning()["centre_lanes"] == 0
+    with pytest.raises(PimdError) as ei:
+        water.set_tuning(centre_lanes=1)
+    assert ei.value.status == PIMD_E_UNSUPPORTED
     f64 = _engine(wl, precision="fp64-mlp")
     with pytest.raises(PimdError) as ei:
         f64.set_tuning(mlp_rows=32)
