@@ -195,8 +195,8 @@ def plain_fp32(wl, steps, warmup, device, shape=None, skin=0.0):
                  potential="gfn" if hasattr(wl.model, "width") else "bpnn",
                  neighbor_skin=skin if np.any(np.asarray(s.box) > 0) else 0.0)
         e.set_graph(False)
-        if shape is not None:
-            e.set_tuning(**shape)
+        if shape is not None:   # the same shape; the register-chained MLP is a BF16 kernel
+            e.set_tuning(**dict(shape, mlp_chain=0))
         e.set_state(torch.from_numpy(q[off:off + n]).to(device), torch.from_numpy(p[off:off + n]).to(device))
         engines.append(e)
         off += n

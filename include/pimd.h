@@ -450,7 +450,7 @@ pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled);
 /* Launch shapes of the force kernels.  Many ring polymers and beads run as
  * one flat batch (the concurrent-trajectory parallelism of Sec. 2.3 and the
  * multi-trajectory point of Sec. 4); these fields only change how that batch
- * is cut into workgroups, never the results (centre_lanes aside, below):
+ * is cut into workgroups, never the results (centre_lanes and mlp_chain aside, below):
  * each centre atom is one wave and each MLP row runs the same MFMA chain
  * whatever the shape.
  *   centre_waves  waves (one centre atom each) per workgroup of the neighbour,
@@ -482,7 +482,19 @@ pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled);
  *                 the adjoint from the partners' lanes; 0 = one wave per centre
  *                 as above.  The two differ in summation order only (results
  *                 agree to rounding, not bitwise); every other field leaves
- *                 the results of either bitwise unchanged */
+ *                 the results of either bitwise unchanged
+ *   mlp_chain     BF16 precisions and the network shapes the chained kernel
+ *                 is built for (65 to 96 features, a multiple of 4, with
+ *                 hidden widths 128-128-64 or 64-64; else 0 only,
+ *                 PIMD_E_UNSUPPORTED):
+ *                 1 = one wave per 16 MLP
+ *                 rows with the activations kept in registers between layers
+ *                 (each GEMM taken transposed, weights as the MFMA A operand
+ *                 in a packed order); 0 (default) = activations staged in LDS,
+ *                 mlp_waves waves splitting the output columns.  The two sum
+ *                 the MFMA products in another order (results agree to
+ *                 rounding, not bitwise); within each, every other field
+ *                 leaves the results bitwise unchanged */
 typedef struct {
     int32_t centre_waves;
     int32_t centre_grid;
@@ -491,6 +503,7 @@ typedef struct {
     int32_t mlp_waves;
     int32_t force_rows;
     int32_t centre_lanes;
+    int32_t mlp_chain;
 } pimd_tuning;
 
 pimd_status pimd_get_tuning(const pimd_ctx *ctx, pimd_tuning *out);

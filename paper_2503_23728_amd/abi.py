@@ -56,7 +56,8 @@ class pimd_config(ctypes.Structure):
 class pimd_tuning(ctypes.Structure):
     _fields_ = [("centre_waves", c_int32), ("centre_grid", c_int32), ("mlp_rows", c_int32),
                 ("neighbor_cells", c_int32), ("mlp_waves", c_int32),
-                ("force_rows", c_int32), ("centre_lanes", c_int32)]
+                ("force_rows", c_int32), ("centre_lanes", c_int32),
+                ("mlp_chain", c_int32)]
 
 
 class pimd_estimates(ctypes.Structure):

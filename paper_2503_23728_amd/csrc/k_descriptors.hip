@@ -136,33 +136,39 @@ __device__ __forceinline__ void for_each_triplet_in_range(const BlockWalk &bw, c
     if (bw.s1 < bw.s0)
         return;   // fewer than two slots in a triangle, or an empty partner group
     const int lane = lane_id();
-    // the half shift of an even triangle pairs only the own slots b < s
-    const int s_half = (bw.tri && 2 * bw.s1 == bw.n_own) ? bw.s1 : -1;
+    // the half shift of an even triangle pairs only the own slots b < s; it
+    // runs after the loop so the loop itself tests no slot order
+    const bool has_half = bw.tri && 2 * bw.s1 == bw.n_own;
+    const int s_last = has_half ? bw.s1 - 1 : bw.s1;
     int qh = 0, qn = 0;   // ring head and pairs waiting (wave-uniform)
     for (int b0 = 0; b0 < bw.n_own; b0 += kWave) {
         const int b = b0 + lane;
         const bool own_ok = b < bw.n_own;
         const int bb = own_ok ? b : 0;
         const int ia = bw.o_own + bb;
-        const float4 A = recD[ia];
-        // partner slot p = (b + s) mod n_par, advanced by one per shift
+        // lanes past the own group sit far away: their test fails by distance
+        const float4 A = own_ok ? recD[ia] : make_float4(3e18f, 3e18f, 3e18f, 0.0f);
+        const uint32_t key_a = (uint32_t)ia << 16;
+        // partner slot p = (b + s) mod n_par, advanced by one per shift; its
+        // record is loaded one shift ahead
         int p = (bw.tri ? bb : bb % bw.n_par) + bw.s0;
         p -= p >= bw.n_par ? bw.n_par : 0;
-        for (int s = bw.s0; s <= bw.s1; ++s) {
+        float4 C = recD[bw.o_par + p];
+        auto test = [&](bool ok) {
             const int ic = bw.o_par + p;
-            const float4 C = recD[ic];
+            p = p + 1 == bw.n_par ? 0 : p + 1;
+            const float4 Cn = recD[bw.o_par + p];
             const float jx = C.x - A.x, jy = C.y - A.y, jz = C.z - A.z;
+            C = Cn;
             // bitwise (not short-circuit) so the test stays branch-free
-            const bool inr = own_ok & ((s != s_half) | (b < s)) & (jx * jx + jy * jy + jz * jz < rc2);
-            const uint64_t m = __ballot(inr);
+            const bool inr = ok & (jx * jx + jy * jy + jz * jz < rc2);
+            const uint64_t m = __builtin_amdgcn_ballot_w64(inr);
             if (inr) {
                 const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                queue[(qh + qn + (int)below) & (kQueue - 1)] = ((uint32_t)ia << 16) | (uint32_t)ic;
+                queue[(qh + qn + (int)below) & (kQueue - 1)] = key_a | (uint32_t)ic;
             }
             qn = __builtin_amdgcn_readfirstlane(qn + (int)__popcll(m));   // uniform: a scalar branch below
-            ++p;
-            p -= p >= bw.n_par ? bw.n_par : 0;
             if (qn >= kWave) {
                 wave_sync();
                 const uint32_t q = queue[(qh + lane) & (kQueue - 1)];
@@ -171,7 +177,11 @@ __device__ __forceinline__ void for_each_triplet_in_range(const BlockWalk &bw, c
                 qh = (qh + kWave) & (kQueue - 1);
                 qn -= kWave;
             }
-        }
+        };
+        for (int s = bw.s0; s <= s_last; ++s)
+            test(true);
+        if (has_half)
+            test(b < bw.s1);
     }
     if (qn > 0) {
         wave_sync();
@@ -179,6 +189,13 @@ __device__ __forceinline__ void for_each_triplet_in_range(const BlockWalk &bw, c
         body(q >> 16, q & 0xFFFFu, lane < qn);
         wave_sync();
     }
+}
+
+// A wave-uniform float moved to a scalar register.  The builtin takes and
+// returns int: the value passes through it as bits, not converted.
+__device__ __forceinline__ float uniform_float(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
 }
 
 __device__ __forceinline__ float block_scale(int q)
@@ -406,24 +423,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         for (int e1 = 0; e1 < dp.n_el; ++e1)
             for (int e2 = e1; e2 < dp.n_el; ++e2, ++pair) {
                 const int n_pairs_block = tri_cnt[(int64_t)i * kMaxPairs + pair];
-                // block coefficients with the 2^(1-zeta) factors folded in, and
-                // those of dS/dcos (d/dc (1 +- c)^zeta = +-zeta (1 +- c)^(zeta-1))
-                float gq[8 * NETA], gd[8 * NETA];
-#pragma unroll
-                for (int q = 0; q < 8 * NETA; ++q)
-                    gq[q] = gl[Frad + pair * dp.n_ang + q] * block_scale(q);
+                // S(c) = sum_{zeta, lambda} g 2^(1-zeta) (1 + lambda c)^zeta as a
+                // polynomial in c of degree 8, S = sum_k a_k c^k with
+                // a_k = sum_zeta C(zeta, k) 2^(1-zeta) (g_+ + (-1)^k g_-), and
+                // dS/dc = sum_k b_k c^k, b_k = (k + 1) a_{k+1}: Horner's rule
+                // in the triplet body replaces the powers of 1 +- c.  Every term
+                // of the expansion is bounded by the size of the original terms
+                // (sum_k C(zeta, k) 2^(1-zeta) = 2), so nothing cancels beyond
+                // what the sum itself does; formed in FP64, rounded once.
+                float ga[9 * NETA], gb[8 * NETA];
 #pragma unroll
                 for (int ie = 0; ie < NETA; ++ie) {
-                    const float *g = gq + 8 * ie;
-                    float *h = gd + 8 * ie;
-                    h[0] = g[0] - g[1];
-                    h[1] = 2.0f * g[2];
-                    h[2] = 2.0f * g[3];
-                    h[3] = 4.0f * g[4];
-                    h[4] = 4.0f * g[5];
-                    h[5] = 8.0f * g[6];
-                    h[6] = 8.0f * g[7];
-                    h[7] = 0.0f;
+                    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                    for (int z = 0; z < 4; ++z) {
+                        const int q = 8 * ie + 2 * z;
+                        const double gp = (double)gl[Frad + pair * dp.n_ang + q] * (double)block_scale(q);
+                        const double gm = (double)gl[Frad + pair * dp.n_ang + q + 1] * (double)block_scale(q + 1);
+                        const int zeta = 1 << z;
+                        double binom = 1.0;
+#pragma unroll
+                        for (int k = 0; k <= 8; ++k) {
+                            if (k <= zeta) {
+                                a[k] += binom * (k & 1 ? gp - gm : gp + gm);
+                                binom = binom * (double)(zeta - k) / (double)(k + 1);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 9; ++k)
+                        ga[9 * ie + k] = uniform_float((float)a[k]);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        gb[8 * ie + k] = uniform_float((float)((double)(k + 1) * a[k + 1]));
                 }
                 auto body = [&](uint32_t ia, uint32_t ic, bool ok) {
                     if (!ok)
@@ -437,12 +469,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     cutoff_fn(rjk * inv_rc, dp.pi_over_rc, fcjk, dfcjk);
                     const float iab = Ad.w * Cd.w;
                     const float cs = (Ad.x * Cd.x + Ad.y * Cd.y + Ad.z * Cd.z) * iab;
-                    const float p1 = 1.0f + cs, m1 = 1.0f - cs;
-                    const float p2 = p1 * p1, m2 = m1 * m1;
-                    const float p3 = p2 * p1, m3 = m2 * m1;
-                    const float p4 = p2 * p2, m4 = m2 * m2;
-                    const float p7 = p4 * p3, m7 = m4 * m3;
-                    const float p8 = p4 * p4, m8 = m4 * m4;
                     // per eta, with Y = exp(-eta r_jk^2) f_c(r_jk):
                     //   dE/dcos:  Sd Ea Eb Y;  dE/dr_ij: S dEa Eb Y;  dE/dr_ik: S Ea dEb Y
                     //   dE/dr_jk: S Ea Eb exp(-eta r_jk^2) (f_c' - 2 eta r_jk f_c)
@@ -455,11 +481,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     }
 #pragma unroll
                     for (int ie = 0; ie < NETA; ++ie) {
-                        const float *g = gq + ie * 8;
-                        const float *h = gd + ie * 8;
-                        const float S = g[0] * p1 + g[1] * m1 + g[2] * p2 + g[3] * m2 + g[4] * p4 + g[5] * m4 +
-                                        g[6] * p8 + g[7] * m8;
-                        const float Sd = h[0] + h[1] * p1 - h[2] * m1 + h[3] * p3 - h[4] * m3 + h[5] * p7 - h[6] * m7;
+                        const float *a = ga + 9 * ie, *b = gb + 8 * ie;
+                        float S = a[8], Sd = b[7];
+#pragma unroll
+                        for (int k = 7; k >= 0; --k)
+                            S = fmaf(S, cs, a[k]);
+#pragma unroll
+                        for (int k = 6; k >= 0; --k)
+                            Sd = fmaf(Sd, cs, b[k]);
                         const float X = ie == 0 ? X0 : X1;
                         const float Ea = ie == 0 ? Ae.x : Ae.y, Eb = ie == 0 ? Ce.x : Ce.y;
                         const float dEa = ie == 0 ? Ae.z : Ae.w, dEb = ie == 0 ? Ce.z : Ce.w;
@@ -489,10 +518,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     atomicAdd(vc + 1, (double)(kc * Cd.y + kb * Ad.y));
                     atomicAdd(vc + 2, (double)(kc * Cd.z + kb * Ad.z));
                 };
-                // the block's in-range slot pairs as the forward found them, one per lane
+                // the block's in-range slot pairs as the forward found them, one
+                // per lane; the next batch's pairs load while this one runs
+                // (clamped to the block's last pair: every lane loads, no branch)
+                const int last = n_pairs_block - 1;
+                uint32_t nxt = n_pairs_block > 0 ? kept[min(lane, last)] : 0u;
                 for (int t0 = 0; t0 < n_pairs_block; t0 += kWave) {
                     const int t = t0 + lane;
-                    const uint32_t v = t < n_pairs_block ? kept[t] : 0u;
+                    const uint32_t v = nxt;
+                    nxt = kept[min(t + kWave, last)];
                     body(v >> 8, v & 0xFFu, t < n_pairs_block);
                 }
                 kept += n_pairs_block;

@@ -322,36 +322,55 @@ __device__ __forceinline__ void gemm_bf16(const uint16_t *ahi, const uint16_t *a
 #pragma unroll
         for (int t = 0; t < CT; ++t)
             acc[r][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // weight fragments of up to four 32-deep steps are loaded together, so
+    // one latency of the (L2-resident) weights covers 4 RT MFMA groups
     int k0 = 0;
-    for (; k0 + 32 <= K; k0 += 32) {
-        i16x8 ah[RT], al[RT];
-#pragma unroll
-        for (int r = 0; r < RT; ++r) {
-            const int o = (16 * r + lr) * SB + k0 + 8 * lg;
-            ah[r] = *reinterpret_cast<const i16x8 *>(ahi + o);
-            if (split_act<MODE>())
-                al[r] = *reinterpret_cast<const i16x8 *>(alo + o);
-        }
+    for (; k0 + 32 <= K; k0 += 128) {
+        const int nsteps = min(4, (K - k0) >> 5);
+        i16x8 bh[CT][4], bl[CT][4];
 #pragma unroll
         for (int t = 0; t < CT; ++t) {
             const int ct = w + NW * t;
             if (ct < nct) {
-                const int64_t o = (int64_t)(ct * 16 + lr) * ldb + k0 + 8 * lg;
-                const i16x8 bh = *reinterpret_cast<const i16x8 *>(Bh + o);
-                i16x8 bl;
-                if (MODE == 1)
-                    bl = *reinterpret_cast<const i16x8 *>(Bl + o);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (u < nsteps) {
+                        const int64_t o = (int64_t)(ct * 16 + lr) * ldb + k0 + 32 * u + 8 * lg;
+                        bh[t][u] = *reinterpret_cast<const i16x8 *>(Bh + o);
+                        if (MODE == 1)
+                            bl[t][u] = *reinterpret_cast<const i16x8 *>(Bl + o);
+                    }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (u < nsteps) {
+                i16x8 ah[RT], al[RT];
 #pragma unroll
                 for (int r = 0; r < RT; ++r) {
-                    acc[r][t] = mfma_k32(ah[r], bh, acc[r][t]);
+                    const int o = (16 * r + lr) * SB + k0 + 32 * u + 8 * lg;
+                    ah[r] = *reinterpret_cast<const i16x8 *>(ahi + o);
                     if (split_act<MODE>())
-                        acc[r][t] = mfma_k32(al[r], bh, acc[r][t]);
-                    if (MODE == 1)
-                        acc[r][t] = mfma_k32(ah[r], bl, acc[r][t]);
+                        al[r] = *reinterpret_cast<const i16x8 *>(alo + o);
+                }
+#pragma unroll
+                for (int t = 0; t < CT; ++t) {
+                    const int ct = w + NW * t;
+                    if (ct < nct) {
+#pragma unroll
+                        for (int r = 0; r < RT; ++r) {
+                            acc[r][t] = mfma_k32(ah[r], bh[t][u], acc[r][t]);
+                            if (split_act<MODE>())
+                                acc[r][t] = mfma_k32(al[r], bh[t][u], acc[r][t]);
+                            if (MODE == 1)
+                                acc[r][t] = mfma_k32(ah[r], bl[t][u], acc[r][t]);
+                        }
+                    }
                 }
             }
         }
     }
+    k0 = K & ~31;
     if (k0 < K) {   // K is a multiple of 16: one 16-deep step remains
         i16x4 ah[RT], al[RT];
 #pragma unroll
@@ -400,7 +419,8 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_bf16(const int32_t *__restrict_
     // NW = 8: the second half of the waves hands its per-lane readout partials
     // to the first half, so the sums keep the order of the four-wave layout
     __shared__ float ehand[NW == 8 ? 4 * 64 * 4 * RT : 1];
-    const int lane = lane_id(), w = threadIdx.x >> 6;
+    // the wave index is wave-uniform: column-tile tests become scalar branches
+    const int lane = lane_id(), w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lr = lane & 15, lg = lane >> 4;
     const MlpTile tile = tiles[blockIdx.x];
     const MlpNet &net = nets.net[tile.e];
@@ -714,6 +734,271 @@ __global__ __launch_bounds__(256) void k_mlp_f64(const int32_t *__restrict__ row
     }
 }
 
+// ---------------------------------------------------------------------------
+// Register-chained BF16 MLP (modes 1, 2, 4): one wave per 16 rows of one
+// element; activations never leave the registers and no wave waits for
+// another.  Every GEMM is taken transposed, Y^T = W X^T: the weights are the
+// A operand (its rows are output features) and the wave's 16 rows are the
+// columns of the B operand.  The MFMA result of a 16-feature output tile
+// leaves features 4g .. 4g+3 of row r in lane (r, g) (r = lane mod 16,
+// g = lane / 16); two output tiles 2b and 2b+1 thus give lane (r, g) the eight
+// features {32b + 4g + j, 32b + 16 + 4g + j : j < 4}, which is a B operand of
+// a 32-deep k-step when the step's k index runs over the features in that
+// order.  The weight fragments are packed on the host in the same order (one
+// 16-byte fragment per lane per output tile and k-step), so the tanh outputs
+// of a layer, split into bfloat16 parts in place, are the next layer's
+// operand.  The backward chain is the same with W^T as the A operand, and
+// (1 - h^2) of every layer stays in registers in the output layout.
+// Fragments are read from global memory (a few hundred kB per element,
+// L2-resident).  Limits: widths and D at most 128, D a multiple of 4.
+constexpr int kChainTiles = 8;   // output tiles of 16 features
+constexpr int kChainSteps = 4;   // 32-deep k-steps
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two floats as nearest-even bfloat16 values, the first in the low half.
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+
+// Four values of one output tile into the k-step operand words: half 0 or 1
+// of block b (elements 4 half .. 4 half + 3), hi parts and, when split, the
+// bfloat16 remainders v - hi.
+template <bool SPLIT>
+__device__ __forceinline__ void chain_put(const f32x4 &v, int half, u32x4 &xh, u32x4 &xl)
+{
+    const uint32_t h0 = pack_bf16x2(v[0], v[1]), h1 = pack_bf16x2(v[2], v[3]);
+    if (half == 0) {
+        xh[0] = h0;
+        xh[1] = h1;
+    } else {
+        xh[2] = h0;
+        xh[3] = h1;
+    }
+    if (SPLIT) {
+        const uint32_t l0 = pack_bf16x2(v[0] - __uint_as_float(h0 << 16), v[1] - __uint_as_float(h0 & 0xFFFF0000u));
+        const uint32_t l1 = pack_bf16x2(v[2] - __uint_as_float(h1 << 16), v[3] - __uint_as_float(h1 & 0xFFFF0000u));
+        if (half == 0) {
+            xl[0] = l0;
+            xl[1] = l1;
+        } else {
+            xl[2] = l0;
+            xl[3] = l1;
+        }
+    }
+}
+
+__device__ __forceinline__ i16x8 as_op(const u32x4 &v) { return __builtin_bit_cast(i16x8, v); }
+
+
+// acc[o] = sum over the KB k-steps of fragment (o, b) x operand b, o < OT.
+// The fragments of step b + 1 are loaded while step b's MFMAs run (two
+// buffers); scheduling barriers keep the compiler from hoisting further
+// loads, which would hold every fragment of the layer in registers.
+template <int MODE, int OT, int KB>
+__device__ __forceinline__ void chain_load(const uint16_t *__restrict__ F, const uint16_t *__restrict__ Flo, int b,
+                                           i16x8 (&fh)[OT], i16x8 (&fl)[OT])
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 0; o < OT; ++o) {
+        const int64_t at = ((int64_t)(o * KB + b) * 64 + lane) * 8;
+        fh[o] = *reinterpret_cast<const i16x8 *>(F + at);
+        if (MODE == 1)
+            fl[o] = *reinterpret_cast<const i16x8 *>(Flo + at);
+    }
+}
+
+template <int MODE, int OT, int KB>
+__device__ __forceinline__ void chain_gemm(const uint16_t *__restrict__ F, const uint16_t *__restrict__ Flo,
+                                           const u32x4 (&xh)[kChainSteps], const u32x4 (&xl)[kChainSteps],
+                                           f32x4 (&acc)[kChainTiles])
+{
+#pragma unroll
+    for (int o = 0; o < OT; ++o)
+        acc[o] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    i16x8 fh[2][OT], fl[2][OT];
+    chain_load<MODE, OT, KB>(F, Flo, 0, fh[0], fl[0]);
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+        if (b + 1 < KB)
+            chain_load<MODE, OT, KB>(F, Flo, b + 1, fh[(b + 1) & 1], fl[(b + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int o = 0; o < OT; ++o) {
+            const i16x8 a = fh[b & 1][o];
+            acc[o] = mfma_k32(a, as_op(xh[b]), acc[o]);
+            if (split_act<MODE>())
+                acc[o] = mfma_k32(a, as_op(xl[b]), acc[o]);
+            if (MODE == 1)
+                acc[o] = mfma_k32(fl[b & 1][o], as_op(xh[b]), acc[o]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Output tiles 0 .. OT-1 of acc (times s, when given) into the operand of the
+// next GEMM: k-steps 0 .. (OT+1)/2 - 1, the half of an odd last step zeroed.
+template <bool SPLIT, int OT>
+__device__ __forceinline__ void chain_operand(const f32x4 (&v)[kChainTiles], u32x4 (&xh)[kChainSteps],
+                                              u32x4 (&xl)[kChainSteps])
+{
+#pragma unroll
+    for (int o = 0; o < OT; ++o)
+        chain_put<SPLIT>(v[o], o & 1, xh[o >> 1], xl[o >> 1]);
+    if (OT & 1)
+        chain_put<SPLIT>(f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 1, xh[OT >> 1], xl[OT >> 1]);
+}
+
+// One wave per 16 rows; the network shape is compile-time: D in KB0 32-deep
+// steps, hidden widths H1, H2 and H3 (H3 = 0: two hidden layers).
+// Two waves per SIMD where the registers allow it (the three-product mode,
+// with both weight parts in flight, would spill).
+template <int MODE, int KB0, int H1, int H2, int H3>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? 1 : 2))) void k_mlp_chain(const int32_t *__restrict__ rows,
+                                                   const MlpTile *__restrict__ tiles,
+                                                   const float *__restrict__ xhat, int D, MlpNets nets,
+                                                   float *__restrict__ E_atom, float *__restrict__ dEdG)
+{
+    constexpr bool SPLIT = split_act<MODE>();
+    constexpr int NH = H3 ? 3 : 2;
+    constexpr int OT1 = H1 / 16, OT2 = H2 / 16, OT3 = H3 / 16;
+    constexpr int OTL = NH == 3 ? OT3 : OT2;   // tiles of the last hidden layer
+    constexpr int KB1 = (OT1 + 1) / 2, KB2 = (OT2 + 1) / 2, KB3 = (OT3 + 1) / 2;
+    constexpr int OTD = KB0 * 2;               // tiles of dE/dx (features >= D are dropped)
+    const int lane = lane_id(), w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r = lane & 15, g = lane >> 4;
+    const MlpTile tile = tiles[blockIdx.x];
+    const int nrw = min(16, tile.nrows - 16 * w);   // rows of this wave
+    if (nrw <= 0)
+        return;
+    const MlpNet &net = nets.net[tile.e];
+    const bool row_ok = r < nrw;
+    const int64_t row = row_ok ? (int64_t)rows[tile.row0 + 16 * w + r] : 0;
+
+    u32x4 xh[kChainSteps], xl[kChainSteps];
+    f32x4 acc[kChainTiles];   // GEMM results, overwritten in place by h, g and their products
+    f32x4 ds1[kChainTiles], ds2[kChainTiles], ds3[kChainTiles];
+    // input operand: features {32b + 4g + j, 32b + 16 + 4g + j} of the lane's row
+#pragma unroll
+    for (int b = 0; b < KB0; ++b)
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int f = 32 * b + 16 * half + 4 * g;
+            f32x4 v = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (row_ok && f < D)
+                v = *reinterpret_cast<const f32x4 *>(xhat + row * D + f);
+            chain_put<SPLIT>(v, half, xh[b], xl[b]);
+        }
+    float e_part = 0.0f;
+    // forward: h = tanh(W x + b), ds = 1 - h^2; the last layer's h feeds the readout
+    auto layer = [&](const MlpLayer &L, auto OTc, f32x4 (&ds)[kChainTiles], bool last) {
+        constexpr int OT = decltype(OTc)::value;
+#pragma unroll
+        for (int o = 0; o < OT; ++o) {
+            const f32x4 bias = *reinterpret_cast<const f32x4 *>(L.b + 16 * o + 4 * g);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                // tanh and sech^2 from e = exp(-2|z|), as in k_mlp_bf16
+                const float z = acc[o][j] + bias[j];
+                const float e = __builtin_amdgcn_exp2f(-2.8853900817779268f * fabsf(z));
+                const float rope = __builtin_amdgcn_rcpf(1.0f + e);
+                acc[o][j] = copysignf((1.0f - e) * rope, z);
+                ds[o][j] = 4.0f * e * rope * rope;
+            }
+            if (last) {
+                const f32x4 wo = *reinterpret_cast<const f32x4 *>(net.wo + 16 * o + 4 * g);
+                e_part += (acc[o][0] * wo[0] + acc[o][1] * wo[1]) + (acc[o][2] * wo[2] + acc[o][3] * wo[3]);
+            }
+        }
+    };
+    chain_gemm<MODE, OT1, KB0>(net.layer[0].Wc, net.layer[0].Wc_lo, xh, xl, acc);
+    layer(net.layer[0], std::integral_constant<int, OT1>{}, ds1, false);
+    chain_operand<SPLIT, OT1>(acc, xh, xl);
+    chain_gemm<MODE, OT2, KB1>(net.layer[1].Wc, net.layer[1].Wc_lo, xh, xl, acc);
+    layer(net.layer[1], std::integral_constant<int, OT2>{}, ds2, NH == 2);
+    if constexpr (NH == 3) {
+        chain_operand<SPLIT, OT2>(acc, xh, xl);
+        chain_gemm<MODE, OT3, KB2>(net.layer[2].Wc, net.layer[2].Wc_lo, xh, xl, acc);
+        layer(net.layer[2], std::integral_constant<int, OT3>{}, ds3, true);
+    }
+    // energy: the four lane groups of a row hold disjoint features
+    e_part += __shfl_xor(e_part, 16);
+    e_part += __shfl_xor(e_part, 32);
+    if (g == 0 && row_ok)
+        E_atom[row] = e_part + net.bo;
+    // g_L = w_o (1 - h_L^2); g_{l-1} = (W_l^T g_l)(1 - h_{l-1}^2); dE/dx = W_1^T g_1
+    const f32x4(&dsL)[kChainTiles] = NH == 3 ? ds3 : ds2;
+#pragma unroll
+    for (int o = 0; o < OTL; ++o) {
+        const f32x4 wo = *reinterpret_cast<const f32x4 *>(net.wo + 16 * o + 4 * g);
+        acc[o] = wo * dsL[o];
+    }
+    chain_operand<SPLIT, OTL>(acc, xh, xl);
+    if constexpr (NH == 3) {
+        chain_gemm<MODE, OT2, KB3>(net.layer[2].WTc, net.layer[2].WTc_lo, xh, xl, acc);
+#pragma unroll
+        for (int o = 0; o < OT2; ++o)
+            acc[o] *= ds2[o];
+        chain_operand<SPLIT, OT2>(acc, xh, xl);
+    }
+    chain_gemm<MODE, OT1, KB2>(net.layer[1].WTc, net.layer[1].WTc_lo, xh, xl, acc);
+#pragma unroll
+    for (int o = 0; o < OT1; ++o)
+        acc[o] *= ds1[o];
+    chain_operand<SPLIT, OT1>(acc, xh, xl);
+    chain_gemm<MODE, OTD, KB1>(net.layer[0].WTc, net.layer[0].WTc_lo, xh, xl, acc);
+    if (row_ok) {
+#pragma unroll
+        for (int o = 0; o < OTD; ++o) {
+            const int f = 16 * o + 4 * g;
+            if (f < D) {
+                const f32x4 is = *reinterpret_cast<const f32x4 *>(net.inv_scale + f);
+                *reinterpret_cast<f32x4 *>(dEdG + row * D + f) = acc[o] * is;
+            }
+        }
+    }
+}
+
+// Network shapes with a chained kernel: (32-deep steps of D, hidden widths).
+struct ChainShape {
+    int kb0, h1, h2, h3;
+};
+constexpr ChainShape kChainShapes[] = {{3, 128, 128, 64}, {3, 64, 64, 0}};
+
+bool mlp_chain_shape(int D, int n_hidden, const int *hidden)
+{
+    if (D % 4 != 0 || n_hidden < 2 || n_hidden > 3)
+        return false;
+    for (const ChainShape &c : kChainShapes)
+        if ((D + 31) / 32 == c.kb0 && hidden[0] == c.h1 && hidden[1] == c.h2 &&
+            (n_hidden == 3 ? hidden[2] == c.h3 : c.h3 == 0))
+            return true;
+    return false;
+}
+
+// Launches the instantiation of the nets' shape; false when there is none.
+template <int MODE>
+static bool launch_mlp_chain(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int rows, hipStream_t s)
+{
+    const MlpNet &n = nets.net[0];
+    if (!n.layer[0].Wc)
+        return false;
+    const int kb0 = (D + 31) / 32, h1 = n.layer[0].out, h2 = n.layer[1].out, h3 = n.n_hidden == 3 ? n.layer[2].out : 0;
+    if (kb0 == 3 && h1 == 128 && h2 == 128 && h3 == 64)
+        hipLaunchKernelGGL((k_mlp_chain<MODE, 3, 128, 128, 64>), dim3(n_tiles), dim3(4 * rows), 0, s, d.elem_rows,
+                           d.mlp_tiles, d.xhat, D, nets, d.E_atom, d.dEdG);
+    else if (kb0 == 3 && h1 == 64 && h2 == 64 && h3 == 0)
+        hipLaunchKernelGGL((k_mlp_chain<MODE, 3, 64, 64, 0>), dim3(n_tiles), dim3(4 * rows), 0, s, d.elem_rows,
+                           d.mlp_tiles, d.xhat, D, nets, d.E_atom, d.dEdG);
+    else
+        return false;
+    return true;
+}
+
 static void launch_mlp_fp32(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int rows,
                             hipStream_t s)
 {
@@ -744,9 +1029,15 @@ static void launch_mlp_bf16(const DevBuffers &d, const MlpNets &nets, int n_tile
 }
 
 void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int mlp_mode, int rows,
-                int waves, hipStream_t s)
+                int waves, bool chain, hipStream_t s)
 {
     if (n_tiles <= 0)
+        return;
+    if (chain && mlp_mode == 4 && launch_mlp_chain<4>(d, nets, n_tiles, D, rows, s))
+        return;
+    if (chain && mlp_mode == 1 && launch_mlp_chain<1>(d, nets, n_tiles, D, rows, s))
+        return;
+    if (chain && mlp_mode == 2 && launch_mlp_chain<2>(d, nets, n_tiles, D, rows, s))
         return;
     if (mlp_mode == 3)
         hipLaunchKernelGGL(k_mlp_f64, dim3(n_tiles), dim3(256), 0, s, d.elem_rows, d.mlp_tiles, d.xhat, D, Dp, nets,

@@ -50,6 +50,8 @@ struct Plan {
     std::vector<int> cells_per_sys;            // cells per bead of each system
     std::vector<std::array<int, 3>> nc;
     size_t mlp_f32_floats = 0, mlp_bf16_elems = 0, mlp_f64_elems = 0, cmat_elems = 0, modes = 0;
+    bool chain = false;                        // register-chained BF16 MLP available (widths, D <= 128)
+    size_t mlp_chain_elems = 0;                // its packed weight fragments (bfloat16, hi and lo)
     std::vector<int> distinct_P;
     bool any_box = false;                      // some system has a box (metadynamics minimum image)
     bool metad = false;                        // well-tempered metadynamics bias
@@ -294,14 +296,20 @@ pimd_status validate(const pimd_config *cfg, Plan &pl, std::string *err)
         pl.cmat_elems += 2 * (size_t)P + 2;
     if (pl.bpnn) {
         int in = pl.Dp;
+        pl.chain = mlp_chain_shape(pl.D, m->n_hidden, m->hidden);
         for (int e = 0; e < pl.n_el; ++e) {
             in = pl.Dp;
+            int in_c = pl.D;
             for (int l = 0; l < m->n_hidden; ++l) {
                 const int out = m->hidden[l];
                 pl.mlp_f32_floats += 2 * (size_t)out * in + out;
                 pl.mlp_bf16_elems += 4 * (size_t)out * in;
                 pl.mlp_f64_elems += 2 * (size_t)out * in;
+                if (pl.chain)   // W: out/16 tiles x ceil(in/32) steps; W^T: 2 ceil(in/32) tiles x ceil(out/32) steps
+                    pl.mlp_chain_elems += 2 * (size_t)kWave * 8 *
+                                          ((size_t)(out / 16) * ((in_c + 31) / 32) + (size_t)(2 * ((in_c + 31) / 32)) * ((out + 31) / 32));
                 in = out;
+                in_c = out;
             }
             pl.mlp_f32_floats += in;
         }
@@ -418,6 +426,8 @@ Layout make_layout(const Plan &pl)
         L.add("mlp_f32", pl.mlp_f32_floats * 4);
         L.add("mlp_bf16", pl.mlp_bf16_elems * 2);
         L.add("mlp_f64", pl.mlp_f64_elems * 8);
+        if (pl.chain)
+            L.add("mlp_chain", pl.mlp_chain_elems * 2);
         L.add("norm", (size_t)pl.n_el * 2 * D * 4);
         L.add("elem_rows", B * 4);
         L.add("mlp_tiles", (B / 16 + kMaxElements + 1) * sizeof(MlpTile));
@@ -590,8 +600,7 @@ void launch_force_stage(pimd_ctx *c, int stage, const float *q, float *E_out, fl
         if (c->pl.bpnn)
             launch_mlp(d, c->nets, c->n_mlp_tiles, c->pl.D, c->pl.Dp,
                        c->precision == PIMD_PREC_BF16_MLP && c->mlp_weights_bf16 ? 4 : c->precision, c->tn.mlp_rows,
-                       c->tn.mlp_waves,
-                       s);
+                       c->tn.mlp_waves, c->tn.mlp_chain != 0, s);
         break;
     case 3:
         if (c->pl.gfn) {
@@ -851,6 +860,7 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     d.mlp_f32 = (float *)at("mlp_f32");
     d.mlp_bf16 = (uint16_t *)at("mlp_bf16");
     d.mlp_f64 = (double *)at("mlp_f64");
+    d.mlp_chain = pl.chain ? (uint16_t *)at("mlp_chain") : nullptr;
     d.norm = (float *)at("norm");
     d.elem_rows = (int32_t *)at("elem_rows");
     d.mlp_tiles = (MlpTile *)at("mlp_tiles");
@@ -1204,9 +1214,41 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         push(d.norm, norm.data(), norm.size() * 4);
         // weights: f32 W[out][in_pad], WT[in_pad][out], b[out] per layer, then w_out; bf16 W, WT
         std::vector<float> wf;
-        std::vector<uint16_t> wb;
+        std::vector<uint16_t> wb, wc;
         std::vector<double> w64;
         const float *src = m->params;
+        // Fragments of the register-chained MLP: A operands of the 16 x 16 x 32
+        // MFMA, one 16-byte run of eight bfloat16 values per lane, for output
+        // tile o (rows 16 o + lane mod 16) and k-step b; the k index of lane
+        // group g runs over the features 32 b + 4 g + j, then 32 b + 16 + 4 g + j
+        // (j < 4), the order in which a layer's output tiles leave them.
+        // value(row, k) gives the matrix entry, zero outside it; hi and lo
+        // (the bfloat16 remainder) parts.  Returns the offset of the hi part.
+        // The row tiles of W^T (input features) are padded to whole 32-feature
+        // steps, as the kernel's last GEMM takes them (rows_to32).
+        auto pack_chain = [&](int n_rows, int n_k, bool rows_to32, auto value, size_t &lo_at) {
+            const int OT = rows_to32 ? 2 * ((n_rows + 31) / 32) : (n_rows + 15) / 16, KB = (n_k + 31) / 32;
+            const size_t n = (size_t)OT * KB * kWave * 8, hi_at = wc.size();
+            wc.resize(hi_at + 2 * n, 0);
+            lo_at = hi_at + n;
+            for (int o = 0; o < OT; ++o)
+                for (int b = 0; b < KB; ++b)
+                    for (int lane = 0; lane < kWave; ++lane)
+                        for (int j = 0; j < 8; ++j) {
+                            const int row = 16 * o + (lane & 15), g = lane >> 4;
+                            const int k = 32 * b + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+                            const float v = (row < n_rows && k < n_k) ? value(row, k) : 0.0f;
+                            const size_t at = (((size_t)o * KB + b) * kWave + lane) * 8 + j;
+                            const uint16_t h = bf16_bits(v);
+                            uint32_t u = (uint32_t)h << 16;
+                            float hv;
+                            std::memcpy(&hv, &u, 4);
+                            wc[hi_at + at] = h;
+                            wc[lo_at + at] = bf16_bits(v - hv);
+                        }
+            return hi_at;
+        };
+        std::vector<std::array<size_t, 4>> chain_at;   // per (element, layer): W hi, W lo, WT hi, WT lo
         for (int e = 0; e < pl.n_el; ++e) {
             MlpNet net{};
             net.n_hidden = m->n_hidden;
@@ -1243,6 +1285,14 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
                 size_t bW, bWl, bWT, bWTl;
                 split(oW, bW, bWl);
                 split(oWT, bWT, bWTl);
+                if (pl.chain) {
+                    const float *Wl = wf.data() + oW;   // [out][in_pad]
+                    const int ip = in_pad;
+                    std::array<size_t, 4> at{};
+                    at[0] = pack_chain(out, in, false, [&](int o, int k) { return Wl[(size_t)o * ip + k]; }, at[1]);
+                    at[2] = pack_chain(in, out, true, [&](int k, int o) { return Wl[(size_t)o * ip + k]; }, at[3]);
+                    chain_at.push_back(at);
+                }
                 const size_t dW = w64.size();
                 for (size_t t = 0; t < (size_t)out * in_pad; ++t)
                     w64.push_back((double)wf[oW + t]);
@@ -1259,6 +1309,13 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
                 Ly.WTb_lo = d.mlp_bf16 + bWTl;
                 Ly.W64 = d.mlp_f64 + dW;
                 Ly.WT64 = d.mlp_f64 + dWT;
+                if (pl.chain) {
+                    const std::array<size_t, 4> &at = chain_at.back();
+                    Ly.Wc = d.mlp_chain + at[0];
+                    Ly.Wc_lo = d.mlp_chain + at[1];
+                    Ly.WTc = d.mlp_chain + at[2];
+                    Ly.WTc_lo = d.mlp_chain + at[3];
+                }
                 Ly.in_pad = in_pad;
                 Ly.out = out;
                 in = out;
@@ -1275,6 +1332,13 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
         }
         push(d.mlp_f32, wf.data(), wf.size() * 4);
         push(d.mlp_bf16, wb.data(), wb.size() * 2);
+        if (pl.chain) {
+            if (wc.size() != pl.mlp_chain_elems) {   // the layout and the packing disagree
+                delete c;
+                return fail(&g_init_error, PIMD_E_DEVICE, "internal: chained MLP fragment count");
+            }
+            push(d.mlp_chain, wc.data(), wc.size() * 2);
+        }
         // weights that are bfloat16 values already leave every lo part zero: the
         // split BF16 mode then needs two products per term instead of three
         c->mlp_weights_bf16 = true;
@@ -2002,8 +2066,15 @@ pimd_status pimd_get_tuning(const pimd_ctx *ctx, pimd_tuning *out)
     if (!ctx || !out)
         return PIMD_E_ARG;
     *out = pimd_tuning{ctx->tn.centre_waves, ctx->tn.centre_grid, ctx->tn.mlp_rows, ctx->tn.nl_cells,
-                       ctx->tn.mlp_waves, ctx->tn.force_rows, ctx->tn.centre_lanes};
+                       ctx->tn.mlp_waves, ctx->tn.force_rows, ctx->tn.centre_lanes, ctx->tn.mlp_chain};
     return PIMD_OK;
+}
+
+// The register-chained MLP: a BF16 precision and a model within its limits.
+static bool chain_ok(const pimd_ctx *ctx)
+{
+    return ctx->pl.bpnn && ctx->pl.chain &&
+           (ctx->precision == PIMD_PREC_BF16_MLP || ctx->precision == PIMD_PREC_BF16_PLAIN);
 }
 
 static pimd_status apply_tuning(pimd_ctx *ctx, const Tuning &tn)
@@ -2036,10 +2107,15 @@ pimd_status pimd_set_tuning(pimd_ctx *ctx, const pimd_tuning *t)
     const bool rows_ok = t->mlp_rows == 16 || t->mlp_rows == 32 || t->mlp_rows == 64;
     if (!waves_ok || !rows_ok || t->centre_grid < 0 || (t->neighbor_cells != 0 && t->neighbor_cells != 1) ||
         (t->mlp_waves != 4 && t->mlp_waves != 8) || (t->force_rows != 0 && t->force_rows != 1) ||
-        (t->centre_lanes != 0 && t->centre_lanes != 1)) {
+        (t->centre_lanes != 0 && t->centre_lanes != 1) || (t->mlp_chain != 0 && t->mlp_chain != 1)) {
         ctx->err = "tuning: centre_waves in {1, 2, 4}, centre_grid >= 0, mlp_rows in {16, 32, 64}, "
-                   "neighbor_cells in {0, 1}, mlp_waves in {4, 8}, force_rows in {0, 1}, centre_lanes in {0, 1}";
+                   "neighbor_cells in {0, 1}, mlp_waves in {4, 8}, force_rows in {0, 1}, centre_lanes in {0, 1}, "
+                   "mlp_chain in {0, 1}";
         return PIMD_E_ARG;
+    }
+    if (t->mlp_chain && !chain_ok(ctx)) {
+        ctx->err = "mlp_chain = 1 needs a BF16 MLP of a shape the chained kernel is built for";
+        return PIMD_E_UNSUPPORTED;
     }
     if (t->centre_lanes && !ctx->pl.small) {
         ctx->err = "centre_lanes = 1 needs G4 molecules without a box of at most 16 atoms each";
@@ -2050,7 +2126,7 @@ pimd_status pimd_set_tuning(pimd_ctx *ctx, const pimd_tuning *t)
         return PIMD_E_UNSUPPORTED;
     }
     return apply_tuning(ctx, Tuning{t->centre_waves, t->centre_grid, t->mlp_rows, t->neighbor_cells, t->mlp_waves,
-                                    t->force_rows, t->centre_lanes});
+                                    t->force_rows, t->centre_lanes, t->mlp_chain});
 }
 
 // Mean milliseconds of one force evaluation of the current positions.
@@ -2147,6 +2223,16 @@ pimd_status pimd_autotune(pimd_ctx *ctx, int32_t n_reps, pimd_tuning *best)
             cand.mlp_waves = 12 - top.mlp_waves;
             if ((st = consider(cand)) != PIMD_OK)
                 return st;
+        }
+        if (chain_ok(ctx)) {
+            const int other = 1 - top.mlp_chain;   // the other MLP kernel, at each tile size
+            for (int rows : {16, 32, 64}) {
+                Tuning cand = top;
+                cand.mlp_chain = other;
+                cand.mlp_rows = rows;
+                if ((st = consider(cand)) != PIMD_OK)
+                    return st;
+            }
         }
         if (ctx->z.any_periodic) {
             Tuning cand = top;

@@ -68,6 +68,8 @@ struct MlpLayer {
     const uint16_t *WTb;
     const uint16_t *Wb_lo; // ... and of the rounding remainders W - bf16(W)
     const uint16_t *WTb_lo;
+    const uint16_t *Wc, *Wc_lo;   // fragments of W and W^T for the register-chained BF16 kernel
+    const uint16_t *WTc, *WTc_lo; // (hi and lo parts; null when the model exceeds its limits)
     const double *W64;     // FP64 copies of W and WT
     const double *WT64;
     const float *b;        // [out]
@@ -213,6 +215,7 @@ struct DevBuffers {
     int32_t *col_sys;              // [ncol] system of each column
     float *mlp_f32;                // packed f32 weights (W, WT, b, wo per element)
     uint16_t *mlp_bf16;            // packed bf16 weights (W, WT per element)
+    uint16_t *mlp_chain;           // MFMA fragments of W and W^T for the register-chained MLP (or null)
     double *mlp_f64;               // packed f64 weights (W, WT per element)
     float *norm;                   // [n_el][2][D] shift, 1/scale
     float *gfn_params;             // direct-force head: packed weights
@@ -244,6 +247,8 @@ struct Tuning {
     int32_t force_rows;    // 1: the adjoint also stores each slot value at the neighbour's reverse slot and the
                            // force assembly reads rows; 0: the assembly gathers through the reverse-slot search
     int32_t centre_lanes;  // 1: small molecules, one lane per centre (whole beads per wave); 0: one wave per centre
+    int32_t mlp_chain;     // BF16 MLP: 1 activations kept in registers between layers (a wave per 16 rows),
+                           // 0 activations staged in LDS (mlp_waves waves split the output columns)
 };
 
 // Workgroups of a per-centre launch over B centres.
@@ -283,10 +288,14 @@ void launch_cell_scan(const DevBuffers &d, const Sizes &z, hipStream_t s);
 void launch_cell_fill(const DevBuffers &d, const Sizes &z, hipStream_t s);
 void launch_neighbors(const DevBuffers &d, const Sizes &z, float rc2, int n_el, const Tuning &tn, hipStream_t s);
 void launch_descriptors(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s);
-// mlp_mode: 0 FP32 operands; 1 BF16 operands, three-term split; 2 BF16 operands, one term; 3 FP64
-// rows: rows per tile of d.mlp_tiles (16, 32 or 64; mode 3 takes 16 only); waves: 4 or 8 (BF16 modes)
+// mlp_mode: 0 FP32 operands; 1 BF16 operands, three-term split; 2 BF16 operands, one term; 3 FP64;
+// 4 BF16 split activations on bfloat16-valued weights
+// rows: rows per tile of d.mlp_tiles (16, 32 or 64; mode 3 takes 16 only); waves: 4 or 8 (BF16 modes);
+// chain: the register-chained kernel (modes 1, 2, 4; the nets' chain fragments must exist)
 void launch_mlp(const DevBuffers &d, const MlpNets &nets, int n_tiles, int D, int Dp, int mlp_mode, int rows,
-                int waves, hipStream_t s);
+                int waves, bool chain, hipStream_t s);
+// The register-chained kernel exists for this network shape (features, hidden widths).
+bool mlp_chain_shape(int D, int n_hidden, const int *hidden);
 void launch_adjoint(const DevBuffers &d, const Sizes &z, const DescParams &dp, const Tuning &tn, hipStream_t s);
 void launch_gfn_layers(const DevBuffers &d, const Sizes &z, const DescParams &dp, const GfnParams &gp,
                        const Tuning &tn, hipStream_t s);

@@ -12,7 +12,8 @@ import hashlib
 import json
 import os
 
-FIELDS = ("centre_waves", "centre_grid", "mlp_rows", "neighbor_cells", "mlp_waves", "force_rows", "centre_lanes")
+FIELDS = ("centre_waves", "centre_grid", "mlp_rows", "neighbor_cells", "mlp_waves", "force_rows", "centre_lanes",
+          "mlp_chain")
 
 
 def cache_path():

@@ -170,11 +170,13 @@ def test_fp32_energy_forces_virial(name, prec):
     assert we < 1e-4
 
 
+@pytest.mark.parametrize("chain", [0, 1])
 @pytest.mark.parametrize("name", ["water64-P32", "ice96-P32", "fad-P4"])
-def test_bf16_mlp_forces(name):
+def test_bf16_mlp_forces(name, chain):
     wl = WORKLOADS[name]()
-    say(f"bf16 forces {name}")
+    say(f"bf16 forces {name} mlp_chain {chain}")
     eng = _engine(wl, precision="bf16")
+    eng.set_tuning(mlp_chain=chain)
     q = _q(wl, seed=6)
     E, F, _ = eng.energy_forces(torch.from_numpy(q).cuda())
     E_ref, F_ref, _, A = _oracle_beads(wl, q)
@@ -187,17 +189,19 @@ FLOAT32_WEIGHTS = {"water64-P32": lambda: S.workload(2, bf16_weights=False),
                    "fad-P4": lambda: S.small_workload("fad", n_beads=4, bf16_weights=False)}
 
 
+@pytest.mark.parametrize("chain", [0, 1])
 @pytest.mark.parametrize("name", list(FLOAT32_WEIGHTS))
-def test_bf16_split_with_float32_valued_weights(name):
+def test_bf16_split_with_float32_valued_weights(name, chain):
     # the synthetic weights are bfloat16 values, so the split mode multiplies
     # two activation parts by one weight part; weights with float32 mantissas
     # (a model trained in FP32) make it split the weights too (three products)
     wl = FLOAT32_WEIGHTS[name]()
     assert any(np.any(W.view(np.uint32) & 0xFFFF) for layers in wl.model.weights for W, _ in layers)
-    say(f"bf16 split, float32-valued weights {name}")
+    say(f"bf16 split, float32-valued weights {name}, mlp_chain {chain}")
     q = _q(wl, seed=6)
     E_ref, F_ref, _, A = _oracle_beads(wl, q)
     eng = _engine(wl, precision="bf16")
+    eng.set_tuning(mlp_chain=chain)
     E, F, _ = eng.energy_forces(torch.from_numpy(q).cuda())
     fe = force_error(F.cpu().numpy(), F_ref)
     ee = energy_error(E.cpu().numpy(), E_ref, A)
@@ -206,13 +210,15 @@ def test_bf16_split_with_float32_valued_weights(name):
     eng.close()
 
 
+@pytest.mark.parametrize("chain", [0, 1])
 @pytest.mark.parametrize("name", ["water64-P32", "fad-P4"])
-def test_bf16_plain_mlp_matches_its_emulation(name):
+def test_bf16_plain_mlp_matches_its_emulation(name, chain):
     # one-term BF16 operands: compared with the oracle's BF16-operand emulation
     # (which carries the same roundings), and its error against FP64 reported
     wl = WORKLOADS[name]()
-    say(f"bf16-plain forces {name}")
+    say(f"bf16-plain forces {name} mlp_chain {chain}")
     eng = _engine(wl, precision="bf16-plain")
+    eng.set_tuning(mlp_chain=chain)
     q = _q(wl, seed=6)
     _, F, _ = eng.energy_forces(torch.from_numpy(q).cuda())
     F = F.cpu().numpy()
@@ -399,12 +405,14 @@ def test_every_launch_shape_gives_bitwise_identical_results(name, prec):
     say(f"launch shapes {name} {prec}")
     eng = _engine(wl, precision=prec)
     q = torch.from_numpy(_q(wl, seed=9)).cuda()
-    # molecules without a box: every shape within each of the two kernel
-    # families (lane per centre, wave per centre); the families agree to rounding
+    # every shape within each kernel family: lane or wave per centre (molecules
+    # without a box), and the register-chained or LDS-staged BF16 MLP; the
+    # families agree to rounding
     lanes_modes = (1, 0) if eng.get_tuning()["centre_lanes"] else (0,)
+    chain_modes = (0, 1) if prec == "bf16" else (0,)
     first = None
-    for lanes in lanes_modes:
-        eng.set_tuning(centre_lanes=lanes, centre_waves=4, centre_grid=0, mlp_rows=32)
+    for lanes, chain in [(a, b) for a in lanes_modes for b in chain_modes]:
+        eng.set_tuning(centre_lanes=lanes, mlp_chain=chain, centre_waves=4, centre_grid=0, mlp_rows=32)
         E0, F0, W0 = eng.energy_forces(q, virial=True)
         x0 = eng.debug_descriptors()
         if first is None:
@@ -426,7 +434,7 @@ def test_every_launch_shape_gives_bitwise_identical_results(name, prec):
                     eng.set_tuning(centre_waves=waves, centre_grid=grid, mlp_rows=rows, neighbor_cells=cells,
                                    mlp_waves=mw, force_rows=fr)
                     E, F, W = eng.energy_forces(q, virial=True)
-                    shape = (lanes, waves, grid, rows, cells, mw, fr)
+                    shape = (lanes, chain, waves, grid, rows, cells, mw, fr)
                     assert torch.equal(E, E0) and torch.equal(F, F0) and torch.equal(W, W0), shape
                     assert torch.equal(eng.debug_descriptors(), x0), shape
 
@@ -445,8 +453,14 @@ def test_autotune_picks_a_valid_shape_and_the_cache_reapplies_it(tmp_path, monke
     assert shape["centre_waves"] in (1, 2, 4) and shape["mlp_rows"] in (16, 32, 64) and shape["centre_grid"] >= 0
     assert shape["neighbor_cells"] in (0, 1) and shape["mlp_waves"] in (4, 8) and shape["force_rows"] in (0, 1)
     # the state does not move and the forces are those of the same positions
+    # (bitwise within a kernel family; the chained and LDS-staged MLPs sum in
+    # another order)
     _, _, F_after, step1 = a.get_state()
-    assert step1 == step0 and torch.equal(F_before, F_after)
+    assert step1 == step0
+    if shape["mlp_chain"] == 0:
+        assert torch.equal(F_before, F_after)
+    else:
+        assert rel_max(F_after.cpu().numpy(), F_before.cpu().numpy()) < 1e-5
     assert tuning.load(a.tuning_key()) == shape
     b = _engine(wl, precision="bf16")
     b.set_state(torch.from_numpy(q0).cuda(), torch.from_numpy(p0).cuda())
@@ -464,7 +478,7 @@ def test_bad_launch_shapes_are_rejected():
     wl = WORKLOADS["fad-P4"]()
     eng = _engine(wl)
     for bad in ({"centre_waves": 3}, {"centre_waves": 8}, {"mlp_rows": 48}, {"centre_grid": -1}, {"neighbor_cells": 2},
-                {"mlp_waves": 6}, {"force_rows": 2}, {"centre_lanes": 2}):
+                {"mlp_waves": 6}, {"force_rows": 2}, {"centre_lanes": 2}, {"mlp_chain": 2}):
         with pytest.raises(PimdError) as ei:
             eng.set_tuning(**bad)
         assert ei.value.status == PIMD_E_ARG
@@ -477,5 +491,9 @@ def test_bad_launch_shapes_are_rejected():
     with pytest.raises(PimdError) as ei:
         f64.set_tuning(mlp_rows=32)
     assert ei.value.status == PIMD_E_UNSUPPORTED
+    for prec in ("fp32", "fp64-mlp"):          # the chained MLP is a BF16 kernel
+        with pytest.raises(PimdError) as ei:
+            _engine(wl, precision=prec).set_tuning(mlp_chain=1)
+        assert ei.value.status == PIMD_E_UNSUPPORTED
     with pytest.raises(PimdError):
         eng.autotune(n_reps=1, cache=False)     # no state yet

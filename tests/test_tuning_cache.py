@@ -42,11 +42,11 @@ def test_store_and_load_round_trip(tmp_path):
     path = str(tmp_path / "sub" / "t.json")
     assert tuning.load("k", path) is None
     shape = {"centre_waves": 2, "centre_grid": 0, "mlp_rows": 32, "neighbor_cells": 1, "mlp_waves": 8,
-             "force_rows": 1, "centre_lanes": 0}
+             "force_rows": 1, "centre_lanes": 0, "mlp_chain": 0}
     assert tuning.store("k", shape, path)
     assert tuning.load("k", path) == shape
     assert tuning.store("k2", {"centre_waves": 4, "centre_grid": 512, "mlp_rows": 16, "neighbor_cells": 0,
-                               "mlp_waves": 4, "force_rows": 0, "centre_lanes": 1}, path)
+                               "mlp_waves": 4, "force_rows": 0, "centre_lanes": 1, "mlp_chain": 1}, path)
     assert tuning.load("k", path)["mlp_rows"] == 32
     assert set(json.load(open(path))) == {"k", "k2"}
 
@@ -61,7 +61,7 @@ def test_corrupt_or_partial_entries_are_ignored(tmp_path):
     path.write_text(json.dumps({"k": {"centre_waves": 2, "centre_grid": 0, "mlp_rows": 16, "neighbor_cells": 0}}))
     assert tuning.load("k", str(path)) is None
     assert tuning.store("k", {"centre_waves": 1, "centre_grid": 0, "mlp_rows": 64, "neighbor_cells": 0,
-                              "mlp_waves": 4, "force_rows": 1, "centre_lanes": 0}, str(path))
+                              "mlp_waves": 4, "force_rows": 1, "centre_lanes": 0, "mlp_chain": 0}, str(path))
     assert tuning.load("k", str(path))["centre_waves"] == 1
 
 
