@@ -458,8 +458,9 @@ pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled);
  *                 (default 4)
  *   centre_grid   0 (default): one wave per centre atom; > 0: at most this
  *                 many workgroups, whose waves stride over the centres
- *   mlp_rows      rows per MLP workgroup tile: 16, 32 or 64 (default 32
- *                 with a BF16 MLP, else 16); PIMD_PREC_FP64_MLP takes 16 only
+ *   mlp_rows      rows per MLP workgroup tile: 16, 32 or 64 (default 16
+ *                 with the chained BF16 MLP, 32 with the other BF16 MLP, else
+ *                 16); PIMD_PREC_FP64_MLP takes 16 only
  *   neighbor_cells  periodic neighbour search: 0 = one wave per centre
  *                 gathering its stencil from global memory, 1 = one workgroup
  *                 per cell with the stencil staged in LDS once for all of the
@@ -486,11 +487,10 @@ pimd_status pimd_set_graph(pimd_ctx *ctx, int32_t enabled);
  *   mlp_chain     BF16 precisions and the network shapes the chained kernel
  *                 is built for (65 to 96 features, a multiple of 4, with
  *                 hidden widths 128-128-64 or 64-64; else 0 only,
- *                 PIMD_E_UNSUPPORTED):
- *                 1 = one wave per 16 MLP
- *                 rows with the activations kept in registers between layers
- *                 (each GEMM taken transposed, weights as the MFMA A operand
- *                 in a packed order); 0 (default) = activations staged in LDS,
+ *                 PIMD_E_UNSUPPORTED): 1 (default there) = one wave per 16
+ *                 MLP rows with the activations kept in registers between
+ *                 layers (each GEMM taken transposed, weights as the MFMA A
+ *                 operand in a packed order); 0 = activations staged in LDS,
  *                 mlp_waves waves splitting the output columns.  The two sum
  *                 the MFMA products in another order (results agree to
  *                 rounding, not bitwise); within each, every other field

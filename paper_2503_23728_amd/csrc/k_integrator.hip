@@ -113,7 +113,12 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
 {
     constexpr bool STAGING = XF == kStaging, PRIMITIVE = XF == kPrimitive, NM = XF == kNormalModes;
     extern __shared__ double ism[];
-    const IntegUnit u = a.units[blockIdx.x];
+    // Units of neighbouring columns share cache lines of q, p and F (a column
+    // reads one float per bead row); workgroups go round-robin over the 8 XCDs,
+    // each with its own L2, so the unit index is remapped to give every XCD a
+    // contiguous run of units.
+    const int ui = xcd_block(blockIdx.x, gridDim.x);
+    const IntegUnit u = a.units[ui];
     const SysInfo S = a.sys[u.sys];
     const int P = S.P, N = S.N;
     double *tw = ism;
@@ -165,9 +170,16 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
     const double kick = 0.5 * (double)a.dt / kMvv2e;
     double dke = 0.0;
     double pt = 0.0, qt = 0.0;
+    // Twiddles by rotation: (x, y) turns by the angle 2 pi kk / P per term,
+    // whose cos and sin the table holds correctly rounded (exact at quarter
+    // turns); the recurrence adds ~1e-16 per step, ~P 1e-16 in all, where a
+    // table read per term and thread (each lane a different address) cost
+    // more LDS bandwidth than the four FP64 operations of a turn.
+    const double Cw = NM ? tw[kk] : 1.0, Sw = NM ? tw[P + kk] : 0.0;
     if (valid) {
         const double nrm = (kk == 0 || kk == halfP) ? tw[2 * P] : tw[2 * P + 1];
-        const double *tk = tw + (kk > halfP ? P : 0);   // the twiddles of mode kk
+        // mode kk takes cos(j theta) (kk <= P/2) or sin(j theta) = cos(j theta - pi/2)
+        const double x0 = kk > halfP ? 0.0 : 1.0, y0 = kk > halfP ? -1.0 : 0.0;
         const double *sp = s0 + cl * P, *sf = s1 + cl * P, *sq = s2 + cl * P;
         const ModeInfo M = a.modes[S.mode0 + kk];
         const double mk = m * M.mfac;                 // kinetic mass of mode kk
@@ -183,13 +195,14 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
                 Ft = sf[kk] + spring_force(sq, kk, P, m * M.w * M.w);
                 qt = sq[kk];
             } else {
-                for (int j = 0, m = 0; j < P; ++j) {
-                    const double c = tk[m];
-                    pt += c * sp[j];
-                    Ft += c * sf[j];
-                    qt += c * sq[j];
-                    m += kk;
-                    m -= m >= P ? P : 0;
+                double x = x0, y = y0;
+                for (int j = 0; j < P; ++j) {
+                    pt += x * sp[j];
+                    Ft += x * sf[j];
+                    qt += x * sq[j];
+                    const double xn = x * Cw - y * Sw;
+                    y = y * Cw + x * Sw;
+                    x = xn;
                 }
                 pt *= nrm;
                 Ft *= nrm;
@@ -217,10 +230,12 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
             } else if (PRIMITIVE) {
                 pt = sp[kk] + kick * (sf[kk] + spring_force(sq, kk, P, m * M.w * M.w));
             } else {
-                for (int j = 0, m = 0; j < P; ++j) {
-                    pt += tk[m] * (sp[j] + kick * sf[j]);
-                    m += kk;
-                    m -= m >= P ? P : 0;
+                double x = x0, y = y0;
+                for (int j = 0; j < P; ++j) {
+                    pt += x * (sp[j] + kick * sf[j]);
+                    const double xn = x * Cw - y * Sw;
+                    y = y * Cw + x * Sw;
+                    x = xn;
                 }
                 pt *= nrm;
             }
@@ -248,15 +263,26 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
             pj = pt;
             qj = qt;
         } else {
-            // back to beads: x_j = sum_k C[j][k] x~_k, with j = kk
-            for (int k = 0, m = 0; k < P; ++k) {
-                const double c = ((k == 0 || k == halfP) ? tw[2 * P] : tw[2 * P + 1]) * tw[(k > halfP ? P : 0) + m];
+            // back to beads: x_j = sum_k C[j][k] x~_k, with j = kk: (x, y) =
+            // (cos k phi, sin k phi), phi = 2 pi j / P; cos up to k = P/2, sin
+            // above, normalisation 1/sqrt(P) at k = 0 and P/2, sqrt(2/P) between
+            const double n0 = tw[2 * P], n1 = tw[2 * P + 1];
+            double x = 1.0, y = 0.0;
+            auto term = [&](double c, int k) {
                 pj += c * sp[k];
                 if (PRE)
                     qj += c * sq[k];
-                m += kk;
-                m -= m >= P ? P : 0;
-            }
+                const double xn = x * Cw - y * Sw;
+                y = y * Cw + x * Sw;
+                x = xn;
+            };
+            term(n0, 0);
+            for (int k = 1; k < halfP; ++k)
+                term(n1 * x, k);
+            if (P > 1)
+                term(n0 * x, halfP);
+            for (int k = halfP + 1; k < P; ++k)
+                term(n1 * y, k);
         }
         a.p[row * 3 + cc] = (float)pj;
         if (PRE)
@@ -264,7 +290,7 @@ __global__ __launch_bounds__(256) void k_integrate(IntegArgs a)
     }
     const double tot = block_sum_double(dke, red);
     if (tid == 0)
-        a.dke_part[2 * blockIdx.x + (PRE ? 0 : 1)] = tot;
+        a.dke_part[2 * ui + (PRE ? 0 : 1)] = tot;
 }
 
 // PILE-G: the centroid mode of every system is thermostatted by one factor

@@ -820,21 +820,27 @@ __device__ __forceinline__ void chain_gemm(const uint16_t *__restrict__ F, const
 #pragma unroll
     for (int o = 0; o < OT; ++o)
         acc[o] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    i16x8 fh[2][OT], fl[2][OT];
-    chain_load<MODE, OT, KB>(F, Flo, 0, fh[0], fl[0]);
+    // NB buffers: the loads run NB - 1 steps ahead of the MFMAs (a step of
+    // OT x 2 MFMAs is shorter than an L2 round trip)
+    constexpr int NB = MODE == 1 ? 2 : 3;
+    i16x8 fh[NB][OT], fl[NB][OT];
+#pragma unroll
+    for (int b = 0; b < NB - 1; ++b)
+        if (b < KB)
+            chain_load<MODE, OT, KB>(F, Flo, b, fh[b], fl[b]);
 #pragma unroll
     for (int b = 0; b < KB; ++b) {
-        if (b + 1 < KB)
-            chain_load<MODE, OT, KB>(F, Flo, b + 1, fh[(b + 1) & 1], fl[(b + 1) & 1]);
+        if (b + NB - 1 < KB)
+            chain_load<MODE, OT, KB>(F, Flo, b + NB - 1, fh[(b + NB - 1) % NB], fl[(b + NB - 1) % NB]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int o = 0; o < OT; ++o) {
-            const i16x8 a = fh[b & 1][o];
+            const i16x8 a = fh[b % NB][o];
             acc[o] = mfma_k32(a, as_op(xh[b]), acc[o]);
             if (split_act<MODE>())
                 acc[o] = mfma_k32(a, as_op(xl[b]), acc[o]);
             if (MODE == 1)
-                acc[o] = mfma_k32(fl[b & 1][o], as_op(xh[b]), acc[o]);
+                acc[o] = mfma_k32(fl[b % NB][o], as_op(xh[b]), acc[o]);
         }
         __builtin_amdgcn_sched_barrier(0);
     }

@@ -906,6 +906,10 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
     if (c->precision == PIMD_PREC_BF16_MLP || c->precision == PIMD_PREC_BF16_PLAIN) {
         c->tn.mlp_rows = 32;    // 32-row tiles, one 16-column tile per wave: fastest at 64 to 16384 bead-atoms
         c->tn.mlp_waves = 8;
+        if (pl.chain) {         // the register-chained kernel, where built: faster on every workload measured
+            c->tn.mlp_chain = 1;
+            c->tn.mlp_rows = 16;
+        }
     }
     z.any_open = pl.any_open ? 1 : 0;
     z.any_box = pl.any_box ? 1 : 0;
