@@ -56,8 +56,8 @@ __device__ __forceinline__ int stage_neighbors(int i, const float4 &pi, const Be
         const float r2 = r * r;
         float fc, dfc;
         cutoff_fn(r * (1.0f / dp.rc), dp.pi_over_rc, fc, dfc);
-        const float g0 = expf(-dp.ang_eta[0] * r2);
-        const float g1 = NETA > 1 ? expf(-dp.ang_eta[1] * r2) : 0.0f;
+        const float g0 = exp2_hw(-dp.ang_eta[0] * kLog2e * r2);
+        const float g1 = NETA > 1 ? exp2_hw(-dp.ang_eta[1] * kLog2e * r2) : 0.0f;
         rec.D[n] = make_float4(d.x, d.y, d.z, inv_r);
         // dE_eta/dr = exp(-eta r^2) (-2 eta r f_c + f_c')
         rec.E[n] = make_float4(g0 * fc, g1 * fc, ADJ ? g0 * (-2.0f * dp.ang_eta[0] * r * fc + dfc) : 0.0f,
@@ -211,13 +211,26 @@ __device__ __forceinline__ float exp_small(float neg_eta_log2e, float x)
     return __builtin_amdgcn_exp2f(neg_eta_log2e * x);
 }
 
+// Coefficients of the angular sums as polynomials in cos: per element-pair
+// block and eta, a_0 .. a_8 of S and b_0 .. b_7 of dS/dcos (17 floats).
+__host__ __device__ inline int adjoint_coef_count(const DescParams &dp)
+{
+    return dp.n_el * (dp.n_el + 1) / 2 * dp.n_ang_eta * 17;
+}
+
+// Binomial coefficients C(zeta, k) for zeta = 1, 2, 4, 8.
+__constant__ double kBinomZeta[4][9] = {{1, 1, 0, 0, 0, 0, 0, 0, 0},
+                                        {1, 2, 1, 0, 0, 0, 0, 0, 0},
+                                        {1, 4, 6, 4, 1, 0, 0, 0, 0},
+                                        {1, 8, 28, 56, 70, 56, 28, 8, 1}};
+
 // LDS per wave of the adjoint kernel: records D and E (16 B each per slot),
-// the FP64 slot accumulators (24 B per slot), the dE/dG row and the reverse
-// slots (2 B per slot), rounded up to 16 bytes.  The pair terms of the radial part never leave registers.
+// the FP64 slot accumulators (24 B per slot), the dE/dG row, the reverse
+// slots (2 B per slot) and the polynomial coefficients, rounded up to 16 bytes.  The pair terms of the radial part never leave registers.
 __host__ __device__ inline size_t adjoint_wave_bytes(const DescParams &dp)
 {
     const int Dcap = (dp.D + 3) & ~3;
-    const size_t b = (size_t)58 * dp.Kmax + 4 * (size_t)Dcap;
+    const size_t b = (size_t)58 * dp.Kmax + 4 * (size_t)Dcap + 4 * (size_t)adjoint_coef_count(dp);
     return (b + 15) & ~(size_t)15;
 }
 
@@ -278,7 +291,7 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
                     // (eta up to ~5/A^2) would turn the float rounding of r into
                     // 1e-6 relative errors
                     const float x = (q.x - Rs) + (q.w - Rs_lo);
-                    acc += expf(-eta * x * x) * q.y;
+                    acc += exp2_hw(-eta * kLog2e * x * x) * q.y;
                 }
             }
             acc += __shfl_xor(acc, 32, kWave);
@@ -381,6 +394,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     float *gl = reinterpret_cast<float *>(base + 56 * dp.Kmax);
     // reverse slots: where atom j = nbr[i][n] keeps the pair (j, i)
     int16_t *rev = reinterpret_cast<int16_t *>(gl + ((dp.D + 3) & ~3));
+    float *coef = reinterpret_cast<float *>(rev + dp.Kmax);   // Kmax is a multiple of 16
     const int Frad = dp.n_el * dp.n_rad;
     const float nel0 = -dp.ang_eta[0] * 1.4426950408889634f, nel1 = -dp.ang_eta[1] * 1.4426950408889634f;
     const float inv_rc = 1.0f / dp.rc;
@@ -410,7 +424,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 for (int t = 0; t < dp.n_rad; ++t) {
                     const float x = (r - dp.rad_center[t]) + (r_lo - dp.rad_center_lo[t]);
                     const float eta = dp.rad_eta[t];
-                    acc += gl[e * dp.n_rad + t] * expf(-eta * x * x) * (-2.0f * eta * x * fc + dfc);
+                    acc += gl[e * dp.n_rad + t] * exp2_hw(-eta * kLog2e * x * x) * (-2.0f * eta * x * fc + dfc);
                 }
                 const float c = acc * inv_r;
                 vacc[3 * n] = (double)(c * d.x);
@@ -418,44 +432,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 vacc[3 * n + 2] = (double)(c * d.z);
             });
         wave_sync();
+        // S(c) = sum_{zeta, lambda} g 2^(1-zeta) (1 + lambda c)^zeta as a
+        // polynomial in c of degree 8, S = sum_k a_k c^k with
+        // a_k = sum_zeta C(zeta, k) 2^(1-zeta) (g_+ + (-1)^k g_-), and
+        // dS/dc = sum_k b_k c^k, b_k = (k + 1) a_{k+1}: Horner's rule in the
+        // triplet body replaces the powers of 1 +- c.  Every term of the
+        // expansion is bounded by the size of the original terms
+        // (sum_k C(zeta, k) 2^(1-zeta) = 2), so nothing cancels beyond what the
+        // sum itself does.  One coefficient per lane, formed in FP64 and
+        // rounded once, for every block of the centre.
+        const int n_coef = adjoint_coef_count(dp);
+        for (int t = lane; t < n_coef; t += kWave) {
+            const int c = t % 17, pe = t / 17, ie = pe % dp.n_ang_eta, blk = pe / dp.n_ang_eta;
+            const int k = c < 9 ? c : c - 8;   // a_c, or b_{c-9} = k a_k with k = c - 8
+            double a = 0.0;
+            for (int z = 0; z < 4; ++z) {
+                if (k <= (1 << z)) {
+                    const int q = 8 * ie + 2 * z;
+                    const double gp = (double)gl[Frad + blk * dp.n_ang + q] * (double)block_scale(q);
+                    const double gm = (double)gl[Frad + blk * dp.n_ang + q + 1] * (double)block_scale(q + 1);
+                    a += kBinomZeta[z][k] * (k & 1 ? gp - gm : gp + gm);
+                }
+            }
+            coef[t] = (float)(c < 9 ? a : (double)k * a);
+        }
+        wave_sync();
         const uint16_t *kept = tri_pairs + (int64_t)i * tri_capacity(dp.Kmax);
         int pair = 0;
         for (int e1 = 0; e1 < dp.n_el; ++e1)
             for (int e2 = e1; e2 < dp.n_el; ++e2, ++pair) {
                 const int n_pairs_block = tri_cnt[(int64_t)i * kMaxPairs + pair];
-                // S(c) = sum_{zeta, lambda} g 2^(1-zeta) (1 + lambda c)^zeta as a
-                // polynomial in c of degree 8, S = sum_k a_k c^k with
-                // a_k = sum_zeta C(zeta, k) 2^(1-zeta) (g_+ + (-1)^k g_-), and
-                // dS/dc = sum_k b_k c^k, b_k = (k + 1) a_{k+1}: Horner's rule
-                // in the triplet body replaces the powers of 1 +- c.  Every term
-                // of the expansion is bounded by the size of the original terms
-                // (sum_k C(zeta, k) 2^(1-zeta) = 2), so nothing cancels beyond
-                // what the sum itself does; formed in FP64, rounded once.
+                // the block's polynomial coefficients, in scalar registers
                 float ga[9 * NETA], gb[8 * NETA];
 #pragma unroll
                 for (int ie = 0; ie < NETA; ++ie) {
-                    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-                    for (int z = 0; z < 4; ++z) {
-                        const int q = 8 * ie + 2 * z;
-                        const double gp = (double)gl[Frad + pair * dp.n_ang + q] * (double)block_scale(q);
-                        const double gm = (double)gl[Frad + pair * dp.n_ang + q + 1] * (double)block_scale(q + 1);
-                        const int zeta = 1 << z;
-                        double binom = 1.0;
-#pragma unroll
-                        for (int k = 0; k <= 8; ++k) {
-                            if (k <= zeta) {
-                                a[k] += binom * (k & 1 ? gp - gm : gp + gm);
-                                binom = binom * (double)(zeta - k) / (double)(k + 1);
-                            }
-                        }
-                    }
+                    const float *cb = coef + (pair * dp.n_ang_eta + ie) * 17;
 #pragma unroll
                     for (int k = 0; k < 9; ++k)
-                        ga[9 * ie + k] = uniform_float((float)a[k]);
+                        ga[9 * ie + k] = uniform_float(cb[k]);
 #pragma unroll
                     for (int k = 0; k < 8; ++k)
-                        gb[8 * ie + k] = uniform_float((float)((double)(k + 1) * a[k + 1]));
+                        gb[8 * ie + k] = uniform_float(cb[9 + k]);
                 }
                 auto body = [&](uint32_t ia, uint32_t ic, bool ok) {
                     if (!ok)

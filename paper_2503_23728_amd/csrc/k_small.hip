@@ -113,11 +113,12 @@ __global__ __launch_bounds__(64) void k_sm_forward(const float4 *__restrict__ po
         cutoff_fn(r * inv_rc, dp.pi_over_rc, fc, dfc);
         for (int s = 0; s < dp.n_rad; ++s) {
             const float x = (r - dp.rad_center[s]) + (r_lo - dp.rad_center_lo[s]);
-            G[(ej * dp.n_rad + s) * kWave + lane] += expf(-dp.rad_eta[s] * x * x) * fc;
+            G[(ej * dp.n_rad + s) * kWave + lane] += exp2_hw(-dp.rad_eta[s] * kLog2e * x * x) * fc;
         }
         const float r2 = r * r;
         rD[j] = make_float4(d.x, d.y, d.z, inv_r);
-        rE[j] = make_float2(expf(-dp.ang_eta[0] * r2) * fc, NETA > 1 ? expf(-dp.ang_eta[1] * r2) * fc : 0.0f);
+        rE[j] = make_float2(exp2_hw(-dp.ang_eta[0] * kLog2e * r2) * fc,
+                            NETA > 1 ? exp2_hw(-dp.ang_eta[1] * kLog2e * r2) * fc : 0.0f);
     }
     // neighbour list in key order: by element, then row
     if (L.act) {
@@ -246,15 +247,15 @@ __global__ __launch_bounds__(64) void k_sm_adjoint(const float4 *__restrict__ po
         for (int t = 0; t < dp.n_rad; ++t) {
             const float x = (r - dp.rad_center[t]) + (r_lo - dp.rad_center_lo[t]);
             const float eta = dp.rad_eta[t];
-            acc += g[(ej * dp.n_rad + t) * kWave + lane] * expf(-eta * x * x) * (-2.0f * eta * x * fc + dfc);
+            acc += g[(ej * dp.n_rad + t) * kWave + lane] * exp2_hw(-eta * kLog2e * x * x) * (-2.0f * eta * x * fc + dfc);
         }
         const float c = acc * inv_r;
         v[j][0] = (double)(c * d.x);
         v[j][1] = (double)(c * d.y);
         v[j][2] = (double)(c * d.z);
         const float r2 = r * r;
-        const float g0 = expf(-dp.ang_eta[0] * r2);
-        const float g1 = NETA > 1 ? expf(-dp.ang_eta[1] * r2) : 0.0f;
+        const float g0 = exp2_hw(-dp.ang_eta[0] * kLog2e * r2);
+        const float g1 = NETA > 1 ? exp2_hw(-dp.ang_eta[1] * kLog2e * r2) : 0.0f;
         rD[j] = make_float4(d.x, d.y, d.z, inv_r);
         rE[j] = make_float4(g0 * fc, g1 * fc, g0 * (-2.0f * dp.ang_eta[0] * r * fc + dfc),
                             NETA > 1 ? g1 * (-2.0f * dp.ang_eta[1] * r * fc + dfc) : 0.0f);

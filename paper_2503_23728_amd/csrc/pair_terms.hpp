@@ -7,6 +7,15 @@
 
 namespace pimd {
 
+constexpr float kLog2e = 1.4426950408889634f;
+
+// exp2 on the hardware transcendental unit (about 1 ulp).  The pair terms
+// take exp(-eta x^2) as exp2_hw(-eta kLog2e x^2): the float32 rounding of the
+// argument already costs ~1e-7 |a| relative, and the library exp's range
+// reduction (a dozen instructions per call, 16 calls per slot in the radial
+// terms) buys no accuracy beyond that.
+__device__ __forceinline__ float exp2_hw(float a) { return __builtin_amdgcn_exp2f(a); }
+
 // Displacement d_ij = q_j - q_i (minimum image) of the unwrapped float32
 // positions, formed in FP64 with the FP64 box and rounded once to float32, so
 // it carries no rounding from wrapping large coordinates.  The neighbour set
