@@ -218,11 +218,14 @@ __host__ __device__ inline int adjoint_coef_count(const DescParams &dp)
     return dp.n_el * (dp.n_el + 1) / 2 * dp.n_ang_eta * 17;
 }
 
-// Binomial coefficients C(zeta, k) for zeta = 1, 2, 4, 8.
-__constant__ double kBinomZeta[4][9] = {{1, 1, 0, 0, 0, 0, 0, 0, 0},
-                                        {1, 2, 1, 0, 0, 0, 0, 0, 0},
-                                        {1, 4, 6, 4, 1, 0, 0, 0, 0},
-                                        {1, 8, 28, 56, 70, 56, 28, 8, 1}};
+// Binomial coefficient C(zeta, k) for zeta = 2^z (z < 4), k <= zeta: the rows
+// packed 7 bits per entry into one 64-bit immediate each, so a lane with its
+// own k reads it with a shift instead of a memory load.
+__device__ __forceinline__ double binom_zeta(int z, int k)
+{
+    constexpr uint64_t rows[4] = {0x81ull, 0x4101ull, 0x10818201ull, 0x11071c467070401ull};
+    return (double)(int)((rows[z] >> (7 * k)) & 127u);
+}
 
 // LDS per wave of the adjoint kernel: records D and E (16 B each per slot),
 // the FP64 slot accumulators (24 B per slot), the dE/dG row, the reverse
@@ -443,15 +446,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         // rounded once, for every block of the centre.
         const int n_coef = adjoint_coef_count(dp);
         for (int t = lane; t < n_coef; t += kWave) {
-            const int c = t % 17, pe = t / 17, ie = pe % dp.n_ang_eta, blk = pe / dp.n_ang_eta;
+            const int c = t % 17, pe = t / 17, ie = pe % NETA, blk = pe / NETA;
             const int k = c < 9 ? c : c - 8;   // a_c, or b_{c-9} = k a_k with k = c - 8
             double a = 0.0;
+#pragma unroll
             for (int z = 0; z < 4; ++z) {
                 if (k <= (1 << z)) {
                     const int q = 8 * ie + 2 * z;
                     const double gp = (double)gl[Frad + blk * dp.n_ang + q] * (double)block_scale(q);
                     const double gm = (double)gl[Frad + blk * dp.n_ang + q + 1] * (double)block_scale(q + 1);
-                    a += kBinomZeta[z][k] * (k & 1 ? gp - gm : gp + gm);
+                    a += binom_zeta(z, k) * (k & 1 ? gp - gm : gp + gm);
                 }
             }
             coef[t] = (float)(c < 9 ? a : (double)k * a);
@@ -466,7 +470,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 float ga[9 * NETA], gb[8 * NETA];
 #pragma unroll
                 for (int ie = 0; ie < NETA; ++ie) {
-                    const float *cb = coef + (pair * dp.n_ang_eta + ie) * 17;
+                    const float *cb = coef + (pair * NETA + ie) * 17;
 #pragma unroll
                     for (int k = 0; k < 9; ++k)
                         ga[9 * ie + k] = uniform_float(cb[k]);
