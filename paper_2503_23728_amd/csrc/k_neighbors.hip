@@ -569,6 +569,15 @@ __global__ __launch_bounds__(256) void k_skin_filter(const float4 *__restrict__ 
         int32_t *out = nbr + (int64_t)i * Kmax;
         int count = 0;
         int grp[kMaxElements] = {0, 0, 0, 0};
+        // list candidates: keys loaded two chunks ahead and positions one
+        // chunk ahead, so a chunk's two dependent loads are in flight while
+        // the chunks before it are tested
+        // (only on the list path: a whole-bead scan has no list, and key 0 names
+        // the bead's first row, so every prefetch stays inside the bead)
+        const int n_list = scan_all ? 0 : n_cand;
+        int c_next = lane < n_list ? cand[lane] : 0;
+        int c_after = kWave + lane < n_list ? cand[kWave + lane] : 0;
+        float4 p_next = pos4[bi.ba0 + (c_next & (int)kRowMask)];
         for (int t0 = 0; t0 < n_cand; t0 += kWave) {
             const int t = t0 + lane;
             int key = 0;
@@ -581,11 +590,17 @@ __global__ __launch_bounds__(256) void k_skin_filter(const float4 *__restrict__ 
                     acc = __float_as_int(pj.w) == e && within_cutoff(pi, pj, bi, rc2);
                     key = (e << kKeyShift) | j;
                 }
-            } else if (t < n_cand) {
-                const int c = cand[t];
-                const int j = bi.ba0 + (c & (int)kRowMask);
-                acc = within_cutoff(pi, pos4[j], bi, rc2);
-                key = (c & ~(int)kRowMask) | j;
+            } else {
+                const int c = c_next;
+                const float4 pj = p_next;
+                c_next = c_after;
+                c_after = t + 2 * kWave < n_list ? cand[t + 2 * kWave] : 0;
+                p_next = pos4[bi.ba0 + (c_next & (int)kRowMask)];
+                if (t < n_cand) {
+                    const int j = bi.ba0 + (c & (int)kRowMask);
+                    acc = within_cutoff(pi, pj, bi, rc2);
+                    key = (c & ~(int)kRowMask) | j;
+                }
             }
             const uint64_t m = __ballot(acc);
             const int pos = count + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
