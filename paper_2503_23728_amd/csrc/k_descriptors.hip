@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
     uint32_t *queue = reinterpret_cast<uint32_t *>(base + 3 * dp.Kmax + Dcap / 4);
     const int Frad = dp.n_el * dp.n_rad;
     const float nel0 = -dp.ang_eta[0] * 1.4426950408889634f, nel1 = -dp.ang_eta[1] * 1.4426950408889634f;
-    const float inv_rc = 1.0f / dp.rc;
+    const float inv_rc2 = 1.0f / dp.rc2;
 
     const CentreRange cr = centre_range(B);
     for (int ci = cr.begin; ci < cr.end; ++ci) {
@@ -323,9 +323,7 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
                     const float4 Ad = rec.D[ia], Cd = rec.D[ic], Ae = rec.E[ia], Ce = rec.E[ic];
                     const float jx = Cd.x - Ad.x, jy = Cd.y - Ad.y, jz = Cd.z - Ad.z;
                     const float r2jk = jx * jx + jy * jy + jz * jz;
-                    const float rjk = __builtin_amdgcn_sqrtf(r2jk);
-                    float fcjk, dfcjk;
-                    cutoff_fn(rjk * inv_rc, dp.pi_over_rc, fcjk, dfcjk);
+                    const float fcjk = cutoff_sq_fc(r2jk * inv_rc2);
                     const float cs = (Ad.x * Cd.x + Ad.y * Cd.y + Ad.z * Cd.z) * (Ad.w * Cd.w);
                     const float p1 = 1.0f + cs, m1 = 1.0f - cs;
                     const float p2 = p1 * p1, m2 = m1 * m1;
@@ -400,7 +398,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     float *coef = reinterpret_cast<float *>(rev + dp.Kmax);   // Kmax is a multiple of 16
     const int Frad = dp.n_el * dp.n_rad;
     const float nel0 = -dp.ang_eta[0] * 1.4426950408889634f, nel1 = -dp.ang_eta[1] * 1.4426950408889634f;
-    const float inv_rc = 1.0f / dp.rc;
+    const float inv_rc2 = 1.0f / dp.rc2;
 
     const CentreRange cr = centre_range(B);
     for (int ci = cr.begin; ci < cr.end; ++ci) {
@@ -466,17 +464,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         for (int e1 = 0; e1 < dp.n_el; ++e1)
             for (int e2 = e1; e2 < dp.n_el; ++e2, ++pair) {
                 const int n_pairs_block = tri_cnt[(int64_t)i * kMaxPairs + pair];
-                // the block's polynomial coefficients, in scalar registers
+                // the block's polynomial coefficients in scalar registers, the
+                // leading ones in vector registers: an FMA takes one scalar
+                // operand, so the first Horner step then needs no move
                 float ga[9 * NETA], gb[8 * NETA];
 #pragma unroll
                 for (int ie = 0; ie < NETA; ++ie) {
                     const float *cb = coef + (pair * NETA + ie) * 17;
 #pragma unroll
-                    for (int k = 0; k < 9; ++k)
-                        ga[9 * ie + k] = uniform_float(cb[k]);
-#pragma unroll
                     for (int k = 0; k < 8; ++k)
+                        ga[9 * ie + k] = uniform_float(cb[k]);
+                    ga[9 * ie + 8] = cb[8];
+#pragma unroll
+                    for (int k = 0; k < 7; ++k)
                         gb[8 * ie + k] = uniform_float(cb[9 + k]);
+                    gb[8 * ie + 7] = cb[16];
                 }
                 auto body = [&](uint32_t ia, uint32_t ic, bool ok) {
                     if (!ok)
@@ -484,15 +486,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     const float4 Ad = rec.D[ia], Cd = rec.D[ic], Ae = rec.E[ia], Ce = rec.E[ic];
                     const float jx = Cd.x - Ad.x, jy = Cd.y - Ad.y, jz = Cd.z - Ad.z;
                     const float r2jk = jx * jx + jy * jy + jz * jz;
-                    const float inv_rjk = __builtin_amdgcn_rsqf(r2jk);
-                    const float rjk = r2jk * inv_rjk;
+                    // dfcjk = (1/r_jk) d f_c/d r_jk
                     float fcjk, dfcjk;
-                    cutoff_fn(rjk * inv_rc, dp.pi_over_rc, fcjk, dfcjk);
+                    cutoff_sq(r2jk * inv_rc2, fcjk, dfcjk);
+                    dfcjk *= 2.0f * inv_rc2;
                     const float iab = Ad.w * Cd.w;
                     const float cs = (Ad.x * Cd.x + Ad.y * Cd.y + Ad.z * Cd.z) * iab;
                     // per eta, with Y = exp(-eta r_jk^2) f_c(r_jk):
                     //   dE/dcos:  Sd Ea Eb Y;  dE/dr_ij: S dEa Eb Y;  dE/dr_ik: S Ea dEb Y
-                    //   dE/dr_jk: S Ea Eb exp(-eta r_jk^2) (f_c' - 2 eta r_jk f_c)
+                    //   dE/dr_jk / r_jk: S Ea Eb exp(-eta r_jk^2) (f_c'/r_jk - 2 eta f_c)
                     float Pc = 0.0f, Pa = 0.0f, Pb = 0.0f, Pjk = 0.0f;
                     const float X0 = exp_small(nel0, r2jk);
                     float X1 = 0.0f;
@@ -519,7 +521,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                         Pa = fmaf(dEa, Eb * SY, Pa);
                         Pb = fmaf(dEb, Ea * SY, Pb);
                         Pc = fmaf(Sd, EaEb * Y, Pc);
-                        const float gjk = fmaf(-2.0f * dp.ang_eta[ie] * rjk, fcjk, dfcjk);
+                        const float gjk = fmaf(-2.0f * dp.ang_eta[ie], fcjk, dfcjk);
                         Pjk = fmaf(S * EaEb, X * gjk, Pjk);
                     }
                     // dE/d d_ij = alpha_a d_ij + beta d_ik - gam d_jk and
@@ -527,7 +529,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     // d_jk = d_ik - d_ij, regrouped onto d_ij and d_ik
                     const float ia_ = Ad.w, ib_ = Cd.w;
                     const float Pcs = Pc * cs;
-                    const float gam = Pjk * inv_rjk;
+                    const float gam = Pjk;
                     const float ka = (Pa - Pcs * ia_) * ia_ + gam;
                     const float kc = (Pb - Pcs * ib_) * ib_ + gam;
                     const float kb = Pc * iab - gam;
@@ -540,15 +542,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     atomicAdd(vc + 2, (double)(kc * Cd.z + kb * Ad.z));
                 };
                 // the block's in-range slot pairs as the forward found them, one
-                // per lane; the next batch's pairs load while this one runs
-                // (clamped to the block's last pair: every lane loads, no branch)
-                const int last = n_pairs_block - 1;
-                uint32_t nxt = n_pairs_block > 0 ? kept[min(lane, last)] : 0u;
+                // per lane; the next batch's pairs load while this one runs.
+                // Every lane loads from a wave-uniform base: the loads past the
+                // block's last pair (at most 127 entries, inside the centre's
+                // capacity) are never used.
+                const uint16_t *ahead = kept + kWave;
+                uint32_t nxt = kept[lane];
                 for (int t0 = 0; t0 < n_pairs_block; t0 += kWave) {
-                    const int t = t0 + lane;
                     const uint32_t v = nxt;
-                    nxt = kept[min(t + kWave, last)];
-                    body(v >> 8, v & 0xFFu, t < n_pairs_block);
+                    nxt = ahead[lane];
+                    ahead += kWave;
+                    body(v >> 8, v & 0xFFu, t0 + lane < n_pairs_block);
                 }
                 kept += n_pairs_block;
             }

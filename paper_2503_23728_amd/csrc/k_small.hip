@@ -83,7 +83,7 @@ __global__ __launch_bounds__(64) void k_sm_forward(const float4 *__restrict__ po
     const SmUnit u = units[blockIdx.x];
     const SmLane L = sm_lane(u, pos4, posu4, beads, bead_of_ba);
     const int Frad = dp.n_el * dp.n_rad;
-    const float inv_rc = 1.0f / dp.rc;
+    const float inv_rc = 1.0f / dp.rc, inv_rc2 = 1.0f / dp.rc2;
     sw[lane] = L.pw;
     su[lane] = L.pu;
     for (int f = 0; f < dp.D; ++f)
@@ -154,9 +154,7 @@ __global__ __launch_bounds__(64) void k_sm_forward(const float4 *__restrict__ po
                 continue;
             const int ej = (int)((epack >> (2 * j)) & 3u), ek = (int)((epack >> (2 * k)) & 3u);
             float *gb = G + (Frad + pair_block(ej, ek, dp.n_el) * dp.n_ang) * kWave + lane;
-            const float rjk = __builtin_amdgcn_sqrtf(r2jk);
-            float fcjk, dfcjk;
-            cutoff_fn(rjk * inv_rc, dp.pi_over_rc, fcjk, dfcjk);
+            const float fcjk = cutoff_sq_fc(r2jk * inv_rc2);
             const float cs = (A.x * C.x + A.y * C.y + A.z * C.z) * (A.w * C.w);
             const float p1 = 1.0f + cs, m1 = 1.0f - cs;
             const float p2 = p1 * p1, m2 = m1 * m1;
@@ -213,7 +211,7 @@ __global__ __launch_bounds__(64) void k_sm_adjoint(const float4 *__restrict__ po
     const SmUnit u = units[blockIdx.x];
     const SmLane L = sm_lane(u, pos4, posu4, beads, bead_of_ba);
     const int Frad = dp.n_el * dp.n_rad;
-    const float inv_rc = 1.0f / dp.rc;
+    const float inv_rc = 1.0f / dp.rc, inv_rc2 = 1.0f / dp.rc2;
     sw[lane] = L.pw;
     su[lane] = L.pu;
     if (L.act)
@@ -275,10 +273,10 @@ __global__ __launch_bounds__(64) void k_sm_adjoint(const float4 *__restrict__ po
                 continue;
             const int ej = (int)((epack >> (2 * j)) & 3u), ek = (int)((epack >> (2 * k)) & 3u);
             const float *gb = g + (Frad + pair_block(ej, ek, dp.n_el) * dp.n_ang) * kWave + lane;
-            const float inv_rjk = __builtin_amdgcn_rsqf(r2jk);
-            const float rjk = r2jk * inv_rjk;
+            // dfcjk = (1/r_jk) d f_c/d r_jk
             float fcjk, dfcjk;
-            cutoff_fn(rjk * inv_rc, dp.pi_over_rc, fcjk, dfcjk);
+            cutoff_sq(r2jk * inv_rc2, fcjk, dfcjk);
+            dfcjk *= 2.0f * inv_rc2;
             const float iab = A.w * C.w;
             const float cs = (A.x * C.x + A.y * C.y + A.z * C.z) * iab;
             const float p1 = 1.0f + cs, m1 = 1.0f - cs;
@@ -307,13 +305,13 @@ __global__ __launch_bounds__(64) void k_sm_adjoint(const float4 *__restrict__ po
                 Pa = fmaf(dEa, Eb * SY, Pa);
                 Pb = fmaf(dEb, Ea * SY, Pb);
                 Pc = fmaf(Sd, EaEb * Y, Pc);
-                const float gjk = fmaf(-2.0f * dp.ang_eta[ie] * rjk, fcjk, dfcjk);
+                const float gjk = fmaf(-2.0f * dp.ang_eta[ie], fcjk, dfcjk);
                 Pjk = fmaf(S * EaEb, X * gjk, Pjk);
             }
             // dE/d d_ij = ka d_ij + kb d_ik,  dE/d d_ik = kc d_ik + kb d_ij
             const float ia_ = A.w, ib_ = C.w;
             const float Pcs = Pc * cs;
-            const float gam = Pjk * inv_rjk;
+            const float gam = Pjk;
             const float ka = (Pa - Pcs * ia_) * ia_ + gam;
             const float kc = (Pb - Pcs * ib_) * ib_ + gam;
             const float kb = Pc * iab - gam;

@@ -67,4 +67,42 @@ __device__ __forceinline__ void cutoff_fn(float x, float pi_over_rc, float &fc, 
     dfc = -pi_over_rc * sn * cs;
 }
 
+// Cutoff function of u = (r/rc)^2 in [0, 1], for the triplet terms, which
+// have r^2 and no other use for r:
+//   f_c = (cos(pi r/rc) + 1)/2 = c^2,  c(u) = cos(pi sqrt(u)/2),
+//   d f_c/du = 2 c c',  (1/r) d f_c/dr = 2 (d f_c/du)/rc^2.
+// c(u) = sum_n (-1)^n (pi^2/4)^n u^n/(2n)! is an entire function of u; its
+// Taylor polynomials of degree 6 (c) and 5 (c') leave alternating remainders
+// below 7e-9 and 5e-8 on [0, 1], under the ~1e-7 absolute rounding of the
+// float32 sums.  No square root and no argument reduction.
+__device__ __forceinline__ float cutoff_sq_c(float u)
+{
+    float c = 4.7108747788e-07f;
+    c = fmaf(c, u, -2.5202042373e-05f);
+    c = fmaf(c, u, 9.1926027484e-04f);
+    c = fmaf(c, u, -2.0863480763e-02f);
+    c = fmaf(c, u, 2.5366950790e-01f);
+    c = fmaf(c, u, -1.2337005501e+00f);
+    return fmaf(c, u, 1.0f);
+}
+
+__device__ __forceinline__ float cutoff_sq_fc(float u)
+{
+    const float c = cutoff_sq_c(u);
+    return c * c;
+}
+
+__device__ __forceinline__ void cutoff_sq(float u, float &fc, float &dfc_du)
+{
+    const float c = cutoff_sq_c(u);
+    float d = 2.8265248673e-06f;
+    d = fmaf(d, u, -1.2601021187e-04f);
+    d = fmaf(d, u, 3.6770410994e-03f);
+    d = fmaf(d, u, -6.2590442290e-02f);
+    d = fmaf(d, u, 5.0733901580e-01f);
+    d = fmaf(d, u, -1.2337005501e+00f);
+    fc = c * c;
+    dfc_du = 2.0f * c * d;
+}
+
 }  // namespace pimd

