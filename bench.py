@@ -34,6 +34,11 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X published dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X published FP64 vector peak
+# the adjoint's translation unit and every local header it includes
+ADJOINT_SOURCES = ["paper_2503_23728_amd/csrc/k_descriptors.hip", "paper_2503_23728_amd/csrc/device_common.hpp",
+                   "paper_2503_23728_amd/csrc/pair_terms.hpp", "paper_2503_23728_amd/csrc/pimd_internal.hpp"]
+
+
 def traffic_file(workload):
     return os.path.join(ROOT, "profiles", f"adjoint_traffic_{workload}.json")
 
@@ -41,11 +46,13 @@ def traffic_file(workload):
 def measured_traffic(workload):
     """HBM bytes per k_adjoint launch from the committed rocprofv3 counters, when
     they were taken on this workload and the kernel's sources have not changed
-    since (SHA-256 over the listed files, in order)."""
+    since (SHA-256 over ADJOINT_SOURCES, in order)."""
     import hashlib
     try:
         rec = json.load(open(traffic_file(workload)))
-        src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])
+        if rec["sources"] != ADJOINT_SOURCES:
+            return None
+        src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in ADJOINT_SOURCES)
     except (OSError, ValueError, KeyError, TypeError):
         return None
     if rec.get("workload") != workload or hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):

@@ -372,8 +372,10 @@ __global__ __launch_bounds__(256) void k_descriptors(const float4 *__restrict__ 
 // ---------------------------------------------------------------------------
 // adjoint: v[i][slot] = dE/d d_{i, slot}; per-atom virial -sum d (x) v
 // ---------------------------------------------------------------------------
+// At most 96 VGPRs (five waves per SIMD; the LDS of two-wave workgroups
+// admits five as well): 1-2 % faster than 101 VGPRs and four waves.
 template <int NETA, bool POW4>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adjoint(const float4 *__restrict__ posu, const BeadInfo *__restrict__ beads,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_adjoint(const float4 *__restrict__ posu, const BeadInfo *__restrict__ beads,
                                                  const int32_t *__restrict__ bead_of_ba, const int32_t *__restrict__ order,
                                                  const int32_t *__restrict__ nbr,
                                                  const int32_t *__restrict__ nbr_cnt,

@@ -14,9 +14,9 @@ constexpr int kMaxRad = 32;
 constexpr int kMaxPairs = kMaxElements * (kMaxElements + 1) / 2;   // element-pair blocks
 // slot pairs kept per centre by the descriptor forward for the adjoint: every
 // unordered pair of Kmax slots (16 bits each: the two slot indices)
-// Kept slot pairs per centre: all K(K-1)/2 pairs, and 128 entries that the
+// Kept slot pairs per centre: all K(K-1)/2 pairs, and 256 entries that the
 // adjoint's look-ahead loads may read past a block's last pair.
-__host__ __device__ inline int64_t tri_capacity(int Kmax) { return (int64_t)Kmax * (Kmax - 1) / 2 + 128; }
+__host__ __device__ inline int64_t tri_capacity(int Kmax) { return (int64_t)Kmax * (Kmax - 1) / 2 + 256; }
 constexpr int kG5Mom = 84;       // floats per (centre, element, eta) of the G5 moments: 81 and 3 of padding
 constexpr int kMaxBeads = 128;
 constexpr int kMaxNeighbors = 256;

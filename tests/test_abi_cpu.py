@@ -66,14 +66,14 @@ def test_skin_configs(lib):
 def test_g5_workspace_holds_the_moments(lib):
     # G5: per centre 84 floats of moments per (element, eta); G4 instead keeps
     # the in-range slot pairs for its adjoint (16 bits per pair of the 128 slots,
-    # and 128 entries of room for the adjoint's look-ahead loads) and ten block
+    # and 256 entries of room for the adjoint's look-ahead loads) and ten block
     # counts
     wl = S.workload(2)
     a = abi.pimd_workspace_size(_cfg(wl)[0])[1]
     b = abi.pimd_workspace_size(_cfg(S.with_g5(wl))[0])[1]
     m = wl.model
     moments = wl.bead_atoms * m.n_elements * len(m.ang_eta) * 84 * 4
-    pairs = wl.bead_atoms * ((128 * 127 // 2 + 128) * 2 + 10 * 4)
+    pairs = wl.bead_atoms * ((128 * 127 // 2 + 256) * 2 + 10 * 4)
     assert abs((b - a) - (moments - pairs)) <= 4096
 
 
