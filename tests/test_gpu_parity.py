@@ -145,7 +145,8 @@ def test_descriptors_match_oracle(name):
             worst = max(worst, np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-2)))
             off += s.n_atoms
     say(f"  descriptor rel err {worst:.2e}")
-    assert worst < 1e-5
+    # float32 sums of ~1e3 triplet terms, each rounded at ~6e-8 (measured 0.9-2.1e-6)
+    assert worst < 5e-6
 
 
 # ---------------------------------------------------------------- energies and forces
