@@ -149,17 +149,21 @@ __device__ __forceinline__ void for_each_triplet_in_range(const BlockWalk &bw, c
         // lanes past the own group sit far away: their test fails by distance
         const float4 A = own_ok ? recD[ia] : make_float4(3e18f, 3e18f, 3e18f, 0.0f);
         const uint32_t key_a = (uint32_t)ia << 16;
-        // partner slot p = (b + s) mod n_par, advanced by one per shift; its
-        // record is loaded one shift ahead
-        int p = (bw.tri ? bb : bb % bw.n_par) + bw.s0;
-        p -= p >= bw.n_par ? bw.n_par : 0;
-        float4 C = recD[bw.o_par + p];
-        auto test = [&](bool ok) {
-            const int ic = bw.o_par + p;
-            p = p + 1 == bw.n_par ? 0 : p + 1;
-            const float4 Cn = recD[bw.o_par + p];
+        // partner slot ic = o_par + (b + s) mod n_par, advanced by one per
+        // shift; its record is loaded one shift ahead, into the other of two
+        // registers (the shifts run in pairs, so no register copy per shift)
+        const int p_end = bw.o_par + bw.n_par;
+        // the wrap target in a vector register (the select per shift then
+        // needs no move); a lane shuffle yields a value the compiler keeps there
+        const int o_par_v = __shfl(bw.o_par, lane, kWave);
+        int ic_next = (bw.tri ? bb : bb % bw.n_par) + bw.s0;
+        ic_next = bw.o_par + ic_next - (ic_next >= bw.n_par ? bw.n_par : 0);
+        float4 Ca = recD[ic_next], Cb;
+        auto test = [&](bool ok, const float4 &C, float4 &Cn) {
+            const int ic = ic_next;
+            ic_next = ic + 1 == p_end ? o_par_v : ic + 1;
+            Cn = recD[ic_next];
             const float jx = C.x - A.x, jy = C.y - A.y, jz = C.z - A.z;
-            C = Cn;
             // bitwise (not short-circuit) so the test stays branch-free
             const bool inr = ok & (jx * jx + jy * jy + jz * jz < rc2);
             const uint64_t m = __builtin_amdgcn_ballot_w64(inr);
@@ -178,10 +182,17 @@ __device__ __forceinline__ void for_each_triplet_in_range(const BlockWalk &bw, c
                 qn -= kWave;
             }
         };
-        for (int s = bw.s0; s <= s_last; ++s)
-            test(true);
+        int s = bw.s0;
+        for (; s + 1 <= s_last; s += 2) {
+            test(true, Ca, Cb);
+            test(true, Cb, Ca);
+        }
+        if (s <= s_last) {
+            test(true, Ca, Cb);
+            Ca = Cb;
+        }
         if (has_half)
-            test(b < bw.s1);
+            test(b < bw.s1, Ca, Cb);
     }
     if (qn > 0) {
         wave_sync();
