@@ -383,12 +383,13 @@ def _nve_drift(wl, q, p, precision, dt, ps=0.25, samples=50, max_neighbors=192):
 
 
 def test_ice_nve_conserves_H_P_and_bf16_matches_fp32():
-    # energy conservation of the ice workload in NVE from one state
-    # equilibrated for 0.1 ps with PILE-L.  A per-step error in the
-    # normal-mode propagation (e.g. float32 rotation coefficients, whose
-    # cos^2 + sin^2 misses 1 by ~1e-7) shows as a drift per ps that grows as
-    # dt shrinks; the propagation is exact to rounding, so the drift stays at
-    # the noise level at dt/4, and the split BF16 MLP conserves H_P like FP32.
+    # energy conservation of the ice workload over 1 ps of NVE (4000 steps at
+    # dt = 0.25 fs) from one state equilibrated for 0.1 ps (400 steps) with
+    # PILE-L.  A per-step error in the normal-mode propagation (e.g. float32
+    # rotation coefficients, whose cos^2 + sin^2 misses 1 by ~1e-7) shows as a
+    # drift per ps that grows as dt shrinks; the propagation is exact to
+    # rounding, so the drift stays at the noise level at dt/4, and the split
+    # BF16 MLP conserves H_P like FP32.
     # Bead fluctuations in ice reach ~125 neighbours within 6 A: 192 slots.
     wl = S.workload(3)
     q0, p0 = S.initial_state(wl)
@@ -399,7 +400,7 @@ def test_ice_nve_conserves_H_P_and_bf16_matches_fp32():
     nvt.close()
     out = {}
     for prec, dt in (("fp32", 0.25), ("bf16", 0.25), ("bf16-plain", 0.25), ("fp32", 0.0625)):
-        out[prec, dt] = _nve_drift(wl, q, p, prec, dt)
+        out[prec, dt] = _nve_drift(wl, q, p, prec, dt, ps=1.0, samples=200)
         say(f"ice NVE {prec} dt {dt} fs: drift {out[prec, dt][0]:+.3e} eV/ps/atom, "
             f"rms {out[prec, dt][1]:.3e} eV/atom, median step-to-step {out[prec, dt][2]:.3e} eV/atom")
     kT = 8.617333262e-5 * wl.systems[0].temperature
@@ -407,14 +408,14 @@ def test_ice_nve_conserves_H_P_and_bf16_matches_fp32():
     # exact normal-mode propagation: no drift at dt/4
     assert abs(out["fp32", 0.0625][0]) < 0.25 * kT
     # at dt the velocity-Verlet error in H_P is O(dt^2) and follows the
-    # trajectory (a 0.25 ps window from a state 0.1 ps out of the lattice
-    # still relaxes): FP32 and the split BF16 MLP share one trajectory for
-    # most of the window, so their trends agree, and the error shrinks with
-    # dt like an O(dt^2) error (a propagation error would not).  H_P moves in
-    # steps at close approaches, whose timing late in the window is chaotic
-    # (it changes with the rounding of the forces), and one such step can
-    # dominate the rms of the residual; the median change between samples
-    # 5 fs apart measures the typical error (ratio ~6.5 for dt/4 here)
-    assert abs(out["bf16", 0.25][0] - out["fp32", 0.25][0]) < 0.5 * kT
+    # trajectory (the state, 0.1 ps out of the lattice, still relaxes), so its
+    # linear trend is bounded, not zero, and shrinks with dt like an O(dt^2)
+    # error (a propagation error would not).  H_P moves in steps at close
+    # approaches, whose timing is chaotic (it changes with the rounding of the
+    # forces): one such step can set the rms of the residual, and over 1 ps
+    # the FP32 and BF16 trajectories part, so their trends differ by chance.
+    # The median change of H_P between samples 5 fs apart measures the typical
+    # error: it falls ~8x at dt/4, and the BF16 split matches FP32 in it
     assert abs(out["fp32", 0.25][0]) < 4 * kT and abs(out["bf16", 0.25][0]) < 4 * kT
     assert out["fp32", 0.25][2] > 4 * out["fp32", 0.0625][2]
+    assert abs(out["bf16", 0.25][2] - out["fp32", 0.25][2]) < 0.25 * out["fp32", 0.25][2]
