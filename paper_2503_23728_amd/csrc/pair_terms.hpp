@@ -21,6 +21,13 @@ __device__ __forceinline__ float exp2_hw(float a) { return __builtin_amdgcn_exp2
 // it carries no rounding from wrapping large coordinates.  The neighbour set
 // itself comes from the float32 test of the neighbour kernel; for |d| < rc <
 // L/2 the minimum image is unique, so both choose the same image.
+// r = r_f + r_lo without an FP64 square root or division: r_f is the float32
+// square root of r^2 (rounded), and the residual e = r^2 - r_f^2 is exact in
+// FP64 (r_f^2 has 48 significant bits and the two terms are within a factor 2
+// of each other), so r = r_f + e/(2 r_f) up to e^2/(8 r_f^3) ~ 1e-14 r; r_lo
+// is that correction in float32.  1/r is the float32 reciprocal of r_f after
+// one Newton step on r_f + r_lo (as accurate as the rounded FP64 quotient in a
+// float32 emulation).
 __device__ __forceinline__ void displacement(const float4 &pi, const float4 &pj, const BeadInfo &bi, float3 &d,
                                              float &r, float &r_lo, float &inv_r)
 {
@@ -30,11 +37,15 @@ __device__ __forceinline__ void displacement(const float4 &pi, const float4 &pj,
         dy -= bi.L64[1] * rint(dy * bi.invL64[1]);
         dz -= bi.L64[2] * rint(dz * bi.invL64[2]);
     }
-    const double r64 = sqrt(dx * dx + dy * dy + dz * dz);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const float rf = __builtin_amdgcn_sqrtf((float)r2);
+    const double e = fma(-(double)rf, (double)rf, r2);
+    const float inv = __builtin_amdgcn_rcpf(rf);
     d = make_float3((float)dx, (float)dy, (float)dz);
-    r = (float)r64;
-    r_lo = (float)(r64 - (double)r);
-    inv_r = (float)(1.0 / r64);
+    r = rf;
+    r_lo = (float)e * (0.5f * inv);
+    const float t = fmaf(-rf, inv, 1.0f) - r_lo * inv;
+    inv_r = fmaf(inv, t, inv);
 }
 
 // Cutoff function and derivative from x = r/rc in [0, 1):
