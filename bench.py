@@ -218,13 +218,24 @@ def plain_fp32(wl, steps, warmup, device, shape=None, skin=0.0):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(wl, budget_s=20.0):
+def force_error(F, F_ref):
+    """max_i |F_i - F_i^ref| / max(|F_i^ref|, 0.1 F_rms^ref): the parity tests' metric."""
+    F = np.asarray(F, dtype=np.float64).reshape(-1, 3)
+    F_ref = np.asarray(F_ref, dtype=np.float64).reshape(-1, 3)
+    nref = np.linalg.norm(F_ref, axis=1)
+    floor = 0.1 * np.sqrt(np.mean(nref ** 2))
+    return float(np.max(np.linalg.norm(F - F_ref, axis=1) / np.maximum(nref, floor)))
+
+
+def cpu_baseline(wl, budget_s=20.0, gpu_forces=None):
     """FP64 oracle on the host cores over a bounded sample of the workload:
     whole integrator steps of the first ring polymer(s), repeated until about
     budget_s seconds have passed; when one step of the first ring polymer is
     itself too large for that (more than 20,000 bead-atoms), force evaluations
     of its beads one at a time (every atom of a bead with all its neighbours;
-    the integrator is a few percent of a step on either side)."""
+    the integrator is a few percent of a step on either side).  gpu_forces:
+    the benchmarked path's forces at the same initial state, compared with the
+    oracle's forces of the sample (force_err_vs_fp64)."""
     from paper_2503_23728_amd import synthetic as S
     from oracle import bpnn, gfn, ring
     q, p = S.initial_state(wl)
@@ -235,22 +246,28 @@ def cpu_baseline(wl, budget_s=20.0):
         n_at = first.n_atoms
         t0 = time.perf_counter()
         k = 0
+        err = 0.0
         while True:
             qb = q[k * n_at:(k + 1) * n_at]
             if hasattr(wl.model, "width"):
                 sub = S.Workload(wl.name, [S.System(n_at, 1, first.temperature, first.box, first.species,
                                                     first.q0)], wl.model, wl.dt, wl.tau0, wl.pile_lambda,
                                  wl.n_steps, wl.philox_seed, wl.momentum_seed)
-                gfn.forces(sub, qb)
+                F_ref = gfn.forces(sub, qb)
             else:
-                bpnn.bead_energy_forces(wl.model, qb, first.species, first.box)
+                F_ref = bpnn.bead_energy_forces(wl.model, qb, first.species, first.box)[1]
+            if gpu_forces is not None:
+                err = max(err, force_error(gpu_forces[k * n_at:(k + 1) * n_at], F_ref))
             k += 1
             if time.perf_counter() - t0 > budget_s or k >= first.n_beads:
                 break
         dt = time.perf_counter() - t0
-        return dict(value=n_at * k / dt, unit="bead-atom force evals/s", cores=threads, kind="oracle",
-                    sample=f"{k} FP64 oracle force evaluations of whole beads of {n_at} atoms "
-                           f"({n_at * k} bead-atoms, {dt:.1f} s)")
+        out = dict(value=n_at * k / dt, unit="bead-atom force evals/s", cores=threads, kind="oracle",
+                   sample=f"{k} FP64 oracle force evaluations of whole beads of {n_at} atoms "
+                          f"({n_at * k} bead-atoms, {dt:.1f} s)")
+        if gpu_forces is not None:
+            out["force_err_vs_fp64"] = {"value": err, "sample": f"every atom of beads 0-{k - 1} at the initial state"}
+        return out
     systems, rows, n_sys = [], 0, 0
     for s in wl.systems:
         systems.append(s)
@@ -269,6 +286,7 @@ def cpu_baseline(wl, budget_s=20.0):
     rp = ring.RingPolymers([(s.n_atoms, s.n_beads, s.temperature, wl.model.masses[s.species]) for s in systems],
                            wl.dt, wl.tau0, wl.pile_lambda, wl.philox_seed, fn)
     rp.set_state(q[:rows].astype(np.float64), p[:rows].astype(np.float64))
+    err = force_error(gpu_forces[:rows], fn(q[:rows])[1]) if gpu_forces is not None else None
     t0 = time.perf_counter()
     n = 0
     while True:
@@ -277,9 +295,13 @@ def cpu_baseline(wl, budget_s=20.0):
         if time.perf_counter() - t0 > budget_s or n >= 200:
             break
     dt = time.perf_counter() - t0
-    return dict(value=rows * n / dt, unit="bead-atom force evals/s", cores=threads, kind="oracle",
-                sample=f"{n} FP64 oracle integrator steps of {len(systems)} ring polymer(s), {rows} bead-atoms "
-                       f"({dt:.1f} s)")
+    out = dict(value=rows * n / dt, unit="bead-atom force evals/s", cores=threads, kind="oracle",
+               sample=f"{n} FP64 oracle integrator steps of {len(systems)} ring polymer(s), {rows} bead-atoms "
+                      f"({dt:.1f} s)")
+    if err is not None:
+        out["force_err_vs_fp64"] = {"value": err, "sample": f"every bead-atom of the first {len(systems)} ring "
+                                                            f"polymer(s) at the initial state"}
+    return out
 
 
 def extra_keys(args, wl, eng, skin, shape, device):
@@ -534,7 +556,17 @@ def main():
     if not args.no_extras and not gfn_mode and not args.metad and args.angular == "g4":
         out.update(extra_keys(args, wl, eng, skin, shape, device))
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl)
+        # the benchmarked path's forces at the initial state, for the oracle sample to check
+        # (the potential alone: not with a metadynamics bias)
+        F_init = None
+        if spec is None:
+            q_init, _ = S.initial_state(wl)
+            F_init = eng.energy_forces(torch.from_numpy(q_init).to(device))[1].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(wl, gpu_forces=F_init)
+        if "force_err_vs_fp64" in out["cpu_baseline"]:
+            out["force_err_vs_fp64"] = dict(out["cpu_baseline"]["force_err_vs_fp64"],
+                                            metric="max_i |F_i - F_i^FP64| / max(|F_i^FP64|, 0.1 F_rms)")
+            print(f"[bench] force err vs FP64 {out['force_err_vs_fp64']['value']:.2e}", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 
