@@ -436,9 +436,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
                 }
                 float acc = 0.0f;
                 for (int t = 0; t < dp.n_rad; ++t) {
-                    const float x = (r - dp.rad_center[t]) + (r_lo - dp.rad_center_lo[t]);
-                    const float eta = dp.rad_eta[t];
-                    acc += gl[e * dp.n_rad + t] * exp2_hw(-eta * kLog2e * x * x) * (-2.0f * eta * x * fc + dfc);
+                    const float4 rp = dp.rad_pack[t];
+                    const float x = (r - rp.x) + (r_lo - rp.y);
+                    acc += gl[e * dp.n_rad + t] * exp2_hw(rp.z * x * x) * (rp.w * x * fc + dfc);
                 }
                 const float c = acc * inv_r;
                 vacc[3 * n] = (double)(c * d.x);

@@ -243,9 +243,9 @@ __global__ __launch_bounds__(64) void k_sm_adjoint(const float4 *__restrict__ po
         cutoff_fn(r * inv_rc, dp.pi_over_rc, fc, dfc);
         float acc = 0.0f;
         for (int t = 0; t < dp.n_rad; ++t) {
-            const float x = (r - dp.rad_center[t]) + (r_lo - dp.rad_center_lo[t]);
-            const float eta = dp.rad_eta[t];
-            acc += g[(ej * dp.n_rad + t) * kWave + lane] * exp2_hw(-eta * kLog2e * x * x) * (-2.0f * eta * x * fc + dfc);
+            const float4 rp = dp.rad_pack[t];
+            const float x = (r - rp.x) + (r_lo - rp.y);
+            acc += g[(ej * dp.n_rad + t) * kWave + lane] * exp2_hw(rp.z * x * x) * (rp.w * x * fc + dfc);
         }
         const float c = acc * inv_r;
         v[j][0] = (double)(c * d.x);

@@ -1091,6 +1091,8 @@ pimd_status pimd_init(const pimd_config *cfg, void *workspace_dev, size_t ws_byt
             dp.rad_center[s] = (float)mv.rad_center[s];
             dp.rad_center_lo[s] = (float)(mv.rad_center[s] - (double)dp.rad_center[s]);
             dp.rad_eta[s] = (float)mv.rad_eta[s];
+            dp.rad_pack[s] = make_float4(dp.rad_center[s], dp.rad_center_lo[s], -dp.rad_eta[s] * 1.4426950408889634f,
+                                         -2.0f * dp.rad_eta[s]);
         }
     }
     if (pl.gfn) {

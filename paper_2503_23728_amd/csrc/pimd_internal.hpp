@@ -56,6 +56,10 @@ struct DescParams {
     float rad_center[kMaxRad];     // R_s rounded to float ...
     float rad_center_lo[kMaxRad];  // ... and the remainder R_s - float(R_s)
     float rad_eta[kMaxRad];
+    // per radial function, as the slot derivatives use it: R_s, its remainder,
+    // the exponent factor -eta log2(e) (float product) and -2 eta; one
+    // 16-byte scalar load per function
+    float4 rad_pack[kMaxRad];
     float ang_eta[2];
     int32_t eta_pow4;              // 1: ang_eta[1] == 4 ang_eta[0] exactly, so exp(-eta_1 x) = exp(-eta_0 x)^4
     int32_t angular;               // 0: G4 angular functions, 1: G5
